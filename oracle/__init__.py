@@ -1,0 +1,358 @@
+"""CPU oracle for the Heat-bath CI variational step -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct implementations of what the GPU library
+computes, used only by ``tests/``, ``__graft_entry__.smoke()`` and the
+benchmark's CPU-baseline leg.  The product path never imports this package.
+It shares no code with the GPU library; the only common dependency is the
+seeded input generator ``hci_synth``, which holds none of the method's
+arithmetic.
+
+Where each function comes from (paper sections/equations):
+
+* ``hamiltonian_by_operators`` / ``hij`` -- the second-quantised active-space
+  Hamiltonian applied to determinants, by the operator definition and by the
+  textbook Slater-Condon rules (the paper notes double-excitation elements
+  depend on the orbitals only: Sec. "Variational Stage").
+* ``select`` -- the HCI criterion, Sec. "Variational Stage", eq. (criteria) and
+  the HCI importance function: D_a is kept when |H_ai c_i| > eps1 for some
+  D_i in V.  Written as its definition (every excitation of every D_i is
+  evaluated), not as the heat-bath walk.
+* ``select_bruteforce`` -- the same criterion evaluated over the whole
+  determinant space with the operator-built H (tiny spaces).
+* ``hci`` -- the variational macro-iteration V <- V + C(eps1) followed by
+  re-diagonalisation (Sec. "Variational Stage", Fig. 1a), with a library
+  eigensolver standing in for Davidson (eq. variational).
+* ``rdm12`` -- density matrices by operator application (Sec.
+  "Computational Details": contracted with integral derivatives in
+  eq. vdedk2 / eq. lambda).
+* ``pt2_*`` -- eps2-screened Epstein-Nesbet PT2 and its pieces
+  (eq. h0, eq. pt, eq. pt_hci, Hylleraas functional eq. hylleraas).
+* ``zvector_dense`` -- the Lagrange-multiplier equation for lambda_c
+  (eq. lagd, eq. lagc and the simplified form after them).
+
+Readings where the paper is silent (sign convention, integral notation,
+RDM index order, threshold rounding) are listed in the C source header.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hci_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+u64p = ctypes.POINTER(ctypes.c_uint64)
+f64p = ctypes.POINTER(ctypes.c_double)
+i64p = ctypes.POINTER(ctypes.c_long)
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB_PATH)
+        L.orc_diag.restype = ctypes.c_double
+        L.orc_diag.argtypes = [ctypes.c_int, f64p, f64p, ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_hij.restype = ctypes.c_double
+        L.orc_hij.argtypes = [ctypes.c_int, f64p, f64p] + [ctypes.c_uint64] * 4
+        L.orc_excitations.restype = ctypes.c_long
+        L.orc_excitations.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, u64p, ctypes.c_long]
+        L.orc_find.restype = ctypes.c_long
+        L.orc_find.argtypes = [u64p, ctypes.c_long, ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_select.restype = ctypes.c_long
+        L.orc_select.argtypes = [ctypes.c_int, f64p, f64p, u64p, ctypes.c_long, f64p,
+                                 ctypes.c_double, u64p, ctypes.c_long]
+        L.orc_sigma_rows.restype = None
+        L.orc_sigma_rows.argtypes = [ctypes.c_int, f64p, f64p, u64p, ctypes.c_long, f64p,
+                                     i64p, ctypes.c_long, f64p]
+        L.orc_row_counts.restype = None
+        L.orc_row_counts.argtypes = [ctypes.c_int, u64p, ctypes.c_long, i64p]
+        L.orc_csr_fill.restype = None
+        L.orc_csr_fill.argtypes = [ctypes.c_int, f64p, f64p, u64p, ctypes.c_long, i64p, i64p, f64p]
+        L.orc_rdm12.restype = None
+        L.orc_rdm12.argtypes = [ctypes.c_int, u64p, ctypes.c_long, f64p, f64p, f64p, f64p]
+        L.orc_rdm2_element.restype = ctypes.c_double
+        L.orc_rdm2_element.argtypes = [ctypes.c_int, u64p, ctypes.c_long, f64p, f64p] + [ctypes.c_int] * 4
+        L.orc_rdm1_element.restype = ctypes.c_double
+        L.orc_rdm1_element.argtypes = [ctypes.c_int, u64p, ctypes.c_long, f64p, f64p] + [ctypes.c_int] * 2
+        L.orc_apply_h.restype = ctypes.c_long
+        L.orc_apply_h.argtypes = [ctypes.c_int, f64p, f64p, ctypes.c_uint64, ctypes.c_uint64,
+                                  u64p, f64p, ctypes.c_long]
+        _lib = L
+    return _lib
+
+
+def _f64(x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return x, x.ctypes.data_as(f64p)
+
+
+def _u64(x):
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    return x, x.ctypes.data_as(u64p)
+
+
+def _i64(x):
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    return x, x.ctypes.data_as(i64p)
+
+
+# ---------------------------------------------------------------- elements
+def diag(h, g, det) -> float:
+    n = h.shape[0]
+    h, hp = _f64(h)
+    g, gp = _f64(g)
+    return lib().orc_diag(n, hp, gp, int(det[0]), int(det[1]))
+
+
+def hij(h, g, det_i, det_j) -> float:
+    """<D_j|H|D_i> by the Slater-Condon rules."""
+    n = h.shape[0]
+    h, hp = _f64(h)
+    g, gp = _f64(g)
+    return lib().orc_hij(n, hp, gp, int(det_i[0]), int(det_i[1]), int(det_j[0]), int(det_j[1]))
+
+
+def excitations(n, det) -> np.ndarray:
+    L = lib()
+    m = L.orc_excitations(n, int(det[0]), int(det[1]), None, 0)
+    out = np.zeros((m, 2), dtype=np.uint64)
+    L.orc_excitations(n, int(det[0]), int(det[1]), out.ctypes.data_as(u64p), m)
+    return out
+
+
+def apply_h(h, g, det):
+    """H|D> as {det: amplitude}, by applying each operator term (no rules)."""
+    n = h.shape[0]
+    h, hp = _f64(h)
+    g, gp = _f64(g)
+    L = lib()
+    cap = (2 * n) ** 2 + (2 * n) ** 4
+    dets = np.zeros((cap, 2), dtype=np.uint64)
+    amp = np.zeros(cap)
+    k = L.orc_apply_h(n, hp, gp, int(det[0]), int(det[1]), dets.ctypes.data_as(u64p),
+                      amp.ctypes.data_as(f64p), cap)
+    out = {}
+    for t in range(k):
+        key = (int(dets[t, 0]), int(dets[t, 1]))
+        out[key] = out.get(key, 0.0) + float(amp[t])
+    return out
+
+
+def hamiltonian_by_operators(h, g, dets) -> np.ndarray:
+    """Dense H on a determinant list built by operator application."""
+    dets = np.asarray(dets, dtype=np.uint64)
+    index = {(int(a), int(b)): k for k, (a, b) in enumerate(dets)}
+    m = len(dets)
+    H = np.zeros((m, m))
+    for j in range(m):
+        for key, amp in apply_h(h, g, dets[j]).items():
+            i = index.get(key)
+            if i is not None:
+                H[i, j] += amp
+    return H
+
+
+def row_counts(n, V) -> np.ndarray:
+    V, vp = _u64(V)
+    cnt = np.zeros(len(V), dtype=np.int64)
+    lib().orc_row_counts(n, vp, len(V), cnt.ctypes.data_as(i64p))
+    return cnt
+
+
+def hamiltonian_csr(h, g, V):
+    """Sparse H on the sorted space V by the Slater-Condon rules (scipy CSR)."""
+    import scipy.sparse as sp
+    n = h.shape[0]
+    h, hp = _f64(h)
+    g, gp = _f64(g)
+    V, vp = _u64(V)
+    cnt = row_counts(n, V)
+    rowptr = np.zeros(len(V) + 1, dtype=np.int64)
+    np.cumsum(cnt, out=rowptr[1:])
+    cols = np.zeros(rowptr[-1], dtype=np.int64)
+    vals = np.zeros(rowptr[-1])
+    lib().orc_csr_fill(n, hp, gp, vp, len(V), rowptr.ctypes.data_as(i64p),
+                       cols.ctypes.data_as(i64p), vals.ctypes.data_as(f64p))
+    return sp.csr_matrix((vals, cols, rowptr), shape=(len(V), len(V)))
+
+
+def sigma(h, g, V, c, rows=None) -> np.ndarray:
+    """sigma_i = sum_j H_ij c_j (j over V), for all rows or the listed ones."""
+    n = h.shape[0]
+    h, hp = _f64(h)
+    g, gp = _f64(g)
+    V, vp = _u64(V)
+    c, cp = _f64(c)
+    if rows is None:
+        out = np.zeros(len(V))
+        lib().orc_sigma_rows(n, hp, gp, vp, len(V), cp, None, 0, out.ctypes.data_as(f64p))
+    else:
+        rows, rp = _i64(rows)
+        out = np.zeros(len(rows))
+        lib().orc_sigma_rows(n, hp, gp, vp, len(V), cp, rp, len(rows), out.ctypes.data_as(f64p))
+    return out
+
+
+# ---------------------------------------------------------------- spaces
+def sort_unique(dets) -> np.ndarray:
+    dets = np.asarray(dets, dtype=np.uint64).reshape(-1, 2)
+    if len(dets) == 0:
+        return dets
+    order = np.lexsort((dets[:, 1], dets[:, 0]))
+    d = dets[order]
+    keep = np.ones(len(d), dtype=bool)
+    keep[1:] = (d[1:, 0] != d[:-1, 0]) | (d[1:, 1] != d[:-1, 1])
+    return np.ascontiguousarray(d[keep])
+
+
+def merge(V, C) -> np.ndarray:
+    return sort_unique(np.concatenate([np.asarray(V, np.uint64).reshape(-1, 2),
+                                       np.asarray(C, np.uint64).reshape(-1, 2)]))
+
+
+def select(h, g, V, c, eps) -> np.ndarray:
+    """C(eps): every determinant outside V with fl(|H_ai| |c_i|) > eps for some
+    D_i in V (HCI criterion, eq. criteria), sorted and unique."""
+    n = h.shape[0]
+    h, hp = _f64(h)
+    g, gp = _f64(g)
+    V, vp = _u64(V)
+    c, cp = _f64(c)
+    L = lib()
+    total = L.orc_select(n, hp, gp, vp, len(V), cp, float(eps), None, 0)
+    out = np.zeros((max(total, 1), 2), dtype=np.uint64)
+    L.orc_select(n, hp, gp, vp, len(V), cp, float(eps), out.ctypes.data_as(u64p), total)
+    return sort_unique(out[:total])
+
+
+def select_bruteforce(h, g, V, c, eps, space) -> np.ndarray:
+    """The same criterion over a whole determinant space with the
+    operator-built H: keep a outside V when max_i |H_ai c_i| > eps."""
+    space = np.asarray(space, dtype=np.uint64)
+    Hs = hamiltonian_by_operators(h, g, space)
+    index = {(int(a), int(b)): k for k, (a, b) in enumerate(space)}
+    vi = np.array([index[(int(a), int(b))] for a, b in V], dtype=np.int64)
+    inV = np.zeros(len(space), dtype=bool)
+    inV[vi] = True
+    f = np.max(np.abs(Hs[:, vi]) * np.abs(np.asarray(c))[None, :], axis=1)
+    keep = (f > eps) & ~inV
+    return sort_unique(space[keep])
+
+
+# ---------------------------------------------------------------- solvers
+def lowest_eigenpair(h, g, V, tol=1e-12, v0=None, dense_max=3000):
+    """Lowest eigenpair of H on V: dense LAPACK below dense_max, else Lanczos
+    (scipy eigsh) on the CSR matrix.  Sign fixed so the largest |c_i| is > 0."""
+    m = len(V)
+    if m <= dense_max:
+        H = hamiltonian_csr(h, g, V).toarray()
+        w, U = np.linalg.eigh(H)
+        e, c = float(w[0]), U[:, 0].copy()
+    else:
+        import scipy.sparse.linalg as sla
+        H = hamiltonian_csr(h, g, V)
+        w, U = sla.eigsh(H, k=1, which="SA", tol=tol, v0=v0)
+        e, c = float(w[0]), U[:, 0].copy()
+    k = int(np.argmax(np.abs(c)))
+    if c[k] < 0:
+        c = -c
+    return e, c
+
+
+def hci(h, g, nalpha, nbeta, eps1, max_iter=20, V0=None, tol=1e-12, dense_max=3000):
+    """HCI variational stage: start from the aufbau determinant (or V0), select
+    C(eps1), merge, re-diagonalise, until nothing new is added or max_iter."""
+    n = h.shape[0]
+    if V0 is None:
+        V = np.array([[(1 << nalpha) - 1, (1 << nbeta) - 1]], dtype=np.uint64)
+    else:
+        V = sort_unique(V0)
+    e, c = lowest_eigenpair(h, g, V, tol=tol, dense_max=dense_max)
+    history = [(len(V), e)]
+    for _ in range(max_iter):
+        C = select(h, g, V, c, eps1)
+        if len(C) == 0:
+            break
+        Vn = merge(V, C)
+        # warm start: previous coefficients placed at their new rows
+        pos = np.searchsorted(_keys(Vn), _keys(V))
+        v0 = np.zeros(len(Vn))
+        v0[pos] = c
+        V = Vn
+        e, c = lowest_eigenpair(h, g, V, tol=tol, v0=v0, dense_max=dense_max)
+        history.append((len(V), e))
+    return V, c, e, history
+
+
+def _keys(V):
+    """Structured view for ordered searches over (alpha, beta)."""
+    V = np.ascontiguousarray(V, dtype=np.uint64)
+    return V.view(np.dtype([("a", np.uint64), ("b", np.uint64)])).ravel()
+
+
+def find(V, dets) -> np.ndarray:
+    """Row index in sorted V of each determinant (-1 if absent)."""
+    kv, kd = _keys(V), _keys(np.asarray(dets, np.uint64).reshape(-1, 2))
+    pos = np.searchsorted(kv, kd)
+    ok = pos < len(kv)
+    res = np.full(len(kd), -1, dtype=np.int64)
+    res[ok] = np.where(kv[pos[ok]] == kd[ok], pos[ok], -1)
+    return res
+
+
+# ---------------------------------------------------------------- RDMs
+def rdm12(n, V, bra, ket) -> Tuple[np.ndarray, np.ndarray]:
+    """gamma_pq = sum_s <bra|a+_ps a_qs|ket>,
+    Gamma_pqrs = sum_st <bra|a+_ps a+_rt a_st a_qs|ket>, by operator application."""
+    V, vp = _u64(V)
+    bra, bp = _f64(bra)
+    ket, kp = _f64(ket)
+    r1 = np.zeros((n, n))
+    r2 = np.zeros((n, n, n, n))
+    lib().orc_rdm12(n, vp, len(V), bp, kp, r1.ctypes.data_as(f64p), r2.ctypes.data_as(f64p))
+    return r1, r2
+
+
+def rdm2_element(n, V, bra, ket, p, q, r, s) -> float:
+    V, vp = _u64(V)
+    bra, bp = _f64(bra)
+    ket, kp = _f64(ket)
+    return lib().orc_rdm2_element(n, vp, len(V), bp, kp, p, q, r, s)
+
+
+def rdm1_element(n, V, bra, ket, p, q) -> float:
+    V, vp = _u64(V)
+    bra, bp = _f64(bra)
+    ket, kp = _f64(ket)
+    return lib().orc_rdm1_element(n, vp, len(V), bp, kp, p, q)
+
+
+def energy_from_rdms(h, g, r1, r2, ecore=0.0) -> float:
+    """E = E_core + sum h_pq gamma_pq + 1/2 sum (pq|rs) Gamma_pqrs."""
+    return float(ecore + np.sum(h * r1) + 0.5 * np.sum(g * r2))
+
+
+def symmetrize8(t) -> np.ndarray:
+    """Average of a 4-index tensor over the 8 real-orbital integral symmetries."""
+    perms = [(0, 1, 2, 3), (1, 0, 2, 3), (0, 1, 3, 2), (1, 0, 3, 2),
+             (2, 3, 0, 1), (3, 2, 0, 1), (2, 3, 1, 0), (3, 2, 1, 0)]
+    return sum(np.transpose(t, p) for p in perms) / 8.0
