@@ -1,0 +1,232 @@
+/*
+ * hci.h -- C ABI of the MI355X (gfx950) Heat-bath CI variational step.
+ *
+ * Method: Smith, Mussard, Holmes, Sharma, "Cheap and near exact CASSCF with
+ * large active spaces" (arXiv:1708.07544).  The library takes active-space
+ * integrals in and returns the variational energy, the wavefunction, the
+ * one- and two-particle density matrices and the energy's derivatives with
+ * respect to the integrals (the quantities an orbital optimiser consumes:
+ * Sec. "HCI self-consistent field", eq. vdedk2 and eq. lambda).
+ *
+ * Conventions used by every entry point:
+ *   - A determinant is two 64-bit occupation words {alpha, beta}; orbital p
+ *     is bit p (norb <= 64).  Fermion signs follow Jordan-Wigner order with
+ *     all alpha creators to the left of all beta creators, ascending orbital
+ *     index within a spin.
+ *   - Determinant lists are uint64_t[n][2] = {alpha, beta}, strictly
+ *     ascending in (alpha, beta) lexicographic order, every row with
+ *     popcount(alpha) == nalpha and popcount(beta) == nbeta.
+ *   - Integrals: h[p][q] (symmetric) and g[p][q][r][s] = (pq|rs) in chemist
+ *     notation, 8-fold symmetric, both float64 row-major.
+ *   - H = ecore + sum_{pq,s} h_pq a+_ps a_qs
+ *         + 1/2 sum_{pqrs,st} (pq|rs) a+_ps a+_rt a_st a_qs.
+ *   - Density matrices are spin-traced:
+ *       rdm1[p][q]       = sum_s  <bra| a+_ps a_qs |ket>
+ *       rdm2[p][q][r][s] = sum_st <bra| a+_ps a+_rt a_st a_qs |ket>
+ *     so that E = ecore + sum h_pq rdm1_pq + 1/2 sum (pq|rs) rdm2_pqrs
+ *     (the paper's Gamma_ijkl = <a+_i a+_j a_k a_l> with indices reordered).
+ *
+ * Memory and streams:
+ *   - Every pointer argument marked "device" is a caller-owned device buffer
+ *     on the context's GPU; "host" pointers are ordinary host memory.  The
+ *     library never frees caller memory.
+ *   - Scratch and cached structures are allocated through the context's
+ *     allocator (or hipMalloc when none is given) and released by
+ *     hci_ctx_destroy.  The context caches, for the most recently used
+ *     determinant list, its bucket/adjacency structure and the stored
+ *     Hamiltonian; the cache is keyed by the list's address, length and a
+ *     content hash computed on the GPU, so editing a list in place is safe.
+ *   - All work is enqueued on `stream` (a hipStream_t; NULL = default
+ *     stream).  Calls that return host scalars synchronise that stream.
+ *
+ * Errors: every entry point returns an hci_status.  No C++ exception crosses
+ * the ABI.  hci_last_error() returns a thread-local message for the last
+ * failing call.  A context must not be used by two threads at once.
+ */
+#ifndef HCI_MI355X_H
+#define HCI_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HCI_OK = 0,
+    HCI_E_ARG = -1,         /* invalid argument or malformed determinant list */
+    HCI_E_NOMEM = -2,       /* an allocation failed */
+    HCI_E_CAPACITY = -3,    /* output capacity too small; required size reported */
+    HCI_E_NOCONV = -4,      /* iterative solver hit max_iter; best result written */
+    HCI_E_HIP = -5,         /* a HIP runtime call failed */
+    HCI_E_UNSUPPORTED = -6  /* option not available */
+} hci_status;
+
+typedef enum { HCI_FP64 = 0, HCI_FP32_MIXED = 1 } hci_precision;
+
+typedef enum {
+    HCI_SIGMA_AUTO = 0,      /* stored when the Hamiltonian fits the memory budget */
+    HCI_SIGMA_STORED = 1,    /* build the sparse Hamiltonian once, then stream it */
+    HCI_SIGMA_RECOMPUTE = 2  /* regenerate connections and elements every product */
+} hci_sigma_mode;
+
+typedef struct {
+    void* (*alloc)(size_t bytes, void* stream, void* user); /* NULL on failure */
+    void (*free)(void* ptr, void* user);
+    void* user;
+} hci_allocator;
+
+typedef struct hci_ctx_s* hci_ctx;
+
+/* ------------------------------------------------------------------ context
+ * Stage the integrals on the GPU and build the heat-bath tables: for every
+ * occupied pair the double-excitation magnitudes |H| sorted in descending
+ * order, computed once per integral set (Sec. "Variational Stage": the
+ * magnitudes depend on the orbitals only and are sorted before the run;
+ * Fig. 1b).
+ *   norb in [1,64]; 0 <= nalpha, nbeta <= norb.
+ *   h: device float64 [norb][norb]; g: device float64 [norb]^4; both are
+ *   copied, the caller may free them after the call returns.
+ *   alloc: optional; copied by value.  stream: hipStream_t for the set-up.
+ *   out: receives the new context.  Errors: HCI_E_ARG, HCI_E_NOMEM, HCI_E_HIP. */
+int hci_ctx_create(int norb, int nalpha, int nbeta, const double* h, const double* g,
+                   double ecore, const hci_allocator* alloc, void* stream, hci_ctx* out);
+
+/* Replace the integrals (same norb) and rebuild the tables; drops the cached
+ * Hamiltonian.  Same argument rules as hci_ctx_create. */
+int hci_ctx_update_integrals(hci_ctx ctx, const double* h, const double* g, double ecore,
+                             void* stream);
+
+/* Release everything the context owns.  NULL is accepted. */
+int hci_ctx_destroy(hci_ctx ctx);
+
+/* Memory budget (bytes) for the stored Hamiltonian in HCI_SIGMA_AUTO mode
+ * (default: 64 GiB). */
+int hci_ctx_set_stored_budget(hci_ctx ctx, int64_t bytes);
+
+/* Per-kernel timing with HIP events on the launch stream (off by default).
+ * When enabled, every library kernel launch is bracketed by events and its
+ * duration accumulated under the kernel's name. */
+int hci_ctx_set_timing(hci_ctx ctx, int enable);
+
+/* Accumulated launches and milliseconds for a kernel name since the last
+ * reset (synchronises the context's recorded events).  Unknown names give
+ * count 0.  reset != 0 clears all counters after reading. */
+int hci_ctx_kernel_time(hci_ctx ctx, const char* name, int64_t* launches, double* total_ms,
+                        int reset);
+
+/* Thread-local description of the last error ("" if none). */
+const char* hci_last_error(void);
+
+/* ---------------------------------------------------------------- selection
+ * One HCI selection step (Sec. "Variational Stage", eq. criteria with the
+ * HCI importance function): C(eps1) is the set of determinants D_a not in V
+ * for which |H_ai c_i| > eps1 for at least one D_i in V; the routine writes
+ * V + C(eps1), sorted and unique, to out_dets.  Doubles are found by walking
+ * the pre-sorted heat-bath lists of each occupied pair of D_i only while the
+ * magnitude can still pass (Fig. 1b); singles are evaluated exactly.  The
+ * test is fl(|H_ai| * |c_i|) > eps1 in float64 (strict), identical on every
+ * path.
+ *   dets: device [n_var][2] sorted unique list V; c: device float64 [n_var].
+ *   out_dets: device [cap][2]; may not alias dets.  n_out (host) receives the
+ *   size of V + C; on HCI_E_CAPACITY it holds the required capacity and
+ *   out_dets is unspecified.  Synchronises the stream. */
+int hci_select(hci_ctx ctx, const uint64_t* dets, const double* c, int64_t n_var,
+               double eps1, uint64_t* out_dets, int64_t cap, int64_t* n_out, void* stream);
+
+/* Carry a vector from V to a superset V' (both sorted unique lists), as the
+ * warm start of the next Davidson solve after V' = V + C (Fig. 1a):
+ * c_new[k'] = c[k] where V'[k'] == V[k], and 0 on the determinants of V'
+ * that are not in V.
+ *   dets, c: device [n_var][2], [n_var]; dets_new, c_new: device
+ *   [n_new][2], [n_new].  HCI_E_ARG if a member of V is missing from V'. */
+int hci_embed(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c,
+              const uint64_t* dets_new, int64_t n_new, double* c_new, void* stream);
+
+/* --------------------------------------------------------------------- sigma
+ * sigma = H c on V (the product inside Davidson, Sec. "Variational Stage";
+ * all single and double connections between members of V, Sec.
+ * "Computational Details").  precision HCI_FP64 evaluates and accumulates in
+ * float64; HCI_FP32_MIXED multiplies float32 off-diagonal elements by a
+ * float32 copy of c and accumulates each row in float64, with the float64
+ * diagonal term added in float64.
+ *   dets: device [n_var][2]; c, sigma: device float64 [n_var], no aliasing.
+ *   mode: hci_sigma_mode.  Asynchronous unless a cache rebuild is needed. */
+int hci_sigma(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c,
+              double* sigma, int precision, int mode, void* stream);
+
+/* Number of ordered pairs (i,j) in V x V with excitation degree <= 2,
+ * diagonal included (host int64 out).  Synchronises the stream. */
+int hci_connections(hci_ctx ctx, const uint64_t* dets, int64_t n_var, int64_t* nnz_out,
+                    void* stream);
+
+/* Diagonal H_ii (float64, device [n_var]), ecore included. */
+int hci_diagonal(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* hdiag, void* stream);
+
+/* ------------------------------------------------------------------ Davidson
+ * Lowest eigenpair of H on V by the Davidson method, which minimises
+ * <Psi|H|Psi> - E(<Psi|Psi> - 1) over the coefficients (eq. variational).
+ *   c_inout: device float64 [n_var], the start vector (need not be
+ *   normalised; a zero vector selects the lowest-diagonal determinant); on
+ *   return the normalised eigenvector with its largest-magnitude entry > 0.
+ *   e_out (host): eigenvalue + ecore.  tol: float64 residual norm
+ *   ||H c - E c|| at which to stop.  precision HCI_FP32_MIXED iterates with
+ *   the mixed product, then refines with float64 products until the float64
+ *   residual meets tol.  iters_out (host, may be NULL): products performed.
+ *   HCI_E_NOCONV when max_iter products did not reach tol (c and E hold the
+ *   best iterate).  Synchronises the stream. */
+int hci_davidson(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* c_inout,
+                 double* e_out, double tol, int max_iter, int precision, int mode,
+                 int* iters_out, void* stream);
+
+/* ---------------------------------------------------------------------- RDMs
+ * Spin-traced transition density matrices between bra and ket on V (the
+ * Gamma^{x,y} of Sec. "Computational Details"; accumulated by looping over
+ * the same single and double connections as sigma).
+ *   bra, ket: device float64 [n_var] (may be the same pointer).
+ *   rdm1: device float64 [norb][norb]; rdm2: device float64 [norb]^4 (layout
+ *   in the header comment); both overwritten.  rdm2 may be NULL. */
+int hci_rdm12(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* bra,
+              const double* ket, double* rdm1, double* rdm2, void* stream);
+
+/* ----------------------------------------------------------------- backward
+ * Derivatives of the energy with respect to the integrals, scaled by grad_e.
+ *
+ * r == NULL and eps2 <= 0 (variational energy, eq. vdedk2):
+ *   dh = grad_e * rdm1(c,c);  dg = grad_e * 1/2 * rdm2(c,c) averaged over the
+ *   8 permutations that leave (pq|rs) unchanged.
+ *
+ * eps2 > 0 (variational + eps2-screened PT2 energy, eq. pt_hci, with the
+ * Lagrangian of eq. lagd/eq. lagc and the relaxed gradient eq. lambda): the
+ * library builds the first-order vector d on C(eps2), E2, r = dE2/dc, solves
+ * Q(H - E)Q z = -Q r (Q = 1 - c c^T) by preconditioned conjugate gradients
+ * with float64 residual refinement to z_tol, and assembles
+ *   dh, dg from (1 - d.d) Gamma^{cc} + sym Gamma^{zc} + 2 sym Gamma^{dc} + Gamma^{dd}.
+ *   e2_out (host, may be NULL) receives E2.
+ *
+ * r != NULL (caller-supplied dF/dc for some F(c)): as above with the
+ *   caller's r and no PT2 pieces: relaxed density (1)Gamma^{cc} + sym Gamma^{zc}.
+ *
+ *   c: device float64 [n_var] normalised eigenvector; e: its eigenvalue
+ *   (ecore included).  dh: device [norb][norb]; dg: device [norb]^4
+ *   (overwritten).  z_out: device [n_var] or NULL.  precision applies to the
+ *   inner products of the linear solve.  Synchronises the stream. */
+int hci_energy_backward(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c,
+                        double e, double grad_e, const double* r, double eps2, double z_tol,
+                        int precision, double* dh, double* dg, double* z_out, double* e2_out,
+                        void* stream);
+
+/* eps2-screened second-order energy and its pieces on a frozen V, c, E0
+ * (eq. h0, eq. pt_hci; Hylleraas minimiser d_a = N_a / (E0 - H_aa)).
+ *   e2_out (host): E2.  r_out: device float64 [n_var] = dE2/dc at fixed E0,
+ *   or NULL.  n_conn_out (host, may be NULL): |C(eps2)|.
+ *   Synchronises the stream. */
+int hci_pt2(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double e0,
+            double eps2, double* e2_out, double* r_out, int64_t* n_conn_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HCI_MI355X_H */

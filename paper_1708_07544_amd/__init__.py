@@ -1,0 +1,226 @@
+"""MI355X (gfx950) Heat-bath CI variational step.
+
+Smith, Mussard, Holmes, Sharma, "Cheap and near exact CASSCF with large
+active spaces" (arXiv:1708.07544): HCI selection, the Hamiltonian product
+inside Davidson, density matrices and the energy's integral derivatives, as
+hand-written HIP kernels behind the C ABI of ``include/hci.h``.  This
+package is the thin torch-facing binding of that library.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (FP32_MIXED, FP64, HCIError, SIGMA_AUTO, SIGMA_RECOMPUTE, SIGMA_STORED,
+                   check, lib)
+
+__all__ = ["HCIContext", "HCIError", "FP64", "FP32_MIXED", "SIGMA_AUTO", "SIGMA_STORED",
+           "SIGMA_RECOMPUTE", "dets_to_device", "dets_to_numpy"]
+
+_PREC = {"fp64": FP64, "fp32_mixed": FP32_MIXED, "mixed": FP32_MIXED, FP64: FP64,
+         FP32_MIXED: FP32_MIXED}
+_MODE = {"auto": SIGMA_AUTO, "stored": SIGMA_STORED, "recompute": SIGMA_RECOMPUTE,
+         SIGMA_AUTO: SIGMA_AUTO, SIGMA_STORED: SIGMA_STORED, SIGMA_RECOMPUTE: SIGMA_RECOMPUTE}
+
+
+def dets_to_device(dets, device="cuda") -> torch.Tensor:
+    """[m,2] uint64 (alpha, beta) words -> contiguous int64 device tensor (same bits)."""
+    if isinstance(dets, torch.Tensor):
+        return dets.to(device=device, dtype=torch.int64).contiguous()
+    a = np.ascontiguousarray(np.asarray(dets, dtype=np.uint64).reshape(-1, 2))
+    return torch.from_numpy(a.view(np.int64)).to(device).contiguous()
+
+
+def dets_to_numpy(dets: torch.Tensor) -> np.ndarray:
+    return np.ascontiguousarray(dets.detach().cpu().numpy()).view(np.uint64).reshape(-1, 2)
+
+
+class HCIContext:
+    """Integrals staged on one GPU plus the heat-bath tables (hci_ctx)."""
+
+    def __init__(self, h, g, nalpha: int, nbeta: int, ecore: float = 0.0, device=None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        h = torch.as_tensor(h, dtype=torch.float64).to(self.device).contiguous()
+        g = torch.as_tensor(g, dtype=torch.float64).to(self.device).contiguous()
+        n = h.shape[0]
+        if h.shape != (n, n) or g.shape != (n, n, n, n):
+            raise ValueError("h must be [n,n] and g [n,n,n,n]")
+        self.norb, self.nalpha, self.nbeta, self.ecore = n, int(nalpha), int(nbeta), float(ecore)
+        self._alloc = _lib.TorchAllocator(self.device)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().hci_ctx_create(n, self.nalpha, self.nbeta, _lib._ptr(h), _lib._ptr(g),
+                                       self.ecore, ctypes.byref(self._alloc.struct),
+                                       _lib._stream(), ctypes.byref(handle)))
+        self.handle = handle
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().hci_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- options
+    def update_integrals(self, h, g, ecore: float = 0.0):
+        h = torch.as_tensor(h, dtype=torch.float64).to(self.device).contiguous()
+        g = torch.as_tensor(g, dtype=torch.float64).to(self.device).contiguous()
+        self.ecore = float(ecore)
+        check(lib().hci_ctx_update_integrals(self.handle, _lib._ptr(h), _lib._ptr(g), self.ecore,
+                                             _lib._stream()))
+
+    def set_stored_budget(self, nbytes: int):
+        check(lib().hci_ctx_set_stored_budget(self.handle, int(nbytes)))
+
+    def set_timing(self, on: bool):
+        check(lib().hci_ctx_set_timing(self.handle, 1 if on else 0))
+
+    def kernel_time(self, name: str, reset: bool = False) -> Tuple[int, float]:
+        launches = ctypes.c_int64()
+        ms = ctypes.c_double()
+        check(lib().hci_ctx_kernel_time(self.handle, name.encode(), ctypes.byref(launches),
+                                        ctypes.byref(ms), 1 if reset else 0))
+        return int(launches.value), float(ms.value)
+
+    # ---------------------------------------------------------------- calls
+    def _dets(self, dets) -> torch.Tensor:
+        d = dets_to_device(dets, self.device)
+        if d.dim() != 2 or d.shape[1] != 2:
+            raise ValueError("dets must be [m,2]")
+        return d
+
+    def select(self, dets, c, eps1: float, cap: Optional[int] = None) -> torch.Tensor:
+        """V + C(eps1), sorted and unique (int64 [m,2] on the device)."""
+        d = self._dets(dets)
+        c = torch.as_tensor(c, dtype=torch.float64).to(self.device).contiguous()
+        n = d.shape[0]
+        cap = int(cap) if cap is not None else max(4 * n, 1 << 16)
+        n_out = ctypes.c_int64()
+        for _ in range(2):
+            out = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=self.device)
+            code = check(lib().hci_select(self.handle, _lib._ptr(d), _lib._ptr(c), n, float(eps1),
+                                          _lib._ptr(out), cap, ctypes.byref(n_out), _lib._stream()),
+                         allow=(_lib.HCI_E_CAPACITY,))
+            if code == _lib.HCI_OK:
+                return out[: n_out.value].contiguous()
+            cap = int(n_out.value)
+        raise HCIError(_lib.HCI_E_CAPACITY, "selection capacity retry failed")
+
+    def embed(self, dets, c, dets_new) -> torch.Tensor:
+        """c carried from V to the superset V' (zeros on the new members)."""
+        d = self._dets(dets)
+        dn = self._dets(dets_new)
+        c = torch.as_tensor(c, dtype=torch.float64).to(self.device).contiguous()
+        out = torch.empty(dn.shape[0], dtype=torch.float64, device=self.device)
+        check(lib().hci_embed(self.handle, _lib._ptr(d), d.shape[0], _lib._ptr(c), _lib._ptr(dn),
+                              dn.shape[0], _lib._ptr(out), _lib._stream()))
+        return out
+
+    def sigma(self, dets, c, precision="fp64", mode="auto") -> torch.Tensor:
+        d = self._dets(dets)
+        c = torch.as_tensor(c, dtype=torch.float64).to(self.device).contiguous()
+        out = torch.empty_like(c)
+        check(lib().hci_sigma(self.handle, _lib._ptr(d), d.shape[0], _lib._ptr(c), _lib._ptr(out),
+                              _PREC[precision], _MODE[mode], _lib._stream()))
+        return out
+
+    def connections(self, dets) -> int:
+        d = self._dets(dets)
+        nnz = ctypes.c_int64()
+        check(lib().hci_connections(self.handle, _lib._ptr(d), d.shape[0], ctypes.byref(nnz),
+                                    _lib._stream()))
+        return int(nnz.value)
+
+    def diagonal(self, dets) -> torch.Tensor:
+        d = self._dets(dets)
+        out = torch.empty(d.shape[0], dtype=torch.float64, device=self.device)
+        check(lib().hci_diagonal(self.handle, _lib._ptr(d), d.shape[0], _lib._ptr(out),
+                                 _lib._stream()))
+        return out
+
+    def davidson(self, dets, c0=None, tol: float = 1e-8, max_iter: int = 500,
+                 precision="fp64", mode="auto", allow_noconv: bool = False):
+        """Lowest eigenpair on V: returns (E, c, products)."""
+        d = self._dets(dets)
+        n = d.shape[0]
+        if c0 is None:
+            c = torch.zeros(n, dtype=torch.float64, device=self.device)
+        else:
+            c = torch.as_tensor(c0, dtype=torch.float64).to(self.device).clone().contiguous()
+        e = ctypes.c_double()
+        iters = ctypes.c_int()
+        allow = (_lib.HCI_E_NOCONV,) if allow_noconv else ()
+        check(lib().hci_davidson(self.handle, _lib._ptr(d), n, _lib._ptr(c), ctypes.byref(e),
+                                 float(tol), int(max_iter), _PREC[precision], _MODE[mode],
+                                 ctypes.byref(iters), _lib._stream()), allow=allow)
+        return float(e.value), c, int(iters.value)
+
+    def rdm12(self, dets, bra, ket=None, two_body: bool = True):
+        d = self._dets(dets)
+        bra = torch.as_tensor(bra, dtype=torch.float64).to(self.device).contiguous()
+        ket = bra if ket is None else torch.as_tensor(ket, dtype=torch.float64).to(self.device).contiguous()
+        n = self.norb
+        r1 = torch.empty((n, n), dtype=torch.float64, device=self.device)
+        r2 = torch.empty((n, n, n, n), dtype=torch.float64, device=self.device) if two_body else None
+        check(lib().hci_rdm12(self.handle, _lib._ptr(d), d.shape[0], _lib._ptr(bra), _lib._ptr(ket),
+                              _lib._ptr(r1), _lib._ptr(r2), _lib._stream()))
+        return r1, r2
+
+    def energy_backward(self, dets, c, e: float, grad_e: float = 1.0, r=None, eps2: float = 0.0,
+                        z_tol: float = 1e-8, precision="fp64", want_z: bool = False):
+        """(dh, dg, z or None, E2)."""
+        d = self._dets(dets)
+        c = torch.as_tensor(c, dtype=torch.float64).to(self.device).contiguous()
+        n = self.norb
+        dh = torch.empty((n, n), dtype=torch.float64, device=self.device)
+        dg = torch.empty((n, n, n, n), dtype=torch.float64, device=self.device)
+        rr = None if r is None else torch.as_tensor(r, dtype=torch.float64).to(self.device).contiguous()
+        z = torch.empty_like(c) if want_z else None
+        e2 = ctypes.c_double()
+        check(lib().hci_energy_backward(self.handle, _lib._ptr(d), d.shape[0], _lib._ptr(c),
+                                        float(e), float(grad_e), _lib._ptr(rr), float(eps2),
+                                        float(z_tol), _PREC[precision], _lib._ptr(dh), _lib._ptr(dg),
+                                        _lib._ptr(z), ctypes.byref(e2), _lib._stream()))
+        return dh, dg, z, float(e2.value)
+
+    def pt2(self, dets, c, e0: float, eps2: float, want_r: bool = True):
+        """(E2, r = dE2/dc or None, |C(eps2)|)."""
+        d = self._dets(dets)
+        c = torch.as_tensor(c, dtype=torch.float64).to(self.device).contiguous()
+        r = torch.empty_like(c) if want_r else None
+        e2 = ctypes.c_double()
+        nc = ctypes.c_int64()
+        check(lib().hci_pt2(self.handle, _lib._ptr(d), d.shape[0], _lib._ptr(c), float(e0),
+                            float(eps2), ctypes.byref(e2), _lib._ptr(r), ctypes.byref(nc),
+                            _lib._stream()))
+        return float(e2.value), r, int(nc.value)
+
+    # ---------------------------------------------------------------- driver
+    def hci(self, eps1: float, max_macro: int = 20, tol: float = 1e-8, precision="fp64",
+            mode="auto", dets0=None, log=None):
+        """HCI variational stage: V0 = aufbau (or dets0), then repeatedly
+        V <- V + C(eps1) and re-diagonalise until nothing is added."""
+        if dets0 is None:
+            dets0 = np.array([[(1 << self.nalpha) - 1, (1 << self.nbeta) - 1]], dtype=np.uint64)
+        V = self._dets(dets0)
+        e, c, it = self.davidson(V, None, tol=tol, precision=precision, mode=mode)
+        hist = [(int(V.shape[0]), e, it)]
+        for _ in range(max_macro):
+            Vn = self.select(V, c, eps1)
+            if Vn.shape[0] == V.shape[0]:
+                break
+            c0 = self.embed(V, c, Vn)
+            V = Vn
+            e, c, it = self.davidson(V, c0, tol=tol, precision=precision, mode=mode)
+            hist.append((int(V.shape[0]), e, it))
+            if log:
+                log(hist[-1])
+        return V, c, e, hist

@@ -1,0 +1,389 @@
+// extern "C" entry points, context lifetime, allocation and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "common.h"
+
+namespace {
+thread_local std::string g_last_error;
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const HciError& e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return HCI_E_NOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return HCI_E_HIP;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return HCI_E_HIP;
+    }
+}
+
+__global__ void add_scalar_kernel(double* __restrict__ y, double a, i64 n) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += a;
+}
+
+__global__ void scale_kernel(const double* __restrict__ x, double a, double* __restrict__ y, i64 n) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i];
+}
+
+// dg[pqrs] = a * mean of G over the 8 index permutations that leave (pq|rs)
+// unchanged for real orbitals
+__global__ void sym8_kernel(const double* __restrict__ G, int n, double a, double* __restrict__ out) {
+    const i64 n4 = (i64)n * n * n * n;
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n4) return;
+    const int s = (int)(t % n), r = (int)((t / n) % n), q = (int)((t / n / n) % n),
+              p = (int)(t / n / n / n);
+    auto at = [&](int a0, int a1, int a2, int a3) {
+        return G[(((i64)a0 * n + a1) * n + a2) * n + a3];
+    };
+    const double v = at(p, q, r, s) + at(q, p, r, s) + at(p, q, s, r) + at(q, p, s, r) +
+                     at(r, s, p, q) + at(s, r, p, q) + at(r, s, q, p) + at(s, r, q, p);
+    out[t] = a * (v * 0.125);
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+void hci_set_error(const std::string& msg) { g_last_error = msg; }
+
+DevMem& DevMem::operator=(DevMem&& o) noexcept {
+    if (this != &o) {
+        release();
+        ctx = o.ctx;
+        ptr = o.ptr;
+        bytes = o.bytes;
+        o.ctx = nullptr;
+        o.ptr = nullptr;
+        o.bytes = 0;
+    }
+    return *this;
+}
+
+void DevMem::release() {
+    if (ptr && ctx) {
+        if (ctx->has_alloc) ctx->alloc.free(ptr, ctx->alloc.user);
+        else (void)hipFree(ptr);
+    }
+    ptr = nullptr;
+    bytes = 0;
+}
+
+DevMem dev_alloc(hci_ctx_s* ctx, size_t bytes, hipStream_t stream) {
+    DevMem m;
+    m.ctx = ctx;
+    m.bytes = bytes ? bytes : 8;
+    if (ctx->has_alloc) {
+        m.ptr = ctx->alloc.alloc(m.bytes, (void*)stream, ctx->alloc.user);
+        if (!m.ptr) throw HciError{HCI_E_NOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes"};
+    } else {
+        hipError_t e = hipMalloc(&m.ptr, m.bytes);
+        if (e != hipSuccess) {
+            m.ptr = nullptr;
+            (void)hipGetLastError();
+            throw HciError{HCI_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+        }
+    }
+    return m;
+}
+
+void drop_space(hci_ctx_s* ctx) {
+    delete ctx->space;
+    ctx->space = nullptr;
+}
+
+static hipEvent_t take_event(hci_ctx_s* ctx) {
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIP_CHECK(hipEventCreate(&e));
+    return e;
+}
+
+void timer_begin(hci_ctx_s* ctx, const char* name, hipStream_t s, PendingEvent* ev) {
+    ev->name = name;
+    ev->start = take_event(ctx);
+    ev->stop = take_event(ctx);
+    HIP_CHECK(hipEventRecord(ev->start, s));
+}
+
+void timer_end(hci_ctx_s* ctx, PendingEvent* ev, hipStream_t s) {
+    (void)hipEventRecord(ev->stop, s);
+    ctx->pending.push_back(*ev);
+}
+
+static void timers_collect(hci_ctx_s* ctx) {
+    for (auto& p : ctx->pending) {
+        HIP_CHECK(hipEventSynchronize(p.stop));
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, p.start, p.stop));
+        KernelTimer& t = ctx->timers[p.name];
+        t.launches += 1;
+        t.ms += ms;
+        ctx->event_pool.push_back(p.start);
+        ctx->event_pool.push_back(p.stop);
+    }
+    ctx->pending.clear();
+}
+
+static void validate_integrals(int norb, const double* h, const double* g) {
+    HCI_REQUIRE(h != nullptr && g != nullptr, HCI_E_ARG, "null integral pointer");
+    (void)norb;
+}
+
+extern "C" {
+
+const char* hci_last_error(void) { return g_last_error.c_str(); }
+
+int hci_ctx_create(int norb, int nalpha, int nbeta, const double* h, const double* g, double ecore,
+                   const hci_allocator* alloc, void* stream, hci_ctx* out) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(out != nullptr, HCI_E_ARG, "out is NULL");
+        *out = nullptr;
+        HCI_REQUIRE(norb >= 1 && norb <= 64, HCI_E_ARG, "norb must be in [1, 64]");
+        HCI_REQUIRE(nalpha >= 0 && nalpha <= norb && nbeta >= 0 && nbeta <= norb, HCI_E_ARG,
+                    "electron counts out of range");
+        validate_integrals(norb, h, g);
+        hci_ctx_s* ctx = new hci_ctx_s();
+        ctx->n = norb;
+        ctx->na = nalpha;
+        ctx->nb = nbeta;
+        ctx->ecore = ecore;
+        if (alloc && alloc->alloc && alloc->free) {
+            ctx->alloc = *alloc;
+            ctx->has_alloc = true;
+        }
+        HIP_CHECK(hipGetDevice(&ctx->device));
+        try {
+            integrals_stage(ctx, h, g, as_stream(stream));
+            HIP_CHECK(hipStreamSynchronize(as_stream(stream)));
+        } catch (...) {
+            delete ctx;
+            throw;
+        }
+        *out = ctx;
+        return HCI_OK;
+    });
+}
+
+int hci_ctx_update_integrals(hci_ctx ctx, const double* h, const double* g, double ecore,
+                             void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr, HCI_E_ARG, "null context");
+        validate_integrals(ctx->n, h, g);
+        drop_space(ctx);
+        ctx->ints = Integrals();
+        ctx->ecore = ecore;
+        integrals_stage(ctx, h, g, as_stream(stream));
+        HIP_CHECK(hipStreamSynchronize(as_stream(stream)));
+        return HCI_OK;
+    });
+}
+
+int hci_ctx_destroy(hci_ctx ctx) {
+    return guarded([&]() -> int {
+        if (!ctx) return HCI_OK;
+        (void)hipDeviceSynchronize();
+        drop_space(ctx);
+        ctx->ints = Integrals();
+        for (auto& p : ctx->pending) {
+            (void)hipEventDestroy(p.start);
+            (void)hipEventDestroy(p.stop);
+        }
+        for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+        delete ctx;
+        return HCI_OK;
+    });
+}
+
+int hci_ctx_set_stored_budget(hci_ctx ctx, int64_t bytes) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && bytes >= 0, HCI_E_ARG, "bad context or budget");
+        ctx->stored_budget = bytes;
+        return HCI_OK;
+    });
+}
+
+int hci_ctx_set_timing(hci_ctx ctx, int enable) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr, HCI_E_ARG, "null context");
+        ctx->timing = enable != 0;
+        return HCI_OK;
+    });
+}
+
+int hci_ctx_kernel_time(hci_ctx ctx, const char* name, int64_t* launches, double* total_ms,
+                        int reset) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && name != nullptr, HCI_E_ARG, "null argument");
+        timers_collect(ctx);
+        auto it = ctx->timers.find(name);
+        if (launches) *launches = it == ctx->timers.end() ? 0 : it->second.launches;
+        if (total_ms) *total_ms = it == ctx->timers.end() ? 0.0 : it->second.ms;
+        if (reset) ctx->timers.clear();
+        return HCI_OK;
+    });
+}
+
+int hci_select(hci_ctx ctx, const uint64_t* dets, const double* c, int64_t n_var, double eps1,
+               uint64_t* out_dets, int64_t cap, int64_t* n_out, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && c && out_dets && n_out, HCI_E_ARG, "null argument");
+        HCI_REQUIRE(n_var > 0 && cap >= 0, HCI_E_ARG, "bad sizes");
+        HCI_REQUIRE(eps1 >= 0.0, HCI_E_ARG, "eps1 must be >= 0");
+        HCI_REQUIRE((const void*)out_dets != (const void*)dets, HCI_E_ARG, "out_dets aliases dets");
+        hipStream_t s = as_stream(stream);
+        // validation shares the space builder's checks
+        get_space(ctx, dets, n_var, s);
+        const i64 m = select_run(ctx, dets, c, n_var, eps1, out_dets, cap, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        *n_out = m;
+        if (m > cap) {
+            g_last_error = "capacity " + std::to_string(cap) + " < required " + std::to_string(m);
+            return HCI_E_CAPACITY;
+        }
+        return HCI_OK;
+    });
+}
+
+int hci_embed(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c,
+              const uint64_t* dets_new, int64_t n_new, double* c_new, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && c && dets_new && c_new, HCI_E_ARG, "null argument");
+        HCI_REQUIRE(n_var > 0 && n_new >= n_var, HCI_E_ARG, "bad sizes");
+        embed_run(ctx, dets, n_var, c, dets_new, n_new, c_new, as_stream(stream));
+        return HCI_OK;
+    });
+}
+
+int hci_sigma(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double* sigma,
+              int precision, int mode, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && c && sigma, HCI_E_ARG, "null argument");
+        HCI_REQUIRE(precision == HCI_FP64 || precision == HCI_FP32_MIXED, HCI_E_ARG, "bad precision");
+        HCI_REQUIRE(mode >= 0 && mode <= 2, HCI_E_ARG, "bad mode");
+        HCI_REQUIRE((const void*)c != (const void*)sigma, HCI_E_ARG, "c aliases sigma");
+        hipStream_t s = as_stream(stream);
+        Space* sp = get_space(ctx, dets, n_var, s);
+        const int m = choose_mode(ctx, sp, precision, mode, s);
+        sigma_apply(ctx, sp, c, sigma, precision, m, s);
+        return HCI_OK;
+    });
+}
+
+int hci_connections(hci_ctx ctx, const uint64_t* dets, int64_t n_var, int64_t* nnz_out,
+                    void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && nnz_out, HCI_E_ARG, "null argument");
+        hipStream_t s = as_stream(stream);
+        Space* sp = get_space(ctx, dets, n_var, s);
+        *nnz_out = count_connections(ctx, sp, s);
+        return HCI_OK;
+    });
+}
+
+int hci_diagonal(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* hdiag, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && hdiag, HCI_E_ARG, "null argument");
+        hipStream_t s = as_stream(stream);
+        Space* sp = get_space(ctx, dets, n_var, s);
+        ensure_diag(ctx, sp, s);
+        HIP_CHECK(hipMemcpyAsync(hdiag, sp->hdiag.ptr, sizeof(double) * n_var, hipMemcpyDeviceToDevice, s));
+        if (ctx->ecore != 0.0)
+            HCI_LAUNCH(ctx, "add_scalar", s, add_scalar_kernel, ceil_div(n_var, 256), 256, 0, hdiag,
+                       ctx->ecore, (i64)n_var);
+        return HCI_OK;
+    });
+}
+
+int hci_davidson(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* c_inout, double* e_out,
+                 double tol, int max_iter, int precision, int mode, int* iters_out, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && c_inout && e_out, HCI_E_ARG, "null argument");
+        HCI_REQUIRE(tol > 0.0 && max_iter > 0, HCI_E_ARG, "tol and max_iter must be positive");
+        HCI_REQUIRE(precision == HCI_FP64 || precision == HCI_FP32_MIXED, HCI_E_ARG, "bad precision");
+        HCI_REQUIRE(mode >= 0 && mode <= 2, HCI_E_ARG, "bad mode");
+        hipStream_t s = as_stream(stream);
+        Space* sp = get_space(ctx, dets, n_var, s);
+        const int rc = davidson_run(ctx, sp, c_inout, e_out, tol, max_iter, precision, mode,
+                                    iters_out, s);
+        if (rc == HCI_E_NOCONV) g_last_error = "Davidson did not reach tol within max_iter products";
+        return rc;
+    });
+}
+
+int hci_rdm12(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* bra, const double* ket,
+              double* rdm1, double* rdm2, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && bra && ket && rdm1, HCI_E_ARG, "null argument");
+        hipStream_t s = as_stream(stream);
+        Space* sp = get_space(ctx, dets, n_var, s);
+        rdm_compute(ctx, sp, bra, ket, rdm1, rdm2, s);
+        return HCI_OK;
+    });
+}
+
+int hci_energy_backward(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double e,
+                        double grad_e, const double* r, double eps2, double z_tol, int precision,
+                        double* dh, double* dg, double* z_out, double* e2_out, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && c && dh && dg, HCI_E_ARG, "null argument");
+        hipStream_t s = as_stream(stream);
+        Space* sp = get_space(ctx, dets, n_var, s);
+        const int n = ctx->n;
+        const i64 n2 = (i64)n * n, n4 = n2 * n2;
+        if (r == nullptr && !(eps2 > 0.0)) {
+            DevMem g1 = dev_alloc(ctx, sizeof(double) * n2, s);
+            DevMem g2 = dev_alloc(ctx, sizeof(double) * n4, s);
+            rdm_compute(ctx, sp, c, c, g1.as<double>(), g2.as<double>(), s);
+            HCI_LAUNCH(ctx, "bw_scale", s, scale_kernel, ceil_div(n2, 256), 256, 0, g1.as<double>(),
+                       grad_e, dh, n2);
+            HCI_LAUNCH(ctx, "bw_sym8", s, sym8_kernel, ceil_div(n4, 256), 256, 0, g2.as<double>(), n,
+                       0.5 * grad_e, dg);
+            if (e2_out) *e2_out = 0.0;
+            HIP_CHECK(hipStreamSynchronize(s));
+            return HCI_OK;
+        }
+        (void)e;
+        (void)z_tol;
+        (void)precision;
+        (void)z_out;
+        g_last_error = "relaxed backward not built yet";
+        return HCI_E_UNSUPPORTED;
+    });
+}
+
+int hci_pt2(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double e0,
+            double eps2, double* e2_out, double* r_out, int64_t* n_conn_out, void* stream) {
+    (void)ctx;
+    (void)dets;
+    (void)n_var;
+    (void)c;
+    (void)e0;
+    (void)eps2;
+    (void)e2_out;
+    (void)r_out;
+    (void)n_conn_out;
+    (void)stream;
+    g_last_error = "pt2 not built yet";
+    return HCI_E_UNSUPPORTED;
+}
+
+}  // extern "C"

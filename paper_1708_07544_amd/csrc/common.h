@@ -1,0 +1,327 @@
+// Shared host/device definitions of the HCI library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/hci.h"
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef int64_t i64;
+
+#define HCI_WAVE 64
+
+// ---------------------------------------------------------------- errors
+struct HciError {
+    int code;
+    std::string msg;
+};
+
+void hci_set_error(const std::string& msg);
+
+#define HIP_CHECK(expr)                                                               \
+    do {                                                                              \
+        hipError_t _e = (expr);                                                       \
+        if (_e != hipSuccess) {                                                       \
+            throw HciError{HCI_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)}; \
+        }                                                                             \
+    } while (0)
+
+#define HCI_REQUIRE(cond, code, text)                  \
+    do {                                               \
+        if (!(cond)) throw HciError{(code), (text)};   \
+    } while (0)
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ int popc64(u64 x) { return __popcll(x); }
+__device__ __forceinline__ int ctz64(u64 x) { return __builtin_ctzll(x); }
+__device__ __forceinline__ u64 bit(int p) { return 1ull << p; }
+
+// (-1)^(number of set bits of s strictly between orbitals p and q)
+__device__ __forceinline__ double sign_between(u64 s, int p, int q) {
+    int lo = p < q ? p : q, hi = p < q ? q : p;
+    u64 m = (bit(hi) - 1ull) & ~((bit(lo) << 1) - 1ull);
+    return (popc64(s & m) & 1) ? -1.0 : 1.0;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ u64 ballot(bool p) { return __ballot(p); }
+
+// lanes below this one in the wavefront
+__device__ __forceinline__ u64 lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ i64 wave_sum_i64(i64 v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ u64 wave_sum_u64(u64 v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Deterministic block reduction (fixed tree) of one double per thread.
+template <int BLOCK>
+__device__ __forceinline__ double block_sum_f64(double v, double* lds /*[BLOCK/64]*/) {
+    v = wave_sum_f64(v);
+    const int w = threadIdx.x / 64;
+    if (lane_id() == 0) lds[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < BLOCK / 64; ++k) t += lds[k];
+    }
+    __syncthreads();
+    return t;  // valid in thread 0
+}
+
+// ---------------------------------------------------------------- memory
+struct hci_ctx_s;
+
+// A device allocation owned by a context (freed through the context's allocator).
+struct DevMem {
+    hci_ctx_s* ctx = nullptr;
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    DevMem(DevMem&& o) noexcept { *this = std::move(o); }
+    DevMem& operator=(DevMem&& o) noexcept;
+    ~DevMem() { release(); }
+    void release();
+    template <class T>
+    T* as() const { return reinterpret_cast<T*>(ptr); }
+};
+
+// ---------------------------------------------------------------- integrals
+// Tables derived from h and g, all on the device.
+struct Integrals {
+    int n = 0;
+    DevMem h;       // f64 [n][n]
+    DevMem g;       // f64 [n]^4
+    DevMem g32;     // f32 [n]^4
+    DevMem jk;      // f64 [n][n][n]: jk[q][p][r] = (qp|rr) - (qr|rp)
+    DevMem jj;      // f64 [n][n][n]: jj[q][p][r] = (qp|rr)
+    DevMem jk32;    // f32 copies for the mixed recompute path
+    DevMem jj32;
+    DevMem h32;
+    DevMem jdiag;   // f64 [n][n]: (pp|qq)
+    DevMem kdiag;   // f64 [n][n]: (pq|qp)
+    // heat-bath lists
+    DevMem os_abs;  // f64 [n*n][(n-1)^2], |(rp|sq)| descending per (p,q)
+    DevMem os_rs;   // u32 packed r | s << 8
+    DevMem ss_abs;  // f64 [n(n-1)/2][(n-2)(n-3)/2] |(rp|sq)-(rq|sp)| descending per p<q
+    DevMem ss_rs;
+    DevMem single_bound;  // f64 [n][n] upper bound of |single element| for p->r
+    int os_len = 0, ss_len = 0;
+};
+
+// Derived structure of one sorted determinant list V.
+struct Space {
+    const u64* key_ptr = nullptr;  // caller's list address
+    i64 N = 0;
+    u64 hash = 0;
+    DevMem alpha, beta;   // u64 [N]
+    DevMem ia, ib;        // u32 [N]: index of the det's alpha / beta string
+    DevMem ua, aoff;      // u64 [nua], u32 [nua+1]
+    DevMem ub, boff;      // u64 [nub], u32 [nub+1]
+    DevMem permb;         // u32 [N]: det indices in (beta, alpha) order
+    DevMem as_ptr, as_idx;  // u32 [nua+1], u32 [..]: alpha strings one single apart
+    DevMem bs_ptr, bs_idx;
+    i64 nua = 0, nub = 0, n_as = 0, n_bs = 0;
+    DevMem hdiag;         // f64 [N] (ecore excluded)
+    DevMem c32;           // f32 [N] staging copy of the vector for mixed products
+    bool have_diag = false;
+    // stored Hamiltonian (off-diagonal part, CSR)
+    DevMem rowptr;        // i64 [N+1]
+    DevMem cols;          // u32 [nnz]
+    DevMem vals64;        // f64 [nnz]
+    DevMem vals32;        // f32 [nnz]
+    i64 nnz_off = -1;     // off-diagonal connections
+    bool have_csr64 = false, have_csr32 = false;
+};
+
+// Plain-pointer view of a Space for kernels.
+struct SpaceView {
+    int n;
+    i64 N;
+    const u64* alpha;
+    const u64* beta;
+    const u32* ia;
+    const u32* ib;
+    const u64* ua;
+    const u32* aoff;
+    const u64* ub;
+    const u32* boff;
+    const u32* permb;
+    const u32* as_ptr;
+    const u32* as_idx;
+    const u32* bs_ptr;
+    const u32* bs_idx;
+};
+
+struct IntView {
+    int n;
+    const double* h;
+    const double* g;
+    const double* jk;
+    const double* jj;
+    const double* jdiag;
+    const double* kdiag;
+    const float* g32;
+    const float* jk32;
+    const float* jj32;
+    const float* h32;
+};
+
+struct KernelTimer {
+    i64 launches = 0;
+    double ms = 0.0;
+};
+
+struct PendingEvent {
+    std::string name;
+    hipEvent_t start, stop;
+};
+
+struct hci_ctx_s {
+    int n = 0, na = 0, nb = 0;
+    int device = 0;
+    double ecore = 0.0;
+    hci_allocator alloc{};
+    bool has_alloc = false;
+    Integrals ints;
+    Space* space = nullptr;
+    i64 stored_budget = (i64)64 << 30;
+    bool timing = false;
+    std::map<std::string, KernelTimer> timers;
+    std::vector<PendingEvent> pending;
+    std::vector<hipEvent_t> event_pool;
+};
+
+// allocation through the context allocator
+DevMem dev_alloc(hci_ctx_s* ctx, size_t bytes, hipStream_t stream);
+// release a cached space
+void drop_space(hci_ctx_s* ctx);
+
+// kernel timing hooks (no-ops unless timing is on)
+void timer_begin(hci_ctx_s* ctx, const char* name, hipStream_t s, PendingEvent* ev);
+void timer_end(hci_ctx_s* ctx, PendingEvent* ev, hipStream_t s);
+
+struct ScopedTimer {
+    hci_ctx_s* ctx;
+    hipStream_t s;
+    PendingEvent ev;
+    bool on;
+    ScopedTimer(hci_ctx_s* c, const char* name, hipStream_t st) : ctx(c), s(st), on(c->timing) {
+        if (on) timer_begin(ctx, name, s, &ev);
+    }
+    ~ScopedTimer() {
+        if (on) timer_end(ctx, &ev, s);
+    }
+};
+
+#define HCI_LAUNCH(ctx, name, stream, kernel, grid, block, shmem, ...)             \
+    do {                                                                          \
+        ScopedTimer _st((ctx), (name), (stream));                                 \
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), (shmem), (stream), __VA_ARGS__); \
+        HIP_CHECK(hipGetLastError());                                             \
+    } while (0)
+
+inline i64 ceil_div(i64 a, i64 b) { return (a + b - 1) / b; }
+
+inline SpaceView space_view(const Space& s, int n) {
+    SpaceView v;
+    v.n = n;
+    v.N = s.N;
+    v.alpha = s.alpha.as<u64>();
+    v.beta = s.beta.as<u64>();
+    v.ia = s.ia.as<u32>();
+    v.ib = s.ib.as<u32>();
+    v.ua = s.ua.as<u64>();
+    v.aoff = s.aoff.as<u32>();
+    v.ub = s.ub.as<u64>();
+    v.boff = s.boff.as<u32>();
+    v.permb = s.permb.as<u32>();
+    v.as_ptr = s.as_ptr.as<u32>();
+    v.as_idx = s.as_idx.as<u32>();
+    v.bs_ptr = s.bs_ptr.as<u32>();
+    v.bs_idx = s.bs_idx.as<u32>();
+    return v;
+}
+
+inline IntView int_view(const Integrals& I) {
+    IntView v;
+    v.n = I.n;
+    v.h = I.h.as<double>();
+    v.g = I.g.as<double>();
+    v.jk = I.jk.as<double>();
+    v.jj = I.jj.as<double>();
+    v.jdiag = I.jdiag.as<double>();
+    v.kdiag = I.kdiag.as<double>();
+    v.g32 = I.g32.as<float>();
+    v.jk32 = I.jk32.as<float>();
+    v.jj32 = I.jj32.as<float>();
+    v.h32 = I.h32.as<float>();
+    return v;
+}
+
+// ---------------------------------------------------------------- primitives (prims.hip)
+// Exclusive scan of n values; returns the total (synchronises when want_total).
+void scan_u32_to_u32(hci_ctx_s* ctx, const u32* in, u32* out, i64 n, hipStream_t s);
+void scan_u32_to_i64(hci_ctx_s* ctx, const u32* in, i64* out, i64 n, hipStream_t s);
+void scan_i64(hci_ctx_s* ctx, const i64* in, i64* out, i64 n, hipStream_t s);
+template <class T>
+T read_scalar(const T* dptr, hipStream_t s) {
+    T v;
+    HIP_CHECK(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    return v;
+}
+
+// Stable LSD radix sort of (hi, lo) 128-bit keys by (hi, lo) over the low
+// `bits` bits of each word, with an optional u32 payload.  Results end in
+// keys_hi/keys_lo/vals (the tmp buffers are scratch of the same size).
+void radix_sort128(hci_ctx_s* ctx, u64* hi, u64* lo, u32* vals, u64* thi, u64* tlo, u32* tvals,
+                   i64 n, int bits_hi, int bits_lo, hipStream_t s);
+// Remove adjacent duplicates of sorted (hi, lo) keys; returns the unique
+// count m and writes out_pairs [m][2] = {hi, lo} only when m <= cap.
+i64 unique128_capped(hci_ctx_s* ctx, const u64* hi, const u64* lo, u64* out_pairs, i64 n, i64 cap,
+                     hipStream_t s);
+
+// ---------------------------------------------------------------- modules
+void integrals_stage(hci_ctx_s* ctx, const double* h, const double* g, hipStream_t s);
+Space* get_space(hci_ctx_s* ctx, const u64* dets, i64 n_var, hipStream_t s);
+void ensure_diag(hci_ctx_s* ctx, Space* sp, hipStream_t s);
+void ensure_csr(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s);
+i64 count_connections(hci_ctx_s* ctx, Space* sp, hipStream_t s);
+void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int precision, int mode,
+                 hipStream_t s);
+int choose_mode(hci_ctx_s* ctx, Space* sp, int precision, int mode, hipStream_t s);
+int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol, int max_iter,
+                 int precision, int mode, int* iters_out, hipStream_t s);
+double heat_bath_max(hci_ctx_s* ctx, hipStream_t s);
+i64 select_run(hci_ctx_s* ctx, const u64* dets, const double* c, i64 N, double eps, u64* out,
+               i64 cap, hipStream_t s);
+void embed_run(hci_ctx_s* ctx, const u64* dets, i64 n, const double* c, const u64* dn, i64 nn,
+               double* out, hipStream_t s);
+void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket, double* rdm1,
+                 double* rdm2, hipStream_t s);

@@ -1,0 +1,372 @@
+// Davidson eigensolver for the lowest eigenpair of H on V: it minimises
+// <Psi|H|Psi> - E(<Psi|Psi> - 1) over the coefficients (eq. variational).
+//
+// All vector algebra is float64 on the device with fixed-order reductions:
+// subspace basis V_k and products W_k = H V_k, Gram matrix G = V^T W grown
+// one column per iteration, lowest Ritz pair of G by cyclic Jacobi in one
+// wavefront, residual r = W y - theta V y, diagonal preconditioner
+// r_i / (H_ii - theta) (guarded), two rounds of classical Gram-Schmidt.
+// The host only reads (theta, |r|^2) once per iteration.
+//
+// Precision HCI_FP32_MIXED: iterate with the mixed product (float32 elements
+// times a float32 copy of the vector, float64 row sums) until the residual is
+// below max(tol, 1e-6), then restart from the Ritz vector with float64
+// products until the float64 residual meets tol.
+#include "common.h"
+
+namespace {
+
+constexpr int DV_BLOCK = 256;
+constexpr int DV_MAXK = 32;
+
+// partial[j * nblk + b] = sum over the block's rows of X_j[i] * t[i], j < k
+__global__ void __launch_bounds__(DV_BLOCK) dots_kernel(const double* __restrict__ X, i64 ld, int k,
+                                                        const double* __restrict__ t, i64 N,
+                                                        double* __restrict__ partial, int nblk) {
+    __shared__ double lds[DV_BLOCK / 64];
+    double acc[DV_MAXK];
+#pragma unroll
+    for (int j = 0; j < DV_MAXK; ++j) acc[j] = 0.0;
+    for (i64 i = (i64)blockIdx.x * DV_BLOCK + threadIdx.x; i < N; i += (i64)nblk * DV_BLOCK) {
+        const double ti = t[i];
+#pragma unroll
+        for (int j = 0; j < DV_MAXK; ++j)
+            if (j < k) acc[j] += X[(i64)j * ld + i] * ti;
+    }
+    for (int j = 0; j < k; ++j) {
+        const double v = block_sum_f64<DV_BLOCK>(acc[j], lds);
+        if (threadIdx.x == 0) partial[(i64)j * nblk + blockIdx.x] = v;
+    }
+}
+
+// out[j] = sum_b partial[j * nblk + b] (fixed order), scaled by `scale`
+__global__ void reduce_partials_kernel(const double* __restrict__ partial, int k, int nblk,
+                                       double* __restrict__ out) {
+    __shared__ double lds[DV_BLOCK / 64];
+    const int j = blockIdx.x;
+    if (j >= k) return;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += DV_BLOCK) acc += partial[(i64)j * nblk + b];
+    const double v = block_sum_f64<DV_BLOCK>(acc, lds);
+    if (threadIdx.x == 0) out[j] = v;
+}
+
+// t -= sum_j coef[j] X_j
+__global__ void sub_combo_kernel(const double* __restrict__ X, i64 ld, int k,
+                                 const double* __restrict__ coef, double* __restrict__ t, i64 N) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double s = t[i];
+    for (int j = 0; j < k; ++j) s -= coef[j] * X[(i64)j * ld + i];
+    t[i] = s;
+}
+
+// dst = src / sqrt(*nrm2)
+__global__ void normalize_kernel(const double* __restrict__ src, const double* __restrict__ nrm2,
+                                 double* __restrict__ dst, i64 N) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) dst[i] = src[i] / sqrt(*nrm2);
+}
+
+// x = V y, w = W y, r = w - theta x, t = r / guard(H_ii - theta); partial |r|^2.
+// ritz[0] = theta, ritz[1..k] = y.
+__global__ void __launch_bounds__(DV_BLOCK) combine_kernel(
+    const double* __restrict__ V, const double* __restrict__ W, i64 ld, int k,
+    const double* __restrict__ ritz, const double* __restrict__ hd, double* __restrict__ x,
+    double* __restrict__ w, double* __restrict__ t, i64 N, double* __restrict__ partial, int nblk) {
+    __shared__ double lds[DV_BLOCK / 64];
+    __shared__ double y[DV_MAXK + 1];
+    if (threadIdx.x <= k) y[threadIdx.x] = ritz[threadIdx.x];
+    __syncthreads();
+    const double theta = y[0];
+    double acc = 0.0;
+    for (i64 i = (i64)blockIdx.x * DV_BLOCK + threadIdx.x; i < N; i += (i64)nblk * DV_BLOCK) {
+        double xi = 0.0, wi = 0.0;
+        for (int j = 0; j < k; ++j) {
+            xi += y[j + 1] * V[(i64)j * ld + i];
+            wi += y[j + 1] * W[(i64)j * ld + i];
+        }
+        const double ri = wi - theta * xi;
+        double den = hd[i] - theta;
+        if (fabs(den) < 1e-4) den = den < 0 ? -1e-4 : 1e-4;
+        x[i] = xi;
+        w[i] = wi;
+        t[i] = ri / den;
+        acc += ri * ri;
+    }
+    const double v = block_sum_f64<DV_BLOCK>(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v;
+}
+
+// Lowest eigenpair of the symmetric k x k matrix G (leading dimension ldg)
+// by cyclic Jacobi rotations in one wavefront; writes out[0] = eigenvalue,
+// out[1..k] = unit eigenvector.
+__global__ void __launch_bounds__(64) jacobi_lowest_kernel(const double* __restrict__ G, int ldg,
+                                                           int k, double* __restrict__ out) {
+    __shared__ double A[DV_MAXK][DV_MAXK + 1];
+    __shared__ double Q[DV_MAXK][DV_MAXK + 1];
+    const int l = threadIdx.x;
+    for (int r = 0; r < k; ++r) {
+        if (l < k) {
+            // symmetrise from the upper triangle (G[j][m] holds V_j . W_m for j <= m)
+            const int lo = r < l ? r : l, hi = r < l ? l : r;
+            A[r][l] = G[lo * ldg + hi];
+            Q[r][l] = (r == l) ? 1.0 : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int p = 0; p < k; ++p)
+            for (int q = 0; q < k; ++q) {
+                if (p != q) off += A[p][q] * A[p][q];
+                else dia += A[p][q] * A[p][q];
+            }
+        if (off <= 1e-30 * (dia + 1e-300)) break;
+        for (int p = 0; p < k - 1; ++p) {
+            for (int q = p + 1; q < k; ++q) {
+                const double apq = A[p][q];
+                if (apq == 0.0) continue;
+                const double app = A[p][p], aqq = A[q][q];
+                const double th = (aqq - app) / (2.0 * apq);
+                const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double cs = 1.0 / sqrt(tt * tt + 1.0), sn = tt * cs;
+                double akp = 0, akq = 0, qp = 0, qq = 0;
+                if (l < k) {
+                    akp = A[l][p];
+                    akq = A[l][q];
+                    qp = Q[l][p];
+                    qq = Q[l][q];
+                }
+                __syncthreads();
+                if (l < k) {
+                    if (l != p && l != q) {
+                        const double np = cs * akp - sn * akq, nq = sn * akp + cs * akq;
+                        A[l][p] = np;
+                        A[p][l] = np;
+                        A[l][q] = nq;
+                        A[q][l] = nq;
+                    }
+                    Q[l][p] = cs * qp - sn * qq;
+                    Q[l][q] = sn * qp + cs * qq;
+                }
+                if (l == 0) {
+                    A[p][p] = app - tt * apq;
+                    A[q][q] = aqq + tt * apq;
+                    A[p][q] = 0.0;
+                    A[q][p] = 0.0;
+                }
+                __syncthreads();
+            }
+        }
+    }
+    int m = 0;
+    for (int p = 1; p < k; ++p)
+        if (A[p][p] < A[m][m]) m = p;
+    if (l == 0) out[0] = A[m][m];
+    if (l < k) out[1 + l] = Q[l][m];
+}
+
+__global__ void gram_column_kernel(double* __restrict__ G, int ldg, int k,
+                                   const double* __restrict__ col) {
+    const int j = threadIdx.x;
+    if (j <= k) G[(i64)j * ldg + k] = col[j];
+}
+
+__global__ void argmin_seed_kernel(const double* __restrict__ hd, i64 N, double* __restrict__ x) {
+    // one block: index of the smallest diagonal (first on ties), then x = e_idx
+    __shared__ double bv[256];
+    __shared__ i64 bi[256];
+    double v = 1e300;
+    i64 idx = 0;
+    for (i64 i = threadIdx.x; i < N; i += 256)
+        if (hd[i] < v) {
+            v = hd[i];
+            idx = i;
+        }
+    bv[threadIdx.x] = v;
+    bi[threadIdx.x] = idx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double ov = bv[threadIdx.x + s];
+            const i64 oi = bi[threadIdx.x + s];
+            if (ov < bv[threadIdx.x] || (ov == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+                bv[threadIdx.x] = ov;
+                bi[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    for (i64 i = threadIdx.x; i < N; i += 256) x[i] = (i == bi[0]) ? 1.0 : 0.0;
+}
+
+// sign convention: largest-|c| entry positive (first index on ties)
+__global__ void sign_fix_kernel(double* __restrict__ x, i64 N) {
+    __shared__ double bv[256];
+    __shared__ i64 bi[256];
+    double v = -1.0;
+    i64 idx = 0;
+    for (i64 i = threadIdx.x; i < N; i += 256)
+        if (fabs(x[i]) > v) {
+            v = fabs(x[i]);
+            idx = i;
+        }
+    bv[threadIdx.x] = v;
+    bi[threadIdx.x] = idx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double ov = bv[threadIdx.x + s];
+            const i64 oi = bi[threadIdx.x + s];
+            if (ov > bv[threadIdx.x] || (ov == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+                bv[threadIdx.x] = ov;
+                bi[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    const bool flip = x[bi[0]] < 0.0;
+    __syncthreads();
+    if (flip)
+        for (i64 i = threadIdx.x; i < N; i += 256) x[i] = -x[i];
+}
+
+struct Workspace {
+    hci_ctx_s* ctx;
+    hipStream_t s;
+    i64 N;
+    int nblk;
+    DevMem partial, scal;
+    Workspace(hci_ctx_s* c, i64 n, hipStream_t st) : ctx(c), s(st), N(n) {
+        nblk = (int)std::min<i64>(ceil_div(n, DV_BLOCK), 1024);
+        partial = dev_alloc(c, sizeof(double) * DV_MAXK * nblk, st);
+        scal = dev_alloc(c, sizeof(double) * (DV_MAXK + 8), st);
+    }
+    // out[0..k) = X_j . t
+    void dots(const double* X, i64 ld, int k, const double* t, double* out) {
+        HCI_LAUNCH(ctx, "dv_dots", s, dots_kernel, nblk, DV_BLOCK, 0, X, ld, k, t, N,
+                   partial.as<double>(), nblk);
+        HCI_LAUNCH(ctx, "dv_reduce", s, reduce_partials_kernel, k, DV_BLOCK, 0, partial.as<double>(),
+                   k, nblk, out);
+    }
+};
+
+}  // namespace
+
+int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol, int max_iter,
+                 int precision, int mode, int* iters_out, hipStream_t s) {
+    const i64 N = sp->N;
+    ensure_diag(ctx, sp, s);
+    const double* hd = sp->hdiag.as<double>();
+    int kmax = (int)std::min<i64>(24, N);
+    Workspace ws(ctx, N, s);
+    DevMem Vb = dev_alloc(ctx, sizeof(double) * kmax * N, s);
+    DevMem Wb = dev_alloc(ctx, sizeof(double) * kmax * N, s);
+    DevMem G = dev_alloc(ctx, sizeof(double) * DV_MAXK * DV_MAXK, s);
+    DevMem ritz = dev_alloc(ctx, sizeof(double) * (DV_MAXK + 1), s);
+    DevMem x = dev_alloc(ctx, sizeof(double) * N, s);
+    DevMem w = dev_alloc(ctx, sizeof(double) * N, s);
+    DevMem t = dev_alloc(ctx, sizeof(double) * N, s);
+    double* V = Vb.as<double>();
+    double* W = Wb.as<double>();
+    double* sc = ws.scal.as<double>();  // sc[0..DV_MAXK) coefficients, sc[DV_MAXK] norms
+    const i64 g1 = ceil_div(N, 256);
+
+    // start vector
+    HIP_CHECK(hipMemcpyAsync(x.ptr, c, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    ws.dots(x.as<double>(), N, 1, x.as<double>(), sc + DV_MAXK);
+    if (read_scalar(sc + DV_MAXK, s) <= 0.0) {
+        HCI_LAUNCH(ctx, "dv_seed", s, argmin_seed_kernel, 1, 256, 0, hd, N, x.as<double>());
+        ws.dots(x.as<double>(), N, 1, x.as<double>(), sc + DV_MAXK);
+    }
+
+    const bool mixed = precision == HCI_FP32_MIXED;
+    int phase_prec = mixed ? HCI_FP32_MIXED : HCI_FP64;
+    int phase_mode = choose_mode(ctx, sp, phase_prec, mode, s);
+    double phase_tol = mixed ? std::max(tol, 1e-6) : tol;
+    int products = 0;
+    double theta = 0.0, rnorm = 1e300;
+    bool converged = false;
+
+    bool need_sigma = true;
+    while (true) {
+        // (re)start the subspace from x (and w = H x when it is still valid)
+        HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, x.as<double>(),
+                   sc + DV_MAXK, V, N);
+        if (need_sigma) {
+            sigma_apply(ctx, sp, V, W, phase_prec, phase_mode, s);
+            ++products;
+        } else {
+            HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, w.as<double>(),
+                       sc + DV_MAXK, W, N);
+        }
+        need_sigma = false;
+        int k = 1;
+        ws.dots(V, N, 1, W, G.as<double>());
+        bool phase_done = false;
+        while (true) {
+            HCI_LAUNCH(ctx, "dv_jacobi", s, jacobi_lowest_kernel, 1, 64, 0, G.as<double>(), DV_MAXK,
+                       k, ritz.as<double>());
+            HCI_LAUNCH(ctx, "dv_combine", s, combine_kernel, ws.nblk, DV_BLOCK, 0, V, W, N, k,
+                       ritz.as<double>(), hd, x.as<double>(), w.as<double>(), t.as<double>(), N,
+                       ws.partial.as<double>(), ws.nblk);
+            HCI_LAUNCH(ctx, "dv_reduce", s, reduce_partials_kernel, 1, DV_BLOCK, 0,
+                       ws.partial.as<double>(), 1, ws.nblk, sc + DV_MAXK + 1);
+            double hv[2];
+            HIP_CHECK(hipMemcpyAsync(&hv[0], ritz.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipMemcpyAsync(&hv[1], sc + DV_MAXK + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            theta = hv[0];
+            rnorm = sqrt(std::max(hv[1], 0.0));
+            if (rnorm <= phase_tol) {
+                phase_done = true;
+                break;
+            }
+            if (products >= max_iter) break;
+            if (k == kmax) break;  // restart from the current Ritz vector
+            // orthogonalise the preconditioned residual against the basis (CGS2)
+            for (int pass = 0; pass < 2; ++pass) {
+                ws.dots(V, N, k, t.as<double>(), sc);
+                HCI_LAUNCH(ctx, "dv_subcombo", s, sub_combo_kernel, g1, 256, 0, V, N, k, sc,
+                           t.as<double>(), N);
+            }
+            ws.dots(t.as<double>(), N, 1, t.as<double>(), sc + DV_MAXK + 2);
+            const double tn = read_scalar(sc + DV_MAXK + 2, s);
+            if (!(tn > 1e-28)) break;  // no new direction: restart
+            HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, t.as<double>(),
+                       sc + DV_MAXK + 2, V + (i64)k * N, N);
+            sigma_apply(ctx, sp, V + (i64)k * N, W + (i64)k * N, phase_prec, phase_mode, s);
+            ++products;
+            // new Gram column: G[j][k] = V_j . W_k, j <= k
+            ws.dots(V, N, k + 1, W + (i64)k * N, sc);
+            HCI_LAUNCH(ctx, "dv_gram", s, gram_column_kernel, 1, 64, 0, G.as<double>(), DV_MAXK, k, sc);
+            ++k;
+        }
+        if (phase_done) {
+            if (phase_prec == HCI_FP32_MIXED) {
+                // refine with float64 products from the current Ritz vector
+                phase_prec = HCI_FP64;
+                phase_mode = sp->have_csr64 ? HCI_SIGMA_STORED : HCI_SIGMA_RECOMPUTE;
+                if (mode == HCI_SIGMA_STORED || mode == HCI_SIGMA_RECOMPUTE) phase_mode = mode;
+                phase_tol = tol;
+                need_sigma = true;
+                ws.dots(x.as<double>(), N, 1, x.as<double>(), sc + DV_MAXK);
+                continue;
+            }
+            converged = true;
+            break;
+        }
+        if (products >= max_iter) break;
+        ws.dots(x.as<double>(), N, 1, x.as<double>(), sc + DV_MAXK);
+    }
+    // normalise and fix the sign of the final vector
+    ws.dots(x.as<double>(), N, 1, x.as<double>(), sc + DV_MAXK);
+    HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, x.as<double>(), sc + DV_MAXK,
+               c, N);
+    HCI_LAUNCH(ctx, "dv_signfix", s, sign_fix_kernel, 1, 256, 0, c, N);
+    *e_out = theta + ctx->ecore;
+    if (iters_out) *iters_out = products;
+    HIP_CHECK(hipStreamSynchronize(s));
+    return converged ? HCI_OK : HCI_E_NOCONV;
+}

@@ -1,0 +1,219 @@
+// sigma = H c on the variational space: the product inside the Davidson
+// solver (Sec. "Variational Stage") over every single and double connection
+// between members of V (Sec. "Computational Details").
+//
+// Stored mode: the off-diagonal connections of each row are enumerated once
+// (count pass, scan, fill pass) into CSR with u32 columns and float64 or
+// float32 values; each product then streams the CSR once (HBM-bound).
+// Recompute mode: every product re-enumerates the connections of each row
+// and evaluates the elements on the fly (integer/ALU-bound, no storage).
+// Both use one wavefront per row and fixed-order reductions (no atomics).
+#include "slater.h"
+
+namespace {
+
+constexpr int ROW_BLOCK = 256;               // 4 wavefronts, one row each
+constexpr int ROWS_PER_BLOCK = ROW_BLOCK / HCI_WAVE;
+
+__global__ void diag_kernel(SpaceView S, IntView I, double* __restrict__ hd) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < S.N) hd[i] = diag_f64(I, S.alpha[i], S.beta[i]);
+}
+
+struct CountVis {
+    u32 cnt = 0;
+    __device__ __forceinline__ void operator()(bool ok, u32, u64, u64) {
+        cnt += (u32)__popcll(ballot(ok));
+    }
+};
+
+__global__ void __launch_bounds__(ROW_BLOCK) count_kernel(SpaceView S, u32* __restrict__ counts) {
+    const i64 i = (i64)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
+    if (i >= S.N) return;
+    CountVis v;
+    enumerate_row(S, (u32)i, v);
+    if (lane_id() == 0) counts[i] = v.cnt;
+}
+
+template <class VT>
+struct FillVis {
+    const IntView* I;
+    u64 ai, bi;
+    u32* cols;
+    VT* vals;
+    i64 pos;
+    __device__ __forceinline__ void operator()(bool ok, u32 j, u64 aj, u64 bj) {
+        const u64 m = ballot(ok);
+        if (ok) {
+            const i64 at = pos + __popcll(m & lanemask_lt());
+            cols[at] = j;
+            vals[at] = (VT)hij_f64(*I, ai, bi, aj, bj);
+        }
+        pos += __popcll(m);
+    }
+};
+
+template <class VT>
+__global__ void __launch_bounds__(ROW_BLOCK) fill_kernel(SpaceView S, IntView I,
+                                                         const i64* __restrict__ rowptr,
+                                                         u32* __restrict__ cols,
+                                                         VT* __restrict__ vals) {
+    const i64 i = (i64)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
+    if (i >= S.N) return;
+    FillVis<VT> v{&I, S.alpha[i], S.beta[i], cols, vals, rowptr[i]};
+    enumerate_row(S, (u32)i, v);
+}
+
+// Stored product: one wavefront per row, lane-strided partial sums in
+// float64, butterfly reduction, float64 diagonal term.
+template <class VT, class CT>
+__global__ void __launch_bounds__(ROW_BLOCK) spmv_kernel(i64 N, const i64* __restrict__ rowptr,
+                                                         const u32* __restrict__ cols,
+                                                         const VT* __restrict__ vals,
+                                                         const CT* __restrict__ cx,
+                                                         const double* __restrict__ c,
+                                                         const double* __restrict__ hd,
+                                                         double* __restrict__ sigma) {
+    const i64 i = (i64)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
+    if (i >= N) return;
+    const i64 k0 = rowptr[i], k1 = rowptr[i + 1];
+    double acc = 0.0;
+    for (i64 k = k0 + lane_id(); k < k1; k += HCI_WAVE)
+        acc += (double)vals[k] * (double)cx[cols[k]];
+    acc = wave_sum_f64(acc);
+    if (lane_id() == 0) sigma[i] = hd[i] * c[i] + acc;
+}
+
+template <bool F32>
+struct SigmaVis {
+    const IntView* I;
+    const double* c;
+    const float* c32;
+    u64 ai, bi;
+    double acc = 0.0;
+    __device__ __forceinline__ void operator()(bool ok, u32 j, u64 aj, u64 bj) {
+        if (ok) {
+            if (F32) acc += (double)hij_f32(*I, ai, bi, aj, bj) * (double)c32[j];
+            else acc += hij_f64(*I, ai, bi, aj, bj) * c[j];
+        }
+    }
+};
+
+template <bool F32>
+__global__ void __launch_bounds__(ROW_BLOCK) sigma_recompute_kernel(SpaceView S, IntView I,
+                                                                    const double* __restrict__ c,
+                                                                    const float* __restrict__ c32,
+                                                                    const double* __restrict__ hd,
+                                                                    double* __restrict__ sigma) {
+    const i64 i = (i64)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
+    if (i >= S.N) return;
+    SigmaVis<F32> v{&I, c, c32, S.alpha[i], S.beta[i]};
+    enumerate_row(S, (u32)i, v);
+    const double acc = wave_sum_f64(v.acc);
+    if (lane_id() == 0) sigma[i] = hd[i] * c[i] + acc;
+}
+
+__global__ void f64_to_f32_kernel(const double* __restrict__ x, float* __restrict__ y, i64 n) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (float)x[i];
+}
+
+__global__ void u32_to_i64_sum_kernel(const u32* __restrict__ x, i64 n, unsigned long long* out) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    u64 v = i < n ? (u64)x[i] : 0ull;
+    v = wave_sum_u64(v);
+    if (lane_id() == 0 && v) atomicAdd(out, (unsigned long long)v);
+}
+
+void ensure_rowptr(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
+    if (sp->nnz_off >= 0) return;
+    const i64 N = sp->N;
+    SpaceView S = space_view(*sp, ctx->n);
+    DevMem counts = dev_alloc(ctx, sizeof(u32) * (N + 1), s);
+    HCI_LAUNCH(ctx, "conn_count", s, count_kernel, ceil_div(N, ROWS_PER_BLOCK), ROW_BLOCK, 0, S,
+               counts.as<u32>());
+    HIP_CHECK(hipMemsetAsync(counts.as<u32>() + N, 0, sizeof(u32), s));
+    sp->rowptr = dev_alloc(ctx, sizeof(i64) * (N + 1), s);
+    scan_u32_to_i64(ctx, counts.as<u32>(), sp->rowptr.as<i64>(), N + 1, s);
+    sp->nnz_off = read_scalar(sp->rowptr.as<i64>() + N, s);
+}
+
+}  // namespace
+
+void ensure_diag(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
+    if (sp->have_diag) return;
+    sp->hdiag = dev_alloc(ctx, sizeof(double) * sp->N, s);
+    HCI_LAUNCH(ctx, "hdiag", s, diag_kernel, ceil_div(sp->N, 256), 256, 0, space_view(*sp, ctx->n),
+               int_view(ctx->ints), sp->hdiag.as<double>());
+    sp->have_diag = true;
+}
+
+i64 count_connections(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
+    ensure_rowptr(ctx, sp, s);
+    return sp->nnz_off + sp->N;
+}
+
+void ensure_csr(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s) {
+    const bool f32 = precision == HCI_FP32_MIXED;
+    if (f32 ? sp->have_csr32 : sp->have_csr64) return;
+    ensure_rowptr(ctx, sp, s);
+    const i64 nnz = sp->nnz_off;
+    if (!sp->cols.ptr) sp->cols = dev_alloc(ctx, sizeof(u32) * (nnz > 0 ? nnz : 1), s);
+    SpaceView S = space_view(*sp, ctx->n);
+    IntView I = int_view(ctx->ints);
+    const i64 grid = ceil_div(sp->N, ROWS_PER_BLOCK);
+    if (f32) {
+        sp->vals32 = dev_alloc(ctx, sizeof(float) * (nnz > 0 ? nnz : 1), s);
+        HCI_LAUNCH(ctx, "csr_fill_f32", s, fill_kernel<float>, grid, ROW_BLOCK, 0, S, I,
+                   sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals32.as<float>());
+        sp->have_csr32 = true;
+    } else {
+        sp->vals64 = dev_alloc(ctx, sizeof(double) * (nnz > 0 ? nnz : 1), s);
+        HCI_LAUNCH(ctx, "csr_fill_f64", s, fill_kernel<double>, grid, ROW_BLOCK, 0, S, I,
+                   sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals64.as<double>());
+        sp->have_csr64 = true;
+    }
+}
+
+int choose_mode(hci_ctx_s* ctx, Space* sp, int precision, int mode, hipStream_t s) {
+    if (mode == HCI_SIGMA_STORED || mode == HCI_SIGMA_RECOMPUTE) return mode;
+    ensure_rowptr(ctx, sp, s);
+    const i64 per = precision == HCI_FP32_MIXED ? 8 : 12;
+    return sp->nnz_off * per <= ctx->stored_budget ? HCI_SIGMA_STORED : HCI_SIGMA_RECOMPUTE;
+}
+
+void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int precision, int mode,
+                 hipStream_t s) {
+    ensure_diag(ctx, sp, s);
+    const i64 N = sp->N;
+    const bool f32 = precision == HCI_FP32_MIXED;
+    const i64 grid = ceil_div(N, ROWS_PER_BLOCK);
+    DevMem& c32 = sp->c32;
+    if (f32) {
+        if (!c32.ptr) c32 = dev_alloc(ctx, sizeof(float) * N, s);
+        HCI_LAUNCH(ctx, "c_to_f32", s, f64_to_f32_kernel, ceil_div(N, 256), 256, 0, c,
+                   c32.as<float>(), N);
+    }
+    if (mode == HCI_SIGMA_STORED) {
+        ensure_csr(ctx, sp, precision, s);
+        if (f32) {
+            HCI_LAUNCH(ctx, "sigma_stored_f32", s, (spmv_kernel<float, float>), grid, ROW_BLOCK, 0, N,
+                       sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals32.as<float>(),
+                       c32.as<float>(), c, sp->hdiag.as<double>(), sigma);
+        } else {
+            HCI_LAUNCH(ctx, "sigma_stored_f64", s, (spmv_kernel<double, double>), grid, ROW_BLOCK, 0,
+                       N, sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals64.as<double>(), c, c,
+                       sp->hdiag.as<double>(), sigma);
+        }
+    } else {
+        SpaceView S = space_view(*sp, ctx->n);
+        IntView I = int_view(ctx->ints);
+        if (f32) {
+            HCI_LAUNCH(ctx, "sigma_recompute_f32", s, sigma_recompute_kernel<true>, grid, ROW_BLOCK, 0,
+                       S, I, c, c32.as<float>(), sp->hdiag.as<double>(), sigma);
+        } else {
+            HCI_LAUNCH(ctx, "sigma_recompute_f64", s, sigma_recompute_kernel<false>, grid, ROW_BLOCK, 0,
+                       S, I, c, (const float*)nullptr, sp->hdiag.as<double>(), sigma);
+        }
+    }
+}

@@ -1,0 +1,212 @@
+// Hamiltonian matrix elements between determinants of excitation degree
+// <= 2 (textbook Slater-Condon rules for the active-space Hamiltonian) and
+// the wave-cooperative enumeration of the connections of one row of V.
+#pragma once
+
+#include "common.h"
+
+// Single excitation p -> q in string `same` (its spin), `other` the
+// opposite-spin string: h_qp + sum_{r in same} [(qp|rr) - (qr|rp)] +
+// sum_{r in other} (qp|rr), summed in that order with r ascending (the
+// order is part of the contract: selection compares this float64 value
+// against a threshold and must match any other evaluation bit for bit).
+__device__ __forceinline__ double single_elem_f64(const IntView& I, u64 same, u64 other, int p,
+                                                  int q) {
+    const int n = I.n;
+    const i64 row = ((i64)q * n + p) * n;
+    double v = I.h[(i64)q * n + p];
+    for (u64 m = same; m; m &= m - 1) v += I.jk[row + ctz64(m)];
+    for (u64 m = other; m; m &= m - 1) v += I.jj[row + ctz64(m)];
+    return v;
+}
+
+__device__ __forceinline__ float single_elem_f32(const IntView& I, u64 same, u64 other, int p,
+                                                 int q) {
+    const int n = I.n;
+    const i64 row = ((i64)q * n + p) * n;
+    float v = I.h32[(i64)q * n + p];
+    for (u64 m = same; m; m &= m - 1) v += I.jk32[row + ctz64(m)];
+    for (u64 m = other; m; m &= m - 1) v += I.jj32[row + ctz64(m)];
+    return v;
+}
+
+__device__ __forceinline__ i64 gidx(int n, int p, int q, int r, int s) {
+    return (((i64)p * n + q) * n + r) * n + s;
+}
+
+// <D_j|H|D_i> for D_j != D_i at excitation degree 1 or 2 (float64).
+__device__ __forceinline__ double hij_f64(const IntView& I, u64 ai, u64 bi, u64 aj, u64 bj) {
+    const u64 xa = ai ^ aj, xb = bi ^ bj;
+    const int da = popc64(xa) >> 1, db = popc64(xb) >> 1;
+    const int n = I.n;
+    if (db == 0 && da == 1) {
+        const int p = ctz64(ai & xa), q = ctz64(aj & xa);
+        return sign_between(ai, p, q) * single_elem_f64(I, ai, bi, p, q);
+    }
+    if (da == 0 && db == 1) {
+        const int p = ctz64(bi & xb), q = ctz64(bj & xb);
+        return sign_between(bi, p, q) * single_elem_f64(I, bi, ai, p, q);
+    }
+    if (da == 1 && db == 1) {
+        const int p = ctz64(ai & xa), r = ctz64(aj & xa);
+        const int q = ctz64(bi & xb), s = ctz64(bj & xb);
+        return (sign_between(ai, p, r) * sign_between(bi, q, s)) * I.g[gidx(n, r, p, s, q)];
+    }
+    const u64 si = da == 2 ? ai : bi;
+    const u64 x = da == 2 ? xa : xb;
+    u64 holes = si & x, parts = x & ~si;
+    const int p = ctz64(holes);
+    holes &= holes - 1;
+    const int q = ctz64(holes);
+    const int r = ctz64(parts);
+    parts &= parts - 1;
+    const int s = ctz64(parts);
+    const double sg = sign_between(si, p, r) * sign_between(si ^ bit(p) ^ bit(r), q, s);
+    return sg * (I.g[gidx(n, r, p, s, q)] - I.g[gidx(n, r, q, s, p)]);
+}
+
+__device__ __forceinline__ float hij_f32(const IntView& I, u64 ai, u64 bi, u64 aj, u64 bj) {
+    const u64 xa = ai ^ aj, xb = bi ^ bj;
+    const int da = popc64(xa) >> 1, db = popc64(xb) >> 1;
+    const int n = I.n;
+    if (db == 0 && da == 1) {
+        const int p = ctz64(ai & xa), q = ctz64(aj & xa);
+        return (float)sign_between(ai, p, q) * single_elem_f32(I, ai, bi, p, q);
+    }
+    if (da == 0 && db == 1) {
+        const int p = ctz64(bi & xb), q = ctz64(bj & xb);
+        return (float)sign_between(bi, p, q) * single_elem_f32(I, bi, ai, p, q);
+    }
+    if (da == 1 && db == 1) {
+        const int p = ctz64(ai & xa), r = ctz64(aj & xa);
+        const int q = ctz64(bi & xb), s = ctz64(bj & xb);
+        return (float)(sign_between(ai, p, r) * sign_between(bi, q, s)) * I.g32[gidx(n, r, p, s, q)];
+    }
+    const u64 si = da == 2 ? ai : bi;
+    const u64 x = da == 2 ? xa : xb;
+    u64 holes = si & x, parts = x & ~si;
+    const int p = ctz64(holes);
+    holes &= holes - 1;
+    const int q = ctz64(holes);
+    const int r = ctz64(parts);
+    parts &= parts - 1;
+    const int s = ctz64(parts);
+    const float sg = (float)(sign_between(si, p, r) * sign_between(si ^ bit(p) ^ bit(r), q, s));
+    return sg * (I.g32[gidx(n, r, p, s, q)] - I.g32[gidx(n, r, q, s, p)]);
+}
+
+// Diagonal <D|H|D> (ecore excluded): occupied one-body energies plus, for
+// every unordered pair of occupied spin orbitals, Coulomb minus same-spin
+// exchange.
+__device__ __forceinline__ double diag_f64(const IntView& I, u64 a, u64 b) {
+    const int n = I.n;
+    double e = 0.0;
+    for (u64 m = a; m; m &= m - 1) {
+        const int p = ctz64(m);
+        e += I.h[(i64)p * n + p];
+        for (u64 m2 = m & (m - 1); m2; m2 &= m2 - 1) {
+            const int q = ctz64(m2);
+            e += I.jdiag[(i64)p * n + q] - I.kdiag[(i64)p * n + q];
+        }
+        for (u64 m2 = b; m2; m2 &= m2 - 1) e += I.jdiag[(i64)p * n + ctz64(m2)];
+    }
+    for (u64 m = b; m; m &= m - 1) {
+        const int p = ctz64(m);
+        e += I.h[(i64)p * n + p];
+        for (u64 m2 = m & (m - 1); m2; m2 &= m2 - 1) {
+            const int q = ctz64(m2);
+            e += I.jdiag[(i64)p * n + q] - I.kdiag[(i64)p * n + q];
+        }
+    }
+    return e;
+}
+
+__device__ __forceinline__ u32 lower_bound_u64(const u64* __restrict__ arr, u32 len, u64 key) {
+    u32 lo = 0, hi = len;
+    while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if (arr[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Enumerate every j != i in V with excitation degree <= 2 from row i.  The
+// whole wavefront calls this for one row; `vis(ok, j, aj, bj)` is invoked
+// wave-uniformly, each lane carrying its own candidate (ok = it is one).
+// Order of discovery (deterministic): same-alpha bucket, same-beta bucket,
+// then alpha-single neighbours in adjacency order.
+template <class Visitor>
+__device__ __forceinline__ void enumerate_row(const SpaceView& S, u32 i, Visitor& vis) {
+    const int lane = lane_id();
+    const u64 A = S.alpha[i], B = S.beta[i];
+    const u32 a = S.ia[i], b = S.ib[i];
+    {  // same alpha string: beta differs by one or two excitations
+        const u32 lo = S.aoff[a], hi = S.aoff[a + 1];
+        for (u32 base = lo; base < hi; base += HCI_WAVE) {
+            const u32 j = base + lane;
+            bool ok = j < hi && j != i;
+            u64 bj = 0;
+            if (ok) {
+                bj = S.beta[j];
+                ok = popc64(B ^ bj) <= 4;
+            }
+            vis(ok, j, A, bj);
+        }
+    }
+    {  // same beta string: alpha differs by one or two excitations
+        const u32 lo = S.boff[b], hi = S.boff[b + 1];
+        for (u32 base = lo; base < hi; base += HCI_WAVE) {
+            const u32 k = base + lane;
+            bool ok = k < hi;
+            u32 j = 0;
+            u64 aj = 0;
+            if (ok) {
+                j = S.permb[k];
+                ok = j != i;
+                if (ok) {
+                    aj = S.alpha[j];
+                    ok = popc64(A ^ aj) <= 4;
+                }
+            }
+            vis(ok, j, aj, B);
+        }
+    }
+    {  // one alpha and one beta excitation
+        const u32 t0 = S.as_ptr[a], t1 = S.as_ptr[a + 1];
+        const u32 s0 = S.bs_ptr[b], s1 = S.bs_ptr[b + 1];
+        const u32 nbs = s1 - s0;
+        for (u32 t = t0; t < t1; ++t) {
+            const u32 a2 = S.as_idx[t];
+            const u64 A2 = S.ua[a2];
+            const u32 lo = S.aoff[a2], hi = S.aoff[a2 + 1];
+            const u32 len = hi - lo;
+            if (len <= 4u * nbs) {
+                for (u32 base = lo; base < hi; base += HCI_WAVE) {
+                    const u32 j = base + lane;
+                    bool ok = j < hi;
+                    u64 bj = 0;
+                    if (ok) {
+                        bj = S.beta[j];
+                        ok = popc64(B ^ bj) == 2;
+                    }
+                    vis(ok, j, A2, bj);
+                }
+            } else {
+                for (u32 base = s0; base < s1; base += HCI_WAVE) {
+                    const u32 k = base + lane;
+                    bool ok = k < s1;
+                    u32 j = 0;
+                    u64 bj = 0;
+                    if (ok) {
+                        bj = S.ub[S.bs_idx[k]];
+                        const u32 pos = lower_bound_u64(S.beta + lo, len, bj);
+                        ok = pos < len && S.beta[lo + pos] == bj;
+                        j = lo + pos;
+                    }
+                    vis(ok, j, A2, bj);
+                }
+            }
+        }
+    }
+}

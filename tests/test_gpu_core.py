@@ -1,0 +1,191 @@
+"""GPU parity of the HIP library against the CPU oracle on small spaces.
+
+Every expected value comes from the oracle (or the seeded generator) on the
+same inputs; tolerances: integer/index results bit-exact, float64 products
+1e-12 relative to the largest entry, energies 1e-8 Ha, mixed-precision
+products 1e-6 relative (float32 element rounding, 2^-24 per term).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import hci_synth as hs
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib_mod(gpu_available):
+    import paper_1708_07544_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def cas8(lib_mod):
+    w = hs.WORKLOADS["cas8"]
+    h, g = hs.workload_integrals(w)
+    sp = hs.full_space(w.norb, w.nalpha, w.nbeta)
+    e_ref, c_ref = O.lowest_eigenpair(h, g, sp)
+    ctx = lib_mod.HCIContext(h, g, w.nalpha, w.nbeta)
+    print(f"[cas8] n_det={len(sp)} e_ref={e_ref:.12f}", flush=True)
+    return dict(w=w, h=h, g=g, sp=sp, e=e_ref, c=c_ref, ctx=ctx)
+
+
+def rel_err(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_diagonal_cas8(cas8):
+    ctx, h, g, sp = cas8["ctx"], cas8["h"], cas8["g"], cas8["sp"]
+    d = ctx.diagonal(sp).cpu().numpy()
+    ref = np.array([O.diag(h, g, x) for x in sp])
+    assert np.abs(d - ref).max() < 1e-12
+
+
+def test_connection_count_cas8(cas8):
+    ctx, sp = cas8["ctx"], cas8["sp"]
+    assert ctx.connections(sp) == int(O.row_counts(8, sp).sum())
+
+
+@pytest.mark.parametrize("mode", ["stored", "recompute"])
+def test_sigma_fp64_cas8(cas8, mode):
+    ctx, h, g, sp = cas8["ctx"], cas8["h"], cas8["g"], cas8["sp"]
+    c = hs.random_coeffs(len(sp), 3)
+    ref = O.sigma(h, g, sp, c)
+    out = ctx.sigma(sp, c, precision="fp64", mode=mode).cpu().numpy()
+    assert rel_err(out, ref) < 1e-12
+
+
+@pytest.mark.parametrize("mode", ["stored", "recompute"])
+def test_sigma_mixed_cas8(cas8, mode):
+    ctx, h, g, sp = cas8["ctx"], cas8["h"], cas8["g"], cas8["sp"]
+    c = hs.random_coeffs(len(sp), 4)
+    ref = O.sigma(h, g, sp, c)
+    out = ctx.sigma(sp, c, precision="fp32_mixed", mode=mode).cpu().numpy()
+    assert rel_err(out, ref) < 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_davidson_cas8(cas8, precision):
+    ctx, sp = cas8["ctx"], cas8["sp"]
+    e, c, it = ctx.davidson(sp, None, tol=1e-10, precision=precision)
+    print(f"[davidson {precision}] products={it} dE={e - cas8['e']:.3e}", flush=True)
+    assert abs(e - cas8["e"]) < 1e-8
+    c = c.cpu().numpy()
+    assert abs(np.linalg.norm(c) - 1) < 1e-12
+    assert np.abs(np.abs(c) - np.abs(cas8["c"])).max() < 1e-6
+    assert abs(abs(c @ cas8["c"]) - 1.0) < 1e-10
+
+
+@pytest.mark.parametrize("n,na,nb,m,seed", [(8, 4, 4, 300, 1), (10, 3, 5, 700, 2), (12, 6, 6, 1500, 3),
+                                           (7, 2, 0, 9, 4), (14, 7, 6, 64, 5)])
+@pytest.mark.parametrize("eps", [0.0, 1e-4, 1e-2])
+def test_select_bit_exact(lib_mod, n, na, nb, m, seed, eps):
+    """Same (V, c) into both: V + C(eps) identical bit for bit."""
+    h, g = hs.make_integrals(n, 3 * n, seed)
+    V = hs.random_dets(n, na, nb, m, seed=seed, bias=0.2)
+    c = hs.random_coeffs(len(V), seed + 100)
+    ref = O.merge(V, O.select(h, g, V, c, eps))
+    ctx = lib_mod.HCIContext(h, g, na, nb)
+    out = lib_mod.dets_to_numpy(ctx.select(V, c, eps))
+    print(f"[select n={n} m={len(V)} eps={eps}] ref={len(ref)} gpu={len(out)}", flush=True)
+    assert out.shape == ref.shape
+    assert np.array_equal(out, ref)
+
+
+def test_hci_eps0_reaches_fci(cas8):
+    """eps1 = 0 keeps every determinant reachable through a nonzero c_i.
+    Determinants whose FCI amplitude vanishes by spin symmetry may stay out
+    (their coupling to V is through c_i that are zero up to rounding), so the
+    check is: the energy is the FCI energy and V holds every determinant of
+    non-negligible FCI weight."""
+    ctx = cas8["ctx"]
+    V, c, e, hist = ctx.hci(0.0, tol=1e-10)
+    assert abs(e - cas8["e"]) < 1e-8
+    Vn = hs_sorted(V)
+    have = {(int(a), int(b)) for a, b in Vn}
+    full = {(int(a), int(b)) for a, b in cas8["sp"]}
+    assert have <= full
+    need = {(int(a), int(b)) for (a, b), x in zip(cas8["sp"], cas8["c"]) if abs(x) > 1e-8}
+    assert need <= have
+
+
+def hs_sorted(V):
+    import paper_1708_07544_amd as P
+    return P.dets_to_numpy(V)
+
+
+def test_rdm_ground_state_cas8(cas8):
+    ctx, sp, c = cas8["ctx"], cas8["sp"], cas8["c"]
+    r1, r2 = ctx.rdm12(sp, c)
+    o1, o2 = O.rdm12(8, sp, c, c)
+    assert np.abs(r1.cpu().numpy() - o1).max() < 1e-12
+    assert np.abs(r2.cpu().numpy() - o2).max() < 1e-12
+
+
+def test_transition_rdm_small(lib_mod):
+    n, na, nb = 6, 3, 2
+    h, g = hs.make_integrals(n, 18, 7)
+    sp = hs.full_space(n, na, nb)
+    rng = np.random.default_rng(1)
+    bra, ket = rng.normal(size=len(sp)), rng.normal(size=len(sp))
+    ctx = lib_mod.HCIContext(h, g, na, nb)
+    r1, r2 = ctx.rdm12(sp, bra, ket)
+    o1, o2 = O.rdm12(n, sp, bra, ket)
+    assert np.abs(r1.cpu().numpy() - o1).max() < 1e-11
+    assert np.abs(r2.cpu().numpy() - o2).max() < 1e-11
+
+
+def test_energy_backward_unrelaxed_cas8(cas8):
+    ctx, sp, c, h, g = cas8["ctx"], cas8["sp"], cas8["c"], cas8["h"], cas8["g"]
+    dh, dg, z, e2 = ctx.energy_backward(sp, c, cas8["e"], grad_e=2.0)
+    o1, o2 = O.rdm12(8, sp, c, c)
+    assert np.abs(dh.cpu().numpy() - 2.0 * o1).max() < 1e-11
+    assert np.abs(dg.cpu().numpy() - 2.0 * 0.5 * O.symmetrize8(o2)).max() < 1e-11
+
+
+def test_invalid_lists_are_rejected(cas8, lib_mod):
+    ctx, sp = cas8["ctx"], cas8["sp"]
+    bad = sp[::-1].copy()
+    with pytest.raises(lib_mod.HCIError) as ei:
+        ctx.sigma(bad, np.ones(len(bad)))
+    assert ei.value.code == lib_mod._lib.HCI_E_ARG
+    wrong = sp[:3].copy()
+    wrong[1, 0] = np.uint64(0b111)  # 3 alpha electrons
+    with pytest.raises(lib_mod.HCIError):
+        ctx.sigma(wrong, np.ones(3))
+
+
+def test_select_capacity_reports_required(cas8, lib_mod):
+    ctx = cas8["ctx"]
+    V = lib_mod.dets_to_device(hs.aufbau_det(4, 4))
+    c = torch.ones(1, dtype=torch.float64, device="cuda")
+    out = torch.empty((2, 2), dtype=torch.int64, device="cuda")
+    n_out = ctypes.c_int64()
+    L = lib_mod._lib
+    code = L.lib().hci_select(ctx.handle, L._ptr(V), L._ptr(c), 1, 0.0, L._ptr(out), 2,
+                              ctypes.byref(n_out), L._stream())
+    assert code == L.HCI_E_CAPACITY
+    assert n_out.value == 361
+
+
+@pytest.mark.parametrize("m", [1, 2, 63, 65, 257])
+def test_ragged_sizes(lib_mod, m):
+    n, na, nb = 9, 4, 3
+    h, g = hs.make_integrals(n, 27, 9)
+    V = hs.random_dets(n, na, nb, m, seed=m, bias=0.1)
+    c = hs.random_coeffs(len(V), m)
+    ctx = lib_mod.HCIContext(h, g, na, nb)
+    for mode in ["stored", "recompute"]:
+        out = ctx.sigma(V, c, mode=mode).cpu().numpy()
+        assert rel_err(out, O.sigma(h, g, V, c)) < 1e-12
+    assert ctx.connections(V) == int(O.row_counts(n, V).sum())
+    r1, r2 = ctx.rdm12(V, c)
+    o1, o2 = O.rdm12(n, V, c, c)
+    assert np.abs(r1.cpu().numpy() - o1).max() < 1e-12
+    assert np.abs(r2.cpu().numpy() - o2).max() < 1e-12
