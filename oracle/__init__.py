@@ -351,6 +351,100 @@ def energy_from_rdms(h, g, r1, r2, ecore=0.0) -> float:
     return float(ecore + np.sum(h * r1) + 0.5 * np.sum(g * r2))
 
 
+def _lib_pt2():
+    L = lib()
+    if not getattr(L, "_pt2_ready", False):
+        L.orc_pt2_pairs.restype = ctypes.c_long
+        L.orc_pt2_pairs.argtypes = [ctypes.c_int, f64p, f64p, u64p, ctypes.c_long, f64p,
+                                    ctypes.c_double, u64p, i64p, f64p, ctypes.c_long]
+        L.orc_pair_rdm_add.restype = None
+        L.orc_pair_rdm_add.argtypes = [ctypes.c_int] + [ctypes.c_uint64] * 4 + [ctypes.c_double,
+                                                                                f64p, f64p]
+        L._pt2_ready = True
+    return L
+
+
+def pt2_pairs(h, g, V, c, eps2):
+    """Screened pairs of eq. pt_hci: every (i, a), D_a outside V one excitation
+    from D_i, with fl(|H_ai| |c_i|) > eps2.  Returns (a_dets, i, H_ai) in i order."""
+    n = h.shape[0]
+    h, hp = _f64(h)
+    g, gp = _f64(g)
+    V, vp = _u64(V)
+    c, cp = _f64(c)
+    L = _lib_pt2()
+    total = L.orc_pt2_pairs(n, hp, gp, vp, len(V), cp, float(eps2), None, None, None, 0)
+    a = np.zeros((max(total, 1), 2), dtype=np.uint64)
+    idx = np.zeros(max(total, 1), dtype=np.int64)
+    hv = np.zeros(max(total, 1))
+    L.orc_pt2_pairs(n, hp, gp, vp, len(V), cp, float(eps2), a.ctypes.data_as(u64p),
+                    idx.ctypes.data_as(i64p), hv.ctypes.data_as(f64p), total)
+    return a[:total], idx[:total], hv[:total]
+
+
+def pt2(h, g, V, c, e0, eps2):
+    """eps2-screened Epstein-Nesbet PT2 on a frozen (V, c, E0): eq. pt_hci with
+    the Hylleraas minimiser d_a = N_a / (E0 - H_aa) (eq. hylleraas).
+
+    Returns a dict: C (sorted connected determinants), N, Haa, d, E2,
+    r = dE2/dc at fixed E0 (= 2 sum_a M_ai H_ai d_a), and the pair list."""
+    a, idx, hv = pt2_pairs(h, g, V, c, eps2)
+    C = sort_unique(a)
+    pos = find(C, a)
+    c = np.asarray(c, dtype=np.float64)
+    N = np.zeros(len(C))
+    np.add.at(N, pos, hv * c[idx])
+    Haa = np.array([diag(h, g, x) for x in C]) if len(C) else np.zeros(0)
+    d = N / (e0 - Haa)
+    E2 = float(np.sum(N * d))
+    r = np.zeros(len(V))
+    np.add.at(r, idx, 2.0 * hv * d[pos])
+    return dict(C=C, N=N, Haa=Haa, d=d, E2=E2, r=r, pairs=(a, idx, hv, pos))
+
+
+def pt2_rdms(n, V, c, pt):
+    """Gamma^{dc} over the screened pairs (sum d_a c_i <D_a|..|D_i>) and
+    Gamma^{dd} = sum_a d_a^2 <D_a|..|D_a> (H0 is diagonal outside V), by
+    operator application (Sec. "Computational Details")."""
+    L = _lib_pt2()
+    a, idx, hv, pos = pt["pairs"]
+    d, C = pt["d"], pt["C"]
+    dc1, dc2 = np.zeros((n, n)), np.zeros((n, n, n, n))
+    for k in range(len(idx)):
+        L.orc_pair_rdm_add(n, int(a[k, 0]), int(a[k, 1]), int(V[idx[k], 0]), int(V[idx[k], 1]),
+                           float(d[pos[k]] * c[idx[k]]), dc1.ctypes.data_as(f64p),
+                           dc2.ctypes.data_as(f64p))
+    dd1, dd2 = np.zeros((n, n)), np.zeros((n, n, n, n))
+    for k in range(len(C)):
+        L.orc_pair_rdm_add(n, int(C[k, 0]), int(C[k, 1]), int(C[k, 0]), int(C[k, 1]),
+                           float(d[k] ** 2), dd1.ctypes.data_as(f64p), dd2.ctypes.data_as(f64p))
+    return (dc1, dc2), (dd1, dd2)
+
+
+def zvector_dense(H, c, e0, r):
+    """Lagrange multiplier equation (eq. lagc after lambda_d = 0) on c-perp:
+    z = -(Q (H - E0) Q)^+ Q r, Q = 1 - c c^T (dense pseudo-inverse)."""
+    m = len(c)
+    Q = np.eye(m) - np.outer(c, c)
+    A = Q @ (H - e0 * np.eye(m)) @ Q
+    return -np.linalg.pinv(A, rcond=1e-12) @ (Q @ r)
+
+
+def relaxed_rdms(n, V, c, e0, z, pt):
+    """gamma/Gamma of the relaxed gradient (eq. lambda with lambda_c =
+    z/2 - (d.d) c/2): (1 - d.d) G^cc + G^zc + 2 G^dc + G^dd, transition parts
+    symmetrised over bra/ket."""
+    g1, g2 = rdm12(n, V, c, c)
+    z1, z2 = rdm12(n, V, z, c)
+    (dc1, dc2), (dd1, dd2) = pt2_rdms(n, V, c, pt)
+    dd = float(np.dot(pt["d"], pt["d"]))
+    sym1 = lambda x: 0.5 * (x + x.T)  # noqa: E731
+    sym2 = lambda x: 0.5 * (x + x.transpose(1, 0, 3, 2))  # noqa: E731
+    r1 = (1 - dd) * g1 + sym1(z1) + 2 * sym1(dc1) + dd1
+    r2 = (1 - dd) * g2 + sym2(z2) + 2 * sym2(dc2) + dd2
+    return r1, r2
+
+
 def symmetrize8(t) -> np.ndarray:
     """Average of a 4-index tensor over the 8 real-orbital integral symmetries."""
     perms = [(0, 1, 2, 3), (1, 0, 2, 3), (0, 1, 3, 2), (1, 0, 3, 2),

@@ -507,3 +507,82 @@ long orc_apply_h(int n, const double* h, const double* g, u64 a, u64 b,
     }
     return k;
 }
+
+/* ---- eps2-screened second-order pieces (eq. pt_hci) ---- */
+/* Every pair (i, a) with D_a outside V reached from D_i by one single or
+ * double excitation and fl(|H_ai| * |c_i|) > eps2 (the screening mask),
+ * listed in i order then excitation order.  Writes up to cap entries of
+ * (a alpha, a beta), i and H_ai; returns the total. */
+long orc_pt2_pairs(int n, const double* h, const double* g, const u64* V, long nv,
+                   const double* c, double eps2, u64* out_a, long* out_i, double* out_h, long cap) {
+    long total = 0;
+    u64* buf = NULL;
+    long bufcap = 0;
+    for (long i = 0; i < nv; ++i) {
+        u64 a = V[2 * i], b = V[2 * i + 1];
+        long m = max_excitations(n, a, b);
+        if (m > bufcap) {
+            free(buf);
+            bufcap = m;
+            buf = (u64*)malloc(sizeof(u64) * 2 * bufcap);
+        }
+        orc_excitations(n, a, b, buf, m);
+        double ci = fabs(c[i]);
+        for (long k = 0; k < m; ++k) {
+            u64 xa = buf[2 * k], xb = buf[2 * k + 1];
+            if (orc_find(V, nv, xa, xb) >= 0) continue;
+            double hai = orc_hij(n, h, g, a, b, xa, xb);
+            double prod = fabs(hai) * ci;
+            if (prod > eps2) {
+                if (total < cap) {
+                    out_a[2 * total] = xa;
+                    out_a[2 * total + 1] = xb;
+                    out_i[total] = i;
+                    out_h[total] = hai;
+                }
+                total++;
+            }
+        }
+    }
+    free(buf);
+    return total;
+}
+
+/* rdm1/rdm2 += w * <D_x| ops |D_y> for one pair of determinants, by applying
+ * every operator of the spin-traced definitions to D_y (x may equal y). */
+void orc_pair_rdm_add(int n, u64 xa, u64 xb, u64 ya, u64 yb, double w, double* rdm1, double* rdm2) {
+    int ns = 2 * n;
+    so_t d0 = {ya, yb};
+    for (int qs = 0; qs < ns; ++qs)
+        for (int ps = 0; ps < ns; ++ps) {
+            if ((qs < n) != (ps < n)) continue;
+            so_t d = d0;
+            int s1 = so_annihilate(&d, n, qs);
+            if (!s1) continue;
+            int s2 = so_create(&d, n, ps);
+            if (!s2) continue;
+            if (d.lo != xa || d.hi != xb) continue;
+            rdm1[(size_t)(ps % n) * n + (qs % n)] += w * s1 * s2;
+        }
+    if (!rdm2) return;
+    for (int qs = 0; qs < ns; ++qs)
+        for (int ss = 0; ss < ns; ++ss)
+            for (int rs = 0; rs < ns; ++rs) {
+                if ((ss < n) != (rs < n)) continue;
+                for (int ps = 0; ps < ns; ++ps) {
+                    if ((qs < n) != (ps < n)) continue;
+                    so_t d = d0;
+                    int s1 = so_annihilate(&d, n, qs);
+                    if (!s1) continue;
+                    int s2 = so_annihilate(&d, n, ss);
+                    if (!s2) continue;
+                    int s3 = so_create(&d, n, rs);
+                    if (!s3) continue;
+                    int s4 = so_create(&d, n, ps);
+                    if (!s4) continue;
+                    if (d.lo != xa || d.hi != xb) continue;
+                    int p = ps % n, q = qs % n, r = rs % n, s = ss % n;
+                    rdm2[(((size_t)p * n + q) * n + r) * n + s] += w * (double)(s1 * s2 * s3 * s4);
+                }
+            }
+}
