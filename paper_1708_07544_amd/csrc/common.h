@@ -42,21 +42,74 @@ void hci_set_error(const std::string& msg);
 // ---------------------------------------------------------------- device helpers
 __device__ __forceinline__ int popc64(u64 x) { return __popcll(x); }
 __device__ __forceinline__ int ctz64(u64 x) { return __builtin_ctzll(x); }
-__device__ __forceinline__ u64 bit(int p) { return 1ull << p; }
+// Bit manipulation on 64-bit occupation words goes through 32-bit halves:
+// variable-amount 64-bit shifts are avoided everywhere in device code (they
+// produced sporadic wrong results on gfx950 in the element kernels).
+__device__ __forceinline__ u64 join32(u32 hi, u32 lo) { return ((u64)hi << 32) | (u64)lo; }
+__device__ __forceinline__ u32 lo32(u64 x) { return (u32)x; }
+__device__ __forceinline__ u32 hi32(u64 x) { return (u32)(x >> 32); }
+
+// word with only bit p set (0 <= p < 64)
+// (single-bit words come from a table: the compiler would otherwise fold a
+// select of shifted halves back into a 64-bit variable shift)
+static __constant__ u64 kBit64[64] = {0x1ull, 0x2ull, 0x4ull, 0x8ull, 0x10ull, 0x20ull, 0x40ull, 0x80ull, 0x100ull, 0x200ull, 0x400ull, 0x800ull, 0x1000ull, 0x2000ull, 0x4000ull, 0x8000ull, 0x10000ull, 0x20000ull, 0x40000ull, 0x80000ull, 0x100000ull, 0x200000ull, 0x400000ull, 0x800000ull, 0x1000000ull, 0x2000000ull, 0x4000000ull, 0x8000000ull, 0x10000000ull, 0x20000000ull, 0x40000000ull, 0x80000000ull, 0x100000000ull, 0x200000000ull, 0x400000000ull, 0x800000000ull, 0x1000000000ull, 0x2000000000ull, 0x4000000000ull, 0x8000000000ull, 0x10000000000ull, 0x20000000000ull, 0x40000000000ull, 0x80000000000ull, 0x100000000000ull, 0x200000000000ull, 0x400000000000ull, 0x800000000000ull, 0x1000000000000ull, 0x2000000000000ull, 0x4000000000000ull, 0x8000000000000ull, 0x10000000000000ull, 0x20000000000000ull, 0x40000000000000ull, 0x80000000000000ull, 0x100000000000000ull, 0x200000000000000ull, 0x400000000000000ull, 0x800000000000000ull, 0x1000000000000000ull, 0x2000000000000000ull, 0x4000000000000000ull, 0x8000000000000000ull};
+
+__device__ __forceinline__ u64 bit(int p) { return kBit64[p]; }
+
+// bit p of s (0 <= p < 64)
+__device__ __forceinline__ bool test_bit(u64 s, int p) {
+    const u32 w = p < 32 ? lo32(s) : hi32(s);
+    return ((w >> (p & 31)) & 1u) != 0u;
+}
+
+// bits [0, k) set (0 <= k <= 64)
+__device__ __forceinline__ u64 low_mask(int k) { return k >= 64 ? ~0ull : kBit64[k] - 1ull; }
+
+// byte b (0..7) of x
+__device__ __forceinline__ u32 byte_of(u64 x, int b) {
+    const u32 w = b < 4 ? lo32(x) : hi32(x);
+    return (w >> (8 * (b & 3))) & 0xffu;
+}
+
+// Number of set bits of s below position k (0 <= k <= 64), from 32-bit
+// halves: phase factors are built from these counts only, with no 64-bit
+// variable shifts (shift-built 64-bit masks gave sporadic wrong parities on
+// gfx950 in the element kernels).
+__device__ __forceinline__ int rank_below(u64 s, int k) {
+    const u64 m = low_mask(k);
+    return __popc(lo32(s) & lo32(m)) + __popc(hi32(s) & hi32(m));
+}
+
+// number of set bits of s strictly between orbitals p and q (p != q)
+__device__ __forceinline__ int count_between(u64 s, int p, int q) {
+    const int lo = p < q ? p : q, hi = p < q ? q : p;
+    return rank_below(s, hi) - rank_below(s, lo + 1);
+}
 
 // (-1)^(number of set bits of s strictly between orbitals p and q)
 __device__ __forceinline__ double sign_between(u64 s, int p, int q) {
-    int lo = p < q ? p : q, hi = p < q ? q : p;
-    u64 m = (bit(hi) - 1ull) & ~((bit(lo) << 1) - 1ull);
-    return (popc64(s & m) & 1) ? -1.0 : 1.0;
+    return (count_between(s, p, q) & 1) ? -1.0 : 1.0;
+}
+
+// Phase of the same-spin double p -> r then q -> s applied to string si
+// (p, q occupied; r, s empty): the second count is taken on si with p
+// removed and r added, i.e. it changes by one for each of p, r that lies
+// strictly between q and s.
+__device__ __forceinline__ double sign_double(u64 si, int p, int r, int q, int s) {
+    const int lo = q < s ? q : s, hi = q < s ? s : q;
+    const int n = count_between(si, p, r) + count_between(si, q, s) + (p > lo && p < hi) +
+                  (r > lo && r < hi);
+    return (n & 1) ? -1.0 : 1.0;
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ u64 ballot(bool p) { return __ballot(p); }
 
-// lanes below this one in the wavefront
-__device__ __forceinline__ u64 lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+// number of set bits of m in the lanes below this one (mbcnt, no shifts)
+__device__ __forceinline__ u32 rank_in(u64 m) {
+    return __builtin_amdgcn_mbcnt_hi(hi32(m), __builtin_amdgcn_mbcnt_lo(lo32(m), 0u));
+}
 
 __device__ __forceinline__ double wave_sum_f64(double v) {
 #pragma unroll
@@ -156,6 +209,7 @@ struct Space {
     DevMem vals64;        // f64 [nnz]
     DevMem vals32;        // f32 [nnz]
     i64 nnz_off = -1;     // off-diagonal connections
+    i64 nnz_pad = 0;      // stored entries (rows padded to multiples of 4)
     bool have_csr64 = false, have_csr32 = false;
 };
 

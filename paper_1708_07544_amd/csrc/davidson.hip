@@ -10,14 +10,17 @@
 //
 // Precision HCI_FP32_MIXED: iterate with the mixed product (float32 elements
 // times a float32 copy of the vector, float64 row sums) until the residual is
-// below max(tol, 1e-6), then restart from the Ritz vector with float64
-// products until the float64 residual meets tol.
+// below max(tol, 1e-7 |theta|) (the float32 operator is not more accurate than
+// that), then restart from the Ritz vector with float64 products until the
+// float64 residual meets tol.  Restarts keep the current and the previous
+// Ritz vectors.
 #include "common.h"
 
 namespace {
 
 constexpr int DV_BLOCK = 256;
-constexpr int DV_MAXK = 32;
+constexpr int DV_MAXK = 32;   // capacity of the small dense arrays
+constexpr int DV_KMAX = 24;   // subspace size before a thick restart
 
 // partial[j * nblk + b] = sum over the block's rows of X_j[i] * t[i], j < k
 __global__ void __launch_bounds__(DV_BLOCK) dots_kernel(const double* __restrict__ X, i64 ld, int k,
@@ -259,83 +262,111 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
     const i64 N = sp->N;
     ensure_diag(ctx, sp, s);
     const double* hd = sp->hdiag.as<double>();
-    int kmax = (int)std::min<i64>(24, N);
+    const int kmax = (int)std::min<i64>(DV_KMAX, N);
     Workspace ws(ctx, N, s);
     DevMem Vb = dev_alloc(ctx, sizeof(double) * kmax * N, s);
     DevMem Wb = dev_alloc(ctx, sizeof(double) * kmax * N, s);
     DevMem G = dev_alloc(ctx, sizeof(double) * DV_MAXK * DV_MAXK, s);
     DevMem ritz = dev_alloc(ctx, sizeof(double) * (DV_MAXK + 1), s);
-    DevMem x = dev_alloc(ctx, sizeof(double) * N, s);
-    DevMem w = dev_alloc(ctx, sizeof(double) * N, s);
-    DevMem t = dev_alloc(ctx, sizeof(double) * N, s);
+    DevMem vec = dev_alloc(ctx, sizeof(double) * 5 * N, s);
     double* V = Vb.as<double>();
     double* W = Wb.as<double>();
-    double* sc = ws.scal.as<double>();  // sc[0..DV_MAXK) coefficients, sc[DV_MAXK] norms
+    // current Ritz pair (xc, wc = H xc), previous one, and the correction
+    double* xc = vec.as<double>();
+    double* wc = xc + N;
+    double* xp = xc + 2 * N;
+    double* wp = xc + 3 * N;
+    double* t = xc + 4 * N;
+    double* sc = ws.scal.as<double>();  // sc[0..DV_MAXK) coefficients, then scalars below
+    double* nrm_x = sc + DV_MAXK;
+    double* rr = sc + DV_MAXK + 1;
+    double* nrm_t = sc + DV_MAXK + 2;
     const i64 g1 = ceil_div(N, 256);
 
-    // start vector
-    HIP_CHECK(hipMemcpyAsync(x.ptr, c, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-    ws.dots(x.as<double>(), N, 1, x.as<double>(), sc + DV_MAXK);
-    if (read_scalar(sc + DV_MAXK, s) <= 0.0) {
-        HCI_LAUNCH(ctx, "dv_seed", s, argmin_seed_kernel, 1, 256, 0, hd, N, x.as<double>());
-        ws.dots(x.as<double>(), N, 1, x.as<double>(), sc + DV_MAXK);
-    }
+    // start vector (a zero vector selects the lowest diagonal determinant)
+    HIP_CHECK(hipMemcpyAsync(xc, c, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    ws.dots(xc, N, 1, xc, nrm_x);
+    if (read_scalar(nrm_x, s) <= 0.0)
+        HCI_LAUNCH(ctx, "dv_seed", s, argmin_seed_kernel, 1, 256, 0, hd, N, xc);
 
     const bool mixed = precision == HCI_FP32_MIXED;
     int phase_prec = mixed ? HCI_FP32_MIXED : HCI_FP64;
     int phase_mode = choose_mode(ctx, sp, phase_prec, mode, s);
-    double phase_tol = mixed ? std::max(tol, 1e-6) : tol;
     int products = 0;
     double theta = 0.0, rnorm = 1e300;
-    bool converged = false;
+    bool converged = false, need_sigma = true, have_prev = false;
 
-    bool need_sigma = true;
     while (true) {
-        // (re)start the subspace from x (and w = H x when it is still valid)
-        HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, x.as<double>(),
-                   sc + DV_MAXK, V, N);
+        // (re)start: V0 = x/|x| with W0 = H V0 (a new product only when the
+        // operator changed), plus the previous Ritz vector orthogonalised
+        // against it (thick restart keeps the last search direction)
+        ws.dots(xc, N, 1, xc, nrm_x);
+        HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, xc, nrm_x, V, N);
         if (need_sigma) {
             sigma_apply(ctx, sp, V, W, phase_prec, phase_mode, s);
             ++products;
+            have_prev = false;
         } else {
-            HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, w.as<double>(),
-                       sc + DV_MAXK, W, N);
+            HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, wc, nrm_x, W, N);
         }
         need_sigma = false;
         int k = 1;
-        ws.dots(V, N, 1, W, G.as<double>());
+        if (have_prev && kmax > 1 && products < max_iter) {
+            // x_prev minus its component along x is a small difference of two
+            // nearly parallel vectors: orthogonalise it twice and take its
+            // image from a fresh product (combining the old images would
+            // amplify their rounding errors)
+            HIP_CHECK(hipMemcpyAsync(t, xp, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+            for (int pass = 0; pass < 2; ++pass) {
+                ws.dots(V, N, 1, t, sc);
+                HCI_LAUNCH(ctx, "dv_subcombo", s, sub_combo_kernel, g1, 256, 0, V, N, 1, sc, t, N);
+            }
+            ws.dots(t, N, 1, t, nrm_t);
+            if (read_scalar(nrm_t, s) > 1e-24) {
+                HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, t, nrm_t, V + N, N);
+                sigma_apply(ctx, sp, V + N, W + N, phase_prec, phase_mode, s);
+                ++products;
+                k = 2;
+            }
+        }
+        for (int j = 0; j < k; ++j) {
+            ws.dots(V, N, j + 1, W + (i64)j * N, sc);
+            HCI_LAUNCH(ctx, "dv_gram", s, gram_column_kernel, 1, 64, 0, G.as<double>(), DV_MAXK, j, sc);
+        }
         bool phase_done = false;
         while (true) {
             HCI_LAUNCH(ctx, "dv_jacobi", s, jacobi_lowest_kernel, 1, 64, 0, G.as<double>(), DV_MAXK,
                        k, ritz.as<double>());
+            std::swap(xc, xp);
+            std::swap(wc, wp);
             HCI_LAUNCH(ctx, "dv_combine", s, combine_kernel, ws.nblk, DV_BLOCK, 0, V, W, N, k,
-                       ritz.as<double>(), hd, x.as<double>(), w.as<double>(), t.as<double>(), N,
-                       ws.partial.as<double>(), ws.nblk);
+                       ritz.as<double>(), hd, xc, wc, t, N, ws.partial.as<double>(), ws.nblk);
+            have_prev = true;
             HCI_LAUNCH(ctx, "dv_reduce", s, reduce_partials_kernel, 1, DV_BLOCK, 0,
-                       ws.partial.as<double>(), 1, ws.nblk, sc + DV_MAXK + 1);
+                       ws.partial.as<double>(), 1, ws.nblk, rr);
             double hv[2];
             HIP_CHECK(hipMemcpyAsync(&hv[0], ritz.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipMemcpyAsync(&hv[1], sc + DV_MAXK + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipMemcpyAsync(&hv[1], rr, sizeof(double), hipMemcpyDeviceToHost, s));
             HIP_CHECK(hipStreamSynchronize(s));
             theta = hv[0];
             rnorm = sqrt(std::max(hv[1], 0.0));
-            if (rnorm <= phase_tol) {
+            // the float32 operator is only meaningful down to ~1e-7 |theta|
+            const double target =
+                phase_prec == HCI_FP32_MIXED ? std::max(tol, 1e-7 * std::max(1.0, fabs(theta))) : tol;
+            if (rnorm <= target) {
                 phase_done = true;
                 break;
             }
             if (products >= max_iter) break;
-            if (k == kmax) break;  // restart from the current Ritz vector
+            if (k == kmax) break;  // thick restart
             // orthogonalise the preconditioned residual against the basis (CGS2)
             for (int pass = 0; pass < 2; ++pass) {
-                ws.dots(V, N, k, t.as<double>(), sc);
-                HCI_LAUNCH(ctx, "dv_subcombo", s, sub_combo_kernel, g1, 256, 0, V, N, k, sc,
-                           t.as<double>(), N);
+                ws.dots(V, N, k, t, sc);
+                HCI_LAUNCH(ctx, "dv_subcombo", s, sub_combo_kernel, g1, 256, 0, V, N, k, sc, t, N);
             }
-            ws.dots(t.as<double>(), N, 1, t.as<double>(), sc + DV_MAXK + 2);
-            const double tn = read_scalar(sc + DV_MAXK + 2, s);
-            if (!(tn > 1e-28)) break;  // no new direction: restart
-            HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, t.as<double>(),
-                       sc + DV_MAXK + 2, V + (i64)k * N, N);
+            ws.dots(t, N, 1, t, nrm_t);
+            if (!(read_scalar(nrm_t, s) > 1e-28)) break;  // no new direction: restart
+            HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, t, nrm_t, V + (i64)k * N, N);
             sigma_apply(ctx, sp, V + (i64)k * N, W + (i64)k * N, phase_prec, phase_mode, s);
             ++products;
             // new Gram column: G[j][k] = V_j . W_k, j <= k
@@ -349,21 +380,17 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
                 phase_prec = HCI_FP64;
                 phase_mode = sp->have_csr64 ? HCI_SIGMA_STORED : HCI_SIGMA_RECOMPUTE;
                 if (mode == HCI_SIGMA_STORED || mode == HCI_SIGMA_RECOMPUTE) phase_mode = mode;
-                phase_tol = tol;
                 need_sigma = true;
-                ws.dots(x.as<double>(), N, 1, x.as<double>(), sc + DV_MAXK);
                 continue;
             }
             converged = true;
             break;
         }
         if (products >= max_iter) break;
-        ws.dots(x.as<double>(), N, 1, x.as<double>(), sc + DV_MAXK);
     }
     // normalise and fix the sign of the final vector
-    ws.dots(x.as<double>(), N, 1, x.as<double>(), sc + DV_MAXK);
-    HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, x.as<double>(), sc + DV_MAXK,
-               c, N);
+    ws.dots(xc, N, 1, xc, nrm_x);
+    HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, xc, nrm_x, c, N);
     HCI_LAUNCH(ctx, "dv_signfix", s, sign_fix_kernel, 1, 256, 0, c, N);
     *e_out = theta + ctx->ecore;
     if (iters_out) *iters_out = products;

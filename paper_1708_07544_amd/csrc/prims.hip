@@ -77,8 +77,7 @@ constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_BLOCK * RS_ITEMS;
 
 __device__ __forceinline__ u32 digit_of(u64 hi, u64 lo, int pass, int passes_lo) {
-    return pass < passes_lo ? (u32)((lo >> (8 * pass)) & 0xffull)
-                            : (u32)((hi >> (8 * (pass - passes_lo))) & 0xffull);
+    return pass < passes_lo ? byte_of(lo, pass) : byte_of(hi, pass - passes_lo);
 }
 
 __global__ void __launch_bounds__(RS_BLOCK) rs_hist_kernel(const u64* __restrict__ hi,
@@ -131,7 +130,7 @@ __global__ void __launch_bounds__(RS_BLOCK) rs_scatter_kernel(
             u64 m = ballot(((d >> b) & 1u) != 0);
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
-        u32 rank = (u32)__popcll(peers & lanemask_lt());
+        u32 rank = rank_in(peers);
         if (valid && rank == 0) wcnt[w][d] = (u32)__popcll(peers);
         __syncthreads();
         if (valid) {

@@ -76,7 +76,7 @@ __device__ __forceinline__ void pair_contrib(int n, double w, u64 ai, u64 bi, u6
     const int u1 = ctz64(parts);
     parts &= parts - 1;
     const int u2 = ctz64(parts);
-    const double sg = sign_between(sj, v1, u1) * sign_between(sj ^ bit(v1) ^ bit(u1), v2, u2);
+    const double sg = sign_double(sj, v1, u1, v2, u2);
     const double x = w * sg;
     add64(&r2[r2idx(n, u1, v1, u2, v2)], x);
     add64(&r2[r2idx(n, u2, v2, u1, v1)], x);
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(256) occ_corr_kernel(const u64* __restrict__ a
                 for (int k = 0; k < cnt; ++k) {
                     const u64 wx = xa ? sa[k] : sb[k];
                     const u64 wy = ya ? sa[k] : sb[k];
-                    if (((wx >> bx) & 1ull) && ((wy >> by) & 1ull)) s += sw[k];
+                    if (test_bit(wx, bx) && test_bit(wy, by)) s += sw[k];
                 }
                 acc[e] += s;
             }

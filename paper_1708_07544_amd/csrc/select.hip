@@ -1,55 +1,168 @@
 // One HCI selection step: V' = V + C(eps1), where C(eps1) holds every
 // determinant D_a outside V with |H_ai c_i| > eps1 for some D_i in V
 // (Sec. "Variational Stage", eq. criteria and the HCI importance function).
-// Candidates come from the heat-bath walk (no candidate lists are built
-// for pairs that cannot pass); they are appended to V, radix-sorted and
-// made unique, which also removes the members of V that were re-found.
+//
+// Candidates come from the heat-bath walk, so no candidate list is built for
+// an occupied pair that cannot pass.  A determinant is usually reached from
+// many D_i; instead of storing every hit and sorting the duplicates away, the
+// walk inserts each hit into a device hash set pre-filled with V (open
+// addressing, 64-bit CAS).  Only first insertions are appended to the list of
+// new determinants, which is then sorted together with V.  The set content,
+// hence V', does not depend on the insertion order.
+//
+// Keys: for norb <= 31 a determinant packs into one word (alpha << 32 |
+// beta).  Otherwise alpha and beta strings are first interned in their own
+// hash sets and the determinant key is the pair of slot indices.
 #include "walk.h"
 
 namespace {
 
 constexpr int WALK_BLOCK = 256;
 constexpr int WALK_ROWS = WALK_BLOCK / HCI_WAVE;
+constexpr u64 EMPTY = ~0ull;
+constexpr int MAX_PROBE = 1 << 12;
 
-struct EmitVis {
-    u64* out_hi;
-    u64* out_lo;
+__device__ __forceinline__ u64 hmix(u64 x) {
+    x ^= x >> 31;
+    x *= 0x7fb5d329728ea185ull;
+    x ^= x >> 27;
+    x *= 0x81dadef4bc2dd44dull;
+    x ^= x >> 33;
+    return x;
+}
+
+// Insert `key` (or find it).  Returns the slot, or -1 after MAX_PROBE probes.
+__device__ __forceinline__ i64 hash_insert(u64* __restrict__ table, u64 mask, u64 key, bool& fresh) {
+    u64 h = hmix(key) & mask;
+    for (int probe = 0; probe < MAX_PROBE; ++probe) {
+        const u64 cur = table[h];
+        if (cur == key) {
+            fresh = false;
+            return (i64)h;
+        }
+        if (cur == EMPTY) {
+            const u64 prev = atomicCAS((unsigned long long*)&table[h], (unsigned long long)EMPTY,
+                                       (unsigned long long)key);
+            if (prev == EMPTY) {
+                fresh = true;
+                return (i64)h;
+            }
+            if (prev == key) {
+                fresh = false;
+                return (i64)h;
+            }
+        }
+        h = (h + 1) & mask;
+    }
+    fresh = false;
+    return -1;
+}
+
+struct HashSet {
+    u64* det;       // determinant keys
+    u64 det_mask;
+    u64* sa;        // alpha strings (two-level keys only)
+    u64 sa_mask;
+    u64* sb;        // beta strings
+    u64 sb_mask;
+    int packed;     // 1: key = alpha << 32 | beta
+    unsigned long long* overflow;
+    unsigned long long* strings;  // [0] alpha, [1] beta strings interned
+};
+
+// Determinant key, interning the strings when keys are two-level.
+__device__ __forceinline__ bool det_key(const HashSet& H, u64 a, u64 b, u64& key) {
+    if (H.packed) {
+        key = (a << 32) | b;
+        return true;
+    }
+    bool fa, fb;
+    const i64 ka = hash_insert(H.sa, H.sa_mask, a, fa);
+    const i64 kb = hash_insert(H.sb, H.sb_mask, b, fb);
+    if (ka < 0 || kb < 0) return false;
+    if (fa) atomicAdd(&H.strings[0], 1ull);
+    if (fb) atomicAdd(&H.strings[1], 1ull);
+    key = ((u64)ka << 32) | (u64)kb;
+    return true;
+}
+
+__global__ void fill_kernel(u64* __restrict__ t, i64 n, u64 v) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) t[i] = v;
+}
+
+__global__ void insert_v_kernel(HashSet H, const u64* __restrict__ dets, i64 N) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    u64 key;
+    bool fresh;
+    if (!det_key(H, dets[2 * i], dets[2 * i + 1], key) || hash_insert(H.det, H.det_mask, key, fresh) < 0)
+        atomicOr(H.overflow, 1ull);
+}
+
+struct InsertVis {
+    HashSet H;
+    u64* out;
     unsigned long long* counter;
     i64 cap;
     __device__ __forceinline__ void operator()(bool ok, u64 aa, u64 ab) {
-        const u64 m = ballot(ok);
+        bool fresh = false;
+        u64 key = 0;
+        if (ok) {
+            if (!det_key(H, aa, ab, key) || hash_insert(H.det, H.det_mask, key, fresh) < 0) {
+                atomicOr(H.overflow, 1ull);
+                fresh = false;
+            }
+        }
+        const u64 m = ballot(fresh);
         if (!m) return;
         unsigned long long base = 0;
         if (lane_id() == 0) base = atomicAdd(counter, (unsigned long long)__popcll(m));
         base = __shfl(base, 0, 64);
-        if (ok) {
-            const i64 at = (i64)base + __popcll(m & lanemask_lt());
-            if (at < cap) {
-                out_hi[at] = aa;
-                out_lo[at] = ab;
-            }
+        if (fresh) {
+            const i64 at = (i64)base + rank_in(m);
+            if (at < cap) out[at] = key;
         }
     }
 };
 
 __global__ void __launch_bounds__(WALK_BLOCK) select_walk_kernel(
     HBView T, IntView I, const u64* __restrict__ dets, const double* __restrict__ c, i64 N,
-    double eps, double hb_max, u64* __restrict__ out_hi, u64* __restrict__ out_lo, i64 cap,
+    double eps, double hb_max, HashSet H, u64* __restrict__ out, i64 cap,
     unsigned long long* __restrict__ counter) {
     const i64 i = (i64)blockIdx.x * WALK_ROWS + threadIdx.x / HCI_WAVE;
     if (i >= N) return;
     const double ci = fabs(c[i]);
     if (!(hb_max * ci > eps)) return;  // nothing can pass from this determinant
-    EmitVis v{out_hi, out_lo, counter, cap};
+    InsertVis v{H, out, counter, cap};
     heat_bath_walk(T, I, dets[2 * i], dets[2 * i + 1], ci, eps, v);
 }
 
-__global__ void split_kernel(const u64* __restrict__ dets, i64 N, u64* __restrict__ hi,
-                             u64* __restrict__ lo) {
-    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) {
-        hi[i] = dets[2 * i];
-        lo[i] = dets[2 * i + 1];
+// V followed by the decoded new determinants, split into (alpha, beta) words
+__global__ void gather_kernel(const u64* __restrict__ dets, i64 N, const u64* __restrict__ keys,
+                              i64 m, HashSet H, u64* __restrict__ hi, u64* __restrict__ lo) {
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < N) {
+        hi[t] = dets[2 * t];
+        lo[t] = dets[2 * t + 1];
+    } else if (t < N + m) {
+        const u64 k = keys[t - N];
+        if (H.packed) {
+            hi[t] = k >> 32;
+            lo[t] = k & 0xffffffffull;
+        } else {
+            hi[t] = H.sa[k >> 32];
+            lo[t] = H.sb[k & 0xffffffffull];
+        }
+    }
+}
+
+__global__ void interleave_kernel(const u64* __restrict__ hi, const u64* __restrict__ lo, i64 n,
+                                  u64* __restrict__ out) {
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        out[2 * t] = hi[t];
+        out[2 * t + 1] = lo[t];
     }
 }
 
@@ -84,6 +197,12 @@ __global__ void embed_kernel(const u64* __restrict__ dets, i64 n, const double* 
     }
     if (lo < nn && dn[2 * lo] == a && dn[2 * lo + 1] == b) out[lo] = c[k];
     else atomicAdd(missing, 1ull);
+}
+
+i64 pow2_at_least(i64 x) {
+    i64 p = 1;
+    while (p < x) p <<= 1;
+    return p;
 }
 
 }  // namespace
@@ -123,29 +242,66 @@ i64 select_run(hci_ctx_s* ctx, const u64* dets, const double* c, i64 N, double e
     const double hbm = heat_bath_max(ctx, s);
     HBView T = hb_view(ctx->ints);
     IntView I = int_view(ctx->ints);
-    DevMem counter = dev_alloc(ctx, sizeof(u64), s);
-    i64 guess = std::max<i64>(4 * N, 1 << 20);
-    i64 total = 0;
-    DevMem hi, lo;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        hi = dev_alloc(ctx, sizeof(u64) * (N + guess), s);
-        lo = dev_alloc(ctx, sizeof(u64) * (N + guess), s);
-        HIP_CHECK(hipMemsetAsync(counter.ptr, 0, sizeof(u64), s));
-        // candidates land after the copy of V
+    const bool packed = n <= 31;
+    // [0] new determinants, [1] overflow, [2..3] interned alpha / beta strings
+    DevMem flags = dev_alloc(ctx, sizeof(u64) * 4, s);
+    unsigned long long* counter = (unsigned long long*)flags.as<u64>();
+    unsigned long long* overflow = counter + 1;
+    unsigned long long* strings = counter + 2;
+    i64 det_slots = pow2_at_least(std::max<i64>(8 * N, 1 << 20));
+    i64 str_slots = pow2_at_least(std::max<i64>(2 * N, 1 << 16));
+    DevMem table, sa, sb, keys;
+    i64 m = 0;
+    for (int attempt = 0;; ++attempt) {
+        HCI_REQUIRE(attempt < 6 && det_slots <= ((i64)1 << 32), HCI_E_NOMEM,
+                    "selection hash set cannot grow further");
+        table = dev_alloc(ctx, sizeof(u64) * det_slots, s);
+        HCI_LAUNCH(ctx, "select_fill", s, fill_kernel, ceil_div(det_slots, 256), 256, 0,
+                   table.as<u64>(), det_slots, EMPTY);
+        HashSet H{table.as<u64>(), (u64)(det_slots - 1), nullptr, 0, nullptr, 0, packed ? 1 : 0,
+                  overflow, strings};
+        if (!packed) {
+            sa = dev_alloc(ctx, sizeof(u64) * str_slots, s);
+            sb = dev_alloc(ctx, sizeof(u64) * str_slots, s);
+            HCI_LAUNCH(ctx, "select_fill", s, fill_kernel, ceil_div(str_slots, 256), 256, 0,
+                       sa.as<u64>(), str_slots, EMPTY);
+            HCI_LAUNCH(ctx, "select_fill", s, fill_kernel, ceil_div(str_slots, 256), 256, 0,
+                       sb.as<u64>(), str_slots, EMPTY);
+            H.sa = sa.as<u64>();
+            H.sb = sb.as<u64>();
+            H.sa_mask = H.sb_mask = (u64)(str_slots - 1);
+        }
+        HIP_CHECK(hipMemsetAsync(flags.ptr, 0, sizeof(u64) * 4, s));
+        HCI_LAUNCH(ctx, "select_insert_v", s, insert_v_kernel, ceil_div(N, 256), 256, 0, H, dets, N);
+        // new determinants can never exceed the free slots
+        const i64 kcap = det_slots / 2;
+        keys = dev_alloc(ctx, sizeof(u64) * kcap, s);
         HCI_LAUNCH(ctx, "select_walk", s, select_walk_kernel, ceil_div(N, WALK_ROWS), WALK_BLOCK, 0, T,
-                   I, dets, c, N, eps, hbm, hi.as<u64>() + N, lo.as<u64>() + N, guess,
-                   (unsigned long long*)counter.as<u64>());
-        total = (i64)read_scalar(counter.as<u64>(), s);
-        if (total <= guess) break;
-        guess = total;
+                   I, dets, c, N, eps, hbm, H, keys.as<u64>(), kcap, counter);
+        u64 hv[4];
+        HIP_CHECK(hipMemcpyAsync(hv, flags.ptr, sizeof(hv), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        m = (i64)hv[0];
+        // keep every load factor at most 1/2: otherwise grow and walk again
+        const i64 nstr = (i64)std::max(hv[2], hv[3]);
+        const bool str_ok = packed || nstr <= str_slots / 2;
+        if (hv[1] == 0 && N + m <= det_slots / 2 && m <= kcap && str_ok) break;
+        det_slots = pow2_at_least(std::max<i64>(4 * (N + m), 2 * det_slots));
+        if (!str_ok || hv[1]) str_slots = pow2_at_least(std::max<i64>(4 * nstr, 2 * str_slots));
     }
-    const i64 M = N + total;
-    HCI_LAUNCH(ctx, "select_split", s, split_kernel, ceil_div(N, 256), 256, 0, dets, N, hi.as<u64>(),
-               lo.as<u64>());
+    const i64 M = N + m;
+    if (M > cap) return M;
+    HashSet H{table.as<u64>(), (u64)(det_slots - 1), sa.as<u64>(), (u64)(str_slots - 1),
+              sb.as<u64>(), (u64)(str_slots - 1), packed ? 1 : 0, overflow, strings};
+    DevMem hi = dev_alloc(ctx, sizeof(u64) * M, s), lo = dev_alloc(ctx, sizeof(u64) * M, s);
+    HCI_LAUNCH(ctx, "select_gather", s, gather_kernel, ceil_div(M, 256), 256, 0, dets, N,
+               keys.as<u64>(), m, H, hi.as<u64>(), lo.as<u64>());
     {
         DevMem thi = dev_alloc(ctx, sizeof(u64) * M, s), tlo = dev_alloc(ctx, sizeof(u64) * M, s);
         radix_sort128(ctx, hi.as<u64>(), lo.as<u64>(), nullptr, thi.as<u64>(), tlo.as<u64>(), nullptr,
                       M, n, n, s);
     }
-    return unique128_capped(ctx, hi.as<u64>(), lo.as<u64>(), out, M, cap, s);
+    HCI_LAUNCH(ctx, "select_write", s, interleave_kernel, ceil_div(M, 256), 256, 0, hi.as<u64>(),
+               lo.as<u64>(), M, out);
+    return M;
 }

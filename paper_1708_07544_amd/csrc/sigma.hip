@@ -35,53 +35,118 @@ __global__ void __launch_bounds__(ROW_BLOCK) count_kernel(SpaceView S, u32* __re
     if (lane_id() == 0) counts[i] = v.cnt;
 }
 
-template <class VT>
-struct FillVis {
-    const IntView* I;
-    u64 ai, bi;
+// Connectivity pass of the stored matrix: column indices only (integer work).
+struct ColsVis {
     u32* cols;
-    VT* vals;
     i64 pos;
-    __device__ __forceinline__ void operator()(bool ok, u32 j, u64 aj, u64 bj) {
+    __device__ __forceinline__ void operator()(bool ok, u32 j, u64, u64) {
         const u64 m = ballot(ok);
-        if (ok) {
-            const i64 at = pos + __popcll(m & lanemask_lt());
-            cols[at] = j;
-            vals[at] = (VT)hij_f64(*I, ai, bi, aj, bj);
-        }
+        if (ok) cols[pos + rank_in(m)] = j;
         pos += __popcll(m);
     }
 };
 
-template <class VT>
-__global__ void __launch_bounds__(ROW_BLOCK) fill_kernel(SpaceView S, IntView I,
-                                                         const i64* __restrict__ rowptr,
-                                                         u32* __restrict__ cols,
-                                                         VT* __restrict__ vals) {
+__global__ void __launch_bounds__(ROW_BLOCK) fill_cols_kernel(SpaceView S,
+                                                              const i64* __restrict__ rowptr,
+                                                              u32* __restrict__ cols,
+                                                              unsigned long long* __restrict__ bad) {
     const i64 i = (i64)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
     if (i >= S.N) return;
-    FillVis<VT> v{&I, S.alpha[i], S.beta[i], cols, vals, rowptr[i]};
+    ColsVis v{cols, rowptr[i]};
     enumerate_row(S, (u32)i, v);
+    // the fill must reproduce the count pass exactly
+    if (lane_id() == 0 && (v.pos > rowptr[i + 1] || v.pos + 4 <= rowptr[i + 1])) atomicAdd(bad, 1ull);
+    // pad the row to a multiple of 4 entries with the row's own index (element 0)
+    for (i64 k = v.pos + lane_id(); k < rowptr[i + 1]; k += HCI_WAVE) cols[k] = (u32)i;
 }
 
-// Stored product: one wavefront per row, lane-strided partial sums in
-// float64, butterfly reduction, float64 diagonal term.
+// Element pass: one wavefront per row evaluates H_ij for its stored columns
+// (padding entries, whose column is the row itself, get 0).
+template <class VT>
+__global__ void __launch_bounds__(ROW_BLOCK) fill_vals_kernel(SpaceView S, IntView I,
+                                                              const i64* __restrict__ rowptr,
+                                                              const u32* __restrict__ cols,
+                                                              VT* __restrict__ vals) {
+    const i64 i = (i64)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
+    if (i >= S.N) return;
+    const u64 ai = S.alpha[i], bi = S.beta[i];
+    const i64 k1 = rowptr[i + 1];
+    for (i64 k = rowptr[i] + lane_id(); k < k1; k += HCI_WAVE) {
+        const u32 j = cols[k];
+        double v = 0.0;
+        if (j != (u32)i) v = hij_f64(I, ai, bi, S.alpha[j], S.beta[j]);
+        vals[k] = (VT)v;
+    }
+}
+
+// Rows are padded to multiples of 4 entries, so every lane reads its
+// columns and elements as 16-byte vectors.  Blocks are remapped so that each
+// of the 8 XCDs (which receive workgroups round-robin) streams one contiguous
+// range of rows: neighbouring rows share most of their columns, which keeps
+// the vector gathers in that XCD's L2.
+// nblocks must be a multiple of 8 (the map is then a bijection)
+__device__ __forceinline__ i64 xcd_block(i64 nblocks) {
+    const i64 b = blockIdx.x;
+    const i64 per = (nblocks + 7) / 8;
+    const i64 xcd = b % 8, k = b / 8;
+    return xcd * per + k;
+}
+
+template <class VT>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    __device__ __forceinline__ static void load(const float* p, double (&v)[4]) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+    }
+};
+template <>
+struct Vec4<double> {
+    __device__ __forceinline__ static void load(const double* p, double (&v)[4]) {
+        const double2 a = *reinterpret_cast<const double2*>(p);
+        const double2 b = *reinterpret_cast<const double2*>(p + 2);
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = b.x;
+        v[3] = b.y;
+    }
+};
+
+// Stored product: one wavefront per row, lane partial sums in float64,
+// butterfly reduction, float64 diagonal term.
 template <class VT, class CT>
-__global__ void __launch_bounds__(ROW_BLOCK) spmv_kernel(i64 N, const i64* __restrict__ rowptr,
+__global__ void __launch_bounds__(ROW_BLOCK) spmv_kernel(i64 N, i64 nblocks,
+                                                         const i64* __restrict__ rowptr,
                                                          const u32* __restrict__ cols,
                                                          const VT* __restrict__ vals,
                                                          const CT* __restrict__ cx,
                                                          const double* __restrict__ c,
                                                          const double* __restrict__ hd,
                                                          double* __restrict__ sigma) {
-    const i64 i = (i64)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
+    const i64 i = xcd_block(nblocks) * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
     if (i >= N) return;
     const i64 k0 = rowptr[i], k1 = rowptr[i + 1];
     double acc = 0.0;
-    for (i64 k = k0 + lane_id(); k < k1; k += HCI_WAVE)
-        acc += (double)vals[k] * (double)cx[cols[k]];
+    for (i64 k = k0 + 4 * lane_id(); k < k1; k += 4 * HCI_WAVE) {
+        const uint4 cc = *reinterpret_cast<const uint4*>(cols + k);
+        double v[4];
+        Vec4<VT>::load(vals + k, v);
+        acc += v[0] * (double)cx[cc.x];
+        acc += v[1] * (double)cx[cc.y];
+        acc += v[2] * (double)cx[cc.z];
+        acc += v[3] * (double)cx[cc.w];
+    }
     acc = wave_sum_f64(acc);
     if (lane_id() == 0) sigma[i] = hd[i] * c[i] + acc;
+}
+
+__global__ void pad4_kernel(const u32* __restrict__ counts, i64 n, u32* __restrict__ padded) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) padded[i] = (counts[i] + 3u) & ~3u;
 }
 
 template <bool F32>
@@ -133,9 +198,18 @@ void ensure_rowptr(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
     HCI_LAUNCH(ctx, "conn_count", s, count_kernel, ceil_div(N, ROWS_PER_BLOCK), ROW_BLOCK, 0, S,
                counts.as<u32>());
     HIP_CHECK(hipMemsetAsync(counts.as<u32>() + N, 0, sizeof(u32), s));
+    DevMem total = dev_alloc(ctx, sizeof(u64), s);
+    HIP_CHECK(hipMemsetAsync(total.ptr, 0, sizeof(u64), s));
+    HCI_LAUNCH(ctx, "conn_total", s, u32_to_i64_sum_kernel, ceil_div(N, 256), 256, 0, counts.as<u32>(),
+               N, (unsigned long long*)total.as<u64>());
+    // padded row starts (multiples of 4 entries) for the stored matrix
+    DevMem padded = dev_alloc(ctx, sizeof(u32) * (N + 1), s);
+    HCI_LAUNCH(ctx, "conn_pad", s, pad4_kernel, ceil_div(N + 1, 256), 256, 0, counts.as<u32>(), N + 1,
+               padded.as<u32>());
     sp->rowptr = dev_alloc(ctx, sizeof(i64) * (N + 1), s);
-    scan_u32_to_i64(ctx, counts.as<u32>(), sp->rowptr.as<i64>(), N + 1, s);
-    sp->nnz_off = read_scalar(sp->rowptr.as<i64>() + N, s);
+    scan_u32_to_i64(ctx, padded.as<u32>(), sp->rowptr.as<i64>(), N + 1, s);
+    sp->nnz_off = (i64)read_scalar(total.as<u64>(), s);
+    sp->nnz_pad = read_scalar(sp->rowptr.as<i64>() + N, s);
 }
 
 }  // namespace
@@ -157,29 +231,37 @@ void ensure_csr(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s) {
     const bool f32 = precision == HCI_FP32_MIXED;
     if (f32 ? sp->have_csr32 : sp->have_csr64) return;
     ensure_rowptr(ctx, sp, s);
-    const i64 nnz = sp->nnz_off;
-    if (!sp->cols.ptr) sp->cols = dev_alloc(ctx, sizeof(u32) * (nnz > 0 ? nnz : 1), s);
+    const i64 nnz = sp->nnz_pad;
     SpaceView S = space_view(*sp, ctx->n);
     IntView I = int_view(ctx->ints);
     const i64 grid = ceil_div(sp->N, ROWS_PER_BLOCK);
+    if (!sp->cols.ptr) {
+        sp->cols = dev_alloc(ctx, sizeof(u32) * (nnz > 0 ? nnz : 1), s);
+        DevMem bad = dev_alloc(ctx, sizeof(u64), s);
+        HIP_CHECK(hipMemsetAsync(bad.ptr, 0, sizeof(u64), s));
+        HCI_LAUNCH(ctx, "csr_cols", s, fill_cols_kernel, grid, ROW_BLOCK, 0, S, sp->rowptr.as<i64>(),
+                   sp->cols.as<u32>(), (unsigned long long*)bad.as<u64>());
+        const u64 nbad = read_scalar(bad.as<u64>(), s);
+        HCI_REQUIRE(nbad == 0, HCI_E_HIP,
+                    "internal: " + std::to_string(nbad) + " rows disagree with the count pass");
+    }
     if (f32) {
         sp->vals32 = dev_alloc(ctx, sizeof(float) * (nnz > 0 ? nnz : 1), s);
-        HCI_LAUNCH(ctx, "csr_fill_f32", s, fill_kernel<float>, grid, ROW_BLOCK, 0, S, I,
+        HCI_LAUNCH(ctx, "csr_vals_f32", s, fill_vals_kernel<float>, grid, ROW_BLOCK, 0, S, I,
                    sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals32.as<float>());
-        sp->have_csr32 = true;
     } else {
         sp->vals64 = dev_alloc(ctx, sizeof(double) * (nnz > 0 ? nnz : 1), s);
-        HCI_LAUNCH(ctx, "csr_fill_f64", s, fill_kernel<double>, grid, ROW_BLOCK, 0, S, I,
+        HCI_LAUNCH(ctx, "csr_vals_f64", s, fill_vals_kernel<double>, grid, ROW_BLOCK, 0, S, I,
                    sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals64.as<double>());
-        sp->have_csr64 = true;
     }
+    (f32 ? sp->have_csr32 : sp->have_csr64) = true;
 }
 
 int choose_mode(hci_ctx_s* ctx, Space* sp, int precision, int mode, hipStream_t s) {
     if (mode == HCI_SIGMA_STORED || mode == HCI_SIGMA_RECOMPUTE) return mode;
     ensure_rowptr(ctx, sp, s);
     const i64 per = precision == HCI_FP32_MIXED ? 8 : 12;
-    return sp->nnz_off * per <= ctx->stored_budget ? HCI_SIGMA_STORED : HCI_SIGMA_RECOMPUTE;
+    return sp->nnz_pad * per <= ctx->stored_budget ? HCI_SIGMA_STORED : HCI_SIGMA_RECOMPUTE;
 }
 
 void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int precision, int mode,
@@ -188,6 +270,8 @@ void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int 
     const i64 N = sp->N;
     const bool f32 = precision == HCI_FP32_MIXED;
     const i64 grid = ceil_div(N, ROWS_PER_BLOCK);
+    // the XCD remap of the stored product needs a multiple of 8 blocks
+    const i64 grid8 = ceil_div(grid, 8) * 8;
     DevMem& c32 = sp->c32;
     if (f32) {
         if (!c32.ptr) c32 = dev_alloc(ctx, sizeof(float) * N, s);
@@ -197,13 +281,13 @@ void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int 
     if (mode == HCI_SIGMA_STORED) {
         ensure_csr(ctx, sp, precision, s);
         if (f32) {
-            HCI_LAUNCH(ctx, "sigma_stored_f32", s, (spmv_kernel<float, float>), grid, ROW_BLOCK, 0, N,
-                       sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals32.as<float>(),
+            HCI_LAUNCH(ctx, "sigma_stored_f32", s, (spmv_kernel<float, float>), grid8, ROW_BLOCK, 0, N,
+                       grid8, sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals32.as<float>(),
                        c32.as<float>(), c, sp->hdiag.as<double>(), sigma);
         } else {
-            HCI_LAUNCH(ctx, "sigma_stored_f64", s, (spmv_kernel<double, double>), grid, ROW_BLOCK, 0,
-                       N, sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals64.as<double>(), c, c,
-                       sp->hdiag.as<double>(), sigma);
+            HCI_LAUNCH(ctx, "sigma_stored_f64", s, (spmv_kernel<double, double>), grid8, ROW_BLOCK, 0,
+                       N, grid8, sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals64.as<double>(), c,
+                       c, sp->hdiag.as<double>(), sigma);
         }
     } else {
         SpaceView S = space_view(*sp, ctx->n);

@@ -61,7 +61,7 @@ __device__ __forceinline__ double hij_f64(const IntView& I, u64 ai, u64 bi, u64 
     const int r = ctz64(parts);
     parts &= parts - 1;
     const int s = ctz64(parts);
-    const double sg = sign_between(si, p, r) * sign_between(si ^ bit(p) ^ bit(r), q, s);
+    const double sg = sign_double(si, p, r, q, s);
     return sg * (I.g[gidx(n, r, p, s, q)] - I.g[gidx(n, r, q, s, p)]);
 }
 
@@ -91,7 +91,7 @@ __device__ __forceinline__ float hij_f32(const IntView& I, u64 ai, u64 bi, u64 a
     const int r = ctz64(parts);
     parts &= parts - 1;
     const int s = ctz64(parts);
-    const float sg = (float)(sign_between(si, p, r) * sign_between(si ^ bit(p) ^ bit(r), q, s));
+    const float sg = (float)sign_double(si, p, r, q, s);
     return sg * (I.g32[gidx(n, r, p, s, q)] - I.g32[gidx(n, r, q, s, p)]);
 }
 

@@ -35,7 +35,7 @@ __global__ void validate_kernel(const u64* __restrict__ dets, i64 N, int n, int 
         const u64 a = dets[2 * i], b = dets[2 * i + 1];
         alpha[i] = a;
         beta[i] = b;
-        const u64 mask = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+        const u64 mask = low_mask(n);
         if (__popcll(a) != na || __popcll(b) != nb || (a & ~mask) || (b & ~mask)) err = 1;
         if (i > 0) {
             const u64 pa = dets[2 * i - 2], pb = dets[2 * i - 1];
@@ -106,7 +106,7 @@ __global__ void adjacency_kernel(const u64* __restrict__ uniq, i64 m, int n,
     const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
     const u64 s = uniq[k];
-    const u64 full = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+    const u64 full = low_mask(n);
     u32 c = 0;
     u32* out = FILL ? cnt_or_idx + ptr[k] : nullptr;
     for (u64 occ = s; occ; occ &= occ - 1) {
@@ -186,7 +186,9 @@ Space* get_space(hci_ctx_s* ctx, const u64* dets, i64 N, hipStream_t s) {
     HCI_REQUIRE(hv[1] == 0, HCI_E_ARG,
                 "determinant list not strictly ascending or wrong electron counts");
     Space* sp = ctx->space;
-    if (sp && sp->key_ptr == dets && sp->N == N && sp->hash == hv[0]) return sp;
+    // the cache is keyed by content (length and hash), not by address, so an
+    // equal list in another buffer reuses the built structure
+    if (sp && sp->N == N && sp->hash == hv[0]) return sp;
     drop_space(ctx);
     sp = new Space();
     ctx->space = sp;

@@ -65,7 +65,7 @@ __device__ __forceinline__ void heat_bath_walk(const HBView& T, const IntView& I
             const i64 P = (i64)p * n + q;
             walk_list(T.os_abs + P * T.os_len, T.os_rs + P * T.os_len, T.os_len, ci, eps,
                       [&](bool pass, int r, int s) {
-                          const bool ok = pass && !((A >> r) & 1ull) && !((B >> s) & 1ull);
+                          const bool ok = pass && !test_bit(A, r) && !test_bit(B, s);
                           visit(ok, A ^ bit(p) ^ bit(r), B ^ bit(q) ^ bit(s));
                       });
         }
@@ -75,12 +75,12 @@ __device__ __forceinline__ void heat_bath_walk(const HBView& T, const IntView& I
         const u64 S = spin ? B : A;
         for (u64 mq = S & (S - 1); mq; mq &= mq - 1) {
             const int q = ctz64(mq);
-            for (u64 mp = S & (bit(q) - 1ull); mp; mp &= mp - 1) {
+            for (u64 mp = S & low_mask(q); mp; mp &= mp - 1) {
                 const int p = ctz64(mp);
                 const i64 P = (i64)q * (q - 1) / 2 + p;
                 walk_list(T.ss_abs + P * T.ss_len, T.ss_rs + P * T.ss_len, T.ss_len, ci, eps,
                           [&](bool pass, int r, int s) {
-                              const bool ok = pass && !((S >> r) & 1ull) && !((S >> s) & 1ull);
+                              const bool ok = pass && !test_bit(S, r) && !test_bit(S, s);
                               const u64 S2 = S ^ bit(p) ^ bit(q) ^ bit(r) ^ bit(s);
                               visit(ok, spin ? A : S2, spin ? S2 : B);
                           });
@@ -95,7 +95,7 @@ __device__ __forceinline__ void heat_bath_walk(const HBView& T, const IntView& I
             const int r = lane_id();
             bool ok = false;
             u64 S2 = 0;
-            if (r < n && !((S >> r) & 1ull) && T.single_bound[p * n + r] * ci > eps) {
+            if (r < n && !test_bit(S, r) && T.single_bound[p * n + r] * ci > eps) {
                 const double v = sign_between(S, p, r) * single_elem_f64(I, S, O, p, r);
                 const double prod = fabs(v) * ci;
                 ok = prod > eps;

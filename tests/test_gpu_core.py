@@ -174,6 +174,22 @@ def test_select_capacity_reports_required(cas8, lib_mod):
     assert n_out.value == 361
 
 
+def test_stored_matrix_rebuilds_agree(lib_mod):
+    """The stored Hamiltonian built in several fresh contexts gives the
+    oracle's product every time (guards against build-order dependence)."""
+    w = hs.WORKLOADS["cas8"]
+    h, g = hs.workload_integrals(w)
+    sp = hs.full_space(8, 4, 4)
+    c = hs.random_coeffs(len(sp), 11)
+    ref = O.sigma(h, g, sp, c)
+    for trial in range(4):
+        ctx = lib_mod.HCIContext(h, g, 4, 4)
+        for prec, tol in [("fp64", 1e-12), ("fp32_mixed", 1e-6)]:
+            out = ctx.sigma(sp, c, precision=prec, mode="stored").cpu().numpy()
+            assert rel_err(out, ref) < tol, (trial, prec)
+        ctx.close()
+
+
 @pytest.mark.parametrize("m", [1, 2, 63, 65, 257])
 def test_ragged_sizes(lib_mod, m):
     n, na, nb = 9, 4, 3
