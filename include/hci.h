@@ -101,6 +101,10 @@ int hci_ctx_update_integrals(hci_ctx ctx, const double* h, const double* g, doub
 /* Release everything the context owns.  NULL is accepted. */
 int hci_ctx_destroy(hci_ctx ctx);
 
+/* Release the cached structure of the last determinant list (buckets,
+ * adjacency, stored Hamiltonian).  The next call on any list rebuilds it. */
+int hci_ctx_release_cache(hci_ctx ctx);
+
 /* Memory budget (bytes) for the stored Hamiltonian in HCI_SIGMA_AUTO mode
  * (default: 64 GiB). */
 int hci_ctx_set_stored_budget(hci_ctx ctx, int64_t bytes);

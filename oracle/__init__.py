@@ -82,7 +82,7 @@ def lib():
                                  ctypes.c_double, u64p, ctypes.c_long]
         L.orc_sigma_rows.restype = None
         L.orc_sigma_rows.argtypes = [ctypes.c_int, f64p, f64p, u64p, ctypes.c_long, f64p,
-                                     i64p, ctypes.c_long, f64p]
+                                     i64p, ctypes.c_long, f64p, i64p]
         L.orc_row_counts.restype = None
         L.orc_row_counts.argtypes = [ctypes.c_int, u64p, ctypes.c_long, i64p]
         L.orc_csr_fill.restype = None
@@ -195,21 +195,25 @@ def hamiltonian_csr(h, g, V):
     return sp.csr_matrix((vals, cols, rowptr), shape=(len(V), len(V)))
 
 
-def sigma(h, g, V, c, rows=None) -> np.ndarray:
-    """sigma_i = sum_j H_ij c_j (j over V), for all rows or the listed ones."""
+def sigma(h, g, V, c, rows=None, with_pairs=False):
+    """sigma_i = sum_j H_ij c_j (j over V), for all rows or the listed ones.
+    with_pairs: also return the number of connected j of each row."""
     n = h.shape[0]
     h, hp = _f64(h)
     g, gp = _f64(g)
     V, vp = _u64(V)
     c, cp = _f64(c)
+    m = len(V) if rows is None else len(rows)
+    out = np.zeros(m)
+    pairs = np.zeros(m, dtype=np.int64)
     if rows is None:
-        out = np.zeros(len(V))
-        lib().orc_sigma_rows(n, hp, gp, vp, len(V), cp, None, 0, out.ctypes.data_as(f64p))
+        lib().orc_sigma_rows(n, hp, gp, vp, len(V), cp, None, 0, out.ctypes.data_as(f64p),
+                             pairs.ctypes.data_as(i64p))
     else:
         rows, rp = _i64(rows)
-        out = np.zeros(len(rows))
-        lib().orc_sigma_rows(n, hp, gp, vp, len(V), cp, rp, len(rows), out.ctypes.data_as(f64p))
-    return out
+        lib().orc_sigma_rows(n, hp, gp, vp, len(V), cp, rp, len(rows), out.ctypes.data_as(f64p),
+                             pairs.ctypes.data_as(i64p))
+    return (out, pairs) if with_pairs else out
 
 
 # ---------------------------------------------------------------- spaces

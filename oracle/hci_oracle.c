@@ -220,9 +220,10 @@ long orc_select(int n, const double* h, const double* g, const u64* V, long nv,
 }
 
 /* sigma_i = sum_j H_ij c_j for the listed rows i (all of V when rows == NULL),
- * with j running over i itself and every excitation of D_i found in V. */
+ * with j running over i itself and every excitation of D_i found in V.
+ * pairs (may be NULL) receives the number of j of each row. */
 void orc_sigma_rows(int n, const double* h, const double* g, const u64* V, long nv,
-                    const double* c, const long* rows, long nrows, double* out) {
+                    const double* c, const long* rows, long nrows, double* out, long* pairs) {
     long cnt = rows ? nrows : nv;
 #pragma omp parallel
     {
@@ -240,12 +241,15 @@ void orc_sigma_rows(int n, const double* h, const double* g, const u64* V, long 
             }
             orc_excitations(n, a, b, buf, m);
             double s = orc_diag(n, h, g, a, b) * c[i];
+            long found = 1;
             for (long e = 0; e < m; ++e) {
                 long j = orc_find(V, nv, buf[2 * e], buf[2 * e + 1]);
                 if (j < 0) continue;
                 s += orc_hij(n, h, g, V[2 * j], V[2 * j + 1], a, b) * c[j];
+                found++;
             }
             out[k] = s;
+            if (pairs) pairs[k] = found;
         }
         free(buf);
     }

@@ -77,6 +77,9 @@ class HCIContext:
         check(lib().hci_ctx_update_integrals(self.handle, _lib._ptr(h), _lib._ptr(g), self.ecore,
                                              _lib._stream()))
 
+    def release_cache(self):
+        check(lib().hci_ctx_release_cache(self.handle))
+
     def set_stored_budget(self, nbytes: int):
         check(lib().hci_ctx_set_stored_budget(self.handle, int(nbytes)))
 

@@ -59,6 +59,7 @@ _SIGNATURES = {
     "hci_ctx_create": [_i32, _i32, _i32, _vp, _vp, _f64, _vp, _vp, _vp],
     "hci_ctx_update_integrals": [_vp, _vp, _vp, _f64, _vp],
     "hci_ctx_destroy": [_vp],
+    "hci_ctx_release_cache": [_vp],
     "hci_ctx_set_stored_budget": [_vp, _i64],
     "hci_ctx_set_timing": [_vp, _i32],
     "hci_ctx_kernel_time": [_vp, ctypes.c_char_p, _vp, _vp, _i32],

@@ -213,6 +213,15 @@ int hci_ctx_destroy(hci_ctx ctx) {
     });
 }
 
+int hci_ctx_release_cache(hci_ctx ctx) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr, HCI_E_ARG, "null context");
+        (void)hipDeviceSynchronize();
+        drop_space(ctx);
+        return HCI_OK;
+    });
+}
+
 int hci_ctx_set_stored_budget(hci_ctx ctx, int64_t bytes) {
     return guarded([&]() -> int {
         HCI_REQUIRE(ctx != nullptr && bytes >= 0, HCI_E_ARG, "bad context or budget");

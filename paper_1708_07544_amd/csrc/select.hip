@@ -248,7 +248,8 @@ i64 select_run(hci_ctx_s* ctx, const u64* dets, const double* c, i64 N, double e
     unsigned long long* counter = (unsigned long long*)flags.as<u64>();
     unsigned long long* overflow = counter + 1;
     unsigned long long* strings = counter + 2;
-    i64 det_slots = pow2_at_least(std::max<i64>(8 * N, 1 << 20));
+    // V' is often 10-200x larger than V: start generous (a retry repeats the walk)
+    i64 det_slots = pow2_at_least(std::max<i64>(64 * N, 1 << 22));
     i64 str_slots = pow2_at_least(std::max<i64>(2 * N, 1 << 16));
     DevMem table, sa, sb, keys;
     i64 m = 0;
@@ -286,7 +287,7 @@ i64 select_run(hci_ctx_s* ctx, const u64* dets, const double* c, i64 N, double e
         const i64 nstr = (i64)std::max(hv[2], hv[3]);
         const bool str_ok = packed || nstr <= str_slots / 2;
         if (hv[1] == 0 && N + m <= det_slots / 2 && m <= kcap && str_ok) break;
-        det_slots = pow2_at_least(std::max<i64>(4 * (N + m), 2 * det_slots));
+        det_slots = pow2_at_least(std::max<i64>(4 * (N + m), 8 * det_slots));
         if (!str_ok || hv[1]) str_slots = pow2_at_least(std::max<i64>(4 * nstr, 2 * str_slots));
     }
     const i64 M = N + m;
