@@ -55,6 +55,22 @@ __global__ void sym8_kernel(const double* __restrict__ G, int n, double a, doubl
     out[t] = a * (v * 0.125);
 }
 
+// out[p][q] = a (x[p][q] + x[q][p]) / 2
+__global__ void sym2_kernel(const double* __restrict__ x, int n, double a, double* __restrict__ out) {
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (i64)n * n) return;
+    const int p = (int)(t / n), q = (int)(t % n);
+    out[t] = a * (0.5 * (x[t] + x[(i64)q * n + p]));
+}
+
+// out = a0 A + a1 B + a2 C + a3 D (out may alias A)
+__global__ void combine4_kernel(double a0, const double* A, double a1, const double* __restrict__ B,
+                                double a2, const double* __restrict__ C, double a3,
+                                const double* __restrict__ D, double* out, i64 m) {
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < m) out[t] = a0 * A[t] + a1 * B[t] + a2 * C[t] + a3 * D[t];
+}
+
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace
@@ -354,45 +370,91 @@ int hci_energy_backward(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const 
                         double* dh, double* dg, double* z_out, double* e2_out, void* stream) {
     return guarded([&]() -> int {
         HCI_REQUIRE(ctx != nullptr && dets && c && dh && dg, HCI_E_ARG, "null argument");
+        HCI_REQUIRE(precision == HCI_FP64 || precision == HCI_FP32_MIXED, HCI_E_ARG, "bad precision");
         hipStream_t s = as_stream(stream);
         Space* sp = get_space(ctx, dets, n_var, s);
         const int n = ctx->n;
         const i64 n2 = (i64)n * n, n4 = n2 * n2;
+        DevMem g1 = dev_alloc(ctx, sizeof(double) * n2, s);
+        DevMem g2 = dev_alloc(ctx, sizeof(double) * n4, s);
+        rdm_compute(ctx, sp, c, c, g1.as<double>(), g2.as<double>(), s);
         if (r == nullptr && !(eps2 > 0.0)) {
-            DevMem g1 = dev_alloc(ctx, sizeof(double) * n2, s);
-            DevMem g2 = dev_alloc(ctx, sizeof(double) * n4, s);
-            rdm_compute(ctx, sp, c, c, g1.as<double>(), g2.as<double>(), s);
-            HCI_LAUNCH(ctx, "bw_scale", s, scale_kernel, ceil_div(n2, 256), 256, 0, g1.as<double>(),
-                       grad_e, dh, n2);
+            // variational energy: unrelaxed density matrices (eq. vdedk2)
+            HCI_LAUNCH(ctx, "bw_sym2", s, sym2_kernel, ceil_div(n2, 256), 256, 0, g1.as<double>(), n,
+                       grad_e, dh);
             HCI_LAUNCH(ctx, "bw_sym8", s, sym8_kernel, ceil_div(n4, 256), 256, 0, g2.as<double>(), n,
                        0.5 * grad_e, dg);
             if (e2_out) *e2_out = 0.0;
             HIP_CHECK(hipStreamSynchronize(s));
             return HCI_OK;
         }
-        (void)e;
-        (void)z_tol;
-        (void)precision;
-        (void)z_out;
-        g_last_error = "relaxed backward not built yet";
-        return HCI_E_UNSUPPORTED;
+        HCI_REQUIRE(z_tol > 0.0, HCI_E_ARG, "z_tol must be positive");
+        // relaxed gradient (eq. lambda with lambda_c = z/2 - (d.d) c/2):
+        // (1 - d.d) G^cc + G^zc + 2 G^dc + G^dd
+        std::unique_ptr<Pt2State> st;
+        const double* rr = r;
+        double dd = 0.0, e2 = 0.0;
+        if (eps2 > 0.0) {
+            st = pt2_run(ctx, dets, n_var, c, e - ctx->ecore, eps2, s);
+            rr = st->r.as<double>();
+            dd = st->dd;
+            e2 = st->e2;
+        }
+        DevMem zbuf;
+        double* z = z_out;
+        if (!z) {
+            zbuf = dev_alloc(ctx, sizeof(double) * n_var, s);
+            z = zbuf.as<double>();
+        }
+        const int prod = zvector_solve(ctx, sp, c, e, rr, z, z_tol, precision, 100000, s);
+        DevMem t1 = dev_alloc(ctx, sizeof(double) * n2, s), t2 = dev_alloc(ctx, sizeof(double) * n4, s);
+        rdm_compute(ctx, sp, z, c, t1.as<double>(), t2.as<double>(), s);
+        DevMem p1 = dev_alloc(ctx, sizeof(double) * n2, s), p2 = dev_alloc(ctx, sizeof(double) * n4, s);
+        DevMem q1 = dev_alloc(ctx, sizeof(double) * n2, s), q2 = dev_alloc(ctx, sizeof(double) * n4, s);
+        HIP_CHECK(hipMemsetAsync(p1.ptr, 0, sizeof(double) * n2, s));
+        HIP_CHECK(hipMemsetAsync(p2.ptr, 0, sizeof(double) * n4, s));
+        HIP_CHECK(hipMemsetAsync(q1.ptr, 0, sizeof(double) * n2, s));
+        HIP_CHECK(hipMemsetAsync(q2.ptr, 0, sizeof(double) * n4, s));
+        if (st) {
+            rdm_add_pt2_pairs(ctx, *st, dets, c, p1.as<double>(), p2.as<double>(), s);
+            rdm_add_diag(ctx, st->ca.as<u64>(), st->cb.as<u64>(), st->d.as<double>(), st->d.as<double>(),
+                         st->nC, q1.as<double>(), q2.as<double>(), s);
+        }
+        HCI_LAUNCH(ctx, "bw_combine", s, combine4_kernel, ceil_div(n2, 256), 256, 0, 1.0 - dd,
+                   g1.as<double>(), 1.0, t1.as<double>(), 2.0, p1.as<double>(), 1.0, q1.as<double>(),
+                   g1.as<double>(), n2);
+        HCI_LAUNCH(ctx, "bw_combine", s, combine4_kernel, ceil_div(n4, 256), 256, 0, 1.0 - dd,
+                   g2.as<double>(), 1.0, t2.as<double>(), 2.0, p2.as<double>(), 1.0, q2.as<double>(),
+                   g2.as<double>(), n4);
+        HCI_LAUNCH(ctx, "bw_sym2", s, sym2_kernel, ceil_div(n2, 256), 256, 0, g1.as<double>(), n, grad_e,
+                   dh);
+        HCI_LAUNCH(ctx, "bw_sym8", s, sym8_kernel, ceil_div(n4, 256), 256, 0, g2.as<double>(), n,
+                   0.5 * grad_e, dg);
+        if (e2_out) *e2_out = e2;
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (prod < 0) {
+            g_last_error = "z-vector solve did not reach z_tol (outputs hold the last iterate)";
+            return HCI_E_NOCONV;
+        }
+        return HCI_OK;
     });
 }
 
 int hci_pt2(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double e0,
             double eps2, double* e2_out, double* r_out, int64_t* n_conn_out, void* stream) {
-    (void)ctx;
-    (void)dets;
-    (void)n_var;
-    (void)c;
-    (void)e0;
-    (void)eps2;
-    (void)e2_out;
-    (void)r_out;
-    (void)n_conn_out;
-    (void)stream;
-    g_last_error = "pt2 not built yet";
-    return HCI_E_UNSUPPORTED;
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && c && e2_out, HCI_E_ARG, "null argument");
+        HCI_REQUIRE(eps2 >= 0.0, HCI_E_ARG, "eps2 must be >= 0");
+        hipStream_t s = as_stream(stream);
+        get_space(ctx, dets, n_var, s);  // validation
+        auto st = pt2_run(ctx, dets, n_var, c, e0 - ctx->ecore, eps2, s);
+        if (r_out)
+            HIP_CHECK(hipMemcpyAsync(r_out, st->r.ptr, sizeof(double) * n_var, hipMemcpyDeviceToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        *e2_out = st->e2;
+        if (n_conn_out) *n_conn_out = st->nC;
+        return HCI_OK;
+    });
 }
 
 }  // extern "C"

@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -377,5 +378,34 @@ i64 select_run(hci_ctx_s* ctx, const u64* dets, const double* c, i64 N, double e
                i64 cap, hipStream_t s);
 void embed_run(hci_ctx_s* ctx, const u64* dets, i64 n, const double* c, const u64* dn, i64 nn,
                double* out, hipStream_t s);
+
+// eps2-screened PT2 pieces on a frozen (V, c, E0).
+struct Pt2State {
+    i64 N = 0;       // |V|
+    i64 M = 0;       // screened (i, a) pairs, in i order
+    DevMem off;      // i64 [N+1] pair range of each i
+    DevMem a_hi, a_lo;  // u64 [M] alpha / beta of a
+    DevMem idx;      // u32 [M] i
+    DevMem hai;      // f64 [M] H_ai
+    DevMem dpair;    // f64 [M] d_a of the pair's a
+    DevMem r;        // f64 [N] dE2/dc at fixed E0
+    i64 nC = 0;      // |C(eps2)|
+    DevMem ca, cb;   // u64 [nC] the connected determinants (sorted)
+    DevMem d;        // f64 [nC] first-order coefficients
+    double e2 = 0.0, dd = 0.0;
+    ~Pt2State();
+};
+std::unique_ptr<Pt2State> pt2_run(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double e0,
+                                  double eps2, hipStream_t s);
+// Q (H - E) Q z = -Q r on c-perp by preconditioned conjugate gradients;
+// returns the number of Hamiltonian products.
+int zvector_solve(hci_ctx_s* ctx, Space* sp, const double* c, double e, const double* r, double* z,
+                  double tol, int precision, int max_products, hipStream_t s);
+// rdm1/rdm2 += sum_pairs w <D_a| ops |D_i> with w = dpair * c_i (Gamma^{dc})
+void rdm_add_pt2_pairs(hci_ctx_s* ctx, const Pt2State& st, const u64* dets, const double* c,
+                       double* rdm1, double* rdm2, hipStream_t s);
+// rdm1/rdm2 += sum_k wa_k wb_k <D_k| ops |D_k> over the listed determinants
+void rdm_add_diag(hci_ctx_s* ctx, const u64* alpha, const u64* beta, const double* wa,
+                  const double* wb, i64 M, double* rdm1, double* rdm2, hipStream_t s);
 void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket, double* rdm1,
                  double* rdm2, hipStream_t s);

@@ -202,7 +202,40 @@ __global__ void diag_terms_kernel(const double* __restrict__ D, int n, double* _
     }
 }
 
+// Gamma^{dc}: one thread per screened pair (i, a), weight d_a c_i, bra D_a,
+// ket D_i (Sec. "Computational Details": the connection list of the PT2).
+__global__ void pt2_pairs_kernel(const u64* __restrict__ a_hi, const u64* __restrict__ a_lo,
+                                 const u32* __restrict__ idx, const double* __restrict__ dpair,
+                                 const u64* __restrict__ dets, const double* __restrict__ c, i64 M,
+                                 int n, double* __restrict__ r1, double* __restrict__ r2) {
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M) return;
+    const u32 i = idx[t];
+    const double w = dpair[t] * c[i];
+    if (w == 0.0) return;
+    pair_contrib(n, w, a_hi[t], a_lo[t], dets[2 * (i64)i], dets[2 * (i64)i + 1], r1, r2);
+}
+
 }  // namespace
+
+// Diagonal-pair terms of sum_k wa_k wb_k <D_k| ops |D_k> added to rdm1/rdm2.
+void rdm_add_diag(hci_ctx_s* ctx, const u64* alpha, const u64* beta, const double* wa,
+                  const double* wb, i64 M, double* rdm1, double* rdm2, hipStream_t s) {
+    if (M <= 0) return;
+    const int n = ctx->n;
+    const i64 n2 = (i64)n * n;
+    const int entries = 4 * n * n;
+    const i64 chunk = std::max<i64>(OCC_CHUNK, ceil_div(M, 512));
+    const int nblk = (int)ceil_div(M, chunk);
+    DevMem part = dev_alloc(ctx, sizeof(double) * (i64)nblk * entries, s);
+    DevMem D = dev_alloc(ctx, sizeof(double) * entries, s);
+    HCI_LAUNCH(ctx, "rdm_occ", s, occ_corr_kernel, dim3(nblk, (unsigned)ceil_div(entries, OCC_TILE)),
+               256, 0, alpha, beta, wa, wb, M, n, chunk, part.as<double>());
+    HCI_LAUNCH(ctx, "rdm_occ_reduce", s, occ_reduce_kernel, ceil_div(entries, 256), 256, 0,
+               part.as<double>(), nblk, entries, D.as<double>());
+    HCI_LAUNCH(ctx, "rdm_diag_terms", s, diag_terms_kernel, ceil_div(n2, 256), 256, 0,
+               D.as<double>(), n, rdm1, rdm2);
+}
 
 void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket, double* rdm1,
                  double* rdm2, hipStream_t s) {
@@ -214,16 +247,13 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
     SpaceView S = space_view(*sp, n);
     HCI_LAUNCH(ctx, "rdm_offdiag", s, rdm_offdiag_kernel, ceil_div(N, ROWS_PER_BLOCK), ROW_BLOCK, 0,
                S, bra, ket, rdm1, rdm2);
-    const int entries = 4 * n * n;
-    const i64 chunk = std::max<i64>(OCC_CHUNK, ceil_div(N, 512));
-    const int nblk = (int)ceil_div(N, chunk);
-    DevMem part = dev_alloc(ctx, sizeof(double) * (i64)nblk * entries, s);
-    DevMem D = dev_alloc(ctx, sizeof(double) * entries, s);
-    HCI_LAUNCH(ctx, "rdm_occ", s, occ_corr_kernel, dim3(nblk, (unsigned)ceil_div(entries, OCC_TILE)),
-               256, 0, sp->alpha.as<u64>(),
-               sp->beta.as<u64>(), bra, ket, N, n, chunk, part.as<double>());
-    HCI_LAUNCH(ctx, "rdm_occ_reduce", s, occ_reduce_kernel, ceil_div(entries, 256), 256, 0,
-               part.as<double>(), nblk, entries, D.as<double>());
-    HCI_LAUNCH(ctx, "rdm_diag_terms", s, diag_terms_kernel, ceil_div(n2, 256), 256, 0,
-               D.as<double>(), n, rdm1, rdm2);
+    rdm_add_diag(ctx, sp->alpha.as<u64>(), sp->beta.as<u64>(), bra, ket, N, rdm1, rdm2, s);
+}
+
+void rdm_add_pt2_pairs(hci_ctx_s* ctx, const Pt2State& st, const u64* dets, const double* c,
+                       double* rdm1, double* rdm2, hipStream_t s) {
+    if (st.M <= 0) return;
+    HCI_LAUNCH(ctx, "rdm_pt2_pairs", s, pt2_pairs_kernel, ceil_div(st.M, 256), 256, 0,
+               st.a_hi.as<u64>(), st.a_lo.as<u64>(), st.idx.as<u32>(), st.dpair.as<double>(), dets, c,
+               st.M, ctx->n, rdm1, rdm2);
 }

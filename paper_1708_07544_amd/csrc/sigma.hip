@@ -79,67 +79,29 @@ __global__ void __launch_bounds__(ROW_BLOCK) fill_vals_kernel(SpaceView S, IntVi
     }
 }
 
-// Rows are padded to multiples of 4 entries, so every lane reads its
-// columns and elements as 16-byte vectors.  Blocks are remapped so that each
-// of the 8 XCDs (which receive workgroups round-robin) streams one contiguous
-// range of rows: neighbouring rows share most of their columns, which keeps
-// the vector gathers in that XCD's L2.
-// nblocks must be a multiple of 8 (the map is then a bijection)
-__device__ __forceinline__ i64 xcd_block(i64 nblocks) {
-    const i64 b = blockIdx.x;
-    const i64 per = (nblocks + 7) / 8;
-    const i64 xcd = b % 8, k = b / 8;
-    return xcd * per + k;
-}
-
-template <class VT>
-struct Vec4;
-template <>
-struct Vec4<float> {
-    __device__ __forceinline__ static void load(const float* p, double (&v)[4]) {
-        const float4 q = *reinterpret_cast<const float4*>(p);
-        v[0] = q.x;
-        v[1] = q.y;
-        v[2] = q.z;
-        v[3] = q.w;
-    }
-};
-template <>
-struct Vec4<double> {
-    __device__ __forceinline__ static void load(const double* p, double (&v)[4]) {
-        const double2 a = *reinterpret_cast<const double2*>(p);
-        const double2 b = *reinterpret_cast<const double2*>(p + 2);
-        v[0] = a.x;
-        v[1] = a.y;
-        v[2] = b.x;
-        v[3] = b.y;
-    }
-};
-
 // Stored product: one wavefront per row, lane partial sums in float64,
-// butterfly reduction, float64 diagonal term.
+// butterfly reduction, float64 diagonal term.  The gathers of c_j dominate
+// (the column/element stream alone runs at ~77% of HBM peak): blocks of 8
+// consecutive rows, which mostly share their alpha-neighbour buckets, keep
+// those gathers in the CU's L1 (measured: 512-thread blocks beat 256 and
+// 1024, and 16-byte vector loads lose to 4-byte lane-contiguous loads
+// because they spread each gather instruction over 4x more cache lines).
+constexpr int SPMV_BLOCK = 512;
+constexpr int SPMV_ROWS = SPMV_BLOCK / HCI_WAVE;
+
 template <class VT, class CT>
-__global__ void __launch_bounds__(ROW_BLOCK) spmv_kernel(i64 N, i64 nblocks,
-                                                         const i64* __restrict__ rowptr,
-                                                         const u32* __restrict__ cols,
-                                                         const VT* __restrict__ vals,
-                                                         const CT* __restrict__ cx,
-                                                         const double* __restrict__ c,
-                                                         const double* __restrict__ hd,
-                                                         double* __restrict__ sigma) {
-    const i64 i = xcd_block(nblocks) * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
+__global__ void __launch_bounds__(SPMV_BLOCK) spmv_kernel(i64 N, const i64* __restrict__ rowptr,
+                                                          const u32* __restrict__ cols,
+                                                          const VT* __restrict__ vals,
+                                                          const CT* __restrict__ cx,
+                                                          const double* __restrict__ c,
+                                                          const double* __restrict__ hd,
+                                                          double* __restrict__ sigma) {
+    const i64 i = (i64)blockIdx.x * SPMV_ROWS + threadIdx.x / HCI_WAVE;
     if (i >= N) return;
     const i64 k0 = rowptr[i], k1 = rowptr[i + 1];
     double acc = 0.0;
-    for (i64 k = k0 + 4 * lane_id(); k < k1; k += 4 * HCI_WAVE) {
-        const uint4 cc = *reinterpret_cast<const uint4*>(cols + k);
-        double v[4];
-        Vec4<VT>::load(vals + k, v);
-        acc += v[0] * (double)cx[cc.x];
-        acc += v[1] * (double)cx[cc.y];
-        acc += v[2] * (double)cx[cc.z];
-        acc += v[3] * (double)cx[cc.w];
-    }
+    for (i64 k = k0 + lane_id(); k < k1; k += HCI_WAVE) acc += (double)vals[k] * (double)cx[cols[k]];
     acc = wave_sum_f64(acc);
     if (lane_id() == 0) sigma[i] = hd[i] * c[i] + acc;
 }
@@ -270,8 +232,7 @@ void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int 
     const i64 N = sp->N;
     const bool f32 = precision == HCI_FP32_MIXED;
     const i64 grid = ceil_div(N, ROWS_PER_BLOCK);
-    // the XCD remap of the stored product needs a multiple of 8 blocks
-    const i64 grid8 = ceil_div(grid, 8) * 8;
+    const i64 gridp = ceil_div(N, SPMV_ROWS);
     DevMem& c32 = sp->c32;
     if (f32) {
         if (!c32.ptr) c32 = dev_alloc(ctx, sizeof(float) * N, s);
@@ -281,12 +242,12 @@ void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int 
     if (mode == HCI_SIGMA_STORED) {
         ensure_csr(ctx, sp, precision, s);
         if (f32) {
-            HCI_LAUNCH(ctx, "sigma_stored_f32", s, (spmv_kernel<float, float>), grid8, ROW_BLOCK, 0, N,
-                       grid8, sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals32.as<float>(),
+            HCI_LAUNCH(ctx, "sigma_stored_f32", s, (spmv_kernel<float, float>), gridp, SPMV_BLOCK, 0,
+                       N, sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals32.as<float>(),
                        c32.as<float>(), c, sp->hdiag.as<double>(), sigma);
         } else {
-            HCI_LAUNCH(ctx, "sigma_stored_f64", s, (spmv_kernel<double, double>), grid8, ROW_BLOCK, 0,
-                       N, grid8, sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals64.as<double>(), c,
+            HCI_LAUNCH(ctx, "sigma_stored_f64", s, (spmv_kernel<double, double>), gridp, SPMV_BLOCK,
+                       0, N, sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals64.as<double>(), c,
                        c, sp->hdiag.as<double>(), sigma);
         }
     } else {
