@@ -1,0 +1,107 @@
+"""Parity at the benchmark's full size and at 44 orbitals.
+
+(16e,16o): the oracle runs the first two HCI macro-iterations itself
+(aufbau -> V1, its own eigenvector c1 by Lanczos), then selects V2 =
+V1 + C(1e-4) by the definition of the criterion.  The GPU selection from
+the same (V1, c1) must give the identical 1,138,281-determinant list.  On
+V2 the GPU products (stored float64 and float32-mixed, the benchmark's
+launch configuration) are compared with the oracle's on sampled rows, and
+the density matrices are checked against identities that hold at any size.
+
+(44e,44o) porphyrin-shaped integrals: two-level hash keys and 64-bit words
+with bits above 32 in use; selection bit-exact and sampled-row products."""
+import numpy as np
+import pytest
+
+import hci_synth as hs
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P(gpu_available):
+    import paper_1708_07544_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def cas16_v2():
+    w = hs.WORKLOADS["cas16"]
+    h, g = hs.workload_integrals(w)
+    V0 = hs.aufbau_det(8, 8)
+    V1 = O.merge(V0, O.select(h, g, V0, np.array([1.0]), w.eps1))
+    e1, c1 = O.lowest_eigenpair(h, g, V1, tol=1e-12)
+    print(f"[cas16] oracle |V1|={len(V1)} E1={e1:.10f}", flush=True)
+    V2 = O.merge(V1, O.select(h, g, V1, c1, w.eps1))
+    print(f"[cas16] oracle |V2|={len(V2)}", flush=True)
+    return h, g, V1, c1, e1, V2
+
+
+def test_selection_full_size_bit_exact(P, cas16_v2):
+    h, g, V1, c1, e1, V2 = cas16_v2
+    ctx = P.HCIContext(h, g, 8, 8)
+    out = P.dets_to_numpy(ctx.select(V1, c1, 1e-4))
+    assert out.shape == V2.shape
+    assert np.array_equal(out, V2)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_mixed", 1e-6)])
+def test_sigma_full_size_sampled_rows(P, cas16_v2, precision, tol):
+    h, g, V1, c1, e1, V2 = cas16_v2
+    ctx = P.HCIContext(h, g, 8, 8)
+    c = hs.random_coeffs(len(V2), 23)
+    out = ctx.sigma(V2, c, precision=precision, mode="stored").cpu().numpy()
+    rows = np.random.default_rng(5).choice(len(V2), 1500, replace=False)
+    rows = np.concatenate([rows, [0, len(V2) - 1]])
+    ref, pairs = O.sigma(h, g, V2, c, rows=rows, with_pairs=True)
+    scale = np.abs(ref).max()
+    assert np.abs(out[rows] - ref).max() <= tol * scale
+
+
+def test_full_size_variational_and_rdm_identities(P, cas16_v2):
+    """E(V2) <= E(V1) (variational, V1 inside V2); tr gamma = N;
+    sum Gamma_pprr = N(N-1); E = sum h gamma + 1/2 sum g Gamma."""
+    h, g, V1, c1, e1, V2 = cas16_v2
+    ctx = P.HCIContext(h, g, 8, 8)
+    c0 = ctx.embed(V1, c1, V2)
+    e, c, it = ctx.davidson(V2, c0, tol=1e-7, precision="fp32_mixed")
+    assert e <= e1 + 1e-9
+    r1, r2 = ctx.rdm12(V2, c)
+    r1 = r1.cpu().numpy()
+    r2 = r2.cpu().numpy()
+    assert abs(np.trace(r1) - 16) < 1e-9
+    assert abs(np.einsum("pprr->", r2) - 16 * 15) < 1e-8
+    assert np.abs(np.einsum("pqrr->pq", r2) - 15 * r1).max() < 1e-8
+    e_rdm = float(np.sum(h * r1) + 0.5 * np.sum(g * r2))
+    assert abs(e_rdm - e) < 1e-7
+
+
+@pytest.fixture(scope="module")
+def cas44():
+    w = hs.WORKLOADS["cas44"]
+    h, g = hs.workload_integrals(w)
+    V = hs.random_dets(44, 22, 22, 40, seed=44, bias=0.08)
+    c = hs.random_coeffs(len(V), 45)
+    return h, g, V, c
+
+
+def test_cas44_selection_bit_exact(P, cas44):
+    h, g, V, c = cas44
+    ref = O.merge(V, O.select(h, g, V, c, 2e-3))
+    print(f"[cas44] |V|={len(V)} |V+C|={len(ref)}", flush=True)
+    ctx = P.HCIContext(h, g, 22, 22)
+    out = P.dets_to_numpy(ctx.select(V, c, 2e-3))
+    assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("mode", ["stored", "recompute"])
+def test_cas44_sigma_sampled_rows(P, cas44, mode):
+    h, g, V, c = cas44
+    Vb = O.merge(V, O.select(h, g, V, c, 2e-3))
+    cb = hs.random_coeffs(len(Vb), 46)
+    ctx = P.HCIContext(h, g, 22, 22)
+    out = ctx.sigma(Vb, cb, precision="fp64", mode=mode).cpu().numpy()
+    rows = np.random.default_rng(1).choice(len(Vb), min(300, len(Vb)), replace=False)
+    ref = O.sigma(h, g, Vb, cb, rows=rows)
+    assert np.abs(out[rows] - ref).max() <= 1e-12 * np.abs(ref).max()
