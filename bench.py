@@ -110,7 +110,8 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
     kernels = {}
-    for name in ["sigma_stored_f32", "sigma_recompute_f64", "select_walk", "csr_cols", "csr_vals_f32",
+    for name in ["sigma_stored_f32", "sigma_stored_f32_g", "sigma_stored_f64", "sigma_stored_f64_g",
+                 "sigma_recompute_f64", "select_walk", "csr_cols", "csr_vals_f32", "csr_vals_f64",
                  "conn_count", "rdm_offdiag", "dv_jacobi", "dv_dots", "dv_combine"]:
         n_, ms = ctx.kernel_time(name)
         if n_:
@@ -119,6 +120,7 @@ def main():
     nv = int(V2.shape[0])
     pairs = ctx.connections(V2)                      # diagonal included
     nnz_off = pairs - nv
+    layout = ctx.layout_info(V2)
     value = total_products * pairs / (t1 - t0)
     # ---------------------------------------------------------------- fp64 path
     fp64 = None
@@ -135,6 +137,9 @@ def main():
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         n64, ms64 = ctx.kernel_time("sigma_stored_f64")
+        ng64, msg64 = ctx.kernel_time("sigma_stored_f64_g")
+        if n64:
+            ms64 = ms64 + (msg64 / ng64 * n64 if ng64 else 0.0)   # per product: both kernels
         ctx.set_timing(False)
         fp64 = {
             "ms_per_step": (t3 - t2) * 1e3 / args.fp64_steps,
@@ -146,12 +151,21 @@ def main():
         }
     # ---------------------------------------------------------------- roofline
     sk = kernels.get("sigma_stored_f32")
+    gk = kernels.get("sigma_stored_f32_g")
     roofline = None
+    product_ms = None
     if sk:
-        # algorithmic bytes per product: float32 element + u32 column per
-        # stored off-diagonal pair, plus per row the row pointer, c_i, H_ii
-        # and sigma_i (8 B each); the gathers of c_j are cache traffic
-        alg_bytes = 8 * nnz_off + 32 * nv
+        product_ms = sk["avg_ms"] + (gk["avg_ms"] if gk else 0.0)
+        if layout["layout"] == 2:
+            # alpha-bucket-staged layout, dominant kernel (all but the
+            # beta-group segments): float32 value + u16 column per stored
+            # entry, 4 B per entry of c copied to LDS, 48 B per row (row
+            # pointer, segment base and starts, c_i, H_ii, sigma_i)
+            s_entries = layout["stored_entries"] - layout["group_entries"]
+            alg_bytes = 6 * s_entries + 4 * layout["staged_c_entries"] + 48 * nv
+        else:
+            # plain CSR: float32 value + u32 column per stored entry, 32 B per row
+            alg_bytes = 8 * layout["stored_entries"] + 32 * nv
         achieved = alg_bytes / (sk["avg_ms"] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -182,7 +196,11 @@ def main():
                    "n_det": nv, "det_pairs": pairs, "norb": w.norb, "nelec": w.nalpha + w.nbeta},
         "davidson_iter_per_s": total_products / (t1 - t0),
         "products_per_step": total_products / args.steps,
-        "sigma_kernel_pairs_per_s": pairs / (sk["avg_ms"] * 1e-3) if sk else None,
+        "sigma_product_ms": product_ms,
+        "sigma_kernel_pairs_per_s": pairs / (product_ms * 1e-3) if product_ms else None,
+        "sigma_speedup_vs_fp64": (fp64["sigma_kernel_avg_ms"] / product_ms)
+        if (fp64 and product_ms) else None,
+        "layout": layout,
         "energy": e_mixed,
         "fp64": fp64,
         "energy_error_vs_fp64": abs(e_mixed - fp64["energy"]) if fp64 else None,

@@ -109,6 +109,16 @@ int hci_ctx_release_cache(hci_ctx ctx);
  * (default: 64 GiB). */
 int hci_ctx_set_stored_budget(hci_ctx ctx, int64_t bytes);
 
+/* Layout of the stored Hamiltonian (Sec. "Variational Stage": the matrix of
+ * the Davidson products).  log2_window > 0 selects the alpha-bucket-staged
+ * layout: for each alpha string, its bucket and the buckets one alpha single
+ * away are read into on-chip memory 2^log2_window entries of c at a time and
+ * columns are stored as 16-bit offsets (6 bytes per float32 entry).  0
+ * selects the plain CSR layout (32-bit columns).  Valid values: 0 or 6..16
+ * (default 14); spaces outside the staged layout's limits use plain CSR.
+ * Changing the layout releases the cached structure.  HCI_E_ARG otherwise. */
+int hci_ctx_set_stage_window(hci_ctx ctx, int log2_window);
+
 /* Per-kernel timing with HIP events on the launch stream (off by default).
  * When enabled, every library kernel launch is bracketed by events and its
  * duration accumulated under the kernel's name. */
@@ -163,6 +173,21 @@ int hci_sigma(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c,
 /* Number of ordered pairs (i,j) in V x V with excitation degree <= 2,
  * diagonal included (host int64 out).  Synchronises the stream. */
 int hci_connections(hci_ctx ctx, const uint64_t* dets, int64_t n_var, int64_t* nnz_out,
+                    void* stream);
+
+/* Statistics of the stored Hamiltonian of V (Sec. "Variational Stage": the
+ * matrix of the Davidson products), for memory planning and traffic
+ * accounting; runs the count pass if needed and synchronises the stream.
+ * info (host int64 [8]):
+ *   [0] layout: 1 plain CSR, 2 alpha-bucket-staged
+ *   [1] off-diagonal connections
+ *   [2] stored entries (staged: segments padded to multiples of 8)
+ *   [3] log2 of the stage window (0 for plain CSR)
+ *   [4] stored entries of the beta-group segments (alpha doubles, same beta)
+ *   [5] entries of c copied into on-chip memory per staged product
+ *   [6] workgroups of the staged product, [7] of the beta-group product
+ * HCI_E_ARG on null arguments or an invalid list. */
+int hci_layout_info(hci_ctx ctx, const uint64_t* dets, int64_t n_var, int64_t* info,
                     void* stream);
 
 /* Diagonal H_ii (float64, device [n_var]), ecore included. */

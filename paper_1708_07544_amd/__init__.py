@@ -83,6 +83,11 @@ class HCIContext:
     def set_stored_budget(self, nbytes: int):
         check(lib().hci_ctx_set_stored_budget(self.handle, int(nbytes)))
 
+    def set_stage_window(self, log2_window: int):
+        """Stored-matrix layout: 0 = plain CSR, 6..16 = alpha-bucket-staged
+        with 2**log2_window entries of c per on-chip window."""
+        check(lib().hci_ctx_set_stage_window(self.handle, int(log2_window)))
+
     def set_timing(self, on: bool):
         check(lib().hci_ctx_set_timing(self.handle, 1 if on else 0))
 
@@ -141,6 +146,17 @@ class HCIContext:
         check(lib().hci_connections(self.handle, _lib._ptr(d), d.shape[0], ctypes.byref(nnz),
                                     _lib._stream()))
         return int(nnz.value)
+
+    def layout_info(self, dets) -> dict:
+        """Statistics of the stored Hamiltonian of `dets` (layout, entries,
+        window, beta-group entries, staged c entries, workgroups)."""
+        d = self._dets(dets)
+        info = (ctypes.c_int64 * 8)()
+        check(lib().hci_layout_info(self.handle, _lib._ptr(d), d.shape[0],
+                                    ctypes.cast(info, ctypes.c_void_p), _lib._stream()))
+        keys = ["layout", "nnz_off", "stored_entries", "log2_window", "group_entries",
+                "staged_c_entries", "workgroups", "group_workgroups"]
+        return dict(zip(keys, (int(x) for x in info)))
 
     def diagonal(self, dets) -> torch.Tensor:
         d = self._dets(dets)

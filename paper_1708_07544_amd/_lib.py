@@ -61,6 +61,8 @@ _SIGNATURES = {
     "hci_ctx_destroy": [_vp],
     "hci_ctx_release_cache": [_vp],
     "hci_ctx_set_stored_budget": [_vp, _i64],
+    "hci_ctx_set_stage_window": [_vp, ctypes.c_int],
+    "hci_layout_info": [_vp, _vp, _i64, _vp, _vp],
     "hci_ctx_set_timing": [_vp, _i32],
     "hci_ctx_kernel_time": [_vp, ctypes.c_char_p, _vp, _vp, _i32],
     "hci_select": [_vp, _vp, _vp, _i64, _f64, _vp, _i64, _vp, _vp],

@@ -246,6 +246,20 @@ int hci_ctx_set_stored_budget(hci_ctx ctx, int64_t bytes) {
     });
 }
 
+int hci_ctx_set_stage_window(hci_ctx ctx, int log2_window) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr, HCI_E_ARG, "null context");
+        HCI_REQUIRE(log2_window == 0 || (log2_window >= 6 && log2_window <= 16), HCI_E_ARG,
+                    "stage window must be 0 or 2^6 .. 2^16");
+        if (ctx->stage_wlog != log2_window) {
+            (void)hipDeviceSynchronize();
+            drop_space(ctx);
+            ctx->stage_wlog = log2_window;
+        }
+        return HCI_OK;
+    });
+}
+
 int hci_ctx_set_timing(hci_ctx ctx, int enable) {
     return guarded([&]() -> int {
         HCI_REQUIRE(ctx != nullptr, HCI_E_ARG, "null context");
@@ -320,6 +334,18 @@ int hci_connections(hci_ctx ctx, const uint64_t* dets, int64_t n_var, int64_t* n
         hipStream_t s = as_stream(stream);
         Space* sp = get_space(ctx, dets, n_var, s);
         *nnz_out = count_connections(ctx, sp, s);
+        return HCI_OK;
+    });
+}
+
+int hci_layout_info(hci_ctx ctx, const uint64_t* dets, int64_t n_var, int64_t* info,
+                    void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && info, HCI_E_ARG, "null argument");
+        hipStream_t s = as_stream(stream);
+        Space* sp = get_space(ctx, dets, n_var, s);
+        (void)count_connections(ctx, sp, s);
+        layout_info(ctx, sp, info, s);
         return HCI_OK;
     });
 }

@@ -212,6 +212,27 @@ struct Space {
     i64 nnz_off = -1;     // off-diagonal connections
     i64 nnz_pad = 0;      // stored entries (rows padded to multiples of 4)
     bool have_csr64 = false, have_csr32 = false;
+    // stored Hamiltonian, alpha-bucket-staged layout (staged.hip)
+    int layout = 0;       // 0 undecided, 1 plain CSR, 2 staged
+    u32 st_wlog = 0;      // window of 2^st_wlog entries of c staged in LDS
+    i64 st_nchunk = 0;    // workgroups of one product
+    DevMem st_xpos;       // u32 [nua + n_as]: start of each stage range
+    DevMem st_len;        // u32 [nua]: stage length of each bucket
+    DevMem st_nseg;       // u32 [nua]: windows + 1 (beta-group segment)
+    DevMem st_cptr;       // u32 [nua + 1]: first workgroup of each bucket
+    DevMem st_gcptr;      // u32 [nub + 1]: first workgroup of each beta group
+    i64 st_gnchunk = 0;   // workgroups of the beta-group product
+    DevMem st_rsb;        // i64 [N + 1]: first segment slot of each row
+    DevMem st_segoff;     // u32 [st_rsb[N]]: segment starts within the row (multiples of 4)
+    DevMem st_segcnt;     // u32 [st_rsb[N]]: entries of each segment before padding
+    DevMem st_rowptr;     // i64 [N + 1]
+    DevMem st_cols;       // u16 [st_nnz]
+    i64 st_nnz = 0;       // stored entries (segments padded to multiples of 4)
+    DevMem st_vals32, st_vals64;
+    DevMem cpb32, cpb64;  // c in beta-major order
+    DevMem rdm_cptr;      // u32 [nua + 1]: first workgroup of each bucket (density matrices)
+    i64 rdm_nchunk = 0;
+    bool st_have32 = false, st_have64 = false;
 };
 
 // Plain-pointer view of a Space for kernels.
@@ -266,6 +287,7 @@ struct hci_ctx_s {
     Integrals ints;
     Space* space = nullptr;
     i64 stored_budget = (i64)64 << 30;
+    int stage_wlog = 14;  // log2 of the staged layout's window; 0 = plain CSR
     bool timing = false;
     std::map<std::string, KernelTimer> timers;
     std::vector<PendingEvent> pending;
@@ -371,6 +393,14 @@ i64 count_connections(hci_ctx_s* ctx, Space* sp, hipStream_t s);
 void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int precision, int mode,
                  hipStream_t s);
 int choose_mode(hci_ctx_s* ctx, Space* sp, int precision, int mode, hipStream_t s);
+// staged layout (staged.hip): prepare returns false when the space does not
+// fit the layout's limits (then the plain CSR is used)
+bool staged_prepare(hci_ctx_s* ctx, Space* sp, hipStream_t s);
+void staged_ensure_vals(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s);
+// info[8] as documented for hci_layout_info (after the count pass)
+void layout_info(hci_ctx_s* ctx, Space* sp, int64_t* info, hipStream_t s);
+void staged_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int precision,
+                  hipStream_t s);
 int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol, int max_iter,
                  int precision, int mode, int* iters_out, hipStream_t s);
 double heat_bath_max(hci_ctx_s* ctx, hipStream_t s);

@@ -378,8 +378,7 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
             if (phase_prec == HCI_FP32_MIXED) {
                 // refine with float64 products from the current Ritz vector
                 phase_prec = HCI_FP64;
-                phase_mode = sp->have_csr64 ? HCI_SIGMA_STORED : HCI_SIGMA_RECOMPUTE;
-                if (mode == HCI_SIGMA_STORED || mode == HCI_SIGMA_RECOMPUTE) phase_mode = mode;
+                phase_mode = choose_mode(ctx, sp, HCI_FP64, mode, s);
                 need_sigma = true;
                 continue;
             }

@@ -25,7 +25,10 @@ __device__ __forceinline__ i64 r2idx(int n, int p, int q, int r, int s) {
 }
 
 // contributions of <D_i| ... |D_j> for a single excitation v -> u in the
-// string sj (spin s) of D_j, with `other` the opposite-spin string of D_j
+// string sj (spin s) of D_j, with `other` the opposite-spin string of D_j.
+// HALF adds only one entry of each pair (pq|rs), (rs|pq) of rdm2 (the two are
+// equal for any bra and ket); the caller then sets rdm2 = T + T^swap.
+template <bool HALF>
 __device__ __forceinline__ void single_contrib(int n, double x, u64 sj, u64 other, int v, int u,
                                                double* r1, double* r2) {
     add64(&r1[(i64)u * n + v], x);
@@ -33,29 +36,32 @@ __device__ __forceinline__ void single_contrib(int n, double x, u64 sj, u64 othe
     for (u64 m = sj & ~bit(v); m; m &= m - 1) {  // same-spin spectators
         const int k = ctz64(m);
         add64(&r2[r2idx(n, u, v, k, k)], x);
-        add64(&r2[r2idx(n, k, k, u, v)], x);
         add64(&r2[r2idx(n, u, k, k, v)], -x);
-        add64(&r2[r2idx(n, k, v, u, k)], -x);
+        if (!HALF) {
+            add64(&r2[r2idx(n, k, k, u, v)], x);
+            add64(&r2[r2idx(n, k, v, u, k)], -x);
+        }
     }
     for (u64 m = other; m; m &= m - 1) {  // opposite-spin spectators
         const int k = ctz64(m);
         add64(&r2[r2idx(n, u, v, k, k)], x);
-        add64(&r2[r2idx(n, k, k, u, v)], x);
+        if (!HALF) add64(&r2[r2idx(n, k, k, u, v)], x);
     }
 }
 
+template <bool HALF>
 __device__ __forceinline__ void pair_contrib(int n, double w, u64 ai, u64 bi, u64 aj, u64 bj,
                                              double* r1, double* r2) {
     const u64 xa = ai ^ aj, xb = bi ^ bj;
     const int da = popc64(xa) >> 1, db = popc64(xb) >> 1;
     if (da == 1 && db == 0) {
         const int v = ctz64(aj & xa), u = ctz64(ai & xa);
-        single_contrib(n, w * sign_between(aj, v, u), aj, bj, v, u, r1, r2);
+        single_contrib<HALF>(n, w * sign_between(aj, v, u), aj, bj, v, u, r1, r2);
         return;
     }
     if (da == 0 && db == 1) {
         const int v = ctz64(bj & xb), u = ctz64(bi & xb);
-        single_contrib(n, w * sign_between(bj, v, u), bj, aj, v, u, r1, r2);
+        single_contrib<HALF>(n, w * sign_between(bj, v, u), bj, aj, v, u, r1, r2);
         return;
     }
     if (!r2) return;
@@ -64,7 +70,7 @@ __device__ __forceinline__ void pair_contrib(int n, double w, u64 ai, u64 bi, u6
         const int v2 = ctz64(bj & xb), u2 = ctz64(bi & xb);
         const double x = w * (sign_between(aj, v1, u1) * sign_between(bj, v2, u2));
         add64(&r2[r2idx(n, u1, v1, u2, v2)], x);
-        add64(&r2[r2idx(n, u2, v2, u1, v1)], x);
+        if (!HALF) add64(&r2[r2idx(n, u2, v2, u1, v1)], x);
         return;
     }
     const u64 sj = da == 2 ? aj : bj;
@@ -79,9 +85,11 @@ __device__ __forceinline__ void pair_contrib(int n, double w, u64 ai, u64 bi, u6
     const double sg = sign_double(sj, v1, u1, v2, u2);
     const double x = w * sg;
     add64(&r2[r2idx(n, u1, v1, u2, v2)], x);
-    add64(&r2[r2idx(n, u2, v2, u1, v1)], x);
     add64(&r2[r2idx(n, u1, v2, u2, v1)], -x);
-    add64(&r2[r2idx(n, u2, v1, u1, v2)], -x);
+    if (!HALF) {
+        add64(&r2[r2idx(n, u2, v2, u1, v1)], x);
+        add64(&r2[r2idx(n, u2, v1, u1, v2)], -x);
+    }
 }
 
 struct RdmVis {
@@ -95,7 +103,7 @@ struct RdmVis {
         if (!ok) return;
         const double w = bra_i * ket[j];
         if (w == 0.0) return;
-        pair_contrib(n, w, ai, bi, aj, bj, r1, r2);
+        pair_contrib<true>(n, w, ai, bi, aj, bj, r1, r2);
     }
 };
 
@@ -213,7 +221,326 @@ __global__ void pt2_pairs_kernel(const u64* __restrict__ a_hi, const u64* __rest
     const u32 i = idx[t];
     const double w = dpair[t] * c[i];
     if (w == 0.0) return;
-    pair_contrib(n, w, a_hi[t], a_lo[t], dets[2 * (i64)i], dets[2 * (i64)i + 1], r1, r2);
+    pair_contrib<false>(n, w, a_hi[t], a_lo[t], dets[2 * (i64)i], dets[2 * (i64)i + 1], r1, r2);
+}
+
+// rdm2 = T + T^swap in place, T^swap[p][q][r][s] = T[r][s][p][q].
+__global__ void swap_sym_kernel(double* __restrict__ r2, int n) {
+    const i64 n2 = (i64)n * n;
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n2 * n2) return;
+    const i64 P = t / n2, R = t % n2;
+    if (R < P) return;
+    if (R == P) {
+        r2[P * n2 + P] *= 2.0;
+        return;
+    }
+    const double v = r2[P * n2 + R] + r2[R * n2 + P];
+    r2[P * n2 + R] = v;
+    r2[R * n2 + P] = v;
+}
+
+// ---------------------------------------------------------------- bucket kernel
+// One workgroup owns up to RDM_CHUNK rows of one alpha bucket A (all rows
+// share the alpha string).  Every contribution whose orbital indices are fixed
+// by A up to a small set goes to a workgroup-private float64 accumulator in
+// LDS and reaches global memory once per workgroup:
+//   alpha single x beta single: per alpha neighbour t of A, [t][u2][v2]
+//     (processed G neighbours at a time);
+//   alpha single (same beta): per neighbour, the sum and its beta-occupation
+//     moments (opposite-spin spectators);
+//   beta single (same alpha): [u][v] and, when it fits, [u][v][k] for the
+//     same-spin spectators k;
+//   alpha double (same beta): one slot per (occupied pair, empty pair) of A.
+// Beta doubles (same alpha) go to global memory directly.  All rdm2 terms are
+// the canonical half T (see single_contrib).
+constexpr int RDM_BLOCK = 512;
+constexpr int RDM_WAVES = RDM_BLOCK / HCI_WAVE;
+constexpr u32 RDM_CHUNK = 512;
+
+struct RdmPlan {
+    int n, G;
+    int npo, npv;                // occupied / empty orbital pairs of an alpha string
+    int o_p11, o_s1a, o_s1b2, o_s1b3, o_d2a, total;  // offsets in doubles
+    bool b3, d2;
+};
+
+__device__ __forceinline__ void lds_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+// index of the unordered pair x < y
+__device__ __forceinline__ int pair_index(int x, int y) { return y * (y - 1) / 2 + x; }
+
+// position of the k-th set bit (k from 0) of s
+__device__ __forceinline__ int select_bit(u64 s, int k) {
+    for (int t = 0; t < k; ++t) s &= s - 1;
+    return ctz64(s);
+}
+
+__global__ void __launch_bounds__(RDM_BLOCK) rdm_bucket_kernel(SpaceView S, RdmPlan P, i64 nua,
+                                                               const u32* __restrict__ cptr,
+                                                               const double* __restrict__ bra,
+                                                               const double* __restrict__ ket,
+                                                               double* __restrict__ r1,
+                                                               double* __restrict__ r2) {
+    extern __shared__ double lds[];
+    __shared__ u32 sh[3];
+    const u32 tid = threadIdx.x;
+    const int lane = lane_id();
+    const u32 wave = tid / HCI_WAVE;
+    const int n = P.n;
+    const int nn = n * n;
+    if (tid == 0) {
+        // bucket of this workgroup: the last a with cptr[a] <= blockIdx.x
+        const u32 w = blockIdx.x;
+        u32 lo = 0, hi = (u32)nua - 1u;
+        while (lo < hi) {
+            const u32 mid = (lo + hi + 1u) >> 1;
+            if (cptr[mid] <= w) lo = mid;
+            else hi = mid - 1u;
+        }
+        const u32 r0 = S.aoff[lo] + (w - cptr[lo]) * RDM_CHUNK;
+        sh[0] = lo;
+        sh[1] = r0;
+        sh[2] = min(r0 + RDM_CHUNK, S.aoff[lo + 1]);
+    }
+    for (int x = (int)tid; x < P.total; x += RDM_BLOCK) lds[x] = 0.0;
+    __syncthreads();
+    const u32 a = sh[0], row0 = sh[1], row1 = sh[2];
+    const u64 A = S.ua[a];
+    const u64 full = low_mask(n);
+    const u64 E = ~A & full;  // empty alpha orbitals
+    const u32 t0 = S.as_ptr[a];
+    const u32 deg = S.as_ptr[a + 1] - t0;
+    double* p11 = lds + P.o_p11;
+    double* s1a = lds + P.o_s1a;
+    double* s1b2 = lds + P.o_s1b2;
+    double* s1b3 = lds + P.o_s1b3;
+    double* d2a = lds + P.o_d2a;
+    const u32 ngroups = deg == 0 ? 1u : (deg + (u32)P.G - 1u) / (u32)P.G;
+    for (u32 g = 0; g < ngroups; ++g) {
+        const u32 tg0 = g * (u32)P.G;
+        const u32 tg1 = min(tg0 + (u32)P.G, deg);
+        for (u32 row = row0 + wave; row < row1; row += RDM_WAVES) {
+            const double wb = bra[row];
+            if (wb == 0.0) continue;  // wave-uniform
+            const u64 B = S.beta[row];
+            const u32 b = S.ib[row];
+            if (g == 0) {
+                {  // same alpha: beta single (LDS) or beta double (global)
+                    const u32 lo = S.aoff[a], hi = S.aoff[a + 1];
+                    for (u32 base = lo; base < hi; base += HCI_WAVE) {
+                        const u32 j = base + lane;
+                        if (j >= hi || j == row) continue;
+                        const u64 bj = S.beta[j];
+                        const u64 xb = B ^ bj;
+                        const int d = popc64(xb);
+                        if (d == 2) {
+                            const int v = ctz64(bj & xb), u = ctz64(B & xb);
+                            const double x = wb * ket[j] * sign_between(bj, v, u);
+                            lds_add(&s1b2[u * n + v], x);
+                            for (u64 m = B & bj; m; m &= m - 1) {  // same-spin spectators
+                                const int k = ctz64(m);
+                                if (P.b3) {
+                                    lds_add(&s1b3[(u * n + v) * n + k], x);
+                                } else {
+                                    add64(&r2[r2idx(n, u, v, k, k)], x);
+                                    add64(&r2[r2idx(n, u, k, k, v)], -x);
+                                }
+                            }
+                        } else if (d == 4) {
+                            u64 holes = bj & xb, parts = B & xb;
+                            const int v1 = ctz64(holes);
+                            holes &= holes - 1;
+                            const int v2 = ctz64(holes);
+                            const int u1 = ctz64(parts);
+                            parts &= parts - 1;
+                            const int u2 = ctz64(parts);
+                            const double x = wb * ket[j] * sign_double(bj, v1, u1, v2, u2);
+                            add64(&r2[r2idx(n, u1, v1, u2, v2)], x);
+                            add64(&r2[r2idx(n, u1, v2, u2, v1)], -x);
+                        }
+                    }
+                }
+                {  // same beta: alpha single (LDS per neighbour) or alpha double
+                    const u32 lo = S.boff[b], hi = S.boff[b + 1];
+                    for (u32 base = lo; base < hi; base += HCI_WAVE) {
+                        const u32 k = base + lane;
+                        if (k >= hi) continue;
+                        const u32 j = S.permb[k];
+                        if (j == row) continue;
+                        const u64 aj = S.alpha[j];
+                        const u64 xa = A ^ aj;
+                        const int d = popc64(xa);
+                        if (d == 2) {
+                            const int v = ctz64(aj & xa), u = ctz64(A & xa);
+                            const double x = wb * ket[j] * sign_between(aj, v, u);
+                            const u32 t = lower_bound_u32(S.as_idx + t0, deg, S.ia[j]);
+                            double* slot = s1a + (i64)t * (1 + n);
+                            lds_add(&slot[0], x);
+                            for (u64 m = B; m; m &= m - 1) lds_add(&slot[1 + ctz64(m)], x);
+                        } else if (d == 4) {
+                            u64 holes = aj & xa, parts = A & xa;
+                            const int v1 = ctz64(holes);
+                            holes &= holes - 1;
+                            const int v2 = ctz64(holes);
+                            const int u1 = ctz64(parts);
+                            parts &= parts - 1;
+                            const int u2 = ctz64(parts);
+                            const double x = wb * ket[j] * sign_double(aj, v1, u1, v2, u2);
+                            if (P.d2) {
+                                const int po = pair_index(rank_below(A, u1), rank_below(A, u2));
+                                const int pv = pair_index(rank_below(E, v1), rank_below(E, v2));
+                                lds_add(&d2a[po * P.npv + pv], x);
+                            } else {
+                                add64(&r2[r2idx(n, u1, v1, u2, v2)], x);
+                                add64(&r2[r2idx(n, u1, v2, u2, v1)], -x);
+                            }
+                        }
+                    }
+                }
+            }
+            // alpha single x beta single for neighbours [tg0, tg1)
+            const u32 s0 = S.bs_ptr[b], s1 = S.bs_ptr[b + 1];
+            const u32 nbs = s1 - s0;
+            for (u32 t = tg0; t < tg1; ++t) {
+                const u32 a2 = S.as_idx[t0 + t];
+                const u64 A2 = S.ua[a2];
+                const u64 xa = A ^ A2;
+                const int v1 = ctz64(A2 & xa), u1 = ctz64(A & xa);
+                const double sa = sign_between(A2, v1, u1);
+                double* slot = p11 + (i64)(t - tg0) * nn;
+                const u32 lo = S.aoff[a2], hi = S.aoff[a2 + 1];
+                const u32 len = hi - lo;
+                if (len <= 4u * nbs) {
+                    for (u32 base = lo; base < hi; base += HCI_WAVE) {
+                        const u32 j = base + lane;
+                        if (j >= hi) continue;
+                        const u64 bj = S.beta[j];
+                        const u64 xb = B ^ bj;
+                        if (popc64(xb) != 2) continue;
+                        const int v2 = ctz64(bj & xb), u2 = ctz64(B & xb);
+                        lds_add(&slot[u2 * n + v2], wb * ket[j] * sa * sign_between(bj, v2, u2));
+                    }
+                } else {
+                    for (u32 base = s0; base < s1; base += HCI_WAVE) {
+                        const u32 k = base + lane;
+                        if (k >= s1) continue;
+                        const u64 bj = S.ub[S.bs_idx[k]];
+                        const u32 pos = lower_bound_u64(S.beta + lo, len, bj);
+                        if (pos >= len || S.beta[lo + pos] != bj) continue;
+                        const u32 j = lo + pos;
+                        const u64 xb = B ^ bj;
+                        const int v2 = ctz64(bj & xb), u2 = ctz64(B & xb);
+                        lds_add(&slot[u2 * n + v2], wb * ket[j] * sa * sign_between(bj, v2, u2));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // flush this group's alpha single x beta single slots
+        for (int x = (int)tid; x < (int)(tg1 - tg0) * nn; x += RDM_BLOCK) {
+            const double val = p11[x];
+            if (val == 0.0) continue;
+            p11[x] = 0.0;
+            const u32 t = tg0 + (u32)(x / nn);
+            const int u2 = (x % nn) / n, v2 = x % n;
+            const u64 A2 = S.ua[S.as_idx[t0 + t]];
+            const u64 xa = A ^ A2;
+            add64(&r2[r2idx(n, ctz64(A & xa), ctz64(A2 & xa), u2, v2)], val);
+        }
+        __syncthreads();
+    }
+    // alpha singles: r1 and same-spin spectators from the sum, opposite-spin
+    // spectators from the beta-occupation moments
+    for (u32 t = tid; t < deg; t += RDM_BLOCK) {
+        const u64 A2 = S.ua[S.as_idx[t0 + t]];
+        const u64 xa = A ^ A2;
+        const int v = ctz64(A2 & xa), u = ctz64(A & xa);
+        const double* slot = s1a + (i64)t * (1 + n);
+        const double X = slot[0];
+        if (X != 0.0) {
+            add64(&r1[u * n + v], X);
+            for (u64 m = A & A2; m; m &= m - 1) {
+                const int k = ctz64(m);
+                add64(&r2[r2idx(n, u, v, k, k)], X);
+                add64(&r2[r2idx(n, u, k, k, v)], -X);
+            }
+        }
+        for (int k = 0; k < n; ++k) {
+            const double Y = slot[1 + k];
+            if (Y != 0.0) add64(&r2[r2idx(n, u, v, k, k)], Y);
+        }
+    }
+    // beta singles: r1 and the alpha spectators from the sum
+    for (int x = (int)tid; x < nn; x += RDM_BLOCK) {
+        const double X = s1b2[x];
+        if (X == 0.0) continue;
+        const int u = x / n, v = x % n;
+        add64(&r1[x], X);
+        for (u64 m = A; m; m &= m - 1) add64(&r2[r2idx(n, u, v, ctz64(m), ctz64(m))], X);
+    }
+    if (P.b3) {
+        for (int x = (int)tid; x < nn * n; x += RDM_BLOCK) {
+            const double X = s1b3[x];
+            if (X == 0.0) continue;
+            const int u = x / nn, v = (x / n) % n, k = x % n;
+            add64(&r2[r2idx(n, u, v, k, k)], X);
+            add64(&r2[r2idx(n, u, k, k, v)], -X);
+        }
+    }
+    if (P.d2) {
+        for (int x = (int)tid; x < P.npo * P.npv; x += RDM_BLOCK) {
+            const double X = d2a[x];
+            if (X == 0.0) continue;
+            const int po = x / P.npv, pv = x % P.npv;
+            int y = 1;
+            while ((y + 1) * y / 2 <= po) ++y;
+            const int ru2 = y, ru1 = po - y * (y - 1) / 2;
+            y = 1;
+            while ((y + 1) * y / 2 <= pv) ++y;
+            const int rv2 = y, rv1 = pv - y * (y - 1) / 2;
+            const int u1 = select_bit(A, ru1), u2 = select_bit(A, ru2);
+            const int v1 = select_bit(E, rv1), v2 = select_bit(E, rv2);
+            add64(&r2[r2idx(n, u1, v1, u2, v2)], X);
+            add64(&r2[r2idx(n, u1, v2, u2, v1)], -X);
+        }
+    }
+}
+
+__global__ void rdm_nchunk_kernel(const u32* __restrict__ aoff, i64 nua, u32* __restrict__ out) {
+    const i64 a = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < nua) out[a] = (aoff[a + 1] - aoff[a] + RDM_CHUNK - 1) / RDM_CHUNK;
+    if (a == nua) out[a] = 0;
+}
+
+// LDS layout of the bucket kernel for this context, within `budget` doubles;
+// false when even one alpha neighbour per pass does not fit.
+bool rdm_plan(int n, int na, int budget, RdmPlan& P) {
+    const int dmax = na * (n - na);
+    const int nn = n * n;
+    P.n = n;
+    P.npo = na * (na - 1) / 2;
+    P.npv = (n - na) * (n - na - 1) / 2;
+    for (int variant = 0; variant < 3; ++variant) {
+        P.b3 = variant == 0;
+        P.d2 = variant <= 1;
+        const int s1a = dmax * (1 + n);
+        const int s1b3 = P.b3 ? nn * n : 0;
+        const int d2 = P.d2 ? P.npo * P.npv : 0;
+        const int rest = s1a + nn + s1b3 + d2;
+        int G = (budget - rest) / nn;
+        if (G < 1) continue;
+        if (G > dmax) G = dmax > 0 ? dmax : 1;
+        P.G = G;
+        P.o_p11 = 0;
+        P.o_s1a = G * nn;
+        P.o_s1b2 = P.o_s1a + s1a;
+        P.o_s1b3 = P.o_s1b2 + nn;
+        P.o_d2a = P.o_s1b3 + s1b3;
+        P.total = P.o_d2a + d2;
+        return true;
+    }
+    return false;
 }
 
 }  // namespace
@@ -245,8 +572,27 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
     HIP_CHECK(hipMemsetAsync(rdm1, 0, sizeof(double) * n2, s));
     if (rdm2) HIP_CHECK(hipMemsetAsync(rdm2, 0, sizeof(double) * n2 * n2, s));
     SpaceView S = space_view(*sp, n);
-    HCI_LAUNCH(ctx, "rdm_offdiag", s, rdm_offdiag_kernel, ceil_div(N, ROWS_PER_BLOCK), ROW_BLOCK, 0,
-               S, bra, ket, rdm1, rdm2);
+    RdmPlan P;
+    if (rdm2 && rdm_plan(n, ctx->na, 8192, P)) {
+        if (!sp->rdm_cptr.ptr) {
+            DevMem cnt = dev_alloc(ctx, sizeof(u32) * (sp->nua + 1), s);
+            HCI_LAUNCH(ctx, "rdm_nchunk", s, rdm_nchunk_kernel, ceil_div(sp->nua + 1, 256), 256, 0,
+                       sp->aoff.as<u32>(), sp->nua, cnt.as<u32>());
+            sp->rdm_cptr = dev_alloc(ctx, sizeof(u32) * (sp->nua + 1), s);
+            scan_u32_to_u32(ctx, cnt.as<u32>(), sp->rdm_cptr.as<u32>(), sp->nua + 1, s);
+            sp->rdm_nchunk = read_scalar(sp->rdm_cptr.as<u32>() + sp->nua, s);
+        }
+        HCI_LAUNCH(ctx, "rdm_offdiag", s, rdm_bucket_kernel, sp->rdm_nchunk, RDM_BLOCK,
+                   sizeof(double) * P.total, S, P, sp->nua, sp->rdm_cptr.as<u32>(), bra, ket, rdm1,
+                   rdm2);
+    } else {
+        HCI_LAUNCH(ctx, "rdm_offdiag", s, rdm_offdiag_kernel, ceil_div(N, ROWS_PER_BLOCK), ROW_BLOCK,
+                   0, S, bra, ket, rdm1, rdm2);
+    }
+    // the off-diagonal passes accumulate one entry of each (pq|rs), (rs|pq) pair
+    if (rdm2) {
+        HCI_LAUNCH(ctx, "rdm_swap_sym", s, swap_sym_kernel, ceil_div(n2 * n2, 256), 256, 0, rdm2, n);
+    }
     rdm_add_diag(ctx, sp->alpha.as<u64>(), sp->beta.as<u64>(), bra, ket, N, rdm1, rdm2, s);
 }
 

@@ -153,7 +153,7 @@ __global__ void u32_to_i64_sum_kernel(const u32* __restrict__ x, i64 n, unsigned
 }
 
 void ensure_rowptr(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
-    if (sp->nnz_off >= 0) return;
+    if (sp->layout == 1) return;
     const i64 N = sp->N;
     SpaceView S = space_view(*sp, ctx->n);
     DevMem counts = dev_alloc(ctx, sizeof(u32) * (N + 1), s);
@@ -172,6 +172,14 @@ void ensure_rowptr(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
     scan_u32_to_i64(ctx, padded.as<u32>(), sp->rowptr.as<i64>(), N + 1, s);
     sp->nnz_off = (i64)read_scalar(total.as<u64>(), s);
     sp->nnz_pad = read_scalar(sp->rowptr.as<i64>() + N, s);
+    sp->layout = 1;
+}
+
+// Count pass of the stored layout: the alpha-bucket-staged layout when the
+// space fits its limits, else the plain CSR.  Sets nnz_off either way.
+void ensure_layout(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
+    if (sp->layout != 0) return;
+    if (!staged_prepare(ctx, sp, s)) ensure_rowptr(ctx, sp, s);
 }
 
 }  // namespace
@@ -185,14 +193,18 @@ void ensure_diag(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
 }
 
 i64 count_connections(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
-    ensure_rowptr(ctx, sp, s);
+    ensure_layout(ctx, sp, s);
     return sp->nnz_off + sp->N;
 }
 
 void ensure_csr(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s) {
+    ensure_layout(ctx, sp, s);
+    if (sp->layout == 2) {
+        staged_ensure_vals(ctx, sp, precision, s);
+        return;
+    }
     const bool f32 = precision == HCI_FP32_MIXED;
     if (f32 ? sp->have_csr32 : sp->have_csr64) return;
-    ensure_rowptr(ctx, sp, s);
     const i64 nnz = sp->nnz_pad;
     SpaceView S = space_view(*sp, ctx->n);
     IntView I = int_view(ctx->ints);
@@ -221,9 +233,11 @@ void ensure_csr(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s) {
 
 int choose_mode(hci_ctx_s* ctx, Space* sp, int precision, int mode, hipStream_t s) {
     if (mode == HCI_SIGMA_STORED || mode == HCI_SIGMA_RECOMPUTE) return mode;
-    ensure_rowptr(ctx, sp, s);
-    const i64 per = precision == HCI_FP32_MIXED ? 8 : 12;
-    return sp->nnz_pad * per <= ctx->stored_budget ? HCI_SIGMA_STORED : HCI_SIGMA_RECOMPUTE;
+    ensure_layout(ctx, sp, s);
+    const bool f32 = precision == HCI_FP32_MIXED;
+    // bytes per stored entry: value + column (u16 staged, u32 plain)
+    const i64 bytes = sp->layout == 2 ? sp->st_nnz * (f32 ? 6 : 10) : sp->nnz_pad * (f32 ? 8 : 12);
+    return bytes <= ctx->stored_budget ? HCI_SIGMA_STORED : HCI_SIGMA_RECOMPUTE;
 }
 
 void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int precision, int mode,
@@ -234,6 +248,13 @@ void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int 
     const i64 grid = ceil_div(N, ROWS_PER_BLOCK);
     const i64 gridp = ceil_div(N, SPMV_ROWS);
     DevMem& c32 = sp->c32;
+    if (mode == HCI_SIGMA_STORED) {
+        ensure_layout(ctx, sp, s);
+        if (sp->layout == 2) {
+            staged_apply(ctx, sp, c, sigma, precision, s);
+            return;
+        }
+    }
     if (f32) {
         if (!c32.ptr) c32 = dev_alloc(ctx, sizeof(float) * N, s);
         HCI_LAUNCH(ctx, "c_to_f32", s, f64_to_f32_kernel, ceil_div(N, 256), 256, 0, c,

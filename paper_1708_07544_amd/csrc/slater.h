@@ -131,6 +131,28 @@ __device__ __forceinline__ u32 lower_bound_u64(const u64* __restrict__ arr, u32 
     return lo;
 }
 
+// first index in sorted arr[0, len) whose value is >= key (u32)
+__device__ __forceinline__ u32 lower_bound_u32(const u32* __restrict__ arr, u32 len, u32 key) {
+    u32 lo = 0, hi = len;
+    while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if (arr[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// first index in sorted arr[0, len) whose value is > key (u32)
+__device__ __forceinline__ u32 upper_bound_u32(const u32* __restrict__ arr, u32 len, u32 key) {
+    u32 lo = 0, hi = len;
+    while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if (arr[mid] <= key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // Enumerate every j != i in V with excitation degree <= 2 from row i.  The
 // whole wavefront calls this for one row; `vis(ok, j, aj, bj)` is invoked
 // wave-uniformly, each lane carrying its own candidate (ok = it is one).

@@ -1,0 +1,764 @@
+// Stored Hamiltonian in an alpha-bucket-staged layout, for the product
+// sigma = H c inside the Davidson solver (Sec. "Variational Stage") over all
+// single and double connections of V (Sec. "Computational Details").
+//
+// V is sorted by (alpha, beta), so each alpha string owns a contiguous bucket
+// of rows.  A connection (i, j) of a row i in bucket A is either
+//   S: j in A itself, or in a bucket A' one alpha single away from A (alpha
+//      single with the same beta, or alpha single x beta single), or
+//   G: an alpha double with the same beta string.
+// The S buckets of A -- A, then its alpha-single neighbours in adjacency
+// order -- are laid end to end; position P of j in that concatenation is
+// stored as window P >> w and local column P & (2^w - 1) (u16).  A G entry
+// stores the offset of j inside the row's beta group (u16), which is
+// contiguous in the beta-major order.
+//
+// A workgroup owns up to 1024 rows of one bucket.  For each window it copies
+// that slice of c into LDS (whole buckets are contiguous in c, so the copy
+// streams), then its waves stream their rows' entries of the window and
+// gather c_j from LDS.  G entries gather from a beta-major copy of c.  Each
+// product therefore reads per entry only the value and a 2-byte column from
+// HBM; the gathers that bound the plain CSR product (every row touches
+// hundreds of distinct cache lines of c) move to LDS.
+//
+// Entries of a row are grouped by segment (windows in order, G last); the
+// layout is built by a count pass, a scan, an integer column pass and a
+// separate element pass per precision.
+#include "slater.h"
+
+namespace {
+
+typedef uint16_t u16;
+
+constexpr int ST_ROW_BLOCK = 256;  // build passes: one wavefront per row
+constexpr int ST_ROWS_PER_BLOCK = ST_ROW_BLOCK / HCI_WAVE;
+constexpr int ST_BLOCK = 1024;     // product: 16 wavefronts
+constexpr int ST_WAVES = ST_BLOCK / HCI_WAVE;
+constexpr u32 ST_CHUNK = 64 * ST_WAVES;  // rows per workgroup (64 per wavefront)
+constexpr u32 ST_MAX_SEG = 64;           // segments per row (lane-held cursors)
+constexpr u32 ST_MAX_GROUP = 65536;      // beta-group offsets are u16
+constexpr u32 ST_VEC = 8;                // entries per lane per load; segments padded to it
+
+struct StView {
+    u32 wlog;
+    i64 nua, nub;
+    const u32* gcptr;
+    const u32* xpos;
+    const u32* len;
+    const u32* nseg;
+    const u32* cptr;
+    const i64* rsb;
+    const u32* segoff;
+    const u32* segcnt;
+    const i64* rowptr;
+    const u16* cols;
+};
+
+StView st_view(const Space& s) {
+    StView v;
+    v.wlog = s.st_wlog;
+    v.nua = s.nua;
+    v.nub = s.nub;
+    v.gcptr = s.st_gcptr.as<u32>();
+    v.xpos = s.st_xpos.as<u32>();
+    v.len = s.st_len.as<u32>();
+    v.nseg = s.st_nseg.as<u32>();
+    v.cptr = s.st_cptr.as<u32>();
+    v.rsb = s.st_rsb.as<i64>();
+    v.segoff = s.st_segoff.as<u32>();
+    v.segcnt = s.st_segcnt.as<u32>();
+    v.rowptr = s.st_rowptr.as<i64>();
+    v.cols = s.st_cols.as<u16>();
+    return v;
+}
+
+// One thread per bucket: stage ranges, stage length, segment count and
+// workgroup count; one thread per beta group: group size limit.  flags[0]
+// counts buckets with too many segments, flags[1] oversized beta groups,
+// flags[2] holds the largest stage length.
+__global__ void st_meta_kernel(SpaceView S, u32 wlog, u32* __restrict__ xpos, u32* __restrict__ len,
+                               u32* __restrict__ nseg, u32* __restrict__ nchunk,
+                               u32* __restrict__ gnchunk, i64 nua, i64 nub,
+                               unsigned long long* __restrict__ flags) {
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nua) {
+        const u32 a = (u32)t;
+        const u32 t0 = S.as_ptr[a], t1 = S.as_ptr[a + 1];
+        const u32 xb = t0 + a;
+        u32 pos = S.aoff[a + 1] - S.aoff[a];
+        xpos[xb] = 0;
+        for (u32 k = t0; k < t1; ++k) {
+            xpos[xb + 1 + (k - t0)] = pos;
+            const u32 a2 = S.as_idx[k];
+            pos += S.aoff[a2 + 1] - S.aoff[a2];
+        }
+        len[a] = pos;
+        const u32 ns = ((pos + (1u << wlog) - 1u) >> wlog) + 1u;
+        nseg[a] = ns;
+        nchunk[a] = (S.aoff[a + 1] - S.aoff[a] + ST_CHUNK - 1) / ST_CHUNK;
+        if (ns > ST_MAX_SEG) atomicAdd(&flags[0], 1ull);
+        atomicMax(&flags[2], (unsigned long long)pos);
+    }
+    if (t < nub) {
+        const u32 gs = S.boff[t + 1] - S.boff[t];
+        gnchunk[t] = (gs + ST_CHUNK - 1) / ST_CHUNK;
+        if (gs > ST_MAX_GROUP) atomicAdd(&flags[1], 1ull);
+    }
+}
+
+__global__ void st_row_nseg_kernel(const u32* __restrict__ ia, const u32* __restrict__ nseg, i64 N,
+                                   u32* __restrict__ out) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) out[i] = nseg[ia[i]];
+    if (i == N) out[i] = 0;
+}
+
+// Every j != i of V at excitation degree <= 2 from row i, with its segment
+// and u16 column in the staged layout.  The whole wavefront calls this for
+// one row; vis(ok, j, aj, bj, seg, col) is invoked wave-uniformly with each
+// lane's own candidate.  Discovery order (deterministic): same-alpha bucket,
+// same-beta group, then alpha-single neighbours in adjacency order.
+template <class Visitor>
+__device__ __forceinline__ void enumerate_row_staged(const SpaceView& S, const u32* __restrict__ xpos,
+                                                     u32 wlog, u32 gseg, u32 i, Visitor& vis) {
+    const int lane = lane_id();
+    const u32 wmask = (1u << wlog) - 1u;
+    const u64 A = S.alpha[i], B = S.beta[i];
+    const u32 a = S.ia[i], b = S.ib[i];
+    const u32 t0 = S.as_ptr[a], t1 = S.as_ptr[a + 1];
+    const u32 xb = t0 + a;
+    {  // same alpha string: stage range 0
+        const u32 lo = S.aoff[a], hi = S.aoff[a + 1];
+        for (u32 base = lo; base < hi; base += HCI_WAVE) {
+            const u32 j = base + lane;
+            bool ok = j < hi && j != i;
+            u64 bj = 0;
+            if (ok) {
+                bj = S.beta[j];
+                ok = popc64(B ^ bj) <= 4;
+            }
+            const u32 P = j - lo;
+            vis(ok, j, A, bj, P >> wlog, P & wmask);
+        }
+    }
+    {  // same beta string: an alpha single lies in a staged neighbour bucket,
+       // an alpha double goes to the beta-group segment
+        const u32 lo = S.boff[b], hi = S.boff[b + 1];
+        for (u32 base = lo; base < hi; base += HCI_WAVE) {
+            const u32 k = base + lane;
+            bool ok = k < hi;
+            u32 j = 0, seg = gseg, col = k - lo;
+            u64 aj = 0;
+            if (ok) {
+                j = S.permb[k];
+                ok = j != i;
+                if (ok) {
+                    aj = S.alpha[j];
+                    const int d = popc64(A ^ aj);
+                    ok = d <= 4;
+                    if (d == 2) {
+                        const u32 a2 = S.ia[j];
+                        const u32 r = lower_bound_u32(S.as_idx + t0, t1 - t0, a2);
+                        const u32 P = xpos[xb + 1 + r] + (j - S.aoff[a2]);
+                        seg = P >> wlog;
+                        col = P & wmask;
+                    }
+                }
+            }
+            vis(ok, j, aj, B, seg, col);
+        }
+    }
+    {  // one alpha and one beta excitation: stage ranges 1, 2, ...
+        const u32 s0 = S.bs_ptr[b], s1 = S.bs_ptr[b + 1];
+        const u32 nbs = s1 - s0;
+        for (u32 t = t0; t < t1; ++t) {
+            const u32 a2 = S.as_idx[t];
+            const u64 A2 = S.ua[a2];
+            const u32 lo = S.aoff[a2], hi = S.aoff[a2 + 1];
+            const u32 len = hi - lo;
+            const u32 P0 = xpos[xb + 1 + (t - t0)];
+            if (len <= 4u * nbs) {
+                for (u32 base = lo; base < hi; base += HCI_WAVE) {
+                    const u32 j = base + lane;
+                    bool ok = j < hi;
+                    u64 bj = 0;
+                    if (ok) {
+                        bj = S.beta[j];
+                        ok = popc64(B ^ bj) == 2;
+                    }
+                    const u32 P = P0 + (j - lo);
+                    vis(ok, j, A2, bj, P >> wlog, P & wmask);
+                }
+            } else {
+                for (u32 base = s0; base < s1; base += HCI_WAVE) {
+                    const u32 k = base + lane;
+                    bool ok = k < s1;
+                    u32 j = 0;
+                    u64 bj = 0;
+                    if (ok) {
+                        bj = S.ub[S.bs_idx[k]];
+                        const u32 pos = lower_bound_u64(S.beta + lo, len, bj);
+                        ok = pos < len && S.beta[lo + pos] == bj;
+                        j = lo + pos;
+                    }
+                    const u32 P = P0 + (j - lo);
+                    vis(ok, j, A2, bj, P >> wlog, P & wmask);
+                }
+            }
+        }
+    }
+}
+
+// Count pass: lane s of the wavefront holds the count of segment s.
+struct StCountVis {
+    u32 cnt = 0;
+    __device__ __forceinline__ void operator()(bool ok, u32, u64, u64, u32 seg, u32) {
+        u64 m = ballot(ok);
+        while (m) {
+            const u32 s = (u32)__shfl((int)seg, ctz64(m), HCI_WAVE);
+            const u64 ms = ballot(ok && seg == s);
+            if ((u32)lane_id() == s) cnt += (u32)__popcll(ms);
+            m &= ~ms;
+        }
+    }
+};
+
+__global__ void __launch_bounds__(ST_ROW_BLOCK) st_count_kernel(SpaceView S, StView T,
+                                                                u32* __restrict__ counts,
+                                                                u32* __restrict__ segoff,
+                                                                u32* __restrict__ segcnt) {
+    const i64 i = (i64)blockIdx.x * ST_ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
+    if (i >= S.N) return;
+    const u32 lane = (u32)lane_id();
+    const u32 ns = T.nseg[S.ia[i]];
+    StCountVis v;
+    enumerate_row_staged(S, T.xpos, T.wlog, ns - 1u, (u32)i, v);
+    // segments padded to multiples of ST_VEC entries (aligned vector loads in
+    // the product); inclusive scan of the padded counts across lanes
+    const u32 pc = (v.cnt + ST_VEC - 1u) & ~(ST_VEC - 1u);
+    int x = (int)pc;
+#pragma unroll
+    for (int off = 1; off < HCI_WAVE; off <<= 1) {
+        const int y = __shfl_up(x, off, HCI_WAVE);
+        if ((int)lane >= off) x += y;
+    }
+    if (lane < ns) {
+        segoff[T.rsb[i] + lane] = (u32)x - pc;
+        segcnt[T.rsb[i] + lane] = v.cnt;
+    }
+    if (lane == HCI_WAVE - 1) counts[i] = (u32)x;
+}
+
+// Column pass: lane s holds the start and the cursor of segment s.
+struct StFillVis {
+    u16* cols;
+    i64 rs;
+    u32 so;
+    u32 cur = 0;
+    __device__ __forceinline__ void operator()(bool ok, u32, u64, u64, u32 seg, u32 col) {
+        u64 m = ballot(ok);
+        while (m) {
+            const u32 s = (u32)__shfl((int)seg, ctz64(m), HCI_WAVE);
+            const bool mine = ok && seg == s;
+            const u64 ms = ballot(mine);
+            const u32 at = (u32)__shfl((int)(so + cur), (int)s, HCI_WAVE);
+            if (mine) cols[rs + at + rank_in(ms)] = (u16)col;
+            if ((u32)lane_id() == s) cur += (u32)__popcll(ms);
+            m &= ~ms;
+        }
+    }
+};
+
+__global__ void __launch_bounds__(ST_ROW_BLOCK) st_cols_kernel(SpaceView S, StView T,
+                                                               u16* __restrict__ cols,
+                                                               unsigned long long* __restrict__ bad) {
+    const i64 i = (i64)blockIdx.x * ST_ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
+    if (i >= S.N) return;
+    const u32 lane = (u32)lane_id();
+    const u32 ns = T.nseg[S.ia[i]];
+    const i64 rs = T.rowptr[i];
+    const u32 rl = (u32)(T.rowptr[i + 1] - rs);
+    const i64 sb = T.rsb[i];
+    StFillVis v{cols, rs, lane < ns ? T.segoff[sb + lane] : 0u};
+    enumerate_row_staged(S, T.xpos, T.wlog, ns - 1u, (u32)i, v);
+    // the fill must reproduce the count pass segment by segment; padding
+    // entries get column 0 (their element is 0)
+    if (lane < ns) {
+        if (v.cur != T.segcnt[sb + lane]) atomicAdd(bad, 1ull);
+        const u32 end = lane + 1 < ns ? T.segoff[sb + lane + 1] : rl;
+        for (u32 k = v.so + v.cur; k < end; ++k) cols[rs + k] = 0;
+    }
+}
+
+// Element pass: decode each stored column back to its determinant and
+// evaluate H_ij in float64 (rounded to the stored precision).
+template <class VT>
+__global__ void __launch_bounds__(ST_ROW_BLOCK) st_vals_kernel(SpaceView S, IntView I, StView T,
+                                                               VT* __restrict__ vals) {
+    const i64 i = (i64)blockIdx.x * ST_ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
+    if (i >= S.N) return;
+    const u32 a = S.ia[i];
+    const u32 ns = T.nseg[a];
+    const u32 t0 = S.as_ptr[a];
+    const u32 nr = 1u + S.as_ptr[a + 1] - t0;
+    const u32* xs = T.xpos + t0 + a;
+    const u64 ai = S.alpha[i], bi = S.beta[i];
+    const i64 rs = T.rowptr[i];
+    const u32 rl = (u32)(T.rowptr[i + 1] - rs);
+    const i64 sb = T.rsb[i];
+    const u32 gb = S.boff[S.ib[i]];
+    for (u32 s = 0; s < ns; ++s) {
+        const i64 k0 = rs + T.segoff[sb + s];
+        const i64 k1 = rs + (s + 1 < ns ? T.segoff[sb + s + 1] : rl);
+        const i64 kr = k0 + T.segcnt[sb + s];
+        for (i64 k = k0 + lane_id(); k < k1; k += HCI_WAVE) {
+            if (k >= kr) {
+                vals[k] = (VT)0;
+                continue;
+            }
+            const u32 col = T.cols[k];
+            u32 j;
+            if (s + 1 < ns) {
+                const u32 P = (s << T.wlog) + col;
+                const u32 e = upper_bound_u32(xs, nr, P) - 1u;
+                const u32 a2 = e == 0 ? a : S.as_idx[t0 + e - 1];
+                j = S.aoff[a2] + (P - xs[e]);
+            } else {
+                j = S.permb[gb + col];
+            }
+            vals[k] = (VT)hij_f64(I, ai, bi, S.alpha[j], S.beta[j]);
+        }
+    }
+}
+
+__global__ void st_sum_kernel(const u32* __restrict__ x, i64 n, unsigned long long* __restrict__ out) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    u64 v = i < n ? (u64)x[i] : 0ull;
+    v = wave_sum_u64(v);
+    if (lane_id() == 0 && v) atomicAdd(out, (unsigned long long)v);
+}
+
+// Entries stored in each row's beta-group segment (last segment).
+__global__ void st_gentries_kernel(SpaceView S, StView T, unsigned long long* __restrict__ out) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    u64 v = 0;
+    if (i < S.N) {
+        const i64 rs = T.rowptr[i];
+        v = (u64)(T.rowptr[i + 1] - rs - T.segoff[T.rsb[i] + T.nseg[S.ia[i]] - 1]);
+    }
+    v = wave_sum_u64(v);
+    if (lane_id() == 0 && v) atomicAdd(out, (unsigned long long)v);
+}
+
+// c (float64) -> the product's alpha-major and beta-major copies.
+template <class CT>
+__global__ void st_prep_kernel(const double* __restrict__ c, const u32* __restrict__ permb, i64 N,
+                               CT* __restrict__ cx, CT* __restrict__ cpb) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    if (cx) cx[i] = (CT)c[i];
+    cpb[i] = (CT)c[permb[i]];
+}
+
+// Four consecutive stored values (16-byte aligned) widened to float64.
+template <class VT>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    static __device__ __forceinline__ void load(const float* p, double v[4]) {
+        const float4 x = *reinterpret_cast<const float4*>(p);
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = x.z;
+        v[3] = x.w;
+    }
+};
+template <>
+struct Vec4<double> {
+    static __device__ __forceinline__ void load(const double* p, double v[4]) {
+        const double2 x = *reinterpret_cast<const double2*>(p);
+        const double2 y = *reinterpret_cast<const double2*>(p + 2);
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = y.x;
+        v[3] = y.y;
+    }
+};
+
+// VEC consecutive stored entries (aligned): u16 columns and values widened
+// to float64.
+template <class VT, int VEC>
+__device__ __forceinline__ void load_entries(const u16* __restrict__ cols, const VT* __restrict__ vals,
+                                             u32 c[VEC], double v[VEC]) {
+    if constexpr (VEC == 4) {
+        const uint2 w = *reinterpret_cast<const uint2*>(cols);
+        c[0] = w.x & 0xffffu;
+        c[1] = w.x >> 16;
+        c[2] = w.y & 0xffffu;
+        c[3] = w.y >> 16;
+    } else {
+#pragma unroll
+        for (int h = 0; h < VEC; h += 8) {
+            const uint4 w = *reinterpret_cast<const uint4*>(cols + h);
+            c[h + 0] = w.x & 0xffffu;
+            c[h + 1] = w.x >> 16;
+            c[h + 2] = w.y & 0xffffu;
+            c[h + 3] = w.y >> 16;
+            c[h + 4] = w.z & 0xffffu;
+            c[h + 5] = w.z >> 16;
+            c[h + 6] = w.w & 0xffffu;
+            c[h + 7] = w.w >> 16;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < VEC; q += 4) Vec4<VT>::load(vals + q, v + q);
+}
+
+// Sum of a value over groups of SUB consecutive lanes (result in every lane).
+template <int SUB>
+__device__ __forceinline__ double group_sum_f64(double v) {
+#pragma unroll
+    for (int off = SUB / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, HCI_WAVE);
+    return v;
+}
+
+// Product kernel.  Workgroup = up to 1024 rows of one bucket; wavefront w owns
+// rows r0 + w + 16 q (lane q holds that row's accumulator, so every wavefront
+// has work even in small buckets); SUB lanes stream one row's segment at a
+// time.
+template <class VT, class CT, int SUB>
+__global__ void __launch_bounds__(ST_BLOCK) st_spmv_kernel(SpaceView S, StView T,
+                                                           const VT* __restrict__ vals,
+                                                           const CT* __restrict__ cx,
+                                                           const double* __restrict__ c,
+                                                           const double* __restrict__ hd,
+                                                           double* __restrict__ sigma) {
+    extern __shared__ __align__(16) unsigned char st_smem[];
+    CT* stage = reinterpret_cast<CT*>(st_smem);
+    __shared__ u32 sh[3];
+    constexpr int GROUPS = HCI_WAVE / SUB;  // rows in flight per wavefront
+    const u32 tid = threadIdx.x;
+    const int lane = lane_id();
+    const u32 wave = tid / HCI_WAVE;
+    if (tid == 0) {
+        // bucket of this workgroup: the last a with cptr[a] <= blockIdx.x
+        const u32 w = blockIdx.x;
+        u32 lo = 0, hi = (u32)T.nua - 1u;
+        while (lo < hi) {
+            const u32 mid = (lo + hi + 1u) >> 1;
+            if (T.cptr[mid] <= w) lo = mid;
+            else hi = mid - 1u;
+        }
+        const u32 r0 = S.aoff[lo] + (w - T.cptr[lo]) * ST_CHUNK;
+        sh[0] = lo;
+        sh[1] = r0;
+        sh[2] = min(r0 + ST_CHUNK, S.aoff[lo + 1]);
+    }
+    __syncthreads();
+    const u32 a = sh[0], r0 = sh[1], r1 = sh[2];
+    const u32 t0 = S.as_ptr[a];
+    const u32 nr = 1u + S.as_ptr[a + 1] - t0;
+    const u32* xs = T.xpos + t0 + a;
+    const u32 ns = T.nseg[a];
+    const u32 slen = T.len[a];
+    const u32 wsize = 1u << T.wlog;
+    // rows r0 + wave + ST_WAVES q (q < 64) belong to this wavefront; lane q holds
+    // row q's metadata and accumulator
+    const u32 nrows = r1 - r0;
+    const int nrw = wave < nrows ? (int)((nrows - wave + ST_WAVES - 1) / ST_WAVES) : 0;
+    const u32 row = r0 + wave + ST_WAVES * (u32)lane;
+    const bool has = lane < nrw;
+    const i64 rs = has ? T.rowptr[row] : 0;
+    const u32 rl = has ? (u32)(T.rowptr[row + 1] - rs) : 0u;
+    const i64 sb = has ? T.rsb[row] : 0;
+    double acc = 0.0;
+    for (u32 g = 0; g + 1 < ns; ++g) {
+        __syncthreads();  // the previous window is consumed
+        const u32 wstart = g << T.wlog;
+        const u32 wend = min(wstart + wsize, slen);
+        u32 p = wstart + tid;
+        if (p < wend) {
+            u32 e = upper_bound_u32(xs, nr, p) - 1u;
+            u32 src = S.aoff[e == 0 ? a : S.as_idx[t0 + e - 1]];
+            u32 xe = xs[e];
+            for (; p < wend; p += ST_BLOCK) {
+                while (e + 1 < nr && xs[e + 1] <= p) {
+                    ++e;
+                    src = S.aoff[S.as_idx[t0 + e - 1]];
+                    xe = xs[e];
+                }
+                stage[p - wstart] = cx[src + (p - xe)];
+            }
+        }
+        __syncthreads();
+        const i64 mk0 = rs + (has ? T.segoff[sb + g] : 0u);
+        const i64 mk1 = rs + (has ? T.segoff[sb + g + 1] : 0u);
+        for (int qb = 0; qb < nrw; qb += GROUPS) {
+            const int q = qb + lane / SUB;
+            const int sl = lane % SUB;
+            const i64 k0 = __shfl(mk0, q, HCI_WAVE);
+            const i64 k1s = __shfl(mk1, q, HCI_WAVE);
+            const i64 k1 = q < nrw ? k1s : k0;
+            double t = 0.0;
+            for (i64 k = k0 + ST_VEC * sl; k < k1; k += ST_VEC * SUB) {
+                u32 cc[ST_VEC];
+                double v[ST_VEC];
+                load_entries<VT, ST_VEC>(T.cols + k, vals + k, cc, v);
+#pragma unroll
+                for (int e = 0; e < (int)ST_VEC; ++e) t += v[e] * (double)stage[cc[e]];
+            }
+            t = group_sum_f64<SUB>(t);
+            const double v = __shfl(t, ((lane - qb) * SUB) & (HCI_WAVE - 1), HCI_WAVE);
+            if (lane >= qb && lane < qb + GROUPS) acc += v;
+        }
+    }
+    if (has) sigma[row] = hd[row] * c[row] + acc;
+}
+
+// Beta-group product: in beta-major order the alpha doubles with the same
+// beta string form diagonal blocks, one per beta group.  A workgroup owns up
+// to ST_CHUNK rows of one group, copies the group's slice of the beta-major c
+// into LDS when it fits the window (else gathers it from global memory) and
+// adds each row's G segment to sigma (after the staged kernel).
+template <class VT, class CT, int SUB, bool LDS>
+__device__ __forceinline__ double g_rows(const StView& T, const VT* __restrict__ vals,
+                                         const CT* __restrict__ src, i64 mk0, i64 mk1, int nrw,
+                                         int lane) {
+    constexpr int GROUPS = HCI_WAVE / SUB;
+    double acc = 0.0;
+    for (int qb = 0; qb < nrw; qb += GROUPS) {
+        const int q = qb + lane / SUB;
+        const int sl = lane % SUB;
+        const i64 k0 = __shfl(mk0, q, HCI_WAVE);
+        const i64 k1s = __shfl(mk1, q, HCI_WAVE);
+        const i64 k1 = q < nrw ? k1s : k0;
+        double t = 0.0;
+        for (i64 k = k0 + ST_VEC * sl; k < k1; k += ST_VEC * SUB) {
+            u32 cc[ST_VEC];
+            double v[ST_VEC];
+            load_entries<VT, ST_VEC>(T.cols + k, vals + k, cc, v);
+#pragma unroll
+            for (int e = 0; e < (int)ST_VEC; ++e) t += v[e] * (double)src[cc[e]];
+        }
+        t = group_sum_f64<SUB>(t);
+        const double v = __shfl(t, ((lane - qb) * SUB) & (HCI_WAVE - 1), HCI_WAVE);
+        if (lane >= qb && lane < qb + GROUPS) acc += v;
+    }
+    return acc;
+}
+
+template <class VT, class CT, int SUB>
+__global__ void __launch_bounds__(ST_BLOCK) st_spmv_g_kernel(SpaceView S, StView T,
+                                                             const VT* __restrict__ vals,
+                                                             const CT* __restrict__ cpb,
+                                                             double* __restrict__ sigma) {
+    extern __shared__ __align__(16) unsigned char st_smem[];
+    CT* stage = reinterpret_cast<CT*>(st_smem);
+    __shared__ u32 sh[3];
+    const u32 tid = threadIdx.x;
+    const int lane = lane_id();
+    const u32 wave = tid / HCI_WAVE;
+    if (tid == 0) {
+        const u32 w = blockIdx.x;
+        u32 lo = 0, hi = (u32)T.nub - 1u;
+        while (lo < hi) {
+            const u32 mid = (lo + hi + 1u) >> 1;
+            if (T.gcptr[mid] <= w) lo = mid;
+            else hi = mid - 1u;
+        }
+        const u32 k0 = S.boff[lo] + (w - T.gcptr[lo]) * ST_CHUNK;
+        sh[0] = lo;
+        sh[1] = k0;
+        sh[2] = min(k0 + ST_CHUNK, S.boff[lo + 1]);
+    }
+    __syncthreads();
+    const u32 b = sh[0], k0 = sh[1], k1 = sh[2];
+    const u32 gb = S.boff[b];
+    const u32 gsz = S.boff[b + 1] - gb;
+    const bool in_lds = gsz <= (1u << T.wlog);
+    if (in_lds) {
+        for (u32 p = tid; p < gsz; p += ST_BLOCK) stage[p] = cpb[gb + p];
+    }
+    __syncthreads();
+    const u32 nrows = k1 - k0;
+    const int nrw = wave < nrows ? (int)((nrows - wave + ST_WAVES - 1) / ST_WAVES) : 0;
+    const bool has = lane < nrw;
+    const u32 i = has ? S.permb[k0 + wave + ST_WAVES * (u32)lane] : 0u;
+    i64 mk0 = 0, mk1 = 0;
+    if (has) {
+        const i64 rs = T.rowptr[i];
+        mk0 = rs + T.segoff[T.rsb[i] + T.nseg[S.ia[i]] - 1];
+        mk1 = T.rowptr[i + 1];
+    }
+    const double acc = in_lds ? g_rows<VT, CT, SUB, true>(T, vals, stage, mk0, mk1, nrw, lane)
+                              : g_rows<VT, CT, SUB, false>(T, vals, cpb + gb, mk0, mk1, nrw, lane);
+    if (has) sigma[i] += acc;
+}
+
+constexpr int ST_SUB = 32;
+
+template <class VT, class CT>
+void launch_spmv(hci_ctx_s* ctx, Space* sp, const char* name, const char* gname, const VT* vals,
+                 const CT* cx, const CT* cpb, const double* c, double* sigma, hipStream_t s) {
+    const size_t shmem = sizeof(CT) << sp->st_wlog;
+    auto kern = st_spmv_kernel<VT, CT, ST_SUB>;
+    auto gkern = st_spmv_g_kernel<VT, CT, ST_SUB>;
+    HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+    HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(gkern),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+    HCI_LAUNCH(ctx, name, s, kern, sp->st_nchunk, ST_BLOCK, shmem, space_view(*sp, ctx->n),
+               st_view(*sp), vals, cx, c, sp->hdiag.as<double>(), sigma);
+    HCI_LAUNCH(ctx, gname, s, gkern, sp->st_gnchunk, ST_BLOCK, shmem, space_view(*sp, ctx->n),
+               st_view(*sp), vals, cpb, sigma);
+}
+
+}  // namespace
+
+bool staged_prepare(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
+    const int wlog = ctx->stage_wlog;
+    if (wlog == 0 || sp->N < 1) return false;
+    int dev = 0, max_shared = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    HIP_CHECK(hipDeviceGetAttribute(&max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if ((i64)sizeof(double) << wlog > (i64)max_shared) return false;
+    const i64 N = sp->N, nua = sp->nua, nub = sp->nub;
+    SpaceView S = space_view(*sp, ctx->n);
+    sp->st_wlog = (u32)wlog;
+    sp->st_xpos = dev_alloc(ctx, sizeof(u32) * (nua + sp->n_as), s);
+    sp->st_len = dev_alloc(ctx, sizeof(u32) * nua, s);
+    sp->st_nseg = dev_alloc(ctx, sizeof(u32) * nua, s);
+    DevMem nchunk = dev_alloc(ctx, sizeof(u32) * (nua + 1), s);
+    DevMem gnchunk = dev_alloc(ctx, sizeof(u32) * (nub + 1), s);
+    HIP_CHECK(hipMemsetAsync(gnchunk.as<u32>() + nub, 0, sizeof(u32), s));
+    DevMem flags = dev_alloc(ctx, sizeof(u64) * 3, s);
+    HIP_CHECK(hipMemsetAsync(flags.ptr, 0, sizeof(u64) * 3, s));
+    HIP_CHECK(hipMemsetAsync(nchunk.as<u32>() + nua, 0, sizeof(u32), s));
+    const i64 m = nua > nub ? nua : nub;
+    HCI_LAUNCH(ctx, "st_meta", s, st_meta_kernel, ceil_div(m, 256), 256, 0, S, (u32)wlog,
+               sp->st_xpos.as<u32>(), sp->st_len.as<u32>(), sp->st_nseg.as<u32>(), nchunk.as<u32>(),
+               gnchunk.as<u32>(), nua, nub, (unsigned long long*)flags.as<u64>());
+    u64 fl[3];
+    HIP_CHECK(hipMemcpyAsync(fl, flags.ptr, sizeof(fl), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (fl[0] != 0 || fl[1] != 0) {
+        sp->st_xpos.release();
+        sp->st_len.release();
+        sp->st_nseg.release();
+        return false;
+    }
+    sp->st_cptr = dev_alloc(ctx, sizeof(u32) * (nua + 1), s);
+    scan_u32_to_u32(ctx, nchunk.as<u32>(), sp->st_cptr.as<u32>(), nua + 1, s);
+    sp->st_nchunk = read_scalar(sp->st_cptr.as<u32>() + nua, s);
+    sp->st_gcptr = dev_alloc(ctx, sizeof(u32) * (nub + 1), s);
+    scan_u32_to_u32(ctx, gnchunk.as<u32>(), sp->st_gcptr.as<u32>(), nub + 1, s);
+    sp->st_gnchunk = read_scalar(sp->st_gcptr.as<u32>() + nub, s);
+    // segment slots per row
+    DevMem rn = dev_alloc(ctx, sizeof(u32) * (N + 1), s);
+    HCI_LAUNCH(ctx, "st_row_nseg", s, st_row_nseg_kernel, ceil_div(N + 1, 256), 256, 0,
+               sp->ia.as<u32>(), sp->st_nseg.as<u32>(), N, rn.as<u32>());
+    sp->st_rsb = dev_alloc(ctx, sizeof(i64) * (N + 1), s);
+    scan_u32_to_i64(ctx, rn.as<u32>(), sp->st_rsb.as<i64>(), N + 1, s);
+    const i64 nslots = read_scalar(sp->st_rsb.as<i64>() + N, s);
+    sp->st_segoff = dev_alloc(ctx, sizeof(u32) * (nslots > 0 ? nslots : 1), s);
+    sp->st_segcnt = dev_alloc(ctx, sizeof(u32) * (nslots > 0 ? nslots : 1), s);
+    // count pass
+    DevMem counts = dev_alloc(ctx, sizeof(u32) * (N + 1), s);
+    HIP_CHECK(hipMemsetAsync(counts.as<u32>() + N, 0, sizeof(u32), s));
+    HCI_LAUNCH(ctx, "conn_count", s, st_count_kernel, ceil_div(N, ST_ROWS_PER_BLOCK), ST_ROW_BLOCK, 0,
+               S, st_view(*sp), counts.as<u32>(), sp->st_segoff.as<u32>(),
+               sp->st_segcnt.as<u32>());
+    sp->st_rowptr = dev_alloc(ctx, sizeof(i64) * (N + 1), s);
+    scan_u32_to_i64(ctx, counts.as<u32>(), sp->st_rowptr.as<i64>(), N + 1, s);
+    sp->st_nnz = read_scalar(sp->st_rowptr.as<i64>() + N, s);
+    // connections without padding: sum of the segment counts
+    DevMem total = dev_alloc(ctx, sizeof(u64), s);
+    HIP_CHECK(hipMemsetAsync(total.ptr, 0, sizeof(u64), s));
+    HCI_LAUNCH(ctx, "conn_total", s, st_sum_kernel, ceil_div(nslots, 256), 256, 0,
+               sp->st_segcnt.as<u32>(), nslots, (unsigned long long*)total.as<u64>());
+    sp->nnz_off = (i64)read_scalar(total.as<u64>(), s);
+    sp->layout = 2;
+    return true;
+}
+
+void staged_ensure_vals(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s) {
+    const bool f32 = precision == HCI_FP32_MIXED;
+    if (f32 ? sp->st_have32 : sp->st_have64) return;
+    const i64 nnz = sp->st_nnz;
+    SpaceView S = space_view(*sp, ctx->n);
+    const i64 grid = ceil_div(sp->N, ST_ROWS_PER_BLOCK);
+    if (!sp->st_cols.ptr) {
+        sp->st_cols = dev_alloc(ctx, sizeof(u16) * (nnz > 0 ? nnz : 1), s);
+        DevMem bad = dev_alloc(ctx, sizeof(u64), s);
+        HIP_CHECK(hipMemsetAsync(bad.ptr, 0, sizeof(u64), s));
+        HCI_LAUNCH(ctx, "csr_cols", s, st_cols_kernel, grid, ST_ROW_BLOCK, 0, S, st_view(*sp),
+                   sp->st_cols.as<u16>(), (unsigned long long*)bad.as<u64>());
+        const u64 nbad = read_scalar(bad.as<u64>(), s);
+        HCI_REQUIRE(nbad == 0, HCI_E_HIP,
+                    "internal: " + std::to_string(nbad) + " row segments disagree with the count pass");
+    }
+    IntView I = int_view(ctx->ints);
+    if (f32) {
+        sp->st_vals32 = dev_alloc(ctx, sizeof(float) * (nnz > 0 ? nnz : 1), s);
+        HCI_LAUNCH(ctx, "csr_vals_f32", s, st_vals_kernel<float>, grid, ST_ROW_BLOCK, 0, S, I,
+                   st_view(*sp), sp->st_vals32.as<float>());
+        sp->st_have32 = true;
+    } else {
+        sp->st_vals64 = dev_alloc(ctx, sizeof(double) * (nnz > 0 ? nnz : 1), s);
+        HCI_LAUNCH(ctx, "csr_vals_f64", s, st_vals_kernel<double>, grid, ST_ROW_BLOCK, 0, S, I,
+                   st_view(*sp), sp->st_vals64.as<double>());
+        sp->st_have64 = true;
+    }
+}
+
+void staged_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int precision,
+                  hipStream_t s) {
+    staged_ensure_vals(ctx, sp, precision, s);
+    const i64 N = sp->N;
+    if (precision == HCI_FP32_MIXED) {
+        if (!sp->c32.ptr) sp->c32 = dev_alloc(ctx, sizeof(float) * N, s);
+        if (!sp->cpb32.ptr) sp->cpb32 = dev_alloc(ctx, sizeof(float) * N, s);
+        HCI_LAUNCH(ctx, "c_to_f32", s, st_prep_kernel<float>, ceil_div(N, 256), 256, 0, c,
+                   sp->permb.as<u32>(), N, sp->c32.as<float>(), sp->cpb32.as<float>());
+        launch_spmv<float, float>(ctx, sp, "sigma_stored_f32", "sigma_stored_f32_g",
+                                  sp->st_vals32.as<float>(),
+                                  sp->c32.as<float>(), sp->cpb32.as<float>(), c, sigma, s);
+    } else {
+        if (!sp->cpb64.ptr) sp->cpb64 = dev_alloc(ctx, sizeof(double) * N, s);
+        HCI_LAUNCH(ctx, "c_perm_f64", s, st_prep_kernel<double>, ceil_div(N, 256), 256, 0, c,
+                   sp->permb.as<u32>(), N, (double*)nullptr, sp->cpb64.as<double>());
+        launch_spmv<double, double>(ctx, sp, "sigma_stored_f64", "sigma_stored_f64_g",
+                                    sp->st_vals64.as<double>(), c,
+                                    sp->cpb64.as<double>(), c, sigma, s);
+    }
+}
+
+void layout_info(hci_ctx_s* ctx, Space* sp, int64_t* info, hipStream_t s) {
+    for (int k = 0; k < 8; ++k) info[k] = 0;
+    info[0] = sp->layout;
+    info[1] = sp->nnz_off;
+    if (sp->layout != 2) {
+        info[2] = sp->nnz_pad;
+        return;
+    }
+    info[2] = sp->st_nnz;
+    info[3] = sp->st_wlog;
+    info[6] = sp->st_nchunk;
+    info[7] = sp->st_gnchunk;
+    DevMem total = dev_alloc(ctx, sizeof(u64), s);
+    HIP_CHECK(hipMemsetAsync(total.ptr, 0, sizeof(u64), s));
+    HCI_LAUNCH(ctx, "st_gentries", s, st_gentries_kernel, ceil_div(sp->N, 256), 256, 0,
+               space_view(*sp, ctx->n), st_view(*sp), (unsigned long long*)total.as<u64>());
+    info[4] = (i64)read_scalar(total.as<u64>(), s);
+    // entries of c staged by the product kernel: every workgroup of a bucket
+    // copies the bucket's whole stage list
+    const i64 nua = sp->nua;
+    std::vector<u32> len(nua), cptr(nua + 1);
+    HIP_CHECK(hipMemcpyAsync(len.data(), sp->st_len.ptr, sizeof(u32) * nua, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(cptr.data(), sp->st_cptr.ptr, sizeof(u32) * (nua + 1),
+                             hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    i64 staged = 0;
+    for (i64 a = 0; a < nua; ++a) staged += (i64)(cptr[a + 1] - cptr[a]) * len[a];
+    info[5] = staged;
+}

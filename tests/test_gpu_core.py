@@ -205,3 +205,59 @@ def test_ragged_sizes(lib_mod, m):
     o1, o2 = O.rdm12(n, V, c, c)
     assert np.abs(r1.cpu().numpy() - o1).max() < 1e-12
     assert np.abs(r2.cpu().numpy() - o2).max() < 1e-12
+
+
+def _layout_space(name):
+    if name == "cas8":
+        w = hs.WORKLOADS["cas8"]
+        h, g = hs.workload_integrals(w)
+        return 8, 4, 4, h, g, hs.full_space(8, 4, 4)
+    if name == "n12":
+        h, g = hs.make_integrals(12, 36, 12)
+        return 12, 6, 5, h, g, hs.random_dets(12, 6, 5, 3000, seed=12, bias=0.15)
+    # (10e,10o) full space: stage lists of 6552 entries, more than 63
+    # windows of 64, so the staged layout declines and plain CSR is used
+    h, g = hs.make_integrals(10, 30, 10)
+    return 10, 5, 5, h, g, hs.full_space(10, 5, 5)
+
+
+@pytest.mark.parametrize("space,wlog", [("cas8", 0), ("cas8", 6), ("cas8", 8), ("cas8", 13),
+                                        ("n12", 0), ("n12", 6), ("n12", 13), ("fci10", 6)])
+def test_stored_layouts(lib_mod, space, wlog):
+    """Plain CSR (window 0) and the alpha-bucket-staged layout at several
+    window sizes (2^6 splits the stage lists into many windows) give the
+    oracle's products in both precisions and the oracle's pair count."""
+    n, na, nb, h, g, V = _layout_space(space)
+    c = hs.random_coeffs(len(V), 31)
+    ref = O.sigma(h, g, V, c)
+    ctx = lib_mod.HCIContext(h, g, na, nb)
+    ctx.set_stage_window(wlog)
+    print(f"[layout {space} |V|={len(V)} wlog={wlog}]", flush=True)
+    assert ctx.connections(V) == int(O.row_counts(n, V).sum())
+    for prec, tol in [("fp64", 1e-12), ("fp32_mixed", 1e-6), ("fp64", 1e-12)]:
+        out = ctx.sigma(V, c, precision=prec, mode="stored").cpu().numpy()
+        assert rel_err(out, ref) < tol, prec
+    ctx.close()
+
+
+def test_stage_window_rejects_bad_values(cas8, lib_mod):
+    ctx = cas8["ctx"]
+    for bad in [-1, 1, 5, 17]:
+        assert lib_mod._lib.lib().hci_ctx_set_stage_window(ctx.handle, bad) == -1
+
+
+@pytest.mark.parametrize("n,na,nb,m", [(20, 10, 9, 500), (24, 12, 12, 300), (44, 22, 22, 20)])
+def test_rdm_larger_orbital_counts(lib_mod, n, na, nb, m):
+    """Density matrices where the on-chip accumulators shrink (n = 20: no
+    same-spin spectator block; n = 24: no alpha-double slots) or do not fit
+    (n = 44: per-pair global accumulation), against the oracle."""
+    h, g = hs.make_integrals(n, 3 * n, n)
+    V = hs.random_dets(n, na, nb, m, seed=n, bias=0.1)
+    bra = hs.random_coeffs(len(V), n)
+    ket = hs.random_coeffs(len(V), n + 1)
+    print(f"[rdm n={n} |V|={len(V)}]", flush=True)
+    ctx = lib_mod.HCIContext(h, g, na, nb)
+    r1, r2 = ctx.rdm12(V, bra, ket)
+    o1, o2 = O.rdm12(n, V, bra, ket)
+    assert np.abs(r1.cpu().numpy() - o1).max() < 1e-11
+    assert np.abs(r2.cpu().numpy() - o2).max() < 1e-11
