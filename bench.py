@@ -112,7 +112,7 @@ def main():
     kernels = {}
     for name in ["sigma_stored_f32", "sigma_stored_f32_g", "sigma_stored_f64", "sigma_stored_f64_g",
                  "sigma_recompute_f64", "select_walk", "csr_cols", "csr_vals_f32", "csr_vals_f64",
-                 "conn_count", "rdm_offdiag", "dv_jacobi", "dv_dots", "dv_combine"]:
+                 "conn_count", "rdm_offdiag", "dv_eig", "dv_dots", "dv_combine"]:
         n_, ms = ctx.kernel_time(name)
         if n_:
             kernels[name] = {"launches": n_, "avg_ms": ms / n_, "total_ms_per_step": ms / args.steps}

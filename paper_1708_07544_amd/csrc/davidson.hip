@@ -14,6 +14,8 @@
 // that), then restart from the Ritz vector with float64 products until the
 // float64 residual meets tol.  Restarts keep the current and the previous
 // Ritz vectors.
+#include <cfloat>
+
 #include "common.h"
 
 namespace {
@@ -101,73 +103,147 @@ __global__ void __launch_bounds__(DV_BLOCK) combine_kernel(
     if (threadIdx.x == 0) partial[blockIdx.x] = v;
 }
 
-// Lowest eigenpair of the symmetric k x k matrix G (leading dimension ldg)
-// by cyclic Jacobi rotations in one wavefront; writes out[0] = eigenvalue,
-// out[1..k] = unit eigenvector.
-__global__ void __launch_bounds__(64) jacobi_lowest_kernel(const double* __restrict__ G, int ldg,
-                                                           int k, double* __restrict__ out) {
+// Lowest eigenpair of the k x k projected matrix (upper triangle of G),
+// one wavefront: Householder reduction to tridiagonal form, the lowest
+// eigenvalue of the tridiagonal matrix by Sturm-count multisection (64 shifts
+// per round), its eigenvector by two steps of inverse iteration (LDL^T
+// factorisation shifted just below the eigenvalue), back-transformation, and
+// the Rayleigh quotient with the original matrix.  out = {theta, y[0..k)}.
+__device__ __forceinline__ double wave_min_f64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__global__ void __launch_bounds__(64) lowest_eig_kernel(const double* __restrict__ G, int ldg,
+                                                        int k, double* __restrict__ out) {
     __shared__ double A[DV_MAXK][DV_MAXK + 1];
-    __shared__ double Q[DV_MAXK][DV_MAXK + 1];
+    __shared__ double H[DV_MAXK][DV_MAXK];  // Householder vector of step j in row j
+    __shared__ double vv[DV_MAXK], pw[DV_MAXK], d[DV_MAXK], e[DV_MAXK], y[DV_MAXK];
     const int l = threadIdx.x;
-    for (int r = 0; r < k; ++r) {
-        if (l < k) {
-            // symmetrise from the upper triangle (G[j][m] holds V_j . W_m for j <= m)
-            const int lo = r < l ? r : l, hi = r < l ? l : r;
-            A[r][l] = G[lo * ldg + hi];
-            Q[r][l] = (r == l) ? 1.0 : 0.0;
+    for (int x = l; x < k * k; x += 64) {
+        const int r = x / k, c = x % k;
+        A[r][c] = G[(r < c ? r : c) * ldg + (r < c ? c : r)];
+    }
+    __syncthreads();
+    // Householder: column j's entries below the subdiagonal are annihilated
+    for (int j = 0; j + 2 < k; ++j) {
+        const int m = k - j - 1;  // trailing rows j+1 .. k-1
+        const double xi = l < m ? A[j + 1 + l][j] : 0.0;
+        const double nrm2 = wave_sum_f64(xi * xi);
+        if (nrm2 == 0.0) {  // already reduced: identity reflector
+            if (l < m) H[j][l] = 0.0;
+            __syncthreads();
+            continue;
+        }
+        const double x0 = __shfl(xi, 0, 64);
+        const double alpha = x0 >= 0.0 ? -sqrt(nrm2) : sqrt(nrm2);
+        double vi = l < m ? xi - (l == 0 ? alpha : 0.0) : 0.0;
+        const double vn = sqrt(wave_sum_f64(vi * vi));
+        vi /= vn;
+        if (l < m) {
+            H[j][l] = vi;
+            vv[l] = vi;
+        }
+        __syncthreads();
+        double pi = 0.0;
+        if (l < m)
+            for (int c = 0; c < m; ++c) pi += A[j + 1 + l][j + 1 + c] * vv[c];
+        const double K = wave_sum_f64(vi * pi);
+        if (l < m) pw[l] = pi - K * vi;
+        __syncthreads();
+        for (int x = l; x < m * m; x += 64) {
+            const int r = x / m, c = x % m;
+            A[j + 1 + r][j + 1 + c] -= 2.0 * (vv[r] * pw[c] + pw[r] * vv[c]);
+        }
+        if (l == 0) {
+            A[j + 1][j] = alpha;
+            A[j][j + 1] = alpha;
+        }
+        __syncthreads();
+    }
+    if (l < k) {
+        d[l] = A[l][l];
+        e[l] = l + 1 < k ? A[l + 1][l] : 0.0;
+    }
+    __syncthreads();
+    // Gershgorin interval of the tridiagonal matrix
+    double glo = 1e300, ghi = -1e300, scale = 0.0;
+    if (l < k) {
+        const double r = fabs(e[l]) + (l > 0 ? fabs(e[l - 1]) : 0.0);
+        glo = d[l] - r;
+        ghi = d[l] + r;
+        scale = fabs(d[l]) + r;
+    }
+    double lo = wave_min_f64(glo), hi = wave_max_f64(ghi);
+    scale = wave_max_f64(scale);
+    const double pivmin = 1e-300 + 1e-30 * scale * scale;
+    // multisection: lane l tests the shift lo + (hi - lo)(l + 1)/65
+    for (int round = 0; round < 16; ++round) {
+        if (!(hi - lo > 4.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) break;
+        const double xl = lo + (hi - lo) * (double)(l + 1) / 65.0;
+        int cnt = 0;
+        double q = 1.0;
+        for (int i = 0; i < k; ++i) {
+            q = d[i] - xl - (i > 0 ? e[i - 1] * e[i - 1] / q : 0.0);
+            if (fabs(q) < pivmin) q = -pivmin;
+            cnt += q < 0.0;
+        }
+        const u64 mask = ballot(cnt >= 1);
+        if (mask == 0) {
+            lo = __shfl(xl, 63, 64);
+        } else {
+            const int f = ctz64(mask);
+            const double xf = __shfl(xl, f, 64);
+            const double xp = __shfl(xl, f > 0 ? f - 1 : 0, 64);
+            hi = xf;
+            if (f > 0) lo = xp;
+        }
+    }
+    // inverse iteration with T - mu I positive definite (mu just below lambda)
+    if (l == 0) {  // LDL^T pivots in vv, multipliers in pw, iterate in y
+        const double mu = lo - 4.0 * DBL_EPSILON * fmax(fabs(lo), scale);
+        vv[0] = fmax(d[0] - mu, pivmin);
+        for (int i = 1; i < k; ++i) {
+            pw[i] = e[i - 1] / vv[i - 1];
+            vv[i] = fmax(d[i] - mu - pw[i] * e[i - 1], pivmin);
+        }
+        for (int i = 0; i < k; ++i) y[i] = 1.0;
+        for (int it = 0; it < 2; ++it) {
+            for (int i = 1; i < k; ++i) y[i] -= pw[i] * y[i - 1];
+            for (int i = 0; i < k; ++i) y[i] /= vv[i];
+            for (int i = k - 2; i >= 0; --i) y[i] -= pw[i + 1] * y[i + 1];
+            double nn = 0.0;
+            for (int i = 0; i < k; ++i) nn += y[i] * y[i];
+            nn = 1.0 / sqrt(nn);
+            for (int i = 0; i < k; ++i) y[i] *= nn;
         }
     }
     __syncthreads();
-    for (int sweep = 0; sweep < 30; ++sweep) {
-        double off = 0.0, dia = 0.0;
-        for (int p = 0; p < k; ++p)
-            for (int q = 0; q < k; ++q) {
-                if (p != q) off += A[p][q] * A[p][q];
-                else dia += A[p][q] * A[p][q];
-            }
-        if (off <= 1e-30 * (dia + 1e-300)) break;
-        for (int p = 0; p < k - 1; ++p) {
-            for (int q = p + 1; q < k; ++q) {
-                const double apq = A[p][q];
-                if (apq == 0.0) continue;
-                const double app = A[p][p], aqq = A[q][q];
-                const double th = (aqq - app) / (2.0 * apq);
-                const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                const double cs = 1.0 / sqrt(tt * tt + 1.0), sn = tt * cs;
-                double akp = 0, akq = 0, qp = 0, qq = 0;
-                if (l < k) {
-                    akp = A[l][p];
-                    akq = A[l][q];
-                    qp = Q[l][p];
-                    qq = Q[l][q];
-                }
-                __syncthreads();
-                if (l < k) {
-                    if (l != p && l != q) {
-                        const double np = cs * akp - sn * akq, nq = sn * akp + cs * akq;
-                        A[l][p] = np;
-                        A[p][l] = np;
-                        A[l][q] = nq;
-                        A[q][l] = nq;
-                    }
-                    Q[l][p] = cs * qp - sn * qq;
-                    Q[l][q] = sn * qp + cs * qq;
-                }
-                if (l == 0) {
-                    A[p][p] = app - tt * apq;
-                    A[q][q] = aqq + tt * apq;
-                    A[p][q] = 0.0;
-                    A[q][p] = 0.0;
-                }
-                __syncthreads();
-            }
-        }
+    // back-transformation y <- H_0 ... H_{k-3} y
+    for (int j = k - 3; j >= 0; --j) {
+        const int m = k - j - 1;
+        const double hv = l < m ? H[j][l] : 0.0;
+        const double yv = l < m ? y[j + 1 + l] : 0.0;
+        const double dot = wave_sum_f64(hv * yv);
+        if (l < m) y[j + 1 + l] = yv - 2.0 * dot * hv;
+        __syncthreads();
     }
-    int m = 0;
-    for (int p = 1; p < k; ++p)
-        if (A[p][p] < A[m][m]) m = p;
-    if (l == 0) out[0] = A[m][m];
-    if (l < k) out[1 + l] = Q[l][m];
+    // Rayleigh quotient with the original matrix
+    const double yl = l < k ? y[l] : 0.0;
+    double ay = 0.0;
+    if (l < k)
+        for (int c = 0; c < k; ++c) ay += G[(l < c ? l : c) * ldg + (l < c ? c : l)] * y[c];
+    const double nrm = wave_sum_f64(yl * yl);
+    const double th = wave_sum_f64(yl * ay) / nrm;
+    if (l == 0) out[0] = th;
+    if (l < k) out[1 + l] = yl / sqrt(nrm);
 }
 
 __global__ void gram_column_kernel(double* __restrict__ G, int ldg, int k,
@@ -335,7 +411,7 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
         }
         bool phase_done = false;
         while (true) {
-            HCI_LAUNCH(ctx, "dv_jacobi", s, jacobi_lowest_kernel, 1, 64, 0, G.as<double>(), DV_MAXK,
+            HCI_LAUNCH(ctx, "dv_eig", s, lowest_eig_kernel, 1, 64, 0, G.as<double>(), DV_MAXK,
                        k, ritz.as<double>());
             std::swap(xc, xp);
             std::swap(wc, wp);

@@ -350,6 +350,48 @@ __global__ void st_gentries_kernel(SpaceView S, StView T, unsigned long long* __
     if (lane_id() == 0 && v) atomicAdd(out, (unsigned long long)v);
 }
 
+// Both precisions in one element pass (the float32-mixed solver refines
+// with float64 products, so both are needed).
+__global__ void __launch_bounds__(ST_ROW_BLOCK) st_vals_both_kernel(SpaceView S, IntView I, StView T,
+                                                                    float* __restrict__ v32,
+                                                                    double* __restrict__ v64) {
+    const i64 i = (i64)blockIdx.x * ST_ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
+    if (i >= S.N) return;
+    const u32 a = S.ia[i];
+    const u32 ns = T.nseg[a];
+    const u32 t0 = S.as_ptr[a];
+    const u32 nr = 1u + S.as_ptr[a + 1] - t0;
+    const u32* xs = T.xpos + t0 + a;
+    const u64 ai = S.alpha[i], bi = S.beta[i];
+    const i64 rs = T.rowptr[i];
+    const u32 rl = (u32)(T.rowptr[i + 1] - rs);
+    const i64 sb = T.rsb[i];
+    const u32 gb = S.boff[S.ib[i]];
+    for (u32 s = 0; s < ns; ++s) {
+        const i64 k0 = rs + T.segoff[sb + s];
+        const i64 k1 = rs + (s + 1 < ns ? T.segoff[sb + s + 1] : rl);
+        const i64 kr = k0 + T.segcnt[sb + s];
+        for (i64 k = k0 + lane_id(); k < k1; k += HCI_WAVE) {
+            double v = 0.0;
+            if (k < kr) {
+                const u32 col = T.cols[k];
+                u32 j;
+                if (s + 1 < ns) {
+                    const u32 P = (s << T.wlog) + col;
+                    const u32 e = upper_bound_u32(xs, nr, P) - 1u;
+                    const u32 a2 = e == 0 ? a : S.as_idx[t0 + e - 1];
+                    j = S.aoff[a2] + (P - xs[e]);
+                } else {
+                    j = S.permb[gb + col];
+                }
+                v = hij_f64(I, ai, bi, S.alpha[j], S.beta[j]);
+            }
+            v32[k] = (float)v;
+            v64[k] = v;
+        }
+    }
+}
+
 // c (float64) -> the product's alpha-major and beta-major copies.
 template <class CT>
 __global__ void st_prep_kernel(const double* __restrict__ c, const u32* __restrict__ permb, i64 N,
@@ -698,7 +740,14 @@ void staged_ensure_vals(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s)
                     "internal: " + std::to_string(nbad) + " row segments disagree with the count pass");
     }
     IntView I = int_view(ctx->ints);
-    if (f32) {
+    if (f32 && !sp->st_have64 && nnz * (i64)(2 + 4 + 8) <= ctx->stored_budget) {
+        sp->st_vals32 = dev_alloc(ctx, sizeof(float) * (nnz > 0 ? nnz : 1), s);
+        sp->st_vals64 = dev_alloc(ctx, sizeof(double) * (nnz > 0 ? nnz : 1), s);
+        HCI_LAUNCH(ctx, "csr_vals_f32", s, st_vals_both_kernel, grid, ST_ROW_BLOCK, 0, S, I,
+                   st_view(*sp), sp->st_vals32.as<float>(), sp->st_vals64.as<double>());
+        sp->st_have32 = true;
+        sp->st_have64 = true;
+    } else if (f32) {
         sp->st_vals32 = dev_alloc(ctx, sizeof(float) * (nnz > 0 ? nnz : 1), s);
         HCI_LAUNCH(ctx, "csr_vals_f32", s, st_vals_kernel<float>, grid, ST_ROW_BLOCK, 0, S, I,
                    st_view(*sp), sp->st_vals32.as<float>());
