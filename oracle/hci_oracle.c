@@ -384,18 +384,21 @@ void orc_rdm12(int n, const u64* V, long nv, const double* bra, const double* ke
             }
         }
         for (int qs = 0; qs < ns; ++qs) {
+            so_t d1 = d0;
+            int s1 = so_annihilate(&d1, n, qs);
+            if (!s1) continue;
             for (int ss = 0; ss < ns; ++ss) {
+                so_t d2 = d1;
+                int s2 = so_annihilate(&d2, n, ss);
+                if (!s2) continue;
                 for (int rs = 0; rs < ns; ++rs) {
                     if ((ss < n) != (rs < n)) continue;
+                    so_t d3 = d2;
+                    int s3 = so_create(&d3, n, rs);
+                    if (!s3) continue;
                     for (int ps = 0; ps < ns; ++ps) {
                         if ((qs < n) != (ps < n)) continue;
-                        so_t d = d0;
-                        int s1 = so_annihilate(&d, n, qs);
-                        if (!s1) continue;
-                        int s2 = so_annihilate(&d, n, ss);
-                        if (!s2) continue;
-                        int s3 = so_create(&d, n, rs);
-                        if (!s3) continue;
+                        so_t d = d3;
                         int s4 = so_create(&d, n, ps);
                         if (!s4) continue;
                         long i = orc_find(V, nv, d.lo, d.hi);
@@ -569,19 +572,30 @@ void orc_pair_rdm_add(int n, u64 xa, u64 xb, u64 ya, u64 yb, double w, double* r
             rdm1[(size_t)(ps % n) * n + (qs % n)] += w * s1 * s2;
         }
     if (!rdm2) return;
-    for (int qs = 0; qs < ns; ++qs)
-        for (int ss = 0; ss < ns; ++ss)
+    /* a+_p a+_r a_s a_q |y>: after the two annihilations the remaining
+     * orbitals must all be occupied in x, and each creation must fill an
+     * orbital occupied in x, or the result cannot be x (those branches
+     * contribute exactly zero and are skipped) */
+    so_t xt = {xa, xb};
+    for (int qs = 0; qs < ns; ++qs) {
+        so_t d1 = d0;
+        int s1 = so_annihilate(&d1, n, qs);
+        if (!s1) continue;
+        for (int ss = 0; ss < ns; ++ss) {
+            so_t d2 = d1;
+            int s2 = so_annihilate(&d2, n, ss);
+            if (!s2) continue;
+            if ((d2.lo & ~xa) || (d2.hi & ~xb)) continue;
             for (int rs = 0; rs < ns; ++rs) {
                 if ((ss < n) != (rs < n)) continue;
+                if (!so_test(&xt, n, rs)) continue;
+                so_t d3 = d2;
+                int s3 = so_create(&d3, n, rs);
+                if (!s3) continue;
                 for (int ps = 0; ps < ns; ++ps) {
                     if ((qs < n) != (ps < n)) continue;
-                    so_t d = d0;
-                    int s1 = so_annihilate(&d, n, qs);
-                    if (!s1) continue;
-                    int s2 = so_annihilate(&d, n, ss);
-                    if (!s2) continue;
-                    int s3 = so_create(&d, n, rs);
-                    if (!s3) continue;
+                    if (!so_test(&xt, n, ps)) continue;
+                    so_t d = d3;
                     int s4 = so_create(&d, n, ps);
                     if (!s4) continue;
                     if (d.lo != xa || d.hi != xb) continue;
@@ -589,4 +603,6 @@ void orc_pair_rdm_add(int n, u64 xa, u64 xb, u64 ya, u64 yb, double w, double* r
                     rdm2[(((size_t)p * n + q) * n + r) * n + s] += w * (double)(s1 * s2 * s3 * s4);
                 }
             }
+        }
+    }
 }
