@@ -193,9 +193,10 @@ std::unique_ptr<Pt2State> pt2_run(hci_ctx_s* ctx, const u64* dets, i64 N, const 
     IntView I = int_view(ctx->ints);
     // hash set of V for the "outside V" test
     const bool packed = n <= 31;
-    DevMem flags = dev_alloc(ctx, sizeof(u64) * 4, s);
+    // flags: [1] overflow, [2..3] interned alpha / beta strings, [4] fill mismatch
+    DevMem flags = dev_alloc(ctx, sizeof(u64) * 5, s);
     unsigned long long* fl = (unsigned long long*)flags.as<u64>();
-    HIP_CHECK(hipMemsetAsync(flags.ptr, 0, sizeof(u64) * 4, s));
+    HIP_CHECK(hipMemsetAsync(flags.ptr, 0, sizeof(u64) * 5, s));
     const i64 slots = p2(std::max<i64>(4 * N, 1 << 16));
     DevMem table = dev_alloc(ctx, sizeof(u64) * slots, s);
     DevMem sa, sb;
@@ -243,8 +244,8 @@ std::unique_ptr<Pt2State> pt2_run(hci_ctx_s* ctx, const u64* dets, i64 N, const 
     }
     HCI_LAUNCH(ctx, "pt2_fill_pairs", s, pt_fill_kernel, ceil_div(N, PT_ROWS), PT_BLOCK, 0, T, I, H,
                dets, c, N, eps2, hbm, st->off.as<i64>(), st->a_hi.as<u64>(), st->a_lo.as<u64>(),
-               st->idx.as<u32>(), st->hai.as<double>(), fl + 3);
-    HCI_REQUIRE(read_scalar(flags.as<u64>() + 3, s) == 0, HCI_E_HIP,
+               st->idx.as<u32>(), st->hai.as<double>(), fl + 4);
+    HCI_REQUIRE(read_scalar(flags.as<u64>() + 4, s) == 0, HCI_E_HIP,
                 "internal: pt2 fill disagrees with the count pass");
     // stable sort of a copy of the keys, payload = pair position
     DevMem khi = dev_alloc(ctx, sizeof(u64) * M, s), klo = dev_alloc(ctx, sizeof(u64) * M, s);
