@@ -542,12 +542,20 @@ __global__ void __launch_bounds__(ST_BLOCK) st_spmv_kernel(SpaceView S, StView T
             const i64 k1s = __shfl(mk1, q, HCI_WAVE);
             const i64 k1 = q < nrw ? k1s : k0;
             double t = 0.0;
-            for (i64 k = k0 + ST_VEC * sl; k < k1; k += ST_VEC * SUB) {
-                u32 cc[ST_VEC];
-                double v[ST_VEC];
+            // two steps per trip: both loads in flight before the first use
+            for (i64 k = k0 + ST_VEC * sl; k < k1; k += 2 * ST_VEC * SUB) {
+                u32 cc[ST_VEC], cc2[ST_VEC];
+                double v[ST_VEC], v2[ST_VEC];
+                const i64 k2 = k + ST_VEC * SUB;
+                const bool two = k2 < k1;
                 load_entries<VT, ST_VEC>(T.cols + k, vals + k, cc, v);
+                if (two) load_entries<VT, ST_VEC>(T.cols + k2, vals + k2, cc2, v2);
 #pragma unroll
                 for (int e = 0; e < (int)ST_VEC; ++e) t += v[e] * (double)stage[cc[e]];
+                if (two) {
+#pragma unroll
+                    for (int e = 0; e < (int)ST_VEC; ++e) t += v2[e] * (double)stage[cc2[e]];
+                }
             }
             t = group_sum_f64<SUB>(t);
             const double v = __shfl(t, ((lane - qb) * SUB) & (HCI_WAVE - 1), HCI_WAVE);
@@ -575,12 +583,19 @@ __device__ __forceinline__ double g_rows(const StView& T, const VT* __restrict__
         const i64 k1s = __shfl(mk1, q, HCI_WAVE);
         const i64 k1 = q < nrw ? k1s : k0;
         double t = 0.0;
-        for (i64 k = k0 + ST_VEC * sl; k < k1; k += ST_VEC * SUB) {
-            u32 cc[ST_VEC];
-            double v[ST_VEC];
+        for (i64 k = k0 + ST_VEC * sl; k < k1; k += 2 * ST_VEC * SUB) {
+            u32 cc[ST_VEC], cc2[ST_VEC];
+            double v[ST_VEC], v2[ST_VEC];
+            const i64 k2 = k + ST_VEC * SUB;
+            const bool two = k2 < k1;
             load_entries<VT, ST_VEC>(T.cols + k, vals + k, cc, v);
+            if (two) load_entries<VT, ST_VEC>(T.cols + k2, vals + k2, cc2, v2);
 #pragma unroll
             for (int e = 0; e < (int)ST_VEC; ++e) t += v[e] * (double)src[cc[e]];
+            if (two) {
+#pragma unroll
+                for (int e = 0; e < (int)ST_VEC; ++e) t += v2[e] * (double)src[cc2[e]];
+            }
         }
         t = group_sum_f64<SUB>(t);
         const double v = __shfl(t, ((lane - qb) * SUB) & (HCI_WAVE - 1), HCI_WAVE);
