@@ -222,6 +222,7 @@ struct Space {
     DevMem st_cptr;       // u32 [nua + 1]: first workgroup of each bucket
     DevMem st_gcptr;      // u32 [nub + 1]: first workgroup of each beta group
     i64 st_gnchunk = 0;   // workgroups of the beta-group product
+    i64 st_gmax = 0;      // largest beta group
     DevMem st_rsb;        // i64 [N + 1]: first segment slot of each row
     DevMem st_segoff;     // u32 [st_rsb[N]]: segment starts within the row (multiples of 4)
     DevMem st_segcnt;     // u32 [st_rsb[N]]: entries of each segment before padding

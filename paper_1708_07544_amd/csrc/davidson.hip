@@ -28,7 +28,6 @@ constexpr int DV_KMAX = 24;   // subspace size before a thick restart
 __global__ void __launch_bounds__(DV_BLOCK) dots_kernel(const double* __restrict__ X, i64 ld, int k,
                                                         const double* __restrict__ t, i64 N,
                                                         double* __restrict__ partial, int nblk) {
-    __shared__ double lds[DV_BLOCK / 64];
     double acc[DV_MAXK];
 #pragma unroll
     for (int j = 0; j < DV_MAXK; ++j) acc[j] = 0.0;
@@ -38,9 +37,23 @@ __global__ void __launch_bounds__(DV_BLOCK) dots_kernel(const double* __restrict
         for (int j = 0; j < DV_MAXK; ++j)
             if (j < k) acc[j] += X[(i64)j * ld + i] * ti;
     }
-    for (int j = 0; j < k; ++j) {
-        const double v = block_sum_f64<DV_BLOCK>(acc[j], lds);
-        if (threadIdx.x == 0) partial[(i64)j * nblk + blockIdx.x] = v;
+    // wavefront sums of every column, one exchange through LDS, then a
+    // fixed-order sum over the block's wavefronts
+    __shared__ double wsum[DV_BLOCK / 64][DV_MAXK];
+    const int w = threadIdx.x / 64;
+#pragma unroll
+    for (int j = 0; j < DV_MAXK; ++j) {
+        if (j < k) {
+            const double v = wave_sum_f64(acc[j]);
+            if (lane_id() == 0) wsum[w][j] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < k) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < DV_BLOCK / 64; ++q) v += wsum[q][threadIdx.x];
+        partial[(i64)threadIdx.x * nblk + blockIdx.x] = v;
     }
 }
 

@@ -24,6 +24,8 @@
 // Entries of a row are grouped by segment (windows in order, G last); the
 // layout is built by a count pass, a scan, an integer column pass and a
 // separate element pass per precision.
+#include <algorithm>
+
 #include "slater.h"
 
 namespace {
@@ -35,6 +37,9 @@ constexpr int ST_ROWS_PER_BLOCK = ST_ROW_BLOCK / HCI_WAVE;
 constexpr int ST_BLOCK = 1024;     // product: 16 wavefronts
 constexpr int ST_WAVES = ST_BLOCK / HCI_WAVE;
 constexpr u32 ST_CHUNK = 64 * ST_WAVES;  // rows per workgroup (64 per wavefront)
+constexpr int GT_BLOCK = 512;      // beta-group product: 8 wavefronts
+constexpr int GT_WAVES = GT_BLOCK / HCI_WAVE;
+constexpr u32 GT_CHUNK = 64 * GT_WAVES;
 constexpr u32 ST_MAX_SEG = 64;           // segments per row (lane-held cursors)
 constexpr u32 ST_MAX_GROUP = 65536;      // beta-group offsets are u16
 constexpr u32 ST_VEC = 8;                // entries per lane per load; segments padded to it
@@ -75,7 +80,7 @@ StView st_view(const Space& s) {
 // One thread per bucket: stage ranges, stage length, segment count and
 // workgroup count; one thread per beta group: group size limit.  flags[0]
 // counts buckets with too many segments, flags[1] oversized beta groups,
-// flags[2] holds the largest stage length.
+// flags[2] holds the largest stage length, flags[3] the largest beta group.
 __global__ void st_meta_kernel(SpaceView S, u32 wlog, u32* __restrict__ xpos, u32* __restrict__ len,
                                u32* __restrict__ nseg, u32* __restrict__ nchunk,
                                u32* __restrict__ gnchunk, i64 nua, i64 nub,
@@ -101,7 +106,8 @@ __global__ void st_meta_kernel(SpaceView S, u32 wlog, u32* __restrict__ xpos, u3
     }
     if (t < nub) {
         const u32 gs = S.boff[t + 1] - S.boff[t];
-        gnchunk[t] = (gs + ST_CHUNK - 1) / ST_CHUNK;
+        gnchunk[t] = (gs + GT_CHUNK - 1) / GT_CHUNK;
+        atomicMax(&flags[3], (unsigned long long)gs);
         if (gs > ST_MAX_GROUP) atomicAdd(&flags[1], 1ull);
     }
 }
@@ -567,7 +573,7 @@ __global__ void __launch_bounds__(ST_BLOCK) st_spmv_kernel(SpaceView S, StView T
 
 // Beta-group product: in beta-major order the alpha doubles with the same
 // beta string form diagonal blocks, one per beta group.  A workgroup owns up
-// to ST_CHUNK rows of one group, copies the group's slice of the beta-major c
+// to GT_CHUNK rows of one group, copies the group's slice of the beta-major c
 // into LDS when it fits the window (else gathers it from global memory) and
 // adds each row's G segment to sigma (after the staged kernel).
 template <class VT, class CT, int SUB, bool LDS>
@@ -605,9 +611,9 @@ __device__ __forceinline__ double g_rows(const StView& T, const VT* __restrict__
 }
 
 template <class VT, class CT, int SUB>
-__global__ void __launch_bounds__(ST_BLOCK) st_spmv_g_kernel(SpaceView S, StView T,
+__global__ void __launch_bounds__(GT_BLOCK) st_spmv_g_kernel(SpaceView S, StView T,
                                                              const VT* __restrict__ vals,
-                                                             const CT* __restrict__ cpb,
+                                                             const CT* __restrict__ cpb, u32 cap,
                                                              double* __restrict__ sigma) {
     extern __shared__ __align__(16) unsigned char st_smem[];
     CT* stage = reinterpret_cast<CT*>(st_smem);
@@ -623,24 +629,24 @@ __global__ void __launch_bounds__(ST_BLOCK) st_spmv_g_kernel(SpaceView S, StView
             if (T.gcptr[mid] <= w) lo = mid;
             else hi = mid - 1u;
         }
-        const u32 k0 = S.boff[lo] + (w - T.gcptr[lo]) * ST_CHUNK;
+        const u32 k0 = S.boff[lo] + (w - T.gcptr[lo]) * GT_CHUNK;
         sh[0] = lo;
         sh[1] = k0;
-        sh[2] = min(k0 + ST_CHUNK, S.boff[lo + 1]);
+        sh[2] = min(k0 + GT_CHUNK, S.boff[lo + 1]);
     }
     __syncthreads();
     const u32 b = sh[0], k0 = sh[1], k1 = sh[2];
     const u32 gb = S.boff[b];
     const u32 gsz = S.boff[b + 1] - gb;
-    const bool in_lds = gsz <= (1u << T.wlog);
+    const bool in_lds = gsz <= cap;
     if (in_lds) {
-        for (u32 p = tid; p < gsz; p += ST_BLOCK) stage[p] = cpb[gb + p];
+        for (u32 p = tid; p < gsz; p += GT_BLOCK) stage[p] = cpb[gb + p];
     }
     __syncthreads();
     const u32 nrows = k1 - k0;
-    const int nrw = wave < nrows ? (int)((nrows - wave + ST_WAVES - 1) / ST_WAVES) : 0;
+    const int nrw = wave < nrows ? (int)((nrows - wave + GT_WAVES - 1) / GT_WAVES) : 0;
     const bool has = lane < nrw;
-    const u32 i = has ? S.permb[k0 + wave + ST_WAVES * (u32)lane] : 0u;
+    const u32 i = has ? S.permb[k0 + wave + GT_WAVES * (u32)lane] : 0u;
     i64 mk0 = 0, mk1 = 0;
     if (has) {
         const i64 rs = T.rowptr[i];
@@ -658,16 +664,20 @@ template <class VT, class CT>
 void launch_spmv(hci_ctx_s* ctx, Space* sp, const char* name, const char* gname, const VT* vals,
                  const CT* cx, const CT* cpb, const double* c, double* sigma, hipStream_t s) {
     const size_t shmem = sizeof(CT) << sp->st_wlog;
+    // the beta-group kernel stages whole groups up to the largest one (groups
+    // beyond the window gather from global memory)
+    const u32 cap = (u32)std::min<i64>((i64)1 << sp->st_wlog, sp->st_gmax);
+    const size_t gshmem = sizeof(CT) * (cap > 0 ? cap : 1);
     auto kern = st_spmv_kernel<VT, CT, ST_SUB>;
     auto gkern = st_spmv_g_kernel<VT, CT, ST_SUB>;
     HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
     HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(gkern),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)gshmem));
     HCI_LAUNCH(ctx, name, s, kern, sp->st_nchunk, ST_BLOCK, shmem, space_view(*sp, ctx->n),
                st_view(*sp), vals, cx, c, sp->hdiag.as<double>(), sigma);
-    HCI_LAUNCH(ctx, gname, s, gkern, sp->st_gnchunk, ST_BLOCK, shmem, space_view(*sp, ctx->n),
-               st_view(*sp), vals, cpb, sigma);
+    HCI_LAUNCH(ctx, gname, s, gkern, sp->st_gnchunk, GT_BLOCK, gshmem, space_view(*sp, ctx->n),
+               st_view(*sp), vals, cpb, cap, sigma);
 }
 
 }  // namespace
@@ -688,15 +698,16 @@ bool staged_prepare(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
     DevMem nchunk = dev_alloc(ctx, sizeof(u32) * (nua + 1), s);
     DevMem gnchunk = dev_alloc(ctx, sizeof(u32) * (nub + 1), s);
     HIP_CHECK(hipMemsetAsync(gnchunk.as<u32>() + nub, 0, sizeof(u32), s));
-    DevMem flags = dev_alloc(ctx, sizeof(u64) * 3, s);
-    HIP_CHECK(hipMemsetAsync(flags.ptr, 0, sizeof(u64) * 3, s));
+    DevMem flags = dev_alloc(ctx, sizeof(u64) * 4, s);
+    HIP_CHECK(hipMemsetAsync(flags.ptr, 0, sizeof(u64) * 4, s));
     HIP_CHECK(hipMemsetAsync(nchunk.as<u32>() + nua, 0, sizeof(u32), s));
     const i64 m = nua > nub ? nua : nub;
     HCI_LAUNCH(ctx, "st_meta", s, st_meta_kernel, ceil_div(m, 256), 256, 0, S, (u32)wlog,
                sp->st_xpos.as<u32>(), sp->st_len.as<u32>(), sp->st_nseg.as<u32>(), nchunk.as<u32>(),
                gnchunk.as<u32>(), nua, nub, (unsigned long long*)flags.as<u64>());
-    u64 fl[3];
+    u64 fl[4];
     HIP_CHECK(hipMemcpyAsync(fl, flags.ptr, sizeof(fl), hipMemcpyDeviceToHost, s));
+    sp->st_gmax = (i64)fl[3];
     HIP_CHECK(hipStreamSynchronize(s));
     if (fl[0] != 0 || fl[1] != 0) {
         sp->st_xpos.release();
