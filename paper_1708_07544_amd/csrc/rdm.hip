@@ -254,9 +254,9 @@ __global__ void swap_sym_kernel(double* __restrict__ r2, int n) {
 //   alpha double (same beta): one slot per (occupied pair, empty pair) of A.
 // Beta doubles (same alpha) go to global memory directly.  All rdm2 terms are
 // the canonical half T (see single_contrib).
-constexpr int RDM_BLOCK = 512;
+constexpr int RDM_BLOCK = 1024;
 constexpr int RDM_WAVES = RDM_BLOCK / HCI_WAVE;
-constexpr u32 RDM_CHUNK = 512;
+constexpr u32 RDM_CHUNK = 1024;
 
 struct RdmPlan {
     int n, G;
