@@ -86,6 +86,19 @@ __global__ void normalize_kernel(const double* __restrict__ src, const double* _
     if (i < N) dst[i] = src[i] / sqrt(*nrm2);
 }
 
+// Normalise a new search direction without a host round trip: a direction
+// with no norm left after orthogonalisation becomes the zero vector and
+// raises *dead (the projected eigensolver then ignores it and the host
+// restarts at its next synchronisation).
+__global__ void normalize_guard_kernel(const double* __restrict__ src, const double* __restrict__ nrm2,
+                                       double* __restrict__ dst, i64 N, double* __restrict__ dead) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    const double nn = *nrm2;
+    const bool ok = nn > 1e-28;
+    if (i < N) dst[i] = ok ? src[i] / sqrt(nn) : 0.0;
+    if (i == 0 && !ok) *dead = 1.0;
+}
+
 // x = V y, w = W y, r = w - theta x, t = r / guard(H_ii - theta); partial |r|^2.
 // ritz[0] = theta, ritz[1..k] = y.
 __global__ void __launch_bounds__(DV_BLOCK) combine_kernel(
@@ -135,7 +148,10 @@ __device__ __forceinline__ double wave_max_f64(double v) {
 }
 
 __global__ void __launch_bounds__(64) lowest_eig_kernel(const double* __restrict__ G, int ldg,
-                                                        int k, double* __restrict__ out) {
+                                                        int kall, const double* __restrict__ dead,
+                                                        double* __restrict__ out) {
+    // a dead newest direction (zero vector) is left out of the eigenproblem
+    const int k = (dead != nullptr && *dead != 0.0) ? kall - 1 : kall;
     __shared__ double A[DV_MAXK][DV_MAXK + 1];
     __shared__ double H[DV_MAXK][DV_MAXK];  // Householder vector of step j in row j
     __shared__ double vv[DV_MAXK], pw[DV_MAXK], d[DV_MAXK], e[DV_MAXK], y[DV_MAXK];
@@ -257,6 +273,7 @@ __global__ void __launch_bounds__(64) lowest_eig_kernel(const double* __restrict
     const double th = wave_sum_f64(yl * ay) / nrm;
     if (l == 0) out[0] = th;
     if (l < k) out[1 + l] = yl / sqrt(nrm);
+    if (l >= k && l < kall) out[1 + l] = 0.0;
 }
 
 __global__ void gram_column_kernel(double* __restrict__ G, int ldg, int k,
@@ -370,6 +387,8 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
     double* nrm_x = sc + DV_MAXK;
     double* rr = sc + DV_MAXK + 1;
     double* nrm_t = sc + DV_MAXK + 2;
+    double* dead = sc + DV_MAXK + 3;  // rr and dead are read back together
+    HIP_CHECK(hipMemsetAsync(dead, 0, sizeof(double), s));
     const i64 g1 = ceil_div(N, 256);
 
     // start vector (a zero vector selects the lowest diagonal determinant)
@@ -425,7 +444,7 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
         bool phase_done = false;
         while (true) {
             HCI_LAUNCH(ctx, "dv_eig", s, lowest_eig_kernel, 1, 64, 0, G.as<double>(), DV_MAXK,
-                       k, ritz.as<double>());
+                       k, (const double*)dead, ritz.as<double>());
             std::swap(xc, xp);
             std::swap(wc, wp);
             HCI_LAUNCH(ctx, "dv_combine", s, combine_kernel, ws.nblk, DV_BLOCK, 0, V, W, N, k,
@@ -433,17 +452,22 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
             have_prev = true;
             HCI_LAUNCH(ctx, "dv_reduce", s, reduce_partials_kernel, 1, DV_BLOCK, 0,
                        ws.partial.as<double>(), 1, ws.nblk, rr);
-            double hv[2];
+            double hv[4];
             HIP_CHECK(hipMemcpyAsync(&hv[0], ritz.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipMemcpyAsync(&hv[1], rr, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipMemcpyAsync(&hv[1], rr, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
             HIP_CHECK(hipStreamSynchronize(s));
             theta = hv[0];
             rnorm = sqrt(std::max(hv[1], 0.0));
+            const bool was_dead = hv[3] != 0.0;  // the newest direction had no norm
             // the float32 operator is only meaningful down to ~1e-7 |theta|
             const double target =
                 phase_prec == HCI_FP32_MIXED ? std::max(tol, 1e-7 * std::max(1.0, fabs(theta))) : tol;
             if (rnorm <= target) {
                 phase_done = true;
+                break;
+            }
+            if (was_dead) {  // no new direction: restart from the Ritz pair
+                HIP_CHECK(hipMemsetAsync(dead, 0, sizeof(double), s));
                 break;
             }
             if (products >= max_iter) break;
@@ -454,8 +478,8 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
                 HCI_LAUNCH(ctx, "dv_subcombo", s, sub_combo_kernel, g1, 256, 0, V, N, k, sc, t, N);
             }
             ws.dots(t, N, 1, t, nrm_t);
-            if (!(read_scalar(nrm_t, s) > 1e-28)) break;  // no new direction: restart
-            HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, t, nrm_t, V + (i64)k * N, N);
+            HCI_LAUNCH(ctx, "dv_normalize", s, normalize_guard_kernel, g1, 256, 0, t, nrm_t,
+                       V + (i64)k * N, N, dead);
             sigma_apply(ctx, sp, V + (i64)k * N, W + (i64)k * N, phase_prec, phase_mode, s);
             ++products;
             // new Gram column: G[j][k] = V_j . W_k, j <= k
