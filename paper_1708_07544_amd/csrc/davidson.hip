@@ -311,34 +311,62 @@ __global__ void argmin_seed_kernel(const double* __restrict__ hd, i64 N, double*
 }
 
 // sign convention: largest-|c| entry positive (first index on ties)
-__global__ void sign_fix_kernel(double* __restrict__ x, i64 N) {
+// Sign convention: the entry of largest magnitude (first index on ties) is
+// made positive.  Block partials of (|x_i|, i), a one-block decision, then a
+// grid-wide multiply by +-1.
+__device__ __forceinline__ void absmax_merge(double& v, i64& idx, double ov, i64 oi) {
+    if (ov > v || (ov == v && oi < idx)) {
+        v = ov;
+        idx = oi;
+    }
+}
+
+__global__ void __launch_bounds__(256) absmax_partial_kernel(const double* __restrict__ x, i64 N,
+                                                             double* __restrict__ pv,
+                                                             i64* __restrict__ pi) {
     __shared__ double bv[256];
     __shared__ i64 bi[256];
     double v = -1.0;
     i64 idx = 0;
-    for (i64 i = threadIdx.x; i < N; i += 256)
-        if (fabs(x[i]) > v) {
-            v = fabs(x[i]);
-            idx = i;
-        }
+    for (i64 i = (i64)blockIdx.x * 256 + threadIdx.x; i < N; i += (i64)gridDim.x * 256)
+        absmax_merge(v, idx, fabs(x[i]), i);
     bv[threadIdx.x] = v;
     bi[threadIdx.x] = idx;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            const double ov = bv[threadIdx.x + s];
-            const i64 oi = bi[threadIdx.x + s];
-            if (ov > bv[threadIdx.x] || (ov == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
-                bv[threadIdx.x] = ov;
-                bi[threadIdx.x] = oi;
-            }
-        }
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) absmax_merge(bv[threadIdx.x], bi[threadIdx.x], bv[threadIdx.x + st],
+                                                bi[threadIdx.x + st]);
         __syncthreads();
     }
-    const bool flip = x[bi[0]] < 0.0;
+    if (threadIdx.x == 0) {
+        pv[blockIdx.x] = bv[0];
+        pi[blockIdx.x] = bi[0];
+    }
+}
+
+__global__ void __launch_bounds__(256) sign_decide_kernel(const double* __restrict__ x,
+                                                          const double* __restrict__ pv,
+                                                          const i64* __restrict__ pi, int nblk,
+                                                          double* __restrict__ factor) {
+    __shared__ double bv[256];
+    __shared__ i64 bi[256];
+    double v = -1.0;
+    i64 idx = 0;
+    for (int b = threadIdx.x; b < nblk; b += 256) absmax_merge(v, idx, pv[b], pi[b]);
+    bv[threadIdx.x] = v;
+    bi[threadIdx.x] = idx;
     __syncthreads();
-    if (flip)
-        for (i64 i = threadIdx.x; i < N; i += 256) x[i] = -x[i];
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) absmax_merge(bv[threadIdx.x], bi[threadIdx.x], bv[threadIdx.x + st],
+                                                bi[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *factor = x[bi[0]] < 0.0 ? -1.0 : 1.0;
+}
+
+__global__ void scale_kernel(double* __restrict__ x, i64 N, const double* __restrict__ factor) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) x[i] *= *factor;
 }
 
 struct Workspace {
@@ -503,7 +531,15 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
     // normalise and fix the sign of the final vector
     ws.dots(xc, N, 1, xc, nrm_x);
     HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, xc, nrm_x, c, N);
-    HCI_LAUNCH(ctx, "dv_signfix", s, sign_fix_kernel, 1, 256, 0, c, N);
+    {
+        DevMem pv = dev_alloc(ctx, sizeof(double) * ws.nblk, s);
+        DevMem pi = dev_alloc(ctx, sizeof(i64) * ws.nblk, s);
+        HCI_LAUNCH(ctx, "dv_signfix", s, absmax_partial_kernel, ws.nblk, 256, 0, c, N, pv.as<double>(),
+                   pi.as<i64>());
+        HCI_LAUNCH(ctx, "dv_signfix", s, sign_decide_kernel, 1, 256, 0, c, pv.as<double>(), pi.as<i64>(),
+                   ws.nblk, nrm_x);
+        HCI_LAUNCH(ctx, "dv_signfix", s, scale_kernel, g1, 256, 0, c, N, (const double*)nrm_x);
+    }
     *e_out = theta + ctx->ecore;
     if (iters_out) *iters_out = products;
     HIP_CHECK(hipStreamSynchronize(s));
