@@ -224,9 +224,8 @@ struct Space {
     i64 st_gnchunk = 0;   // workgroups of the beta-group product
     i64 st_gmax = 0;      // largest beta group
     DevMem st_rsb;        // i64 [N + 1]: first segment slot of each row
-    DevMem st_segoff;     // u32 [st_rsb[N]]: segment starts within the row (multiples of 4)
+    DevMem st_sstart;     // i64 [st_rsb[N]]: absolute start of every (row, segment)
     DevMem st_segcnt;     // u32 [st_rsb[N]]: entries of each segment before padding
-    DevMem st_rowptr;     // i64 [N + 1]
     DevMem st_cols;       // u16 [st_nnz]
     i64 st_nnz = 0;       // stored entries (segments padded to multiples of 4)
     DevMem st_vals32, st_vals64;

@@ -53,9 +53,8 @@ struct StView {
     const u32* nseg;
     const u32* cptr;
     const i64* rsb;
-    const u32* segoff;
-    const u32* segcnt;
-    const i64* rowptr;
+    const i64* sstart;  // absolute start of every (row, segment), padded to ST_VEC
+    const u32* segcnt;  // entries of every (row, segment) before padding
     const u16* cols;
 };
 
@@ -70,9 +69,8 @@ StView st_view(const Space& s) {
     v.nseg = s.st_nseg.as<u32>();
     v.cptr = s.st_cptr.as<u32>();
     v.rsb = s.st_rsb.as<i64>();
-    v.segoff = s.st_segoff.as<u32>();
+    v.sstart = s.st_sstart.as<i64>();
     v.segcnt = s.st_segcnt.as<u32>();
-    v.rowptr = s.st_rowptr.as<i64>();
     v.cols = s.st_cols.as<u16>();
     return v;
 }
@@ -229,37 +227,101 @@ struct StCountVis {
     }
 };
 
+__device__ __forceinline__ u32 pad_vec(u32 x) { return (x + ST_VEC - 1u) & ~(ST_VEC - 1u); }
+
+// Count pass: entries of every (row, segment); per row the padded totals of
+// its windows (wtot) and of its beta-group segment (gtot).
 __global__ void __launch_bounds__(ST_ROW_BLOCK) st_count_kernel(SpaceView S, StView T,
-                                                                u32* __restrict__ counts,
-                                                                u32* __restrict__ segoff,
-                                                                u32* __restrict__ segcnt) {
+                                                                u32* __restrict__ segcnt,
+                                                                u32* __restrict__ wtot,
+                                                                u32* __restrict__ gtot) {
     const i64 i = (i64)blockIdx.x * ST_ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
     if (i >= S.N) return;
     const u32 lane = (u32)lane_id();
     const u32 ns = T.nseg[S.ia[i]];
     StCountVis v;
     enumerate_row_staged(S, T.xpos, T.wlog, ns - 1u, (u32)i, v);
-    // segments padded to multiples of ST_VEC entries (aligned vector loads in
-    // the product); inclusive scan of the padded counts across lanes
-    const u32 pc = (v.cnt + ST_VEC - 1u) & ~(ST_VEC - 1u);
-    int x = (int)pc;
+    if (lane < ns) segcnt[T.rsb[i] + lane] = v.cnt;
+    const u32 wsum = (u32)wave_sum_u64(lane + 1 < ns ? pad_vec(v.cnt) : 0u);
+    const u32 g = (u32)__shfl((int)pad_vec(v.cnt), (int)ns - 1, HCI_WAVE);
+    if (lane == 0) {
+        wtot[i] = wsum;
+        gtot[i] = g;
+    }
+}
+
+// Window-major placement: a workgroup per chunk of rows writes, window by
+// window, the rows' segment starts consecutively (so the product streams
+// each window of a chunk as one contiguous region).
+__global__ void __launch_bounds__(ST_BLOCK) st_place_kernel(SpaceView S, StView T,
+                                                            const i64* __restrict__ wscan,
+                                                            i64* __restrict__ sstart) {
+    __shared__ u32 part[ST_WAVES];
+    __shared__ u32 sh[3];
+    const u32 tid = threadIdx.x;
+    if (tid == 0) {
+        const u32 w = blockIdx.x;
+        u32 lo = 0, hi = (u32)T.nua - 1u;
+        while (lo < hi) {
+            const u32 mid = (lo + hi + 1u) >> 1;
+            if (T.cptr[mid] <= w) lo = mid;
+            else hi = mid - 1u;
+        }
+        const u32 r0 = S.aoff[lo] + (w - T.cptr[lo]) * ST_CHUNK;
+        sh[0] = lo;
+        sh[1] = r0;
+        sh[2] = min(r0 + ST_CHUNK, S.aoff[lo + 1]);
+    }
+    __syncthreads();
+    const u32 a = sh[0], r0 = sh[1], r1 = sh[2];
+    const u32 nw = T.nseg[a] - 1u;
+    const u32 row = r0 + tid;
+    const bool has = row < r1;
+    const i64 sb = has ? T.rsb[row] : 0;
+    i64 base = wscan[r0];  // windows of all earlier rows
+    for (u32 g = 0; g < nw; ++g) {
+        const u32 x = has ? pad_vec(T.segcnt[sb + g]) : 0u;
+        // exclusive block scan of x in row order
+        u32 incl = x;
 #pragma unroll
-    for (int off = 1; off < HCI_WAVE; off <<= 1) {
-        const int y = __shfl_up(x, off, HCI_WAVE);
-        if ((int)lane >= off) x += y;
+        for (int off = 1; off < HCI_WAVE; off <<= 1) {
+            const u32 y = (u32)__shfl_up((int)incl, off, HCI_WAVE);
+            if ((int)lane_id() >= off) incl += y;
+        }
+        if (lane_id() == HCI_WAVE - 1) part[tid / HCI_WAVE] = incl;
+        __syncthreads();
+        u32 before = 0, total = 0;
+        for (int q = 0; q < ST_WAVES; ++q) {
+            const u32 pq = part[q];
+            if (q < (int)(tid / HCI_WAVE)) before += pq;
+            total += pq;
+        }
+        if (has) sstart[sb + g] = base + before + incl - x;
+        base += total;
+        __syncthreads();
     }
-    if (lane < ns) {
-        segoff[T.rsb[i] + lane] = (u32)x - pc;
-        segcnt[T.rsb[i] + lane] = v.cnt;
-    }
-    if (lane == HCI_WAVE - 1) counts[i] = (u32)x;
+}
+
+// Beta-group segments follow all windows, in beta-major row order.
+__global__ void st_place_g_kernel(SpaceView S, StView T, const i64* __restrict__ gscan, i64 gbase,
+                                  i64* __restrict__ sstart) {
+    const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= S.N) return;
+    const u32 i = S.permb[k];
+    sstart[T.rsb[i] + T.nseg[S.ia[i]] - 1] = gbase + gscan[k];
+}
+
+__global__ void st_gather_u32_kernel(const u32* __restrict__ src, const u32* __restrict__ perm, i64 n,
+                                     u32* __restrict__ dst) {
+    const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = src[perm[k]];
+    if (k == n) dst[k] = 0;
 }
 
 // Column pass: lane s holds the start and the cursor of segment s.
 struct StFillVis {
     u16* cols;
-    i64 rs;
-    u32 so;
+    i64 so;
     u32 cur = 0;
     __device__ __forceinline__ void operator()(bool ok, u32, u64, u64, u32 seg, u32 col) {
         u64 m = ballot(ok);
@@ -267,8 +329,8 @@ struct StFillVis {
             const u32 s = (u32)__shfl((int)seg, ctz64(m), HCI_WAVE);
             const bool mine = ok && seg == s;
             const u64 ms = ballot(mine);
-            const u32 at = (u32)__shfl((int)(so + cur), (int)s, HCI_WAVE);
-            if (mine) cols[rs + at + rank_in(ms)] = (u16)col;
+            const i64 at = __shfl(so + (i64)cur, (int)s, HCI_WAVE);
+            if (mine) cols[at + rank_in(ms)] = (u16)col;
             if ((u32)lane_id() == s) cur += (u32)__popcll(ms);
             m &= ~ms;
         }
@@ -282,17 +344,15 @@ __global__ void __launch_bounds__(ST_ROW_BLOCK) st_cols_kernel(SpaceView S, StVi
     if (i >= S.N) return;
     const u32 lane = (u32)lane_id();
     const u32 ns = T.nseg[S.ia[i]];
-    const i64 rs = T.rowptr[i];
-    const u32 rl = (u32)(T.rowptr[i + 1] - rs);
     const i64 sb = T.rsb[i];
-    StFillVis v{cols, rs, lane < ns ? T.segoff[sb + lane] : 0u};
+    StFillVis v{cols, lane < ns ? T.sstart[sb + lane] : (i64)0};
     enumerate_row_staged(S, T.xpos, T.wlog, ns - 1u, (u32)i, v);
     // the fill must reproduce the count pass segment by segment; padding
     // entries get column 0 (their element is 0)
     if (lane < ns) {
-        if (v.cur != T.segcnt[sb + lane]) atomicAdd(bad, 1ull);
-        const u32 end = lane + 1 < ns ? T.segoff[sb + lane + 1] : rl;
-        for (u32 k = v.so + v.cur; k < end; ++k) cols[rs + k] = 0;
+        const u32 cnt = T.segcnt[sb + lane];
+        if (v.cur != cnt) atomicAdd(bad, 1ull);
+        for (i64 k = v.so + v.cur; k < v.so + pad_vec(cnt); ++k) cols[k] = 0;
     }
 }
 
@@ -309,13 +369,11 @@ __global__ void __launch_bounds__(ST_ROW_BLOCK) st_vals_kernel(SpaceView S, IntV
     const u32 nr = 1u + S.as_ptr[a + 1] - t0;
     const u32* xs = T.xpos + t0 + a;
     const u64 ai = S.alpha[i], bi = S.beta[i];
-    const i64 rs = T.rowptr[i];
-    const u32 rl = (u32)(T.rowptr[i + 1] - rs);
     const i64 sb = T.rsb[i];
     const u32 gb = S.boff[S.ib[i]];
     for (u32 s = 0; s < ns; ++s) {
-        const i64 k0 = rs + T.segoff[sb + s];
-        const i64 k1 = rs + (s + 1 < ns ? T.segoff[sb + s + 1] : rl);
+        const i64 k0 = T.sstart[sb + s];
+        const i64 k1 = k0 + pad_vec(T.segcnt[sb + s]);
         const i64 kr = k0 + T.segcnt[sb + s];
         for (i64 k = k0 + lane_id(); k < k1; k += HCI_WAVE) {
             if (k >= kr) {
@@ -348,10 +406,7 @@ __global__ void st_sum_kernel(const u32* __restrict__ x, i64 n, unsigned long lo
 __global__ void st_gentries_kernel(SpaceView S, StView T, unsigned long long* __restrict__ out) {
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     u64 v = 0;
-    if (i < S.N) {
-        const i64 rs = T.rowptr[i];
-        v = (u64)(T.rowptr[i + 1] - rs - T.segoff[T.rsb[i] + T.nseg[S.ia[i]] - 1]);
-    }
+    if (i < S.N) v = pad_vec(T.segcnt[T.rsb[i] + T.nseg[S.ia[i]] - 1]);
     v = wave_sum_u64(v);
     if (lane_id() == 0 && v) atomicAdd(out, (unsigned long long)v);
 }
@@ -369,13 +424,11 @@ __global__ void __launch_bounds__(ST_ROW_BLOCK) st_vals_both_kernel(SpaceView S,
     const u32 nr = 1u + S.as_ptr[a + 1] - t0;
     const u32* xs = T.xpos + t0 + a;
     const u64 ai = S.alpha[i], bi = S.beta[i];
-    const i64 rs = T.rowptr[i];
-    const u32 rl = (u32)(T.rowptr[i + 1] - rs);
     const i64 sb = T.rsb[i];
     const u32 gb = S.boff[S.ib[i]];
     for (u32 s = 0; s < ns; ++s) {
-        const i64 k0 = rs + T.segoff[sb + s];
-        const i64 k1 = rs + (s + 1 < ns ? T.segoff[sb + s + 1] : rl);
+        const i64 k0 = T.sstart[sb + s];
+        const i64 k1 = k0 + pad_vec(T.segcnt[sb + s]);
         const i64 kr = k0 + T.segcnt[sb + s];
         for (i64 k = k0 + lane_id(); k < k1; k += HCI_WAVE) {
             double v = 0.0;
@@ -516,8 +569,6 @@ __global__ void __launch_bounds__(ST_BLOCK) st_spmv_kernel(SpaceView S, StView T
     const int nrw = wave < nrows ? (int)((nrows - wave + ST_WAVES - 1) / ST_WAVES) : 0;
     const u32 row = r0 + wave + ST_WAVES * (u32)lane;
     const bool has = lane < nrw;
-    const i64 rs = has ? T.rowptr[row] : 0;
-    const u32 rl = has ? (u32)(T.rowptr[row + 1] - rs) : 0u;
     const i64 sb = has ? T.rsb[row] : 0;
     double acc = 0.0;
     for (u32 g = 0; g + 1 < ns; ++g) {
@@ -539,8 +590,8 @@ __global__ void __launch_bounds__(ST_BLOCK) st_spmv_kernel(SpaceView S, StView T
             }
         }
         __syncthreads();
-        const i64 mk0 = rs + (has ? T.segoff[sb + g] : 0u);
-        const i64 mk1 = rs + (has ? T.segoff[sb + g + 1] : 0u);
+        const i64 mk0 = has ? T.sstart[sb + g] : (i64)0;
+        const i64 mk1 = mk0 + (has ? pad_vec(T.segcnt[sb + g]) : 0u);
         for (int qb = 0; qb < nrw; qb += GROUPS) {
             const int q = qb + lane / SUB;
             const int sl = lane % SUB;
@@ -649,9 +700,9 @@ __global__ void __launch_bounds__(GT_BLOCK) st_spmv_g_kernel(SpaceView S, StView
     const u32 i = has ? S.permb[k0 + wave + GT_WAVES * (u32)lane] : 0u;
     i64 mk0 = 0, mk1 = 0;
     if (has) {
-        const i64 rs = T.rowptr[i];
-        mk0 = rs + T.segoff[T.rsb[i] + T.nseg[S.ia[i]] - 1];
-        mk1 = T.rowptr[i + 1];
+        const i64 slot = T.rsb[i] + T.nseg[S.ia[i]] - 1;
+        mk0 = T.sstart[slot];
+        mk1 = mk0 + pad_vec(T.segcnt[slot]);
     }
     const double acc = in_lds ? g_rows<VT, CT, SUB, true>(T, vals, stage, mk0, mk1, nrw, lane)
                               : g_rows<VT, CT, SUB, false>(T, vals, cpb + gb, mk0, mk1, nrw, lane);
@@ -728,17 +779,30 @@ bool staged_prepare(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
     sp->st_rsb = dev_alloc(ctx, sizeof(i64) * (N + 1), s);
     scan_u32_to_i64(ctx, rn.as<u32>(), sp->st_rsb.as<i64>(), N + 1, s);
     const i64 nslots = read_scalar(sp->st_rsb.as<i64>() + N, s);
-    sp->st_segoff = dev_alloc(ctx, sizeof(u32) * (nslots > 0 ? nslots : 1), s);
+    sp->st_sstart = dev_alloc(ctx, sizeof(i64) * (nslots > 0 ? nslots : 1), s);
     sp->st_segcnt = dev_alloc(ctx, sizeof(u32) * (nslots > 0 ? nslots : 1), s);
-    // count pass
-    DevMem counts = dev_alloc(ctx, sizeof(u32) * (N + 1), s);
-    HIP_CHECK(hipMemsetAsync(counts.as<u32>() + N, 0, sizeof(u32), s));
+    // count pass: per (row, segment) entries, per row padded window / group totals
+    DevMem wtot = dev_alloc(ctx, sizeof(u32) * (N + 1), s);
+    DevMem gtot = dev_alloc(ctx, sizeof(u32) * (N + 1), s);
+    HIP_CHECK(hipMemsetAsync(wtot.as<u32>() + N, 0, sizeof(u32), s));
     HCI_LAUNCH(ctx, "conn_count", s, st_count_kernel, ceil_div(N, ST_ROWS_PER_BLOCK), ST_ROW_BLOCK, 0,
-               S, st_view(*sp), counts.as<u32>(), sp->st_segoff.as<u32>(),
-               sp->st_segcnt.as<u32>());
-    sp->st_rowptr = dev_alloc(ctx, sizeof(i64) * (N + 1), s);
-    scan_u32_to_i64(ctx, counts.as<u32>(), sp->st_rowptr.as<i64>(), N + 1, s);
-    sp->st_nnz = read_scalar(sp->st_rowptr.as<i64>() + N, s);
+               S, st_view(*sp), sp->st_segcnt.as<u32>(), wtot.as<u32>(), gtot.as<u32>());
+    // windows: chunk by chunk in row order, window-major inside each chunk
+    DevMem wscan = dev_alloc(ctx, sizeof(i64) * (N + 1), s);
+    scan_u32_to_i64(ctx, wtot.as<u32>(), wscan.as<i64>(), N + 1, s);
+    const i64 wtotal = read_scalar(wscan.as<i64>() + N, s);
+    HCI_LAUNCH(ctx, "st_place", s, st_place_kernel, sp->st_nchunk, ST_BLOCK, 0, S, st_view(*sp),
+               wscan.as<i64>(), sp->st_sstart.as<i64>());
+    // beta-group segments after them, in beta-major row order
+    DevMem gperm = dev_alloc(ctx, sizeof(u32) * (N + 1), s);
+    HCI_LAUNCH(ctx, "st_place", s, st_gather_u32_kernel, ceil_div(N + 1, 256), 256, 0, gtot.as<u32>(),
+               sp->permb.as<u32>(), N, gperm.as<u32>());
+    DevMem gscan = dev_alloc(ctx, sizeof(i64) * (N + 1), s);
+    scan_u32_to_i64(ctx, gperm.as<u32>(), gscan.as<i64>(), N + 1, s);
+    const i64 gtotal = read_scalar(gscan.as<i64>() + N, s);
+    HCI_LAUNCH(ctx, "st_place", s, st_place_g_kernel, ceil_div(N, 256), 256, 0, S, st_view(*sp),
+               gscan.as<i64>(), wtotal, sp->st_sstart.as<i64>());
+    sp->st_nnz = wtotal + gtotal;
     // connections without padding: sum of the segment counts
     DevMem total = dev_alloc(ctx, sizeof(u64), s);
     HIP_CHECK(hipMemsetAsync(total.ptr, 0, sizeof(u64), s));
