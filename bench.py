@@ -91,7 +91,7 @@ def main():
         cs = ctx.embed(V1, c1, V2)
         e, c, products = ctx.davidson(V2, cs, tol=args.tol, precision=precision, max_iter=2000)
         dh, dg, _, _ = ctx.energy_backward(V2, c, e)
-        return V2, e, c, products, dh
+        return V2, e, c, products, (dh, dg)
 
     for k in range(args.warmup):
         V2, e, c, products, _ = step("fp32_mixed")
@@ -103,7 +103,7 @@ def main():
     t0 = time.perf_counter()
     total_products = 0
     for k in range(args.steps):
-        V2, e_mixed, c_mixed, products, dh = step("fp32_mixed")
+        V2, e_mixed, c_mixed, products, grads = step("fp32_mixed")
         total_products += products
         log(f"[bench] step {k}: E = {e_mixed:.10f}, products = {products}")
     torch.cuda.synchronize()
@@ -131,7 +131,7 @@ def main():
         t2 = time.perf_counter()
         p64 = 0
         for k in range(args.fp64_steps):
-            _, e64, c64, products64, _ = step("fp64")
+            _, e64, c64, products64, grads64 = step("fp64")
             p64 += products64
             log(f"[bench] fp64 step {k}: E = {e64:.10f}, products = {products64}")
         torch.cuda.synchronize()
@@ -148,6 +148,9 @@ def main():
             "sigma_kernel_avg_ms": ms64 / max(n64, 1),
             "sigma_kernel_pairs_per_s": pairs / (ms64 / max(n64, 1) / 1e3) if n64 else None,
             "energy": e64,
+            # density-matrix difference of the two paths (dE/dh = gamma, dE/dg = Gamma/2 sym.)
+            "gamma_max_abs_diff": float((grads[0] - grads64[0]).abs().max()),
+            "Gamma_max_abs_diff": float(2.0 * (grads[1] - grads64[1]).abs().max()),
         }
     # ---------------------------------------------------------------- roofline
     sk = kernels.get("sigma_stored_f32")
