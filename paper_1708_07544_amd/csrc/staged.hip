@@ -461,59 +461,58 @@ __global__ void st_prep_kernel(const double* __restrict__ c, const u32* __restri
     cpb[i] = (CT)c[permb[i]];
 }
 
-// Four consecutive stored values (16-byte aligned) widened to float64.
+// ST_VEC = 8 consecutive stored entries (aligned), kept as loaded: the eight
+// u16 columns packed in one 128-bit word and the raw values; widened to
+// float64 only in the multiply-add (fewer live registers per step in flight).
 template <class VT>
-struct Vec4;
+struct Entries8;
 template <>
-struct Vec4<float> {
-    static __device__ __forceinline__ void load(const float* p, double v[4]) {
-        const float4 x = *reinterpret_cast<const float4*>(p);
-        v[0] = x.x;
-        v[1] = x.y;
-        v[2] = x.z;
-        v[3] = x.w;
+struct Entries8<float> {
+    uint4 c;
+    float4 a, b;
+    __device__ __forceinline__ void load(const u16* __restrict__ cols, const float* __restrict__ vals) {
+        c = *reinterpret_cast<const uint4*>(cols);
+        a = *reinterpret_cast<const float4*>(vals);
+        b = *reinterpret_cast<const float4*>(vals + 4);
+    }
+    template <class CT>
+    __device__ __forceinline__ double dot(const CT* __restrict__ x, double t) const {
+        t += (double)a.x * (double)x[c.x & 0xffffu];
+        t += (double)a.y * (double)x[c.x >> 16];
+        t += (double)a.z * (double)x[c.y & 0xffffu];
+        t += (double)a.w * (double)x[c.y >> 16];
+        t += (double)b.x * (double)x[c.z & 0xffffu];
+        t += (double)b.y * (double)x[c.z >> 16];
+        t += (double)b.z * (double)x[c.w & 0xffffu];
+        t += (double)b.w * (double)x[c.w >> 16];
+        return t;
     }
 };
 template <>
-struct Vec4<double> {
-    static __device__ __forceinline__ void load(const double* p, double v[4]) {
-        const double2 x = *reinterpret_cast<const double2*>(p);
-        const double2 y = *reinterpret_cast<const double2*>(p + 2);
-        v[0] = x.x;
-        v[1] = x.y;
-        v[2] = y.x;
-        v[3] = y.y;
+struct Entries8<double> {
+    uint4 c;
+    double2 a, b, d, e;
+    __device__ __forceinline__ void load(const u16* __restrict__ cols, const double* __restrict__ vals) {
+        c = *reinterpret_cast<const uint4*>(cols);
+        a = *reinterpret_cast<const double2*>(vals);
+        b = *reinterpret_cast<const double2*>(vals + 2);
+        d = *reinterpret_cast<const double2*>(vals + 4);
+        e = *reinterpret_cast<const double2*>(vals + 6);
+    }
+    template <class CT>
+    __device__ __forceinline__ double dot(const CT* __restrict__ x, double t) const {
+        t += a.x * (double)x[c.x & 0xffffu];
+        t += a.y * (double)x[c.x >> 16];
+        t += b.x * (double)x[c.y & 0xffffu];
+        t += b.y * (double)x[c.y >> 16];
+        t += d.x * (double)x[c.z & 0xffffu];
+        t += d.y * (double)x[c.z >> 16];
+        t += e.x * (double)x[c.w & 0xffffu];
+        t += e.y * (double)x[c.w >> 16];
+        return t;
     }
 };
-
-// VEC consecutive stored entries (aligned): u16 columns and values widened
-// to float64.
-template <class VT, int VEC>
-__device__ __forceinline__ void load_entries(const u16* __restrict__ cols, const VT* __restrict__ vals,
-                                             u32 c[VEC], double v[VEC]) {
-    if constexpr (VEC == 4) {
-        const uint2 w = *reinterpret_cast<const uint2*>(cols);
-        c[0] = w.x & 0xffffu;
-        c[1] = w.x >> 16;
-        c[2] = w.y & 0xffffu;
-        c[3] = w.y >> 16;
-    } else {
-#pragma unroll
-        for (int h = 0; h < VEC; h += 8) {
-            const uint4 w = *reinterpret_cast<const uint4*>(cols + h);
-            c[h + 0] = w.x & 0xffffu;
-            c[h + 1] = w.x >> 16;
-            c[h + 2] = w.y & 0xffffu;
-            c[h + 3] = w.y >> 16;
-            c[h + 4] = w.z & 0xffffu;
-            c[h + 5] = w.z >> 16;
-            c[h + 6] = w.w & 0xffffu;
-            c[h + 7] = w.w >> 16;
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < VEC; q += 4) Vec4<VT>::load(vals + q, v + q);
-}
+static_assert(ST_VEC == 8, "the product kernels read entries in groups of 8");
 
 // Sum of a value over groups of SUB consecutive lanes (result in every lane).
 template <int SUB>
@@ -601,18 +600,13 @@ __global__ void __launch_bounds__(ST_BLOCK) st_spmv_kernel(SpaceView S, StView T
             double t = 0.0;
             // two steps per trip: both loads in flight before the first use
             for (i64 k = k0 + ST_VEC * sl; k < k1; k += 2 * ST_VEC * SUB) {
-                u32 cc[ST_VEC], cc2[ST_VEC];
-                double v[ST_VEC], v2[ST_VEC];
+                Entries8<VT> e1, e2;
                 const i64 k2 = k + ST_VEC * SUB;
                 const bool two = k2 < k1;
-                load_entries<VT, ST_VEC>(T.cols + k, vals + k, cc, v);
-                if (two) load_entries<VT, ST_VEC>(T.cols + k2, vals + k2, cc2, v2);
-#pragma unroll
-                for (int e = 0; e < (int)ST_VEC; ++e) t += v[e] * (double)stage[cc[e]];
-                if (two) {
-#pragma unroll
-                    for (int e = 0; e < (int)ST_VEC; ++e) t += v2[e] * (double)stage[cc2[e]];
-                }
+                e1.load(T.cols + k, vals + k);
+                if (two) e2.load(T.cols + k2, vals + k2);
+                t = e1.dot(stage, t);
+                if (two) t = e2.dot(stage, t);
             }
             t = group_sum_f64<SUB>(t);
             const double v = __shfl(t, ((lane - qb) * SUB) & (HCI_WAVE - 1), HCI_WAVE);
@@ -641,18 +635,13 @@ __device__ __forceinline__ double g_rows(const StView& T, const VT* __restrict__
         const i64 k1 = q < nrw ? k1s : k0;
         double t = 0.0;
         for (i64 k = k0 + ST_VEC * sl; k < k1; k += 2 * ST_VEC * SUB) {
-            u32 cc[ST_VEC], cc2[ST_VEC];
-            double v[ST_VEC], v2[ST_VEC];
+            Entries8<VT> e1, e2;
             const i64 k2 = k + ST_VEC * SUB;
             const bool two = k2 < k1;
-            load_entries<VT, ST_VEC>(T.cols + k, vals + k, cc, v);
-            if (two) load_entries<VT, ST_VEC>(T.cols + k2, vals + k2, cc2, v2);
-#pragma unroll
-            for (int e = 0; e < (int)ST_VEC; ++e) t += v[e] * (double)src[cc[e]];
-            if (two) {
-#pragma unroll
-                for (int e = 0; e < (int)ST_VEC; ++e) t += v2[e] * (double)src[cc2[e]];
-            }
+            e1.load(T.cols + k, vals + k);
+            if (two) e2.load(T.cols + k2, vals + k2);
+            t = e1.dot(src, t);
+            if (two) t = e2.dot(src, t);
         }
         t = group_sum_f64<SUB>(t);
         const double v = __shfl(t, ((lane - qb) * SUB) & (HCI_WAVE - 1), HCI_WAVE);
