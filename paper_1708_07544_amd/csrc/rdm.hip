@@ -276,7 +276,8 @@ __device__ __forceinline__ int select_bit(u64 s, int k) {
     return ctz64(s);
 }
 
-__global__ void __launch_bounds__(RDM_BLOCK) rdm_bucket_kernel(SpaceView S, RdmPlan P, i64 nua,
+// 8 waves per SIMD: two workgroups share a CU (the kernel is latency bound).
+__global__ void __launch_bounds__(RDM_BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8))) rdm_bucket_kernel(SpaceView S, RdmPlan P, i64 nua,
                                                                const u32* __restrict__ cptr,
                                                                const double* __restrict__ bra,
                                                                const double* __restrict__ ket,
@@ -311,6 +312,7 @@ __global__ void __launch_bounds__(RDM_BLOCK) rdm_bucket_kernel(SpaceView S, RdmP
     const u64 E = ~A & full;  // empty alpha orbitals
     const u32 t0 = S.as_ptr[a];
     const u32 deg = S.as_ptr[a + 1] - t0;
+    const int nocc = popc64(A), nvir = n - nocc;
     double* p11 = lds + P.o_p11;
     double* s1a = lds + P.o_s1a;
     double* s1b2 = lds + P.o_s1b2;
@@ -374,8 +376,7 @@ __global__ void __launch_bounds__(RDM_BLOCK) rdm_bucket_kernel(SpaceView S, RdmP
                         if (d == 2) {
                             const int v = ctz64(aj & xa), u = ctz64(A & xa);
                             const double x = wb * ket[j] * sign_between(aj, v, u);
-                            const u32 t = lower_bound_u32(S.as_idx + t0, deg, S.ia[j]);
-                            double* slot = s1a + (i64)t * (1 + n);
+                            double* slot = s1a + (i64)(rank_below(A, u) * nvir + rank_below(E, v)) * (1 + n);
                             lds_add(&slot[0], x);
                             for (u64 m = B; m; m &= m - 1) lds_add(&slot[1 + ctz64(m)], x);
                         } else if (d == 4) {
@@ -450,18 +451,18 @@ __global__ void __launch_bounds__(RDM_BLOCK) rdm_bucket_kernel(SpaceView S, RdmP
         }
         __syncthreads();
     }
-    // alpha singles: r1 and same-spin spectators from the sum, opposite-spin
-    // spectators from the beta-occupation moments
-    for (u32 t = tid; t < deg; t += RDM_BLOCK) {
-        const u64 A2 = S.ua[S.as_idx[t0 + t]];
-        const u64 xa = A ^ A2;
-        const int v = ctz64(A2 & xa), u = ctz64(A & xa);
-        const double* slot = s1a + (i64)t * (1 + n);
+    // alpha singles (slot of the occupied orbital u and the empty orbital v of
+    // A): r1 and same-spin spectators from the sum, opposite-spin spectators
+    // from the beta-occupation moments
+    for (int q = (int)tid; q < nocc * nvir; q += RDM_BLOCK) {
+        const int u = select_bit(A, q / nvir), v = select_bit(E, q % nvir);
+        const double* slot = s1a + (i64)q * (1 + n);
         const double X = slot[0];
         if (X != 0.0) {
             add64(&r1[u * n + v], X);
-            for (u64 m = A & A2; m; m &= m - 1) {
+            for (u64 m = A; m; m &= m - 1) {
                 const int k = ctz64(m);
+                if (k == u) continue;
                 add64(&r2[r2idx(n, u, v, k, k)], X);
                 add64(&r2[r2idx(n, u, k, k, v)], -X);
             }
