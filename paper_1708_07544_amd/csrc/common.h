@@ -226,6 +226,9 @@ struct Space {
     DevMem st_rsb;        // i64 [N + 1]: first segment slot of each row
     DevMem st_sstart;     // i64 [st_rsb[N]]: absolute start of every (row, segment)
     DevMem st_segcnt;     // u32 [st_rsb[N]]: entries of each segment before padding
+    i64 st_nslots = 0;    // st_rsb[N]
+    u32 st_abW = 0;       // beta-string bitmap words per neighbour (0: search instead)
+    u32 st_abG = 0;       // alpha neighbours per bitmap pass
     DevMem st_cols;       // u16 [st_nnz]
     i64 st_nnz = 0;       // stored entries (segments padded to multiples of 4)
     DevMem st_vals32, st_vals64;

@@ -25,6 +25,7 @@
 // layout is built by a count pass, a scan, an integer column pass and a
 // separate element pass per precision.
 #include <algorithm>
+#include <cstdlib>
 
 #include "slater.h"
 
@@ -121,8 +122,8 @@ __global__ void st_row_nseg_kernel(const u32* __restrict__ ia, const u32* __rest
 // and u16 column in the staged layout.  The whole wavefront calls this for
 // one row; vis(ok, j, aj, bj, seg, col) is invoked wave-uniformly with each
 // lane's own candidate.  Discovery order (deterministic): same-alpha bucket,
-// same-beta group, then alpha-single neighbours in adjacency order.
-template <class Visitor>
+// same-beta group, then (AB) alpha-single neighbours in adjacency order.
+template <bool AB, class Visitor>
 __device__ __forceinline__ void enumerate_row_staged(const SpaceView& S, const u32* __restrict__ xpos,
                                                      u32 wlog, u32 gseg, u32 i, Visitor& vis) {
     const int lane = lane_id();
@@ -172,7 +173,7 @@ __device__ __forceinline__ void enumerate_row_staged(const SpaceView& S, const u
             vis(ok, j, aj, B, seg, col);
         }
     }
-    {  // one alpha and one beta excitation: stage ranges 1, 2, ...
+    if constexpr (AB) {  // one alpha and one beta excitation: stage ranges 1, 2, ...
         const u32 s0 = S.bs_ptr[b], s1 = S.bs_ptr[b + 1];
         const u32 nbs = s1 - s0;
         for (u32 t = t0; t < t1; ++t) {
@@ -229,21 +230,32 @@ struct StCountVis {
 
 __device__ __forceinline__ u32 pad_vec(u32 x) { return (x + ST_VEC - 1u) & ~(ST_VEC - 1u); }
 
-// Count pass: entries of every (row, segment); per row the padded totals of
-// its windows (wtot) and of its beta-group segment (gtot).
+// Count pass: entries of every (row, segment) (without the alpha single x
+// beta single part when AB is false: st_ab_kernel adds it).
+template <bool AB>
 __global__ void __launch_bounds__(ST_ROW_BLOCK) st_count_kernel(SpaceView S, StView T,
-                                                                u32* __restrict__ segcnt,
-                                                                u32* __restrict__ wtot,
-                                                                u32* __restrict__ gtot) {
+                                                                u32* __restrict__ segcnt) {
     const i64 i = (i64)blockIdx.x * ST_ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
     if (i >= S.N) return;
     const u32 lane = (u32)lane_id();
     const u32 ns = T.nseg[S.ia[i]];
     StCountVis v;
-    enumerate_row_staged(S, T.xpos, T.wlog, ns - 1u, (u32)i, v);
+    enumerate_row_staged<AB>(S, T.xpos, T.wlog, ns - 1u, (u32)i, v);
     if (lane < ns) segcnt[T.rsb[i] + lane] = v.cnt;
-    const u32 wsum = (u32)wave_sum_u64(lane + 1 < ns ? pad_vec(v.cnt) : 0u);
-    const u32 g = (u32)__shfl((int)pad_vec(v.cnt), (int)ns - 1, HCI_WAVE);
+}
+
+// Per row the padded totals of its windows (wtot) and of its beta-group
+// segment (gtot).
+__global__ void __launch_bounds__(ST_ROW_BLOCK) st_totals_kernel(SpaceView S, StView T,
+                                                                 u32* __restrict__ wtot,
+                                                                 u32* __restrict__ gtot) {
+    const i64 i = (i64)blockIdx.x * ST_ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
+    if (i >= S.N) return;
+    const u32 lane = (u32)lane_id();
+    const u32 ns = T.nseg[S.ia[i]];
+    const u32 cnt = lane < ns ? T.segcnt[T.rsb[i] + lane] : 0u;
+    const u32 wsum = (u32)wave_sum_u64(lane + 1 < ns ? pad_vec(cnt) : 0u);
+    const u32 g = (u32)__shfl((int)pad_vec(cnt), (int)ns - 1, HCI_WAVE);
     if (lane == 0) {
         wtot[i] = wsum;
         gtot[i] = g;
@@ -337,22 +349,162 @@ struct StFillVis {
     }
 };
 
+template <bool AB>
 __global__ void __launch_bounds__(ST_ROW_BLOCK) st_cols_kernel(SpaceView S, StView T,
                                                                u16* __restrict__ cols,
-                                                               unsigned long long* __restrict__ bad) {
+                                                               u32* __restrict__ fill) {
     const i64 i = (i64)blockIdx.x * ST_ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
     if (i >= S.N) return;
     const u32 lane = (u32)lane_id();
     const u32 ns = T.nseg[S.ia[i]];
     const i64 sb = T.rsb[i];
     StFillVis v{cols, lane < ns ? T.sstart[sb + lane] : (i64)0};
-    enumerate_row_staged(S, T.xpos, T.wlog, ns - 1u, (u32)i, v);
-    // the fill must reproduce the count pass segment by segment; padding
-    // entries get column 0 (their element is 0)
-    if (lane < ns) {
-        const u32 cnt = T.segcnt[sb + lane];
-        if (v.cur != cnt) atomicAdd(bad, 1ull);
-        for (i64 k = v.so + v.cur; k < v.so + pad_vec(cnt); ++k) cols[k] = 0;
+    enumerate_row_staged<AB>(S, T.xpos, T.wlog, ns - 1u, (u32)i, v);
+    if (lane < ns) fill[sb + lane] = v.cur;
+}
+
+// The fill must reproduce the count pass segment by segment; padding entries
+// get column 0 (their element is 0).
+__global__ void __launch_bounds__(ST_ROW_BLOCK) st_pad_kernel(SpaceView S, StView T,
+                                                              const u32* __restrict__ fill,
+                                                              u16* __restrict__ cols,
+                                                              unsigned long long* __restrict__ bad) {
+    const i64 i = (i64)blockIdx.x * ST_ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
+    if (i >= S.N) return;
+    const u32 lane = (u32)lane_id();
+    const u32 ns = T.nseg[S.ia[i]];
+    if (lane >= ns) return;
+    const i64 slot = T.rsb[i] + lane;
+    const u32 cnt = T.segcnt[slot], cur = fill[slot];
+    if (cur != cnt) {
+        atomicAdd(bad, 1ull);
+        return;
+    }
+    const i64 so = T.sstart[slot];
+    for (i64 k = so + cur; k < so + pad_vec(cnt); ++k) cols[k] = 0;
+}
+
+// Alpha single x beta single connections of a chunk of rows (one alpha
+// bucket A), G alpha neighbours A2 at a time.  For each neighbour the
+// workgroup keeps in LDS a bitmap over the unique beta strings present in
+// A2's bucket and, per 32-bit word, the number of set bits before it (u16:
+// buckets hold fewer than 65536 rows).  Rows of a bucket are sorted by beta
+// string, so the position of beta string b in A2's bucket is
+// pre[b >> 5] + popc(word & bits below b), and every beta single of row i's
+// beta string (adjacency list order) is resolved by two LDS reads instead of a
+// search.  MODE 0 adds to the segment counts, MODE 1 continues the column
+// cursors left by st_cols_kernel.
+__device__ __forceinline__ void build_beta_maps(const SpaceView& S, u32 t0, u32 tg0, u32 tg1, u32 W,
+                                                u32* bm, u16* pre, u32 tid) {
+    const u32 nt = tg1 - tg0;
+    for (u32 x = tid; x < nt * W; x += ST_BLOCK) bm[x] = 0u;
+    __syncthreads();
+    for (u32 q = 0; q < nt; ++q) {
+        const u32 a2 = S.as_idx[t0 + tg0 + q];
+        const u32 lo = S.aoff[a2], hi = S.aoff[a2 + 1];
+        u32* m = bm + q * W;
+        for (u32 j = lo + tid; j < hi; j += ST_BLOCK) {
+            const u32 b = S.ib[j];
+            atomicOr(&m[b >> 5], 1u << (b & 31u));
+        }
+    }
+    __syncthreads();
+    // exclusive prefix of the word popcounts, one wavefront per neighbour
+    const u32 lane = (u32)lane_id();
+    for (u32 q = tid / HCI_WAVE; q < nt; q += ST_WAVES) {
+        u32 run = 0;
+        for (u32 base = 0; base < W; base += HCI_WAVE) {
+            const u32 w = base + lane;
+            const u32 c = w < W ? (u32)__popc(bm[q * W + w]) : 0u;
+            u32 incl = c;
+#pragma unroll
+            for (int off = 1; off < HCI_WAVE; off <<= 1) {
+                const u32 y = (u32)__shfl_up((int)incl, off, HCI_WAVE);
+                if ((int)lane >= off) incl += y;
+            }
+            if (w < W) pre[q * W + w] = (u16)(run + incl - c);
+            run += (u32)__shfl((int)incl, HCI_WAVE - 1, HCI_WAVE);
+        }
+    }
+    __syncthreads();
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(ST_BLOCK) st_ab_kernel(SpaceView S, StView T, u32 W, u32 G,
+                                                         u32* __restrict__ segcnt, u32* __restrict__ fill,
+                                                         u16* __restrict__ cols) {
+    extern __shared__ __align__(16) unsigned char st_smem[];
+    u32* bm = reinterpret_cast<u32*>(st_smem);
+    u16* pre = reinterpret_cast<u16*>(bm + (size_t)G * W);
+    __shared__ u32 sh[3];
+    const u32 tid = threadIdx.x;
+    const u32 lane = (u32)lane_id();
+    const u32 wave = tid / HCI_WAVE;
+    if (tid == 0) {
+        // bucket of this workgroup: the last a with cptr[a] <= blockIdx.x
+        const u32 w = blockIdx.x;
+        u32 lo = 0, hi = (u32)T.nua - 1u;
+        while (lo < hi) {
+            const u32 mid = (lo + hi + 1u) >> 1;
+            if (T.cptr[mid] <= w) lo = mid;
+            else hi = mid - 1u;
+        }
+        const u32 r0 = S.aoff[lo] + (w - T.cptr[lo]) * ST_CHUNK;
+        sh[0] = lo;
+        sh[1] = r0;
+        sh[2] = min(r0 + ST_CHUNK, S.aoff[lo + 1]);
+    }
+    __syncthreads();
+    const u32 a = sh[0], r0 = sh[1], r1 = sh[2];
+    const u32 t0 = S.as_ptr[a], deg = S.as_ptr[a + 1] - t0;
+    const u32 xb = t0 + a;
+    const u32 ns = T.nseg[a];
+    const u32 wmask = (1u << T.wlog) - 1u;
+    for (u32 tg0 = 0; tg0 < deg; tg0 += G) {
+        const u32 tg1 = min(tg0 + G, deg);
+        __syncthreads();  // the previous maps are consumed
+        build_beta_maps(S, t0, tg0, tg1, W, bm, pre, tid);
+        for (u32 row = r0 + wave; row < r1; row += ST_WAVES) {
+            const i64 sb = T.rsb[row];
+            const u32 b = S.ib[row];
+            const u32 s0 = S.bs_ptr[b], s1 = S.bs_ptr[b + 1];
+            StCountVis vc;
+            StFillVis vf{cols, 0, 0u};
+            if constexpr (MODE == 1) {
+                vf.so = lane < ns ? T.sstart[sb + lane] : (i64)0;
+                vf.cur = lane < ns ? fill[sb + lane] : 0u;
+            }
+            // neighbour by neighbour, beta singles in adjacency order: the
+            // discovery order of the search in enumerate_row_staged
+            auto visit = [&](u32 t, bool has, u32 bp) {
+                const u32 q = t - tg0;
+                const u32 w = bp >> 5, bit = bp & 31u;
+                const u32 word = has ? bm[q * W + w] : 0u;
+                const bool ok = ((word >> bit) & 1u) != 0u;
+                const u32 pos = ok ? (u32)pre[q * W + w] + (u32)__popc(word & ((1u << bit) - 1u)) : 0u;
+                const u32 P = T.xpos[xb + 1 + t] + pos;
+                if constexpr (MODE == 0) vc(ok, 0u, 0ull, 0ull, P >> T.wlog, P & wmask);
+                else vf(ok, 0u, 0ull, 0ull, P >> T.wlog, P & wmask);
+            };
+            if (s1 - s0 <= (u32)HCI_WAVE) {
+                const bool has = s0 + lane < s1;
+                const u32 bp = has ? S.bs_idx[s0 + lane] : 0u;
+                for (u32 t = tg0; t < tg1; ++t) visit(t, has, bp);
+            } else {
+                for (u32 t = tg0; t < tg1; ++t) {
+                    for (u32 base = s0; base < s1; base += HCI_WAVE) {
+                        const u32 k = base + lane;
+                        const bool has = k < s1;
+                        visit(t, has, has ? S.bs_idx[k] : 0u);
+                    }
+                }
+            }
+            if constexpr (MODE == 0) {
+                if (lane < ns && vc.cnt) segcnt[sb + lane] += vc.cnt;
+            } else {
+                if (lane < ns) fill[sb + lane] = vf.cur;
+            }
+        }
     }
 }
 
@@ -720,6 +872,8 @@ void launch_spmv(hci_ctx_s* ctx, Space* sp, const char* name, const char* gname,
                st_view(*sp), vals, cpb, cap, sigma);
 }
 
+size_t ab_lds(const Space& sp) { return (size_t)6 * sp.st_abW * sp.st_abG; }
+
 }  // namespace
 
 bool staged_prepare(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
@@ -768,14 +922,40 @@ bool staged_prepare(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
     sp->st_rsb = dev_alloc(ctx, sizeof(i64) * (N + 1), s);
     scan_u32_to_i64(ctx, rn.as<u32>(), sp->st_rsb.as<i64>(), N + 1, s);
     const i64 nslots = read_scalar(sp->st_rsb.as<i64>() + N, s);
+    sp->st_nslots = nslots;
     sp->st_sstart = dev_alloc(ctx, sizeof(i64) * (nslots > 0 ? nslots : 1), s);
     sp->st_segcnt = dev_alloc(ctx, sizeof(u32) * (nslots > 0 ? nslots : 1), s);
+    // LDS beta-string bitmaps for the alpha single x beta single part: u32
+    // words + u16 prefix counts per neighbour, within 64 KB per workgroup
+    sp->st_abW = 0;
+    sp->st_abG = 0;
+    const char* force_search = std::getenv("HCI_AB_SEARCH");  // "1": always search (tests)
+    if (nub <= 65535 && !(force_search && force_search[0] == '1')) {
+        const i64 W = ceil_div(nub, 32);
+        const i64 dmax = (i64)ctx->na * (ctx->n - ctx->na);
+        const i64 G = std::min<i64>((std::min<i64>(65536, max_shared) - 1024) / (6 * W), std::max<i64>(dmax, 1));
+        if (G >= 1) {
+            sp->st_abW = (u32)W;
+            sp->st_abG = (u32)G;
+        }
+    }
+    const i64 rgrid = ceil_div(N, ST_ROWS_PER_BLOCK);
     // count pass: per (row, segment) entries, per row padded window / group totals
+    if (sp->st_abW) {
+        HCI_LAUNCH(ctx, "conn_count", s, st_count_kernel<false>, rgrid, ST_ROW_BLOCK, 0, S, st_view(*sp),
+                   sp->st_segcnt.as<u32>());
+        HCI_LAUNCH(ctx, "conn_count", s, st_ab_kernel<0>, sp->st_nchunk, ST_BLOCK, ab_lds(*sp), S,
+                   st_view(*sp), sp->st_abW, sp->st_abG, sp->st_segcnt.as<u32>(), (u32*)nullptr,
+                   (u16*)nullptr);
+    } else {
+        HCI_LAUNCH(ctx, "conn_count", s, st_count_kernel<true>, rgrid, ST_ROW_BLOCK, 0, S, st_view(*sp),
+                   sp->st_segcnt.as<u32>());
+    }
     DevMem wtot = dev_alloc(ctx, sizeof(u32) * (N + 1), s);
     DevMem gtot = dev_alloc(ctx, sizeof(u32) * (N + 1), s);
     HIP_CHECK(hipMemsetAsync(wtot.as<u32>() + N, 0, sizeof(u32), s));
-    HCI_LAUNCH(ctx, "conn_count", s, st_count_kernel, ceil_div(N, ST_ROWS_PER_BLOCK), ST_ROW_BLOCK, 0,
-               S, st_view(*sp), sp->st_segcnt.as<u32>(), wtot.as<u32>(), gtot.as<u32>());
+    HCI_LAUNCH(ctx, "conn_count", s, st_totals_kernel, rgrid, ST_ROW_BLOCK, 0, S, st_view(*sp),
+               wtot.as<u32>(), gtot.as<u32>());
     // windows: chunk by chunk in row order, window-major inside each chunk
     DevMem wscan = dev_alloc(ctx, sizeof(i64) * (N + 1), s);
     scan_u32_to_i64(ctx, wtot.as<u32>(), wscan.as<i64>(), N + 1, s);
@@ -810,10 +990,21 @@ void staged_ensure_vals(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s)
     const i64 grid = ceil_div(sp->N, ST_ROWS_PER_BLOCK);
     if (!sp->st_cols.ptr) {
         sp->st_cols = dev_alloc(ctx, sizeof(u16) * (nnz > 0 ? nnz : 1), s);
+        DevMem fill = dev_alloc(ctx, sizeof(u32) * (sp->st_nslots > 0 ? sp->st_nslots : 1), s);
         DevMem bad = dev_alloc(ctx, sizeof(u64), s);
         HIP_CHECK(hipMemsetAsync(bad.ptr, 0, sizeof(u64), s));
-        HCI_LAUNCH(ctx, "csr_cols", s, st_cols_kernel, grid, ST_ROW_BLOCK, 0, S, st_view(*sp),
-                   sp->st_cols.as<u16>(), (unsigned long long*)bad.as<u64>());
+        if (sp->st_abW) {
+            HCI_LAUNCH(ctx, "csr_cols", s, st_cols_kernel<false>, grid, ST_ROW_BLOCK, 0, S, st_view(*sp),
+                       sp->st_cols.as<u16>(), fill.as<u32>());
+            HCI_LAUNCH(ctx, "csr_cols", s, st_ab_kernel<1>, sp->st_nchunk, ST_BLOCK, ab_lds(*sp), S,
+                       st_view(*sp), sp->st_abW, sp->st_abG, (u32*)nullptr, fill.as<u32>(),
+                       sp->st_cols.as<u16>());
+        } else {
+            HCI_LAUNCH(ctx, "csr_cols", s, st_cols_kernel<true>, grid, ST_ROW_BLOCK, 0, S, st_view(*sp),
+                       sp->st_cols.as<u16>(), fill.as<u32>());
+        }
+        HCI_LAUNCH(ctx, "csr_cols", s, st_pad_kernel, grid, ST_ROW_BLOCK, 0, S, st_view(*sp),
+                   (const u32*)fill.as<u32>(), sp->st_cols.as<u16>(), (unsigned long long*)bad.as<u64>());
         const u64 nbad = read_scalar(bad.as<u64>(), s);
         HCI_REQUIRE(nbad == 0, HCI_E_HIP,
                     "internal: " + std::to_string(nbad) + " row segments disagree with the count pass");

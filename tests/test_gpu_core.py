@@ -240,6 +240,50 @@ def test_stored_layouts(lib_mod, space, wlog):
     ctx.close()
 
 
+@pytest.mark.parametrize("space,wlog", [("cas8", 6), ("n12", 6), ("n12", 13), ("cas16s", 14),
+                                        ("n20", 12)])
+def test_stored_layout_beta_maps_match_search(lib_mod, monkeypatch, space, wlog):
+    """The alpha single x beta single connections are found through per-
+    workgroup bitmaps of the neighbours' beta strings, or (HCI_AB_SEARCH=1,
+    and for spaces with more than 65535 beta strings) by searching each
+    neighbour bucket.  Both discover the same entries in the same order, so
+    the stored layouts and the products agree bit for bit; both match the
+    oracle."""
+    if space == "cas16s":
+        w = hs.WORKLOADS["cas16"]
+        h, g = hs.workload_integrals(w)
+        n, na, nb = 16, 8, 8
+        V = hs.random_dets(16, 8, 8, 6000, seed=16, bias=0.2)
+    elif space == "n20":
+        # every pair of (aufbau, aufbau singles) strings of (20e,20o): the
+        # aufbau beta string has 100 beta singles (more than one wavefront)
+        h, g = hs.make_integrals(20, 60, 20)
+        n, na, nb = 20, 10, 10
+        base = (1 << 10) - 1
+        strs = sorted({base} | {(base & ~(1 << i)) | (1 << a) for i in range(10) for a in range(10, 20)})
+        V = np.array([(x, y) for x in strs for y in strs], dtype=np.uint64)
+    else:
+        n, na, nb, h, g, V = _layout_space(space)
+    c = hs.random_coeffs(len(V), 32)
+    ref = O.sigma(h, g, V, c)
+    outs = {}
+    for path in ["maps", "search"]:
+        if path == "search":
+            monkeypatch.setenv("HCI_AB_SEARCH", "1")
+        else:
+            monkeypatch.delenv("HCI_AB_SEARCH", raising=False)
+        print(f"[beta maps {space} |V|={len(V)} wlog={wlog} {path}]", flush=True)
+        ctx = lib_mod.HCIContext(h, g, na, nb)
+        ctx.set_stage_window(wlog)
+        assert ctx.layout_info(V)["layout"] == 2
+        assert ctx.connections(V) == int(O.row_counts(n, V).sum())
+        for prec in ["fp64", "fp32_mixed"]:
+            outs[path, prec] = ctx.sigma(V, c, precision=prec, mode="stored").cpu().numpy()
+        ctx.close()
+    for prec, tol in [("fp64", 1e-12), ("fp32_mixed", 1e-6)]:
+        assert np.array_equal(outs["maps", prec], outs["search", prec]), prec
+        assert rel_err(outs["maps", prec], ref) < tol, prec
+
 def test_stage_window_rejects_bad_values(cas8, lib_mod):
     ctx = cas8["ctx"]
     for bad in [-1, 1, 5, 17]:
