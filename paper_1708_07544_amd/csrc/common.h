@@ -15,6 +15,7 @@
 
 typedef uint64_t u64;
 typedef uint32_t u32;
+typedef uint16_t u16;
 typedef int64_t i64;
 
 #define HCI_WAVE 64

@@ -10,6 +10,8 @@
 // off-diagonal pair (row i, connection j) adds bra_i ket_j times the
 // operator matrix element of the excitation D_j -> D_i to the few
 // rdm entries it touches, with float64 atomics.
+#include <cstdlib>
+
 #include "slater.h"
 
 namespace {
@@ -263,6 +265,9 @@ struct RdmPlan {
     int npo, npv;                // occupied / empty orbital pairs of an alpha string
     int o_p11, o_s1a, o_s1b2, o_s1b3, o_d2a, total;  // offsets in doubles
     bool b3, d2;
+    int W;        // beta-string bitmap words per neighbour (0: search the buckets)
+    int o_bm;     // byte offset of the bitmaps (after the doubles)
+    int bytes;    // LDS of the workgroup
 };
 
 __device__ __forceinline__ void lds_add(double* p, double v) { unsafeAtomicAdd(p, v); }
@@ -277,6 +282,9 @@ __device__ __forceinline__ int select_bit(u64 s, int k) {
 }
 
 // 8 waves per SIMD: two workgroups share a CU (the kernel is latency bound).
+// BM: alpha single x beta single pairs through the LDS beta-string maps of
+// build_beta_maps; otherwise by scanning or searching each neighbour bucket.
+template <bool BM>
 __global__ void __launch_bounds__(RDM_BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8))) rdm_bucket_kernel(SpaceView S, RdmPlan P, i64 nua,
                                                                const u32* __restrict__ cptr,
                                                                const double* __restrict__ bra,
@@ -318,10 +326,13 @@ __global__ void __launch_bounds__(RDM_BLOCK) __attribute__((amdgpu_waves_per_eu(
     double* s1b2 = lds + P.o_s1b2;
     double* s1b3 = lds + P.o_s1b3;
     double* d2a = lds + P.o_d2a;
+    u32* bm = reinterpret_cast<u32*>(reinterpret_cast<unsigned char*>(lds) + P.o_bm);
+    u16* pre = reinterpret_cast<u16*>(bm + (i64)P.G * P.W);
     const u32 ngroups = deg == 0 ? 1u : (deg + (u32)P.G - 1u) / (u32)P.G;
     for (u32 g = 0; g < ngroups; ++g) {
         const u32 tg0 = g * (u32)P.G;
         const u32 tg1 = min(tg0 + (u32)P.G, deg);
+        if constexpr (BM) build_beta_maps<RDM_BLOCK>(S, t0, tg0, tg1, (u32)P.W, bm, pre, tid);
         for (u32 row = row0 + wave; row < row1; row += RDM_WAVES) {
             const double wb = bra[row];
             if (wb == 0.0) continue;  // wave-uniform
@@ -403,7 +414,31 @@ __global__ void __launch_bounds__(RDM_BLOCK) __attribute__((amdgpu_waves_per_eu(
             // alpha single x beta single for neighbours [tg0, tg1)
             const u32 s0 = S.bs_ptr[b], s1 = S.bs_ptr[b + 1];
             const u32 nbs = s1 - s0;
-            for (u32 t = tg0; t < tg1; ++t) {
+            if constexpr (BM) {
+                for (u32 base = s0; base < s1; base += HCI_WAVE) {
+                    const u32 k = base + lane;
+                    if (k >= s1) continue;
+                    const u32 bp = S.bs_idx[k];
+                    const u64 bj = S.ub[bp];
+                    const u64 xb = B ^ bj;
+                    const int v2 = ctz64(bj & xb), u2 = ctz64(B & xb);
+                    const double wsb = wb * sign_between(bj, v2, u2);
+                    const u32 w = bp >> 5, bit = bp & 31u;
+                    for (u32 t = tg0; t < tg1; ++t) {
+                        const u32 q = t - tg0;
+                        const u32 word = bm[q * (u32)P.W + w];
+                        if (((word >> bit) & 1u) == 0u) continue;
+                        const u32 a2 = S.as_idx[t0 + t];
+                        const u64 A2 = S.ua[a2];
+                        const u64 xa = A ^ A2;
+                        const double sa = sign_between(A2, ctz64(A2 & xa), ctz64(A & xa));
+                        const u32 j = S.aoff[a2] + (u32)pre[q * (u32)P.W + w] +
+                                      (u32)__popc(word & ((1u << bit) - 1u));
+                        lds_add(&p11[(i64)q * nn + u2 * n + v2], wsb * ket[j] * sa);
+                    }
+                }
+            }
+            for (u32 t = tg0; t < (BM ? tg0 : tg1); ++t) {
                 const u32 a2 = S.as_idx[t0 + t];
                 const u64 A2 = S.ua[a2];
                 const u64 xa = A ^ A2;
@@ -514,9 +549,10 @@ __global__ void rdm_nchunk_kernel(const u32* __restrict__ aoff, i64 nua, u32* __
     if (a == nua) out[a] = 0;
 }
 
-// LDS layout of the bucket kernel for this context, within `budget` doubles;
-// false when even one alpha neighbour per pass does not fit.
-bool rdm_plan(int n, int na, int budget, RdmPlan& P) {
+// LDS layout of the bucket kernel for this context, within `budget` bytes,
+// with W bitmap words per neighbour (0: no bitmaps); false when even one
+// alpha neighbour per pass does not fit.
+bool rdm_plan(int n, int na, int budget, int W, RdmPlan& P) {
     const int dmax = na * (n - na);
     const int nn = n * n;
     P.n = n;
@@ -529,7 +565,7 @@ bool rdm_plan(int n, int na, int budget, RdmPlan& P) {
         const int s1b3 = P.b3 ? nn * n : 0;
         const int d2 = P.d2 ? P.npo * P.npv : 0;
         const int rest = s1a + nn + s1b3 + d2;
-        int G = (budget - rest) / nn;
+        int G = (budget - 8 * rest) / (8 * nn + 6 * W);
         if (G < 1) continue;
         if (G > dmax) G = dmax > 0 ? dmax : 1;
         P.G = G;
@@ -539,6 +575,9 @@ bool rdm_plan(int n, int na, int budget, RdmPlan& P) {
         P.o_s1b3 = P.o_s1b2 + nn;
         P.o_d2a = P.o_s1b3 + s1b3;
         P.total = P.o_d2a + d2;
+        P.W = W;
+        P.o_bm = 8 * P.total;
+        P.bytes = P.o_bm + ((6 * G * W + 15) & ~15);
         return true;
     }
     return false;
@@ -573,8 +612,17 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
     HIP_CHECK(hipMemsetAsync(rdm1, 0, sizeof(double) * n2, s));
     if (rdm2) HIP_CHECK(hipMemsetAsync(rdm2, 0, sizeof(double) * n2 * n2, s));
     SpaceView S = space_view(*sp, n);
+    // two workgroups per CU: up to 79 KB of LDS each
+    int dev = 0, max_shared = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    HIP_CHECK(hipDeviceGetAttribute(&max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const int budget = std::min(79 * 1024, max_shared);
+    const char* force_search = std::getenv("HCI_AB_SEARCH");  // "1": always search (tests)
+    const int W = sp->nub <= 65535 && !(force_search && force_search[0] == '1') ? (int)ceil_div(sp->nub, 32) : 0;
     RdmPlan P;
-    if (rdm2 && rdm_plan(n, ctx->na, 8192, P)) {
+    bool planned = false;
+    if (rdm2) planned = (W > 0 && rdm_plan(n, ctx->na, budget, W, P)) || rdm_plan(n, ctx->na, budget, 0, P);
+    if (planned) {
         if (!sp->rdm_cptr.ptr) {
             DevMem cnt = dev_alloc(ctx, sizeof(u32) * (sp->nua + 1), s);
             HCI_LAUNCH(ctx, "rdm_nchunk", s, rdm_nchunk_kernel, ceil_div(sp->nua + 1, 256), 256, 0,
@@ -583,9 +631,11 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
             scan_u32_to_u32(ctx, cnt.as<u32>(), sp->rdm_cptr.as<u32>(), sp->nua + 1, s);
             sp->rdm_nchunk = read_scalar(sp->rdm_cptr.as<u32>() + sp->nua, s);
         }
-        HCI_LAUNCH(ctx, "rdm_offdiag", s, rdm_bucket_kernel, sp->rdm_nchunk, RDM_BLOCK,
-                   sizeof(double) * P.total, S, P, sp->nua, sp->rdm_cptr.as<u32>(), bra, ket, rdm1,
-                   rdm2);
+        auto kern = P.W ? rdm_bucket_kernel<true> : rdm_bucket_kernel<false>;
+        HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, P.bytes));
+        HCI_LAUNCH(ctx, "rdm_offdiag", s, kern, sp->rdm_nchunk, RDM_BLOCK, (size_t)P.bytes, S, P, sp->nua,
+                   sp->rdm_cptr.as<u32>(), bra, ket, rdm1, rdm2);
     } else {
         HCI_LAUNCH(ctx, "rdm_offdiag", s, rdm_offdiag_kernel, ceil_div(N, ROWS_PER_BLOCK), ROW_BLOCK,
                    0, S, bra, ket, rdm1, rdm2);

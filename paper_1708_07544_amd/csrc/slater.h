@@ -232,3 +232,47 @@ __device__ __forceinline__ void enumerate_row(const SpaceView& S, u32 i, Visitor
         }
     }
 }
+
+// LDS lookup of beta strings in the alpha neighbours [tg0, tg1) of a bucket
+// (alpha single x beta single connections): per neighbour a bitmap over the
+// unique beta strings (W 32-bit words) with a bit for each beta string present
+// in the neighbour's bucket, and per word the number of set bits before it
+// (u16: buckets hold fewer than 65536 rows).  Rows of a bucket are sorted by
+// beta string, so beta string b sits at position
+// pre[b >> 5] + popc(word & bits below b) of the bucket.  Called by all BLOCK
+// threads of the workgroup; ends with a barrier.
+template <int BLOCK>
+__device__ __forceinline__ void build_beta_maps(const SpaceView& S, u32 t0, u32 tg0, u32 tg1, u32 W,
+                                                u32* bm, u16* pre, u32 tid) {
+    const u32 nt = tg1 - tg0;
+    for (u32 x = tid; x < nt * W; x += BLOCK) bm[x] = 0u;
+    __syncthreads();
+    for (u32 q = 0; q < nt; ++q) {
+        const u32 a2 = S.as_idx[t0 + tg0 + q];
+        const u32 lo = S.aoff[a2], hi = S.aoff[a2 + 1];
+        u32* m = bm + q * W;
+        for (u32 j = lo + tid; j < hi; j += BLOCK) {
+            const u32 b = S.ib[j];
+            atomicOr(&m[b >> 5], 1u << (b & 31u));
+        }
+    }
+    __syncthreads();
+    // exclusive prefix of the word popcounts, one wavefront per neighbour
+    const u32 lane = (u32)lane_id();
+    for (u32 q = tid / HCI_WAVE; q < nt; q += BLOCK / HCI_WAVE) {
+        u32 run = 0;
+        for (u32 base = 0; base < W; base += HCI_WAVE) {
+            const u32 w = base + lane;
+            const u32 c = w < W ? (u32)__popc(bm[q * W + w]) : 0u;
+            u32 incl = c;
+#pragma unroll
+            for (int off = 1; off < HCI_WAVE; off <<= 1) {
+                const u32 y = (u32)__shfl_up((int)incl, off, HCI_WAVE);
+                if ((int)lane >= off) incl += y;
+            }
+            if (w < W) pre[q * W + w] = (u16)(run + incl - c);
+            run += (u32)__shfl((int)incl, HCI_WAVE - 1, HCI_WAVE);
+        }
+    }
+    __syncthreads();
+}

@@ -31,7 +31,6 @@
 
 namespace {
 
-typedef uint16_t u16;
 
 constexpr int ST_ROW_BLOCK = 256;  // build passes: one wavefront per row
 constexpr int ST_ROWS_PER_BLOCK = ST_ROW_BLOCK / HCI_WAVE;
@@ -385,50 +384,11 @@ __global__ void __launch_bounds__(ST_ROW_BLOCK) st_pad_kernel(SpaceView S, StVie
 }
 
 // Alpha single x beta single connections of a chunk of rows (one alpha
-// bucket A), G alpha neighbours A2 at a time.  For each neighbour the
-// workgroup keeps in LDS a bitmap over the unique beta strings present in
-// A2's bucket and, per 32-bit word, the number of set bits before it (u16:
-// buckets hold fewer than 65536 rows).  Rows of a bucket are sorted by beta
-// string, so the position of beta string b in A2's bucket is
-// pre[b >> 5] + popc(word & bits below b), and every beta single of row i's
-// beta string (adjacency list order) is resolved by two LDS reads instead of a
-// search.  MODE 0 adds to the segment counts, MODE 1 continues the column
-// cursors left by st_cols_kernel.
-__device__ __forceinline__ void build_beta_maps(const SpaceView& S, u32 t0, u32 tg0, u32 tg1, u32 W,
-                                                u32* bm, u16* pre, u32 tid) {
-    const u32 nt = tg1 - tg0;
-    for (u32 x = tid; x < nt * W; x += ST_BLOCK) bm[x] = 0u;
-    __syncthreads();
-    for (u32 q = 0; q < nt; ++q) {
-        const u32 a2 = S.as_idx[t0 + tg0 + q];
-        const u32 lo = S.aoff[a2], hi = S.aoff[a2 + 1];
-        u32* m = bm + q * W;
-        for (u32 j = lo + tid; j < hi; j += ST_BLOCK) {
-            const u32 b = S.ib[j];
-            atomicOr(&m[b >> 5], 1u << (b & 31u));
-        }
-    }
-    __syncthreads();
-    // exclusive prefix of the word popcounts, one wavefront per neighbour
-    const u32 lane = (u32)lane_id();
-    for (u32 q = tid / HCI_WAVE; q < nt; q += ST_WAVES) {
-        u32 run = 0;
-        for (u32 base = 0; base < W; base += HCI_WAVE) {
-            const u32 w = base + lane;
-            const u32 c = w < W ? (u32)__popc(bm[q * W + w]) : 0u;
-            u32 incl = c;
-#pragma unroll
-            for (int off = 1; off < HCI_WAVE; off <<= 1) {
-                const u32 y = (u32)__shfl_up((int)incl, off, HCI_WAVE);
-                if ((int)lane >= off) incl += y;
-            }
-            if (w < W) pre[q * W + w] = (u16)(run + incl - c);
-            run += (u32)__shfl((int)incl, HCI_WAVE - 1, HCI_WAVE);
-        }
-    }
-    __syncthreads();
-}
-
+// bucket A), G alpha neighbours at a time, through the LDS beta-string maps
+// of build_beta_maps: every beta single of row i's beta string (adjacency
+// order) resolves to its position in the neighbour bucket with two LDS reads
+// instead of a search.  MODE 0 adds to the segment counts, MODE 1 continues
+// the column cursors left by st_cols_kernel.
 template <int MODE>
 __global__ void __launch_bounds__(ST_BLOCK) st_ab_kernel(SpaceView S, StView T, u32 W, u32 G,
                                                          u32* __restrict__ segcnt, u32* __restrict__ fill,
@@ -463,7 +423,7 @@ __global__ void __launch_bounds__(ST_BLOCK) st_ab_kernel(SpaceView S, StView T, 
     for (u32 tg0 = 0; tg0 < deg; tg0 += G) {
         const u32 tg1 = min(tg0 + G, deg);
         __syncthreads();  // the previous maps are consumed
-        build_beta_maps(S, t0, tg0, tg1, W, bm, pre, tid);
+        build_beta_maps<ST_BLOCK>(S, t0, tg0, tg1, W, bm, pre, tid);
         for (u32 row = r0 + wave; row < r1; row += ST_WAVES) {
             const i64 sb = T.rsb[row];
             const u32 b = S.ib[row];

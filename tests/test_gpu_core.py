@@ -247,8 +247,8 @@ def test_stored_layout_beta_maps_match_search(lib_mod, monkeypatch, space, wlog)
     workgroup bitmaps of the neighbours' beta strings, or (HCI_AB_SEARCH=1,
     and for spaces with more than 65535 beta strings) by searching each
     neighbour bucket.  Both discover the same entries in the same order, so
-    the stored layouts and the products agree bit for bit; both match the
-    oracle."""
+    the stored layouts and the products agree bit for bit, and both match the
+    oracle; the density matrices (same choice of path) agree to rounding."""
     if space == "cas16s":
         w = hs.WORKLOADS["cas16"]
         h, g = hs.workload_integrals(w)
@@ -279,10 +279,20 @@ def test_stored_layout_beta_maps_match_search(lib_mod, monkeypatch, space, wlog)
         assert ctx.connections(V) == int(O.row_counts(n, V).sum())
         for prec in ["fp64", "fp32_mixed"]:
             outs[path, prec] = ctx.sigma(V, c, precision=prec, mode="stored").cpu().numpy()
+        r1, r2 = ctx.rdm12(V, c)
+        outs[path, "rdm"] = (r1.cpu().numpy(), r2.cpu().numpy())
         ctx.close()
     for prec, tol in [("fp64", 1e-12), ("fp32_mixed", 1e-6)]:
         assert np.array_equal(outs["maps", prec], outs["search", prec]), prec
         assert rel_err(outs["maps", prec], ref) < tol, prec
+    # density matrices: same pairs, float64 atomics in another order
+    for k in range(2):
+        a, b = outs["maps", "rdm"][k], outs["search", "rdm"][k]
+        assert np.abs(a - b).max() <= 1e-12 * max(1.0, np.abs(b).max()), k
+    if len(V) <= 5000:  # the oracle's density matrices take seconds here
+        o1, o2 = O.rdm12(n, V, c, c)
+        assert np.abs(outs["maps", "rdm"][0] - o1).max() < 1e-12
+        assert np.abs(outs["maps", "rdm"][1] - o2).max() < 1e-12
 
 def test_stage_window_rejects_bad_values(cas8, lib_mod):
     ctx = cas8["ctx"]
