@@ -57,26 +57,68 @@ __global__ void __launch_bounds__(DV_BLOCK) dots_kernel(const double* __restrict
     }
 }
 
-// out[j] = sum_b partial[j * nblk + b] (fixed order), scaled by `scale`
+// out[j * ostride] = sum_b partial[j * nblk + b] (fixed order); block 0 also
+// copies *copy_src to *copy_dst when given (scalars the host reads together).
 __global__ void reduce_partials_kernel(const double* __restrict__ partial, int k, int nblk,
-                                       double* __restrict__ out) {
+                                       double* __restrict__ out, i64 ostride,
+                                       const double* __restrict__ copy_src, double* __restrict__ copy_dst) {
     __shared__ double lds[DV_BLOCK / 64];
     const int j = blockIdx.x;
     if (j >= k) return;
     double acc = 0.0;
     for (int b = threadIdx.x; b < nblk; b += DV_BLOCK) acc += partial[(i64)j * nblk + b];
     const double v = block_sum_f64<DV_BLOCK>(acc, lds);
-    if (threadIdx.x == 0) out[j] = v;
+    if (threadIdx.x == 0) {
+        out[(i64)j * ostride] = v;
+        if (j == 0 && copy_dst) *copy_dst = *copy_src;
+    }
 }
 
-// t -= sum_j coef[j] X_j
-__global__ void sub_combo_kernel(const double* __restrict__ X, i64 ld, int k,
-                                 const double* __restrict__ coef, double* __restrict__ t, i64 N) {
-    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    double s = t[i];
-    for (int j = 0; j < k; ++j) s -= coef[j] * X[(i64)j * ld + i];
-    t[i] = s;
+// One classical Gram-Schmidt sweep fused with what follows it:
+// t -= sum_j coef[j] X_j, then (NORM) the partial sums of |t|^2, else those of
+// X_j . t (the next sweep's coefficients), with the partition and order of
+// dots_kernel.
+template <bool NORM>
+__global__ void __launch_bounds__(DV_BLOCK) sub_dots_kernel(const double* __restrict__ X, i64 ld, int k,
+                                                            const double* __restrict__ coef,
+                                                            double* __restrict__ t, i64 N,
+                                                            double* __restrict__ partial, int nblk) {
+    __shared__ double cf[DV_MAXK];
+    __shared__ double wsum[DV_BLOCK / 64][DV_MAXK];
+    if ((int)threadIdx.x < k) cf[threadIdx.x] = coef[threadIdx.x];
+    __syncthreads();
+    constexpr int NACC = NORM ? 1 : DV_MAXK;
+    double acc[NACC];
+#pragma unroll
+    for (int j = 0; j < NACC; ++j) acc[j] = 0.0;
+    for (i64 i = (i64)blockIdx.x * DV_BLOCK + threadIdx.x; i < N; i += (i64)nblk * DV_BLOCK) {
+        double si = t[i];
+        for (int j = 0; j < k; ++j) si -= cf[j] * X[(i64)j * ld + i];
+        t[i] = si;
+        if constexpr (NORM) {
+            acc[0] += si * si;
+        } else {
+#pragma unroll
+            for (int j = 0; j < DV_MAXK; ++j)
+                if (j < k) acc[j] += X[(i64)j * ld + i] * si;
+        }
+    }
+    const int kk = NORM ? 1 : k;
+    const int w = threadIdx.x / 64;
+#pragma unroll
+    for (int j = 0; j < NACC; ++j) {
+        if (j < kk) {
+            const double v = wave_sum_f64(acc[j]);
+            if (lane_id() == 0) wsum[w][j] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kk) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < DV_BLOCK / 64; ++q) v += wsum[q][threadIdx.x];
+        partial[(i64)threadIdx.x * nblk + blockIdx.x] = v;
+    }
 }
 
 // dst = src / sqrt(*nrm2)
@@ -276,12 +318,6 @@ __global__ void __launch_bounds__(64) lowest_eig_kernel(const double* __restrict
     if (l >= k && l < kall) out[1 + l] = 0.0;
 }
 
-__global__ void gram_column_kernel(double* __restrict__ G, int ldg, int k,
-                                   const double* __restrict__ col) {
-    const int j = threadIdx.x;
-    if (j <= k) G[(i64)j * ldg + k] = col[j];
-}
-
 __global__ void argmin_seed_kernel(const double* __restrict__ hd, i64 N, double* __restrict__ x) {
     // one block: index of the smallest diagonal (first on ties), then x = e_idx
     __shared__ double bv[256];
@@ -380,12 +416,26 @@ struct Workspace {
         partial = dev_alloc(c, sizeof(double) * DV_MAXK * nblk, st);
         scal = dev_alloc(c, sizeof(double) * (DV_MAXK + 8), st);
     }
-    // out[0..k) = X_j . t
-    void dots(const double* X, i64 ld, int k, const double* t, double* out) {
+    // out[j * ostride] = X_j . t, j < k
+    void dots(const double* X, i64 ld, int k, const double* t, double* out, i64 ostride = 1) {
         HCI_LAUNCH(ctx, "dv_dots", s, dots_kernel, nblk, DV_BLOCK, 0, X, ld, k, t, N,
                    partial.as<double>(), nblk);
+        reduce(k, out, ostride);
+    }
+    void reduce(int k, double* out, i64 ostride = 1, const double* copy_src = nullptr,
+                double* copy_dst = nullptr) {
         HCI_LAUNCH(ctx, "dv_reduce", s, reduce_partials_kernel, k, DV_BLOCK, 0, partial.as<double>(),
-                   k, nblk, out);
+                   k, nblk, out, ostride, copy_src, copy_dst);
+    }
+    // two-sweep classical Gram-Schmidt of t against X_0..X_{k-1}; nrm2 = |t|^2
+    void cgs2(const double* X, i64 ld, int k, double* t, double* coef, double* nrm2) {
+        dots(X, ld, k, t, coef);
+        HCI_LAUNCH(ctx, "dv_subcombo", s, sub_dots_kernel<false>, nblk, DV_BLOCK, 0, X, ld, k,
+                   (const double*)coef, t, N, partial.as<double>(), nblk);
+        reduce(k, coef);
+        HCI_LAUNCH(ctx, "dv_subcombo", s, sub_dots_kernel<true>, nblk, DV_BLOCK, 0, X, ld, k,
+                   (const double*)coef, t, N, partial.as<double>(), nblk);
+        reduce(1, nrm2);
     }
 };
 
@@ -415,7 +465,8 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
     double* nrm_x = sc + DV_MAXK;
     double* rr = sc + DV_MAXK + 1;
     double* nrm_t = sc + DV_MAXK + 2;
-    double* dead = sc + DV_MAXK + 3;  // rr and dead are read back together
+    double* dead = sc + DV_MAXK + 3;
+    double* theta_h = sc + DV_MAXK + 4;  // rr, nrm_t, dead, theta: read back together
     HIP_CHECK(hipMemsetAsync(dead, 0, sizeof(double), s));
     const i64 g1 = ceil_div(N, 256);
 
@@ -453,11 +504,7 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
             // image from a fresh product (combining the old images would
             // amplify their rounding errors)
             HIP_CHECK(hipMemcpyAsync(t, xp, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-            for (int pass = 0; pass < 2; ++pass) {
-                ws.dots(V, N, 1, t, sc);
-                HCI_LAUNCH(ctx, "dv_subcombo", s, sub_combo_kernel, g1, 256, 0, V, N, 1, sc, t, N);
-            }
-            ws.dots(t, N, 1, t, nrm_t);
+            ws.cgs2(V, N, 1, t, sc, nrm_t);
             if (read_scalar(nrm_t, s) > 1e-24) {
                 HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, t, nrm_t, V + N, N);
                 sigma_apply(ctx, sp, V + N, W + N, phase_prec, phase_mode, s);
@@ -465,10 +512,7 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
                 k = 2;
             }
         }
-        for (int j = 0; j < k; ++j) {
-            ws.dots(V, N, j + 1, W + (i64)j * N, sc);
-            HCI_LAUNCH(ctx, "dv_gram", s, gram_column_kernel, 1, 64, 0, G.as<double>(), DV_MAXK, j, sc);
-        }
+        for (int j = 0; j < k; ++j) ws.dots(V, N, j + 1, W + (i64)j * N, G.as<double>() + j, DV_MAXK);
         bool phase_done = false;
         while (true) {
             HCI_LAUNCH(ctx, "dv_eig", s, lowest_eig_kernel, 1, 64, 0, G.as<double>(), DV_MAXK,
@@ -478,15 +522,13 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
             HCI_LAUNCH(ctx, "dv_combine", s, combine_kernel, ws.nblk, DV_BLOCK, 0, V, W, N, k,
                        ritz.as<double>(), hd, xc, wc, t, N, ws.partial.as<double>(), ws.nblk);
             have_prev = true;
-            HCI_LAUNCH(ctx, "dv_reduce", s, reduce_partials_kernel, 1, DV_BLOCK, 0,
-                       ws.partial.as<double>(), 1, ws.nblk, rr);
+            ws.reduce(1, rr, 1, ritz.as<double>(), theta_h);
             double hv[4];
-            HIP_CHECK(hipMemcpyAsync(&hv[0], ritz.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipMemcpyAsync(&hv[1], rr, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipMemcpyAsync(hv, rr, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
             HIP_CHECK(hipStreamSynchronize(s));
-            theta = hv[0];
-            rnorm = sqrt(std::max(hv[1], 0.0));
-            const bool was_dead = hv[3] != 0.0;  // the newest direction had no norm
+            rnorm = sqrt(std::max(hv[0], 0.0));
+            const bool was_dead = hv[2] != 0.0;  // the newest direction had no norm
+            theta = hv[3];
             // the float32 operator is only meaningful down to ~1e-7 |theta|
             const double target =
                 phase_prec == HCI_FP32_MIXED ? std::max(tol, 1e-7 * std::max(1.0, fabs(theta))) : tol;
@@ -501,18 +543,13 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
             if (products >= max_iter) break;
             if (k == kmax) break;  // thick restart
             // orthogonalise the preconditioned residual against the basis (CGS2)
-            for (int pass = 0; pass < 2; ++pass) {
-                ws.dots(V, N, k, t, sc);
-                HCI_LAUNCH(ctx, "dv_subcombo", s, sub_combo_kernel, g1, 256, 0, V, N, k, sc, t, N);
-            }
-            ws.dots(t, N, 1, t, nrm_t);
+            ws.cgs2(V, N, k, t, sc, nrm_t);
             HCI_LAUNCH(ctx, "dv_normalize", s, normalize_guard_kernel, g1, 256, 0, t, nrm_t,
                        V + (i64)k * N, N, dead);
             sigma_apply(ctx, sp, V + (i64)k * N, W + (i64)k * N, phase_prec, phase_mode, s);
             ++products;
             // new Gram column: G[j][k] = V_j . W_k, j <= k
-            ws.dots(V, N, k + 1, W + (i64)k * N, sc);
-            HCI_LAUNCH(ctx, "dv_gram", s, gram_column_kernel, 1, 64, 0, G.as<double>(), DV_MAXK, k, sc);
+            ws.dots(V, N, k + 1, W + (i64)k * N, G.as<double>() + k, DV_MAXK);
             ++k;
         }
         if (phase_done) {
