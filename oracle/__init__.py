@@ -29,6 +29,19 @@ Where each function comes from (paper sections/equations):
   (eq. h0, eq. pt, eq. pt_hci, Hylleraas functional eq. hylleraas).
 * ``zvector_dense`` -- the Lagrange-multiplier equation for lambda_c
   (eq. lagd, eq. lagc and the simplified form after them).
+* ``pt2_sample`` / ``pt2_stochastic*`` / ``pt2_semistochastic`` -- the
+  semistochastic second-order energy, eq. semistoc: a deterministic E2 at a
+  loose eps2_d plus the difference of two sampled estimates (tight eps2 and
+  eps2_d) taken from the same draws.  The paper defers the sampling
+  estimator to its reference; the reading used here is the unbiased estimate
+  of sum_a (sum_i x_ai)^2 / (E0 - H_aa) from N_d draws with replacement
+  (probability p_i, multiplicity w_i, x_ai = H_ai c_i): for each a
+  [S1^2 - S2 + (N_d - 1) S3] / (N_d (N_d - 1)) with S1 = sum w x / p,
+  S2 = sum (w x / p)^2, S3 = sum w x^2 / p (distinct draws give the
+  off-diagonal products, single draws the squares).  p_i = q_i / Q with
+  integer weights q_i = max(1, round(2^31 |c_i| / max|c|)) (c_i != 0), so
+  the cumulative weights are exact integers; draw k picks the row whose
+  cumulative range holds floor(u_k Q) for a caller-supplied uniform u_k.
 
 Readings where the paper is silent (sign convention, integral notation,
 RDM index order, threshold rounding) are listed in the C source header.
@@ -454,3 +467,72 @@ def symmetrize8(t) -> np.ndarray:
     perms = [(0, 1, 2, 3), (1, 0, 2, 3), (0, 1, 3, 2), (1, 0, 3, 2),
              (2, 3, 0, 1), (3, 2, 0, 1), (2, 3, 1, 0), (3, 2, 1, 0)]
     return sum(np.transpose(t, p) for p in perms) / 8.0
+
+
+def pt2_sample(c, u):
+    """Multiplicities of the draws of eq. semistoc's sampled estimate: integer
+    weights q_i = max(1, round(2^31 |c_i| / max|c|)) for c_i != 0 (0 for
+    c_i = 0), Q = sum q, draw k picks the row i with
+    Q_<i <= min(Q - 1, floor(u_k Q)) < Q_<i + q_i.  Returns (w, q, Q)."""
+    c = np.asarray(c, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    cabs = np.abs(c)
+    cmax = float(cabs.max())
+    q = np.zeros(len(c), dtype=np.int64)
+    nz = cabs > 0
+    q[nz] = np.maximum(1, np.floor(np.ldexp(cabs[nz] / cmax, 31) + 0.5)).astype(np.int64)
+    Q = int(q.sum())
+    before = np.concatenate([[0], np.cumsum(q)[:-1]])
+    t = np.minimum(Q - 1, np.floor(u * float(Q)).astype(np.int64))
+    rows = np.searchsorted(before, t, side="right") - 1
+    w = np.bincount(rows, minlength=len(c)).astype(np.int64)
+    return w, q, Q
+
+
+def pt2_stochastic_counts(h, g, V, c, e0, eps_list, w, p, nd):
+    """Sampled estimate of eq. pt_hci for given multiplicities w_i of nd draws
+    with probabilities p_i, one value per threshold in eps_list (every
+    threshold on the same draws): sum_a [S1^2 - S2 + (nd - 1) S3] /
+    (nd (nd - 1) (E0 - H_aa)) over the screened pairs of the drawn rows."""
+    c = np.asarray(c, dtype=np.float64)
+    w = np.asarray(w)
+    cs = np.where(w > 0, c, 0.0)  # only drawn rows produce pairs
+    a, idx, hv = pt2_pairs(h, g, V, cs, min(eps_list))
+    out = []
+    for eps in eps_list:
+        keep = np.abs(hv) * np.abs(c[idx]) > eps
+        ak, ik, hk = a[keep], idx[keep], hv[keep]
+        if len(ik) == 0:
+            out.append(0.0)
+            continue
+        C = sort_unique(ak)
+        pos = find(C, ak)
+        x = hk * c[ik]
+        wp = w[ik] / p[ik]
+        S1, S2, S3 = np.zeros(len(C)), np.zeros(len(C)), np.zeros(len(C))
+        np.add.at(S1, pos, wp * x)
+        np.add.at(S2, pos, (wp * x) ** 2)
+        np.add.at(S3, pos, wp * x * x)
+        Haa = np.array([diag(h, g, y) for y in C])
+        T = (S1 ** 2 - S2 + (nd - 1) * S3) / (nd * (nd - 1))
+        out.append(float(np.sum(T / (e0 - Haa))))
+    return out
+
+
+def pt2_stochastic(h, g, V, c, e0, eps2, eps2_d, u):
+    """One batch (len(u) draws): the sampled estimates E2^S(eps2) and
+    E2^S(eps2_d) of eq. semistoc from the same draws."""
+    w, q, Q = pt2_sample(c, u)
+    p = q / float(Q)
+    return tuple(pt2_stochastic_counts(h, g, V, c, e0, [eps2, eps2_d], w, p, len(u)))
+
+
+def pt2_semistochastic(h, g, V, c, e0, eps2, eps2_d, u_batches):
+    """eq. semistoc: E2^D(eps2_d) + mean over batches of
+    [E2^S(eps2) - E2^S(eps2_d)]; returns (E2, standard error of the mean
+    (nan for one batch), E2^D(eps2_d), per-batch pairs)."""
+    e2d = pt2(h, g, V, c, e0, eps2_d)["E2"]
+    per = [pt2_stochastic(h, g, V, c, e0, eps2, eps2_d, u) for u in u_batches]
+    diff = np.array([x - y for x, y in per])
+    err = float(np.std(diff, ddof=1) / np.sqrt(len(diff))) if len(diff) > 1 else float("nan")
+    return e2d + float(np.mean(diff)), err, e2d, per
