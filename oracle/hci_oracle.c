@@ -526,6 +526,8 @@ long orc_pt2_pairs(int n, const double* h, const double* g, const u64* V, long n
     u64* buf = NULL;
     long bufcap = 0;
     for (long i = 0; i < nv; ++i) {
+        /* |H_ai| * 0 > eps2 never holds (eps2 >= 0): such a row has no pairs */
+        if (c[i] == 0.0 && eps2 >= 0.0) continue;
         u64 a = V[2 * i], b = V[2 * i + 1];
         long m = max_excitations(n, a, b);
         if (m > bufcap) {
