@@ -254,6 +254,46 @@ int hci_energy_backward(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const 
 int hci_pt2(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double e0,
             double eps2, double* e2_out, double* r_out, int64_t* n_conn_out, void* stream);
 
+/* Device memory (bytes) the screened PT2 pairs may hold at once (default
+ * 32 GiB, about 128 B per pair).  hci_pt2 and the deterministic part of
+ * hci_pt2_semistochastic take the pairs in several passes over a hash
+ * partition of the connected determinants when they exceed it (the memory
+ * bottleneck of eq. pt_hci); hci_energy_backward with eps2 > 0 keeps all
+ * pairs and returns HCI_E_NOMEM beyond it.  bytes <= 0: HCI_E_ARG. */
+int hci_ctx_set_pt2_budget(hci_ctx ctx, int64_t bytes);
+
+/* Sampled estimates of the screened second-order energy of eq. pt_hci, the
+ * stochastic terms of eq. semistoc, at two thresholds from the same draws.
+ * Batch b draws n_samp rows of V with replacement: row i has probability
+ * p_i = q_i / Q with integer weights q_i = max(1, round(2^31 |c_i| / max|c|))
+ * (0 for c_i = 0), and draw k picks the row whose cumulative weight range
+ * holds min(Q - 1, floor(u[b][k] Q)).  With multiplicities w_i and
+ * x_ai = H_ai c_i over the screened pairs of the drawn rows,
+ *   E2^S = sum_a [S1^2 - S2 + (n_samp - 1) S3] / (n_samp (n_samp - 1) (E0 - H_aa)),
+ *   S1 = sum w x / p, S2 = sum (w x / p)^2, S3 = sum w x^2 / p,
+ * an unbiased estimate of E2(eps) (the paper defers the estimator to its
+ * reference; this is the reading used).
+ *   dets, c: as hci_pt2; e0: variational energy (ecore included).
+ *   u: device float64 [n_batch][n_samp], the caller's uniforms in [0, 1)
+ *   (a value outside: HCI_E_ARG).  e2s_out, e2sd_out: host [n_batch],
+ *   E2^S(eps2) and E2^S(eps2_d) of each batch.  Needs 0 <= eps2 <= eps2_d,
+ *   n_samp >= 2, n_batch >= 1 and c != 0 (else HCI_E_ARG).
+ *   Synchronises the stream. */
+int hci_pt2_stochastic(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double e0,
+                       double eps2, double eps2_d, const double* u, int64_t n_samp, int64_t n_batch,
+                       double* e2s_out, double* e2sd_out, void* stream);
+
+/* Semistochastic second-order energy, eq. semistoc:
+ *   E2 = E2^D(eps2_d) + mean_b [E2^S_b(eps2) - E2^S_b(eps2_d)],
+ * E2^D by hci_pt2 at eps2_d (in passes when over the pt2 budget), the
+ * batches as hci_pt2_stochastic.  e2_out (host): E2.  err_out (host, may be
+ * NULL): standard error of the mean over batches (NaN for one batch).
+ * e2d_out (host, may be NULL): E2^D(eps2_d).  Arguments and errors as
+ * hci_pt2_stochastic.  Synchronises the stream. */
+int hci_pt2_semistochastic(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double e0,
+                           double eps2, double eps2_d, const double* u, int64_t n_samp, int64_t n_batch,
+                           double* e2_out, double* err_out, double* e2d_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -222,6 +222,44 @@ class HCIContext:
                             _lib._stream()))
         return float(e2.value), r, int(nc.value)
 
+    def set_pt2_budget(self, nbytes: int) -> None:
+        """Device bytes the screened PT2 pairs may hold at once."""
+        check(lib().hci_ctx_set_pt2_budget(self.handle, int(nbytes)))
+
+    def _uniforms(self, u):
+        u = torch.as_tensor(u, dtype=torch.float64).to(self.device).contiguous()
+        if u.dim() != 2:
+            raise ValueError("u must have shape [n_batch, n_samp]")
+        return u
+
+    def pt2_stochastic(self, dets, c, e0: float, eps2: float, eps2_d: float, u):
+        """Per-batch sampled estimates (E2^S(eps2), E2^S(eps2_d)) of eq. semistoc
+        from the uniforms u [n_batch, n_samp] (numpy arrays of n_batch)."""
+        d = self._dets(dets)
+        c = torch.as_tensor(c, dtype=torch.float64).to(self.device).contiguous()
+        u = self._uniforms(u)
+        nb, ns = u.shape
+        a = np.zeros(nb)
+        b = np.zeros(nb)
+        check(lib().hci_pt2_stochastic(self.handle, _lib._ptr(d), d.shape[0], _lib._ptr(c), float(e0),
+                                       float(eps2), float(eps2_d), _lib._ptr(u), ns, nb,
+                                       a.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p),
+                                       _lib._stream()))
+        return a, b
+
+    def pt2_semistochastic(self, dets, c, e0: float, eps2: float, eps2_d: float, u):
+        """eq. semistoc: (E2, standard error over batches, E2^D(eps2_d))."""
+        d = self._dets(dets)
+        c = torch.as_tensor(c, dtype=torch.float64).to(self.device).contiguous()
+        u = self._uniforms(u)
+        nb, ns = u.shape
+        e2, err, e2d = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        check(lib().hci_pt2_semistochastic(self.handle, _lib._ptr(d), d.shape[0], _lib._ptr(c),
+                                           float(e0), float(eps2), float(eps2_d), _lib._ptr(u), ns, nb,
+                                           ctypes.byref(e2), ctypes.byref(err), ctypes.byref(e2d),
+                                           _lib._stream()))
+        return float(e2.value), float(err.value), float(e2d.value)
+
     # ---------------------------------------------------------------- driver
     def hci(self, eps1: float, max_macro: int = 20, tol: float = 1e-8, precision="fp64",
             mode="auto", dets0=None, log=None):

@@ -75,6 +75,10 @@ _SIGNATURES = {
     "hci_energy_backward": [_vp, _vp, _i64, _vp, _f64, _f64, _vp, _f64, _f64, _i32, _vp, _vp,
                             _vp, _vp, _vp],
     "hci_pt2": [_vp, _vp, _i64, _vp, _f64, _f64, _vp, _vp, _vp, _vp],
+    "hci_ctx_set_pt2_budget": [_vp, _i64],
+    "hci_pt2_stochastic": [_vp, _vp, _i64, _vp, _f64, _f64, _f64, _vp, _i64, _i64, _vp, _vp, _vp],
+    "hci_pt2_semistochastic": [_vp, _vp, _i64, _vp, _f64, _f64, _f64, _vp, _i64, _i64, _vp, _vp, _vp,
+                               _vp],
 }
 
 _lib = None

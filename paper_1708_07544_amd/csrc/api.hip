@@ -4,6 +4,9 @@
 #include <cstring>
 #include <string>
 
+#include <vector>
+#include <limits>
+#include <cmath>
 #include "common.h"
 
 namespace {
@@ -473,12 +476,63 @@ int hci_pt2(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, d
         HCI_REQUIRE(eps2 >= 0.0, HCI_E_ARG, "eps2 must be >= 0");
         hipStream_t s = as_stream(stream);
         get_space(ctx, dets, n_var, s);  // validation
-        auto st = pt2_run(ctx, dets, n_var, c, e0 - ctx->ecore, eps2, s);
-        if (r_out)
-            HIP_CHECK(hipMemcpyAsync(r_out, st->r.ptr, sizeof(double) * n_var, hipMemcpyDeviceToDevice, s));
+        i64 nc = 0;
+        const double e2 = pt2_energy(ctx, dets, n_var, c, e0 - ctx->ecore, eps2, r_out, &nc, nullptr, s);
         HIP_CHECK(hipStreamSynchronize(s));
-        *e2_out = st->e2;
-        if (n_conn_out) *n_conn_out = st->nC;
+        *e2_out = e2;
+        if (n_conn_out) *n_conn_out = nc;
+        return HCI_OK;
+    });
+}
+
+int hci_ctx_set_pt2_budget(hci_ctx ctx, int64_t bytes) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && bytes > 0, HCI_E_ARG, "bad context or budget");
+        ctx->pt2_budget = bytes;
+        return HCI_OK;
+    });
+}
+
+int hci_pt2_stochastic(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double e0,
+                       double eps2, double eps2_d, const double* u, int64_t n_samp, int64_t n_batch,
+                       double* e2s_out, double* e2sd_out, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && c && u && e2s_out && e2sd_out, HCI_E_ARG, "null argument");
+        HCI_REQUIRE(eps2 >= 0.0 && eps2_d >= eps2, HCI_E_ARG, "need 0 <= eps2 <= eps2_d");
+        HCI_REQUIRE(n_samp >= 2 && n_batch >= 1, HCI_E_ARG, "need n_samp >= 2 and n_batch >= 1");
+        hipStream_t s = as_stream(stream);
+        get_space(ctx, dets, n_var, s);  // validation
+        pt2_stochastic(ctx, dets, n_var, c, e0 - ctx->ecore, eps2, eps2_d, u, n_samp, n_batch, e2s_out,
+                       e2sd_out, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        return HCI_OK;
+    });
+}
+
+int hci_pt2_semistochastic(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double e0,
+                           double eps2, double eps2_d, const double* u, int64_t n_samp, int64_t n_batch,
+                           double* e2_out, double* err_out, double* e2d_out, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && c && u && e2_out, HCI_E_ARG, "null argument");
+        HCI_REQUIRE(eps2 >= 0.0 && eps2_d >= eps2, HCI_E_ARG, "need 0 <= eps2 <= eps2_d");
+        HCI_REQUIRE(n_samp >= 2 && n_batch >= 1, HCI_E_ARG, "need n_samp >= 2 and n_batch >= 1");
+        hipStream_t s = as_stream(stream);
+        get_space(ctx, dets, n_var, s);  // validation
+        const double e0v = e0 - ctx->ecore;
+        const double e2d = pt2_energy(ctx, dets, n_var, c, e0v, eps2_d, nullptr, nullptr, nullptr, s);
+        std::vector<double> a(n_batch), b(n_batch);
+        pt2_stochastic(ctx, dets, n_var, c, e0v, eps2, eps2_d, u, n_samp, n_batch, a.data(), b.data(), s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        double mean = 0.0;
+        for (int64_t k = 0; k < n_batch; ++k) mean += a[k] - b[k];
+        mean /= (double)n_batch;
+        double var = 0.0;
+        for (int64_t k = 0; k < n_batch; ++k) var += (a[k] - b[k] - mean) * (a[k] - b[k] - mean);
+        *e2_out = e2d + mean;
+        if (err_out)
+            *err_out = n_batch > 1 ? std::sqrt(var / (double)(n_batch - 1)) / std::sqrt((double)n_batch)
+                                   : std::numeric_limits<double>::quiet_NaN();
+        if (e2d_out) *e2d_out = e2d;
         return HCI_OK;
     });
 }

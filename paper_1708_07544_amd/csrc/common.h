@@ -291,6 +291,7 @@ struct hci_ctx_s {
     Integrals ints;
     Space* space = nullptr;
     i64 stored_budget = (i64)64 << 30;
+    i64 pt2_budget = (i64)32 << 30;  // screened PT2 pairs held at once
     int stage_wlog = 14;  // log2 of the staged layout's window; 0 = plain CSR
     bool timing = false;
     std::map<std::string, KernelTimer> timers;
@@ -431,6 +432,17 @@ struct Pt2State {
 };
 std::unique_ptr<Pt2State> pt2_run(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double e0,
                                   double eps2, hipStream_t s);
+// device bytes per screened pair while a pass is processed (pairs, sort, segments)
+constexpr i64 PT2_BYTES_PER_PAIR = 128;
+// E2 of eq. pt_hci (and r = dE2/dc at fixed E0 when r != NULL) in passes over
+// hash partitions of the connected determinants sized to ctx->pt2_budget.
+double pt2_energy(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double e0, double eps2,
+                  double* r, i64* nconn, int* npasses, hipStream_t s);
+// nb batches of nd draws each: sampled E2 estimates at eps2 and eps2_d (host
+// arrays e2s, e2sd) from the uniforms u (device [nb][nd]).
+void pt2_stochastic(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double e0, double eps2,
+                    double eps2_d, const double* u, i64 nd, i64 nb, double* e2s, double* e2sd,
+                    hipStream_t s);
 // Q (H - E) Q z = -Q r on c-perp by preconditioned conjugate gradients;
 // returns the number of Hamiltonian products.
 int zvector_solve(hci_ctx_s* ctx, Space* sp, const double* c, double e, const double* r, double* z,
