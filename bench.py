@@ -52,6 +52,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy a 4 GiB buffer once (calibrates HBM byte counters)")
+    ap.add_argument("--pt2-batches", type=int, default=16,
+                    help="batches of the semistochastic PT2 leg (0: skip the leg)")
+    ap.add_argument("--pt2-samples", type=int, default=2000, help="draws per PT2 batch")
+    ap.add_argument("--pt2-eps2", type=float, default=1e-6, help="sampled PT2 threshold")
+    ap.add_argument("--pt2-eps2d", type=float, default=1e-4, help="deterministic PT2 threshold")
+    ap.add_argument("--pt2-cpu-rows", type=int, default=2000,
+                    help="rows of the final space the oracle's PT2 pair walk times")
     return ap.parse_args()
 
 
@@ -152,6 +159,10 @@ def main():
             "gamma_max_abs_diff": float((grads[0] - grads64[0]).abs().max()),
             "Gamma_max_abs_diff": float(2.0 * (grads[1] - grads64[1]).abs().max()),
         }
+    # ---------------------------------------------------------------- PT2
+    pt2 = None
+    if args.pt2_batches > 0:
+        pt2 = pt2_leg(ctx, h, g, V2, c_mixed, e_mixed, args)
     # ---------------------------------------------------------------- roofline
     sk = kernels.get("sigma_stored_f32")
     gk = kernels.get("sigma_stored_f32_g")
@@ -211,9 +222,73 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "pt2": pt2,
     }
     del dav_time_ms
     print(json.dumps(out))
+
+
+PT2_KERNELS = ["pt2_count", "pt2_fill_pairs", "radix_hist", "radix_scatter", "pt2_reduce", "pt2_r",
+               "pt2_insert_v", "pt2_segflags", "pt2_segstarts", "pt2_sum", "pt2s_weights", "pt2s_draw",
+               "pt2s_reduce"]
+
+
+def pt2_leg(ctx, h, g, V2, c, e, args):
+    """Second-order energy on the final space (eq. semistoc): the screened E2
+    at eps2_d in one call, then the semistochastic total (which repeats the
+    deterministic part and adds the batches of draws at eps2); beside it the
+    oracle's screened-pair walk timed on a bounded random sample of rows."""
+    import numpy as np
+    import torch
+
+    import paper_1708_07544_amd as P
+
+    nb, nd = args.pt2_batches, args.pt2_samples
+    rng = np.random.default_rng(17)
+    u = rng.random((nb, nd))
+    ctx.pt2_stochastic(V2, c, e, args.pt2_eps2, args.pt2_eps2d, u[:1])  # warm-up
+    ctx.set_timing(True)
+    ctx.kernel_time("x", reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e2d, _, nconn = ctx.pt2(V2, c, e, args.pt2_eps2d, want_r=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    e2, err, _ = ctx.pt2_semistochastic(V2, c, e, args.pt2_eps2, args.pt2_eps2d, u)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    kern = {}
+    for name in PT2_KERNELS:
+        n_, ms = ctx.kernel_time(name)
+        if n_:
+            kern[name] = {"launches": n_, "total_ms": round(ms, 3)}
+    ctx.kernel_time("x", reset=True)
+    ctx.set_timing(False)
+    nv = int(V2.shape[0])
+    det_ms = (t1 - t0) * 1e3
+    stoch_ms = (t2 - t1) * 1e3 - det_ms
+    log(f"[bench] pt2: E2^D({args.pt2_eps2d:g}) = {e2d:.10f} ({det_ms:.1f} ms), "
+        f"E2({args.pt2_eps2:g}) = {e2:.10f} +- {err:.2e}")
+    out = {"eps2": args.pt2_eps2, "eps2_d": args.pt2_eps2d, "samples_per_batch": nd, "batches": nb,
+           "e2": e2, "e2_stderr": err, "e2_deterministic": e2d, "connected_dets_deterministic": nconn,
+           "ms_deterministic": round(det_ms, 2), "ms_per_batch": round(stoch_ms / nb, 3),
+           "rows_per_s_deterministic": nv / (det_ms * 1e-3), "kernels": kern}
+    if not args.no_cpu and args.pt2_cpu_rows > 0:
+        import oracle as O
+        Vh = P.dets_to_numpy(V2)
+        ch = c.cpu().numpy()
+        rows = np.sort(np.random.default_rng(18).choice(nv, args.pt2_cpu_rows, replace=False))
+        cs = np.zeros_like(ch)
+        cs[rows] = ch[rows]
+        t3 = time.perf_counter()
+        O.pt2_pairs(h, g, Vh, cs, args.pt2_eps2d)
+        dt = time.perf_counter() - t3
+        out["cpu_oracle"] = {"rows_per_s": len(rows) / dt, "cores": 1, "kind": "oracle",
+                             "sample": f"{len(rows)} random rows of the {nv}-determinant space, "
+                                       f"oracle screened-pair walk at eps2 = {args.pt2_eps2d:g} "
+                                       f"(every excitation evaluated, count and fill walks), "
+                                       f"{dt:.1f} s"}
+    return out
 
 
 def measured_traffic(nv):

@@ -255,7 +255,7 @@ int hci_pt2(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, d
             double eps2, double* e2_out, double* r_out, int64_t* n_conn_out, void* stream);
 
 /* Device memory (bytes) the screened PT2 pairs may hold at once (default
- * 32 GiB, about 128 B per pair).  hci_pt2 and the deterministic part of
+ * 64 GiB, about 128 B per pair).  hci_pt2 and the deterministic part of
  * hci_pt2_semistochastic take the pairs in several passes over a hash
  * partition of the connected determinants when they exceed it (the memory
  * bottleneck of eq. pt_hci); hci_energy_backward with eps2 > 0 keeps all

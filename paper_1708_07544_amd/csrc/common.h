@@ -291,7 +291,7 @@ struct hci_ctx_s {
     Integrals ints;
     Space* space = nullptr;
     i64 stored_budget = (i64)64 << 30;
-    i64 pt2_budget = (i64)32 << 30;  // screened PT2 pairs held at once
+    i64 pt2_budget = (i64)64 << 30;  // screened PT2 pairs held at once
     int stage_wlog = 14;  // log2 of the staged layout's window; 0 = plain CSR
     bool timing = false;
     std::map<std::string, KernelTimer> timers;

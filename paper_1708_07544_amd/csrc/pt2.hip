@@ -300,6 +300,22 @@ __global__ void sum_fixed(const double* __restrict__ x, i64 n, double* __restric
     if (threadIdx.x == 0) *out = red[0];
 }
 
+// First level of a fixed-order sum: block b adds x[k] for k = b*256 + t + j*nb*256
+// (strided per thread, then a tree), part[b] = its total.
+__global__ void sum_partials(const double* __restrict__ x, i64 n, double* __restrict__ part) {
+    __shared__ double red[256];
+    const i64 stride = (i64)gridDim.x * 256;
+    double acc = 0.0;
+    for (i64 k = (i64)blockIdx.x * 256 + threadIdx.x; k < n; k += stride) acc += x[k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 __global__ void sq_kernel_pt(const double* __restrict__ d, i64 n, double* __restrict__ out) {
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = d[i] * d[i];
@@ -353,7 +369,7 @@ void vset_build(hci_ctx_s* ctx, const u64* dets, i64 N, VSet& v, hipStream_t s) 
 // V and in hash partition `part` of `nparts`: count, scan, fill in i order.
 struct Pairs {
     DevMem off, a_hi, a_lo, idx, hai;
-    i64 M = 0;
+    i64 M = -1;  // not counted yet
 };
 
 i64 count_pairs(hci_ctx_s* ctx, const VSet& v, const u64* dets, const double* c, i64 N, double eps,
@@ -369,9 +385,10 @@ i64 count_pairs(hci_ctx_s* ctx, const VSet& v, const u64* dets, const double* c,
     return read_scalar(off.as<i64>() + N, s);
 }
 
+// (P.off and P.M already hold the count of this pass when P.M >= 0 on entry)
 void walk_pairs(hci_ctx_s* ctx, const VSet& v, const u64* dets, const double* c, i64 N, double eps,
                 double hbm, u32 nparts, u32 part, Pairs& P, hipStream_t s) {
-    P.M = count_pairs(ctx, v, dets, c, N, eps, hbm, nparts, part, P.off, s);
+    if (P.M < 0) P.M = count_pairs(ctx, v, dets, c, N, eps, hbm, nparts, part, P.off, s);
     HCI_REQUIRE(P.M < ((i64)1 << 32) - 1, HCI_E_UNSUPPORTED, "pt2: more than 2^32 screened pairs in one pass");
     const i64 Ma = P.M > 0 ? P.M : 1;
     P.a_hi = dev_alloc(ctx, sizeof(u64) * Ma, s);
@@ -422,11 +439,13 @@ void sort_segments(hci_ctx_s* ctx, const u64* a_hi, const u64* a_lo, i64 M, Segs
                M, G.start.as<i64>(), khi.as<u64>(), klo.as<u64>(), G.ca.as<u64>(), G.cb.as<u64>());
 }
 
-// fixed-order sums of x[0, n) into out[0] (one block)
+// fixed-order sum of x[0, n): block partials, then one block over them
 double sum_to_host(hci_ctx_s* ctx, const double* x, i64 n, hipStream_t s) {
-    DevMem out = dev_alloc(ctx, sizeof(double), s);
-    HCI_LAUNCH(ctx, "pt2_sum", s, sum_fixed, 1, 256, 0, x, n, out.as<double>());
-    return read_scalar(out.as<double>(), s);
+    const i64 nb = std::max<i64>(1, std::min<i64>(1024, ceil_div(n, 256 * 8)));
+    DevMem part = dev_alloc(ctx, sizeof(double) * (nb + 1), s);
+    HCI_LAUNCH(ctx, "pt2_sum", s, sum_partials, nb, 256, 0, x, n, part.as<double>());
+    HCI_LAUNCH(ctx, "pt2_sum", s, sum_fixed, 1, 256, 0, part.as<double>(), nb, part.as<double>() + nb);
+    return read_scalar(part.as<double>() + nb, s);
 }
 
 }  // namespace
@@ -489,15 +508,19 @@ double pt2_energy(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, doubl
     // passes over hash partitions of a sized to the pt2 memory budget
     DevMem off_all;
     const i64 Mall = count_pairs(ctx, v, dets, c, N, eps2, hbm, 1, 0, off_all, s);
-    off_all = DevMem();
     const i64 budget = std::max<i64>(ctx->pt2_budget, PT2_BYTES_PER_PAIR);
     const i64 nparts = std::max<i64>(1, ceil_div(Mall * PT2_BYTES_PER_PAIR, budget));
     HCI_REQUIRE(nparts <= 65536, HCI_E_NOMEM, "pt2: more than 65536 passes needed for the memory budget");
+    if (nparts > 1) off_all = DevMem();
     if (r) HIP_CHECK(hipMemsetAsync(r, 0, sizeof(double) * N, s));
     double e2 = 0.0;
     i64 nc = 0;
     for (i64 part = 0; part < nparts; ++part) {
         Pairs P;
+        if (nparts == 1) {  // the sizing count is this pass's count
+            P.M = Mall;
+            P.off = std::move(off_all);
+        }
         walk_pairs(ctx, v, dets, c, N, eps2, hbm, (u32)nparts, (u32)part, P, s);
         if (P.M == 0) continue;
         Segs G;

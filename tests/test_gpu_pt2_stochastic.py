@@ -103,7 +103,7 @@ def test_deterministic_e2_in_passes(case, lib_mod):
     try:
         e2_p, r_p, nc_p = ctx.pt2(V, c, e0, eps2)
     finally:
-        ctx.set_pt2_budget(32 << 30)
+        ctx.set_pt2_budget(64 << 30)
     print(f"[pt2 passes {case['name']}] pairs {npairs} |C| {len(ref['C'])} E2 {e2_1:.15f} {e2_p:.15f}",
           flush=True)
     assert nc_1 == nc_p == len(ref["C"])
