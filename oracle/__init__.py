@@ -29,6 +29,17 @@ Where each function comes from (paper sections/equations):
   (eq. h0, eq. pt, eq. pt_hci, Hylleraas functional eq. hylleraas).
 * ``zvector_dense`` -- the Lagrange-multiplier equation for lambda_c
   (eq. lagd, eq. lagc and the simplified form after them).
+* ``orbital_gradient`` / ``rotate_integrals`` -- the orbital step of
+  aHCISCF (Sec. "HCI self-consistent field", eq. lambda and eq. vdedk2: the
+  energy gradient in the orbital rotation parameters kappa is the integral
+  derivatives contracted with the density matrices).  Only active-active
+  rotations exist here: h' = U^T h U, (pq|rs)' = sum U_ap U_bq U_cr U_ds
+  (ab|cd) with U = exp(kappa), kappa antisymmetric.  The paper refers the
+  integral derivatives to other work; written out for
+  E = sum h_pq gamma_pq + 1/2 sum (pq|rs) Gamma_pqrs they give
+  dE/dkappa_xy = 2 (F_xy - F_yx), F = h gamma + G,
+  G_xy = sum_qrs (xq|rs) Gamma_yqrs (density matrices with the index
+  symmetries of a real state).
 * ``pt2_sample`` / ``pt2_stochastic*`` / ``pt2_semistochastic`` -- the
   semistochastic second-order energy, eq. semistoc: a deterministic E2 at a
   loose eps2_d plus the difference of two sampled estimates (tight eps2 and
@@ -536,3 +547,19 @@ def pt2_semistochastic(h, g, V, c, e0, eps2, eps2_d, u_batches):
     diff = np.array([x - y for x, y in per])
     err = float(np.std(diff, ddof=1) / np.sqrt(len(diff))) if len(diff) > 1 else float("nan")
     return e2d + float(np.mean(diff)), err, e2d, per
+
+
+def orbital_gradient(h, g, rdm1, rdm2):
+    """dE/dkappa for active-active rotations (antisymmetric [n][n], entry
+    (x, y) the derivative along kappa_xy = -kappa_yx): 2 (F - F^T) with
+    F_xy = sum_r h_xr gamma_ry + sum_qrs (xq|rs) Gamma_yqrs."""
+    F = np.asarray(h) @ np.asarray(rdm1) + np.einsum("xqrs,yqrs->xy", g, rdm2)
+    return 2.0 * (F - F.T)
+
+
+def rotate_integrals(h, g, U):
+    """h' = U^T h U and (pq|rs)' = sum_abcd U_ap U_bq U_cr U_ds (ab|cd)."""
+    U = np.asarray(U, dtype=np.float64)
+    h2 = U.T @ np.asarray(h) @ U
+    g2 = np.einsum("abcd,ap,bq,cr,ds->pqrs", g, U, U, U, U, optimize=True)
+    return h2, g2
