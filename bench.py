@@ -35,6 +35,7 @@ if ROOT not in sys.path:
 
 METRIC = "sigma det-pairs/s + Davidson iter/s, FP32-mixed vs FP64 at ≤1e-6 Ha error"
 HBM_PEAK_GBS = 8000.0
+MFMA_F64_PEAK_TFLOPS = 78.6
 
 
 def log(msg):
@@ -57,6 +58,8 @@ def parse():
     ap.add_argument("--pt2-samples", type=int, default=2000, help="draws per PT2 batch")
     ap.add_argument("--pt2-eps2", type=float, default=1e-6, help="sampled PT2 threshold")
     ap.add_argument("--pt2-eps2d", type=float, default=1e-4, help="deterministic PT2 threshold")
+    ap.add_argument("--orbital-reps", type=int, default=20,
+                    help="timed repetitions of the orbital-step leg (0: skip it)")
     ap.add_argument("--pt2-cpu-rows", type=int, default=2000,
                     help="rows of the final space the oracle's PT2 pair walk times")
     return ap.parse_args()
@@ -163,6 +166,9 @@ def main():
     pt2 = None
     if args.pt2_batches > 0:
         pt2 = pt2_leg(ctx, h, g, V2, c_mixed, e_mixed, args)
+    orbital = None
+    if args.orbital_reps > 0:
+        orbital = orbital_leg(args)
     # ---------------------------------------------------------------- roofline
     sk = kernels.get("sigma_stored_f32")
     gk = kernels.get("sigma_stored_f32_g")
@@ -223,6 +229,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "pt2": pt2,
+        "orbital": orbital,
     }
     del dav_time_ms
     print(json.dumps(out))
@@ -289,6 +296,75 @@ def pt2_leg(ctx, h, g, V2, c, e, args):
                                        f"(every excitation evaluated, count and fill walks), "
                                        f"{dt:.1f} s"}
     return out
+
+
+def orbital_leg(args):
+    """Orbital step at (44e,44o) size: gradient dE/dkappa (an n x n^3 by n^3 x n
+    float64 product) and the rotated integrals (four n^3 x n by n x n
+    products), timed by the library's events; beside them the oracle's numpy
+    contractions of the same definitions."""
+    import numpy as np
+    import scipy.linalg
+    import torch
+
+    import hci_synth as hs
+    import paper_1708_07544_amd as P
+
+    w = hs.WORKLOADS["cas44"]
+    h, g = hs.workload_integrals(w)
+    n = w.norb
+    ctx = P.HCIContext(h, g, w.nalpha, w.nbeta)
+    rng = np.random.default_rng(44)
+    r1 = rng.normal(size=(n, n))
+    r1 = r1 + r1.T
+    r2 = rng.normal(size=(n, n, n, n))
+    r2 = r2 + r2.transpose(2, 3, 0, 1)
+    r2 = r2 + r2.transpose(1, 0, 3, 2)
+    k = rng.normal(scale=0.1, size=(n, n))
+    U = scipy.linalg.expm(k - k.T)
+    r1d = torch.as_tensor(r1, device="cuda")
+    r2d = torch.as_tensor(r2, device="cuda")
+    Ud = torch.as_tensor(U, device="cuda")
+    ctx.orbital_gradient(r1d, r2d)
+    ctx.rotate_integrals(Ud)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ctx.kernel_time("x", reset=True)
+    for _ in range(args.orbital_reps):
+        ctx.orbital_gradient(r1d, r2d)
+        ctx.rotate_integrals(Ud)
+    torch.cuda.synchronize()
+    ng, msg = ctx.kernel_time("orb_gradient")
+    nr, msr = ctx.kernel_time("orb_rotate")
+    ctx.kernel_time("x", reset=True)
+    ctx.set_timing(False)
+    ctx.close()
+    grad_ms = msg / args.orbital_reps
+    rot_ms = msr / args.orbital_reps
+    grad_flops = 2.0 * n ** 5 + 4.0 * n ** 3
+    rot_flops = 4 * 2.0 * n ** 5 + 2 * 2.0 * n ** 3
+    rot_bytes = 4 * 16.0 * n ** 4 + 2 * 16.0 * n ** 2 + 8.0 * n ** 2
+    t0 = time.perf_counter()
+    O_grad_s = None
+    import oracle as O
+    O.orbital_gradient(h, g, r1, r2)
+    t1 = time.perf_counter()
+    O.rotate_integrals(h, g, U)
+    t2 = time.perf_counter()
+    O_grad_s = t1 - t0
+    rot_tflops = rot_flops / (rot_ms * 1e-3) / 1e12
+    rot_gbs = rot_bytes / (rot_ms * 1e-3) / 1e9
+    log(f"[bench] orbital n={n}: gradient {grad_ms:.4f} ms, rotation {rot_ms:.4f} ms")
+    return {"n": n, "gradient_ms": round(grad_ms, 4), "rotate_ms": round(rot_ms, 4),
+            "gradient_tflops": round(grad_flops / (grad_ms * 1e-3) / 1e12, 3),
+            "rotate_tflops": round(rot_tflops, 3),
+            "roofline": {"kernel": "quarter transforms of the rotation (4 per call)", "bound": "hbm",
+                         "achieved": round(rot_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(rot_gbs / HBM_PEAK_GBS, 4),
+                         "mfma_f64_frac": round(rot_tflops / MFMA_F64_PEAK_TFLOPS, 4),
+                         "bytes_per_call": rot_bytes, "flops_per_call": rot_flops},
+            "cpu_oracle": {"gradient_ms": round(O_grad_s * 1e3, 2), "rotate_ms": round((t2 - t1) * 1e3, 2),
+                           "kind": "oracle", "sample": "numpy einsum of the same definitions, one call each"}}
 
 
 def measured_traffic(nv):

@@ -254,6 +254,31 @@ int hci_energy_backward(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const 
 int hci_pt2(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double e0,
             double eps2, double* e2_out, double* r_out, int64_t* n_conn_out, void* stream);
 
+/* Orbital gradient for active-active rotations (Sec. "HCI self-consistent
+ * field": eq. vdedk2 with the variational density matrices, eq. lambda with
+ * the relaxed ones).  For orbitals rotated by U = exp(kappa), kappa
+ * antisymmetric (h' = U^T h U, (pq|rs)' = sum U_ap U_bq U_cr U_ds (ab|cd)),
+ * the energy E = sum h_pq gamma_pq + 1/2 sum (pq|rs) Gamma_pqrs of fixed
+ * density matrices has dE/dkappa_xy = 2 (F_xy - F_yx) at kappa = 0, with
+ * F = h gamma + G, G_xy = sum_qrs (xq|rs) Gamma_yqrs (the integrals of the
+ * context).
+ *   rdm1: device float64 [n][n] gamma; rdm2: device float64 [n]^4 Gamma, both
+ *   with the index symmetries of a real state (gamma symmetric,
+ *   Gamma_pqrs = Gamma_rspq = Gamma_qpsr), as hci_rdm12 (bra = ket) returns
+ *   them, or gamma = dh and Gamma = 2 dg of hci_energy_backward.
+ *   grad: device float64 [n][n], antisymmetric (overwritten).
+ *   Asynchronous on the stream. */
+int hci_orbital_gradient(hci_ctx ctx, const double* rdm1, const double* rdm2, double* grad, void* stream);
+
+/* Integrals of the context's h, g in rotated orbitals phi'_p = sum_a phi_a U_ap:
+ * h_out = U^T h U, g_out_pqrs = sum_abcd U_ap U_bq U_cr U_ds (ab|cd) (the
+ * active-space integral transformation of the orbital step).  U: device
+ * float64 [n][n] (row a, column p), normally orthogonal (not checked).
+ * h_out: device [n][n]; g_out: device [n]^4 (overwritten; not aliasing the
+ * context's copies).  Hand them to hci_ctx_update_integrals to continue with
+ * the rotated orbitals.  Scratch: 2 n^4 float64.  Asynchronous on the stream. */
+int hci_rotate_integrals(hci_ctx ctx, const double* U, double* h_out, double* g_out, void* stream);
+
 /* Device memory (bytes) the screened PT2 pairs may hold at once (default
  * 64 GiB, about 128 B per pair).  hci_pt2 and the deterministic part of
  * hci_pt2_semistochastic take the pairs in several passes over a hash

@@ -222,6 +222,31 @@ class HCIContext:
                             _lib._stream()))
         return float(e2.value), r, int(nc.value)
 
+    def orbital_gradient(self, rdm1, rdm2) -> torch.Tensor:
+        """dE/dkappa (antisymmetric [n][n]) of E = sum h gamma + 1/2 sum g Gamma
+        for active-active rotations of this context's orbitals."""
+        r1 = torch.as_tensor(rdm1, dtype=torch.float64).to(self.device).contiguous()
+        r2 = torch.as_tensor(rdm2, dtype=torch.float64).to(self.device).contiguous()
+        n = self.norb
+        if r1.shape != (n, n) or r2.shape != (n, n, n, n):
+            raise ValueError("rdm1 must be [n,n] and rdm2 [n,n,n,n]")
+        grad = torch.empty((n, n), dtype=torch.float64, device=self.device)
+        check(lib().hci_orbital_gradient(self.handle, _lib._ptr(r1), _lib._ptr(r2), _lib._ptr(grad),
+                                         _lib._stream()))
+        return grad
+
+    def rotate_integrals(self, U) -> Tuple[torch.Tensor, torch.Tensor]:
+        """(U^T h U, (U x U x U x U)^T g) of this context's integrals."""
+        n = self.norb
+        U = torch.as_tensor(U, dtype=torch.float64).to(self.device).contiguous()
+        if U.shape != (n, n):
+            raise ValueError("U must be [n,n]")
+        h2 = torch.empty((n, n), dtype=torch.float64, device=self.device)
+        g2 = torch.empty((n, n, n, n), dtype=torch.float64, device=self.device)
+        check(lib().hci_rotate_integrals(self.handle, _lib._ptr(U), _lib._ptr(h2), _lib._ptr(g2),
+                                         _lib._stream()))
+        return h2, g2
+
     def set_pt2_budget(self, nbytes: int) -> None:
         """Device bytes the screened PT2 pairs may hold at once."""
         check(lib().hci_ctx_set_pt2_budget(self.handle, int(nbytes)))

@@ -485,6 +485,22 @@ int hci_pt2(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, d
     });
 }
 
+int hci_orbital_gradient(hci_ctx ctx, const double* rdm1, const double* rdm2, double* grad, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && rdm1 && rdm2 && grad, HCI_E_ARG, "null argument");
+        orbital_gradient(ctx, rdm1, rdm2, grad, as_stream(stream));
+        return HCI_OK;
+    });
+}
+
+int hci_rotate_integrals(hci_ctx ctx, const double* U, double* h_out, double* g_out, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && U && h_out && g_out, HCI_E_ARG, "null argument");
+        rotate_integrals(ctx, U, h_out, g_out, as_stream(stream));
+        return HCI_OK;
+    });
+}
+
 int hci_ctx_set_pt2_budget(hci_ctx ctx, int64_t bytes) {
     return guarded([&]() -> int {
         HCI_REQUIRE(ctx != nullptr && bytes > 0, HCI_E_ARG, "bad context or budget");

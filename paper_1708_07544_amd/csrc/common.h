@@ -432,6 +432,10 @@ struct Pt2State {
 };
 std::unique_ptr<Pt2State> pt2_run(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double e0,
                                   double eps2, hipStream_t s);
+// orbital step (active-active rotations): grad = dE/dkappa (n x n), and the
+// rotated integrals of the context's h, g under U
+void orbital_gradient(hci_ctx_s* ctx, const double* rdm1, const double* rdm2, double* grad, hipStream_t s);
+void rotate_integrals(hci_ctx_s* ctx, const double* U, double* h_out, double* g_out, hipStream_t s);
 // device bytes per screened pair while a pass is processed (pairs, sort, segments)
 constexpr i64 PT2_BYTES_PER_PAIR = 128;
 // E2 of eq. pt_hci (and r = dE2/dc at fixed E0 when r != NULL) in passes over

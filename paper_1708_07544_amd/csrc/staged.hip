@@ -469,40 +469,84 @@ __global__ void __launch_bounds__(ST_BLOCK) st_ab_kernel(SpaceView S, StView T, 
 }
 
 // Element pass: decode each stored column back to its determinant and
-// evaluate H_ij in float64 (rounded to the stored precision).
-template <class VT>
-__global__ void __launch_bounds__(ST_ROW_BLOCK) st_vals_kernel(SpaceView S, IntView I, StView T,
-                                                               VT* __restrict__ vals) {
-    const i64 i = (i64)blockIdx.x * ST_ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
-    if (i >= S.N) return;
-    const u32 a = S.ia[i];
-    const u32 ns = T.nseg[a];
+// evaluate H_ij in float64 (written rounded to float32 when OUT & 1, as
+// float64 when OUT & 2; the float32-mixed solver refines with float64
+// products, so it asks for both).  Workgroup = a chunk of rows of one alpha
+// bucket, as the product: the bucket's stage ranges (start position, first
+// row and alpha string of each range) sit in LDS, so decoding a window
+// column is a binary search there; a beta-group entry has the row's beta
+// string.
+template <int OUT>
+__global__ void __launch_bounds__(ST_BLOCK) st_vals_kernel(SpaceView S, IntView I, StView T,
+                                                           float* __restrict__ v32,
+                                                           double* __restrict__ v64) {
+    extern __shared__ __align__(16) unsigned char st_smem[];
+    __shared__ u32 sh[3];
+    const u32 tid = threadIdx.x;
+    const u32 wave = tid / HCI_WAVE;
+    if (tid == 0) {
+        // bucket of this workgroup: the last a with cptr[a] <= blockIdx.x
+        const u32 w = blockIdx.x;
+        u32 lo = 0, hi = (u32)T.nua - 1u;
+        while (lo < hi) {
+            const u32 mid = (lo + hi + 1u) >> 1;
+            if (T.cptr[mid] <= w) lo = mid;
+            else hi = mid - 1u;
+        }
+        const u32 r0 = S.aoff[lo] + (w - T.cptr[lo]) * ST_CHUNK;
+        sh[0] = lo;
+        sh[1] = r0;
+        sh[2] = min(r0 + ST_CHUNK, S.aoff[lo + 1]);
+    }
+    __syncthreads();
+    const u32 a = sh[0], r0 = sh[1], r1 = sh[2];
     const u32 t0 = S.as_ptr[a];
     const u32 nr = 1u + S.as_ptr[a + 1] - t0;
-    const u32* xs = T.xpos + t0 + a;
-    const u64 ai = S.alpha[i], bi = S.beta[i];
-    const i64 sb = T.rsb[i];
-    const u32 gb = S.boff[S.ib[i]];
-    for (u32 s = 0; s < ns; ++s) {
-        const i64 k0 = T.sstart[sb + s];
-        const i64 k1 = k0 + pad_vec(T.segcnt[sb + s]);
-        const i64 kr = k0 + T.segcnt[sb + s];
-        for (i64 k = k0 + lane_id(); k < k1; k += HCI_WAVE) {
-            if (k >= kr) {
-                vals[k] = (VT)0;
-                continue;
+    u64* ralpha = reinterpret_cast<u64*>(st_smem);        // [nr]
+    u32* rx = reinterpret_cast<u32*>(ralpha + nr);         // [nr] stage start of each range
+    u32* rbase = rx + nr;                                  // [nr] first row of each range
+    for (u32 e = tid; e < nr; e += ST_BLOCK) {
+        const u32 a2 = e == 0 ? a : S.as_idx[t0 + e - 1];
+        ralpha[e] = S.ua[a2];
+        rx[e] = T.xpos[t0 + a + e];
+        rbase[e] = S.aoff[a2];
+    }
+    __syncthreads();
+    const u32 ns = T.nseg[a];
+    const u64 ai = S.ua[a];
+    for (u32 i = r0 + wave; i < r1; i += ST_WAVES) {
+        const u64 bi = S.beta[i];
+        const i64 sb = T.rsb[i];
+        const u32 gb = S.boff[S.ib[i]];
+        for (u32 sg = 0; sg < ns; ++sg) {
+            const i64 k0 = T.sstart[sb + sg];
+            const u32 cnt = T.segcnt[sb + sg];
+            const i64 k1 = k0 + pad_vec(cnt);
+            const i64 kr = k0 + cnt;
+            for (i64 k = k0 + lane_id(); k < k1; k += HCI_WAVE) {
+                double v = 0.0;
+                if (k < kr) {
+                    const u32 col = T.cols[k];
+                    u64 aj, bj;
+                    if (sg + 1 < ns) {
+                        const u32 P = (sg << T.wlog) + col;
+                        u32 lo = 0, hi = nr - 1u;  // last range starting at or before P
+                        while (lo < hi) {
+                            const u32 mid = (lo + hi + 1u) >> 1;
+                            if (rx[mid] <= P) lo = mid;
+                            else hi = mid - 1u;
+                        }
+                        aj = ralpha[lo];
+                        bj = S.beta[rbase[lo] + (P - rx[lo])];
+                    } else {
+                        aj = S.alpha[S.permb[gb + col]];
+                        bj = bi;
+                    }
+                    v = hij_f64(I, ai, bi, aj, bj);
+                }
+                if constexpr ((OUT & 1) != 0) v32[k] = (float)v;
+                if constexpr ((OUT & 2) != 0) v64[k] = v;
             }
-            const u32 col = T.cols[k];
-            u32 j;
-            if (s + 1 < ns) {
-                const u32 P = (s << T.wlog) + col;
-                const u32 e = upper_bound_u32(xs, nr, P) - 1u;
-                const u32 a2 = e == 0 ? a : S.as_idx[t0 + e - 1];
-                j = S.aoff[a2] + (P - xs[e]);
-            } else {
-                j = S.permb[gb + col];
-            }
-            vals[k] = (VT)hij_f64(I, ai, bi, S.alpha[j], S.beta[j]);
         }
     }
 }
@@ -521,46 +565,6 @@ __global__ void st_gentries_kernel(SpaceView S, StView T, unsigned long long* __
     if (i < S.N) v = pad_vec(T.segcnt[T.rsb[i] + T.nseg[S.ia[i]] - 1]);
     v = wave_sum_u64(v);
     if (lane_id() == 0 && v) atomicAdd(out, (unsigned long long)v);
-}
-
-// Both precisions in one element pass (the float32-mixed solver refines
-// with float64 products, so both are needed).
-__global__ void __launch_bounds__(ST_ROW_BLOCK) st_vals_both_kernel(SpaceView S, IntView I, StView T,
-                                                                    float* __restrict__ v32,
-                                                                    double* __restrict__ v64) {
-    const i64 i = (i64)blockIdx.x * ST_ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
-    if (i >= S.N) return;
-    const u32 a = S.ia[i];
-    const u32 ns = T.nseg[a];
-    const u32 t0 = S.as_ptr[a];
-    const u32 nr = 1u + S.as_ptr[a + 1] - t0;
-    const u32* xs = T.xpos + t0 + a;
-    const u64 ai = S.alpha[i], bi = S.beta[i];
-    const i64 sb = T.rsb[i];
-    const u32 gb = S.boff[S.ib[i]];
-    for (u32 s = 0; s < ns; ++s) {
-        const i64 k0 = T.sstart[sb + s];
-        const i64 k1 = k0 + pad_vec(T.segcnt[sb + s]);
-        const i64 kr = k0 + T.segcnt[sb + s];
-        for (i64 k = k0 + lane_id(); k < k1; k += HCI_WAVE) {
-            double v = 0.0;
-            if (k < kr) {
-                const u32 col = T.cols[k];
-                u32 j;
-                if (s + 1 < ns) {
-                    const u32 P = (s << T.wlog) + col;
-                    const u32 e = upper_bound_u32(xs, nr, P) - 1u;
-                    const u32 a2 = e == 0 ? a : S.as_idx[t0 + e - 1];
-                    j = S.aoff[a2] + (P - xs[e]);
-                } else {
-                    j = S.permb[gb + col];
-                }
-                v = hij_f64(I, ai, bi, S.alpha[j], S.beta[j]);
-            }
-            v32[k] = (float)v;
-            v64[k] = v;
-        }
-    }
 }
 
 // c (float64) -> the product's alpha-major and beta-major copies.
@@ -821,7 +825,8 @@ void launch_spmv(hci_ctx_s* ctx, Space* sp, const char* name, const char* gname,
     const u32 cap = (u32)std::min<i64>((i64)1 << sp->st_wlog, sp->st_gmax);
     const size_t gshmem = sizeof(CT) * (cap > 0 ? cap : 1);
     auto kern = st_spmv_kernel<VT, CT, ST_SUB>;
-    auto gkern = st_spmv_g_kernel<VT, CT, ST_SUB>;
+    // beta-group rows are short (a few hundred entries): 16 lanes per row
+    auto gkern = st_spmv_g_kernel<VT, CT, 16>;
     HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
     HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(gkern),
@@ -970,22 +975,25 @@ void staged_ensure_vals(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s)
                     "internal: " + std::to_string(nbad) + " row segments disagree with the count pass");
     }
     IntView I = int_view(ctx->ints);
+    // element pass per row chunk; LDS: alpha string, stage start and first
+    // row of each of the bucket's ranges (at most 1 + N_alpha (n - N_alpha))
+    const size_t vlds = (size_t)16 * (1 + (size_t)ctx->na * (ctx->n - ctx->na));
     if (f32 && !sp->st_have64 && nnz * (i64)(2 + 4 + 8) <= ctx->stored_budget) {
         sp->st_vals32 = dev_alloc(ctx, sizeof(float) * (nnz > 0 ? nnz : 1), s);
         sp->st_vals64 = dev_alloc(ctx, sizeof(double) * (nnz > 0 ? nnz : 1), s);
-        HCI_LAUNCH(ctx, "csr_vals_f32", s, st_vals_both_kernel, grid, ST_ROW_BLOCK, 0, S, I,
+        HCI_LAUNCH(ctx, "csr_vals_f32", s, st_vals_kernel<3>, sp->st_nchunk, ST_BLOCK, vlds, S, I,
                    st_view(*sp), sp->st_vals32.as<float>(), sp->st_vals64.as<double>());
         sp->st_have32 = true;
         sp->st_have64 = true;
     } else if (f32) {
         sp->st_vals32 = dev_alloc(ctx, sizeof(float) * (nnz > 0 ? nnz : 1), s);
-        HCI_LAUNCH(ctx, "csr_vals_f32", s, st_vals_kernel<float>, grid, ST_ROW_BLOCK, 0, S, I,
-                   st_view(*sp), sp->st_vals32.as<float>());
+        HCI_LAUNCH(ctx, "csr_vals_f32", s, st_vals_kernel<1>, sp->st_nchunk, ST_BLOCK, vlds, S, I,
+                   st_view(*sp), sp->st_vals32.as<float>(), (double*)nullptr);
         sp->st_have32 = true;
     } else {
         sp->st_vals64 = dev_alloc(ctx, sizeof(double) * (nnz > 0 ? nnz : 1), s);
-        HCI_LAUNCH(ctx, "csr_vals_f64", s, st_vals_kernel<double>, grid, ST_ROW_BLOCK, 0, S, I,
-                   st_view(*sp), sp->st_vals64.as<double>());
+        HCI_LAUNCH(ctx, "csr_vals_f64", s, st_vals_kernel<2>, sp->st_nchunk, ST_BLOCK, vlds, S, I,
+                   st_view(*sp), (float*)nullptr, sp->st_vals64.as<double>());
         sp->st_have64 = true;
     }
 }
