@@ -40,6 +40,17 @@ Where each function comes from (paper sections/equations):
   dE/dkappa_xy = 2 (F_xy - F_yx), F = h gamma + G,
   G_xy = sum_qrs (xq|rs) Gamma_yqrs (density matrices with the index
   symmetries of a real state).
+* ``extrapolation_*`` -- the extrapolation to the full-CI limit of Sec.
+  "Results and discussion" (butadiene): after the largest HCI calculation,
+  single-step calculations each drop a fraction (0.33) of the least
+  important determinants; a straight line through (E2, E_var + E2) is
+  evaluated at E2 = 0.  Readings: importance is |c_i| of the largest
+  calculation (one ranking, ties by determinant index, so the spaces are
+  nested), each level keeps ceil(m (1 - fraction)) of the previous m, E2 is
+  the deterministic screened E2 of each level's own eigenpair, the line is the
+  least-squares fit over all levels, and the error estimate is 25% of the
+  distance from the extrapolated energy to the largest calculation's total
+  energy (as the paper's Fe-porphyrin table states).
 * ``pt2_sample`` / ``pt2_stochastic*`` / ``pt2_semistochastic`` -- the
   semistochastic second-order energy, eq. semistoc: a deterministic E2 at a
   loose eps2_d plus the difference of two sampled estimates (tight eps2 and
@@ -563,3 +574,47 @@ def rotate_integrals(h, g, U):
     h2 = U.T @ np.asarray(h) @ U
     g2 = np.einsum("abcd,ap,bq,cr,ds->pqrs", g, U, U, U, U, optimize=True)
     return h2, g2
+
+
+def extrapolation_ranking(c):
+    """Determinant indices by decreasing |c_i| (ties: increasing index)."""
+    c = np.asarray(c, dtype=np.float64)
+    return np.lexsort((np.arange(len(c)), -np.abs(c)))
+
+
+def extrapolation_sizes(n, fraction, levels):
+    """m_0 = n, m_k = max(1, ceil(m_{k-1} (1 - fraction)))."""
+    import math
+    m = [int(n)]
+    for _ in range(1, levels):
+        m.append(max(1, math.ceil(m[-1] * (1.0 - fraction))))
+    return m
+
+
+def extrapolation_fit(e2, etot):
+    """Least-squares line etot = a + b e2: (a, b), written out."""
+    x = np.asarray(e2, dtype=np.float64)
+    y = np.asarray(etot, dtype=np.float64)
+    xm, ym = x.mean(), y.mean()
+    b = float(np.sum((x - xm) * (y - ym)) / np.sum((x - xm) ** 2))
+    return float(ym - b * xm), b
+
+
+def extrapolation(h, g, V, c, fraction, levels, eps2):
+    """Levels of the extrapolation: nested spaces ranked by the given c, each
+    level's lowest eigenpair and its screened E2; the line through
+    (E2, E_var + E2) at E2 = 0.  Returns dict(sizes, evar, e2, e_extrap,
+    slope, error)."""
+    V = np.asarray(V)
+    order = extrapolation_ranking(c)
+    sizes = extrapolation_sizes(len(V), fraction, levels)
+    evar, e2 = [], []
+    for m in sizes:
+        Vk = V[np.sort(order[:m])]
+        e, ck = lowest_eigenpair(h, g, Vk)
+        evar.append(e)
+        e2.append(pt2(h, g, Vk, ck, e, eps2)["E2"])
+    etot = np.array(evar) + np.array(e2)
+    a, b = extrapolation_fit(e2, etot)
+    return dict(sizes=sizes, evar=np.array(evar), e2=np.array(e2), e_extrap=a, slope=b,
+                error=0.25 * abs(a - etot[0]))
