@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--pt2-samples", type=int, default=2000, help="draws per PT2 batch")
     ap.add_argument("--pt2-eps2", type=float, default=1e-6, help="sampled PT2 threshold")
     ap.add_argument("--pt2-eps2d", type=float, default=1e-4, help="deterministic PT2 threshold")
+    ap.add_argument("--extrap-levels", type=int, default=3,
+                    help="levels of the full-CI extrapolation leg on the final space (0: skip it)")
     ap.add_argument("--orbital-reps", type=int, default=20,
                     help="timed repetitions of the orbital-step leg (0: skip it)")
     ap.add_argument("--pt2-cpu-rows", type=int, default=2000,
@@ -166,6 +168,20 @@ def main():
     pt2 = None
     if args.pt2_batches > 0:
         pt2 = pt2_leg(ctx, h, g, V2, c_mixed, e_mixed, args)
+    extrap = None
+    if args.extrap_levels >= 2:
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        r = ctx.extrapolate(V2, c_mixed, fraction=0.33, levels=args.extrap_levels, eps2=args.pt2_eps2d,
+                            tol=args.tol, precision="fp32_mixed")
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        extrap = {"levels": args.extrap_levels, "fraction": 0.33, "eps2": args.pt2_eps2d,
+                  "sizes": r["sizes"], "evar": [float(x) for x in r["evar"]], "e2": [float(x) for x in r["e2"]],
+                  "e_extrap": r["e_extrap"], "slope": r["slope"], "error": r["error"],
+                  "seconds": round(t5 - t4, 3)}
+        log(f"[bench] extrapolation: {r['sizes']} -> {r['e_extrap']:.8f} +- {r['error']:.2e} "
+            f"({t5 - t4:.2f} s)")
     orbital = None
     if args.orbital_reps > 0:
         orbital = orbital_leg(args)
@@ -230,6 +246,7 @@ def main():
         "cpu_baseline": cpu,
         "pt2": pt2,
         "orbital": orbital,
+        "extrapolation": extrap,
     }
     del dav_time_ms
     print(json.dumps(out))

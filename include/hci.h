@@ -254,6 +254,26 @@ int hci_energy_backward(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const 
 int hci_pt2(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double e0,
             double eps2, double* e2_out, double* r_out, int64_t* n_conn_out, void* stream);
 
+/* Extrapolation to the full-CI limit (Sec. "Results and discussion": the
+ * procedure of the butadiene calculations).  Starting from the largest
+ * calculation (dets, c), level k keeps the m_k most important determinants
+ * (one ranking by decreasing |c_i|, ties by increasing index, so the levels
+ * are nested; m_0 = n_var, m_k = max(1, ceil(m_{k-1} (1 - fraction)))),
+ * solves for its lowest eigenpair (Davidson from c restricted to the level,
+ * tolerance tol, precision as hci_davidson) and its screened E2 at eps2
+ * (as hci_pt2).  A least-squares line E_var + E2 = a + b E2 over the levels
+ * gives the full-CI estimate a.
+ *   c: device float64 [n_var], the largest calculation's eigenvector (not
+ *   modified).  levels >= 2, 0 < fraction < 1 (the paper uses 0.33),
+ *   eps2 >= 0, tol > 0 (else HCI_E_ARG).
+ *   nvar_out, evar_out, e2_out: host [levels]: m_k, E_var (ecore included),
+ *   E2.  fit_out: host [3]: a, b, and the error estimate
+ *   0.25 |a - (E_var + E2)_0|.  HCI_E_NOCONV when a level's Davidson does
+ *   not converge.  Synchronises the stream. */
+int hci_extrapolate(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double fraction,
+                    int levels, double eps2, double tol, int precision, int64_t* nvar_out, double* evar_out,
+                    double* e2_out, double* fit_out, void* stream);
+
 /* Orbital gradient for active-active rotations (Sec. "HCI self-consistent
  * field": eq. vdedk2 with the variational density matrices, eq. lambda with
  * the relaxed ones).  For orbitals rotated by U = exp(kappa), kappa

@@ -222,6 +222,24 @@ class HCIContext:
                             _lib._stream()))
         return float(e2.value), r, int(nc.value)
 
+    def extrapolate(self, dets, c, fraction: float = 0.33, levels: int = 4, eps2: float = 1e-5,
+                    tol: float = 1e-8, precision="fp64") -> dict:
+        """Extrapolation to the full-CI limit over nested truncations of (dets, c):
+        dict(sizes, evar, e2, e_extrap, slope, error)."""
+        d = self._dets(dets)
+        c = torch.as_tensor(c, dtype=torch.float64).to(self.device).contiguous()
+        nv = np.zeros(levels, dtype=np.int64)
+        ev = np.zeros(levels)
+        e2 = np.zeros(levels)
+        fit = np.zeros(3)
+        vp = ctypes.c_void_p
+        check(lib().hci_extrapolate(self.handle, _lib._ptr(d), d.shape[0], _lib._ptr(c), float(fraction),
+                                    int(levels), float(eps2), float(tol), _PREC[precision],
+                                    nv.ctypes.data_as(vp), ev.ctypes.data_as(vp), e2.ctypes.data_as(vp),
+                                    fit.ctypes.data_as(vp), _lib._stream()))
+        return dict(sizes=[int(x) for x in nv], evar=ev, e2=e2, e_extrap=float(fit[0]), slope=float(fit[1]),
+                    error=float(fit[2]))
+
     def orbital_gradient(self, rdm1, rdm2) -> torch.Tensor:
         """dE/dkappa (antisymmetric [n][n]) of E = sum h gamma + 1/2 sum g Gamma
         for active-active rotations of this context's orbitals."""

@@ -485,6 +485,27 @@ int hci_pt2(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, d
     });
 }
 
+int hci_extrapolate(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double fraction,
+                    int levels, double eps2, double tol, int precision, int64_t* nvar_out, double* evar_out,
+                    double* e2_out, double* fit_out, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && c && nvar_out && evar_out && e2_out && fit_out, HCI_E_ARG,
+                    "null argument");
+        HCI_REQUIRE(levels >= 2 && fraction > 0.0 && fraction < 1.0, HCI_E_ARG,
+                    "need levels >= 2 and 0 < fraction < 1");
+        HCI_REQUIRE(eps2 >= 0.0 && tol > 0.0, HCI_E_ARG, "need eps2 >= 0 and tol > 0");
+        HCI_REQUIRE(precision == HCI_FP64 || precision == HCI_FP32_MIXED, HCI_E_ARG, "bad precision");
+        hipStream_t s = as_stream(stream);
+        get_space(ctx, dets, n_var, s);  // validation
+        drop_space(ctx);
+        static_assert(sizeof(int64_t) == sizeof(i64), "host counts");
+        extrapolate(ctx, dets, n_var, c, fraction, levels, eps2, tol, precision, (i64*)nvar_out, evar_out,
+                    e2_out, fit_out, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        return HCI_OK;
+    });
+}
+
 int hci_orbital_gradient(hci_ctx ctx, const double* rdm1, const double* rdm2, double* grad, void* stream) {
     return guarded([&]() -> int {
         HCI_REQUIRE(ctx != nullptr && rdm1 && rdm2 && grad, HCI_E_ARG, "null argument");

@@ -432,6 +432,11 @@ struct Pt2State {
 };
 std::unique_ptr<Pt2State> pt2_run(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double e0,
                                   double eps2, hipStream_t s);
+// extrapolation to the full-CI limit: per level (host arrays) the determinant
+// count, E_var (ecore included) and E2; fit = {E at E2 = 0, slope, error}
+void extrapolate(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double fraction, int levels,
+                 double eps2, double tol, int precision, i64* nvar, double* evar, double* e2, double* fit,
+                 hipStream_t s);
 // orbital step (active-active rotations): grad = dE/dkappa (n x n), and the
 // rotated integrals of the context's h, g under U
 void orbital_gradient(hci_ctx_s* ctx, const double* rdm1, const double* rdm2, double* grad, hipStream_t s);
