@@ -56,6 +56,8 @@ struct StView {
     const i64* sstart;  // absolute start of every (row, segment), padded to ST_VEC
     const u32* segcnt;  // entries of every (row, segment) before padding
     const u16* cols;
+    const u32* chunk;   // [workgroups][3]: bucket, first row, end row
+    const u32* gchunk;  // [beta-group workgroups][3]: group, first, end position (beta-major)
 };
 
 StView st_view(const Space& s) {
@@ -72,6 +74,8 @@ StView st_view(const Space& s) {
     v.sstart = s.st_sstart.as<i64>();
     v.segcnt = s.st_segcnt.as<u32>();
     v.cols = s.st_cols.as<u16>();
+    v.chunk = s.st_chunk.as<u32>();
+    v.gchunk = s.st_gchunk.as<u32>();
     return v;
 }
 
@@ -107,6 +111,21 @@ __global__ void st_meta_kernel(SpaceView S, u32 wlog, u32* __restrict__ xpos, u3
         gnchunk[t] = (gs + GT_CHUNK - 1) / GT_CHUNK;
         atomicMax(&flags[3], (unsigned long long)gs);
         if (gs > ST_MAX_GROUP) atomicAdd(&flags[1], 1ull);
+    }
+}
+
+// Chunk tables: for workgroup w of the staged kernels its bucket a and rows
+// [r0, r1) (chunks of ST_CHUNK rows of one bucket); for workgroup w of the
+// beta-group kernel its group b and positions [k0, k1) in beta-major order.
+__global__ void st_chunk_table_kernel(const u32* __restrict__ cptr, const u32* __restrict__ off, i64 nbkt,
+                                      u32 chunk, u32* __restrict__ table) {
+    const i64 a = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nbkt) return;
+    for (u32 w = cptr[a]; w < cptr[a + 1]; ++w) {
+        const u32 r0 = off[a] + (w - cptr[a]) * chunk;
+        table[3 * (i64)w] = (u32)a;
+        table[3 * (i64)w + 1] = r0;
+        table[3 * (i64)w + 2] = min(r0 + chunk, off[a + 1]);
     }
 }
 
@@ -268,23 +287,10 @@ __global__ void __launch_bounds__(ST_BLOCK) st_place_kernel(SpaceView S, StView 
                                                             const i64* __restrict__ wscan,
                                                             i64* __restrict__ sstart) {
     __shared__ u32 part[ST_WAVES];
-    __shared__ u32 sh[3];
     const u32 tid = threadIdx.x;
-    if (tid == 0) {
-        const u32 w = blockIdx.x;
-        u32 lo = 0, hi = (u32)T.nua - 1u;
-        while (lo < hi) {
-            const u32 mid = (lo + hi + 1u) >> 1;
-            if (T.cptr[mid] <= w) lo = mid;
-            else hi = mid - 1u;
-        }
-        const u32 r0 = S.aoff[lo] + (w - T.cptr[lo]) * ST_CHUNK;
-        sh[0] = lo;
-        sh[1] = r0;
-        sh[2] = min(r0 + ST_CHUNK, S.aoff[lo + 1]);
-    }
-    __syncthreads();
-    const u32 a = sh[0], r0 = sh[1], r1 = sh[2];
+    // bucket and rows of this workgroup's chunk
+    const u32* ce = T.chunk + 3 * (i64)blockIdx.x;
+    const u32 a = ce[0], r0 = ce[1], r1 = ce[2];
     const u32 nw = T.nseg[a] - 1u;
     const u32 row = r0 + tid;
     const bool has = row < r1;
@@ -396,26 +402,12 @@ __global__ void __launch_bounds__(ST_BLOCK) st_ab_kernel(SpaceView S, StView T, 
     extern __shared__ __align__(16) unsigned char st_smem[];
     u32* bm = reinterpret_cast<u32*>(st_smem);
     u16* pre = reinterpret_cast<u16*>(bm + (size_t)G * W);
-    __shared__ u32 sh[3];
     const u32 tid = threadIdx.x;
     const u32 lane = (u32)lane_id();
     const u32 wave = tid / HCI_WAVE;
-    if (tid == 0) {
-        // bucket of this workgroup: the last a with cptr[a] <= blockIdx.x
-        const u32 w = blockIdx.x;
-        u32 lo = 0, hi = (u32)T.nua - 1u;
-        while (lo < hi) {
-            const u32 mid = (lo + hi + 1u) >> 1;
-            if (T.cptr[mid] <= w) lo = mid;
-            else hi = mid - 1u;
-        }
-        const u32 r0 = S.aoff[lo] + (w - T.cptr[lo]) * ST_CHUNK;
-        sh[0] = lo;
-        sh[1] = r0;
-        sh[2] = min(r0 + ST_CHUNK, S.aoff[lo + 1]);
-    }
-    __syncthreads();
-    const u32 a = sh[0], r0 = sh[1], r1 = sh[2];
+    // bucket and rows of this workgroup's chunk
+    const u32* ce = T.chunk + 3 * (i64)blockIdx.x;
+    const u32 a = ce[0], r0 = ce[1], r1 = ce[2];
     const u32 t0 = S.as_ptr[a], deg = S.as_ptr[a + 1] - t0;
     const u32 xb = t0 + a;
     const u32 ns = T.nseg[a];
@@ -481,25 +473,11 @@ __global__ void __launch_bounds__(ST_BLOCK) st_vals_kernel(SpaceView S, IntView 
                                                            float* __restrict__ v32,
                                                            double* __restrict__ v64) {
     extern __shared__ __align__(16) unsigned char st_smem[];
-    __shared__ u32 sh[3];
     const u32 tid = threadIdx.x;
     const u32 wave = tid / HCI_WAVE;
-    if (tid == 0) {
-        // bucket of this workgroup: the last a with cptr[a] <= blockIdx.x
-        const u32 w = blockIdx.x;
-        u32 lo = 0, hi = (u32)T.nua - 1u;
-        while (lo < hi) {
-            const u32 mid = (lo + hi + 1u) >> 1;
-            if (T.cptr[mid] <= w) lo = mid;
-            else hi = mid - 1u;
-        }
-        const u32 r0 = S.aoff[lo] + (w - T.cptr[lo]) * ST_CHUNK;
-        sh[0] = lo;
-        sh[1] = r0;
-        sh[2] = min(r0 + ST_CHUNK, S.aoff[lo + 1]);
-    }
-    __syncthreads();
-    const u32 a = sh[0], r0 = sh[1], r1 = sh[2];
+    // bucket and rows of this workgroup's chunk
+    const u32* ce = T.chunk + 3 * (i64)blockIdx.x;
+    const u32 a = ce[0], r0 = ce[1], r1 = ce[2];
     const u32 t0 = S.as_ptr[a];
     const u32 nr = 1u + S.as_ptr[a + 1] - t0;
     u64* ralpha = reinterpret_cast<u64*>(st_smem);        // [nr]
@@ -651,27 +629,13 @@ __global__ void __launch_bounds__(ST_BLOCK) st_spmv_kernel(SpaceView S, StView T
                                                            double* __restrict__ sigma) {
     extern __shared__ __align__(16) unsigned char st_smem[];
     CT* stage = reinterpret_cast<CT*>(st_smem);
-    __shared__ u32 sh[3];
     constexpr int GROUPS = HCI_WAVE / SUB;  // rows in flight per wavefront
     const u32 tid = threadIdx.x;
     const int lane = lane_id();
     const u32 wave = tid / HCI_WAVE;
-    if (tid == 0) {
-        // bucket of this workgroup: the last a with cptr[a] <= blockIdx.x
-        const u32 w = blockIdx.x;
-        u32 lo = 0, hi = (u32)T.nua - 1u;
-        while (lo < hi) {
-            const u32 mid = (lo + hi + 1u) >> 1;
-            if (T.cptr[mid] <= w) lo = mid;
-            else hi = mid - 1u;
-        }
-        const u32 r0 = S.aoff[lo] + (w - T.cptr[lo]) * ST_CHUNK;
-        sh[0] = lo;
-        sh[1] = r0;
-        sh[2] = min(r0 + ST_CHUNK, S.aoff[lo + 1]);
-    }
-    __syncthreads();
-    const u32 a = sh[0], r0 = sh[1], r1 = sh[2];
+    // bucket and rows of this workgroup's chunk
+    const u32* ce = T.chunk + 3 * (i64)blockIdx.x;
+    const u32 a = ce[0], r0 = ce[1], r1 = ce[2];
     const u32 t0 = S.as_ptr[a];
     const u32 nr = 1u + S.as_ptr[a + 1] - t0;
     const u32* xs = T.xpos + t0 + a;
@@ -773,25 +737,12 @@ __global__ void __launch_bounds__(GT_BLOCK) st_spmv_g_kernel(SpaceView S, StView
                                                              double* __restrict__ sigma) {
     extern __shared__ __align__(16) unsigned char st_smem[];
     CT* stage = reinterpret_cast<CT*>(st_smem);
-    __shared__ u32 sh[3];
     const u32 tid = threadIdx.x;
     const int lane = lane_id();
     const u32 wave = tid / HCI_WAVE;
-    if (tid == 0) {
-        const u32 w = blockIdx.x;
-        u32 lo = 0, hi = (u32)T.nub - 1u;
-        while (lo < hi) {
-            const u32 mid = (lo + hi + 1u) >> 1;
-            if (T.gcptr[mid] <= w) lo = mid;
-            else hi = mid - 1u;
-        }
-        const u32 k0 = S.boff[lo] + (w - T.gcptr[lo]) * GT_CHUNK;
-        sh[0] = lo;
-        sh[1] = k0;
-        sh[2] = min(k0 + GT_CHUNK, S.boff[lo + 1]);
-    }
-    __syncthreads();
-    const u32 b = sh[0], k0 = sh[1], k1 = sh[2];
+    // beta group and positions (beta-major order) of this workgroup's chunk
+    const u32* ce = T.gchunk + 3 * (i64)blockIdx.x;
+    const u32 b = ce[0], k0 = ce[1], k1 = ce[2];
     const u32 gb = S.boff[b];
     const u32 gsz = S.boff[b + 1] - gb;
     const bool in_lds = gsz <= cap;
@@ -880,6 +831,12 @@ bool staged_prepare(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
     sp->st_gcptr = dev_alloc(ctx, sizeof(u32) * (nub + 1), s);
     scan_u32_to_u32(ctx, gnchunk.as<u32>(), sp->st_gcptr.as<u32>(), nub + 1, s);
     sp->st_gnchunk = read_scalar(sp->st_gcptr.as<u32>() + nub, s);
+    sp->st_chunk = dev_alloc(ctx, sizeof(u32) * 3 * (sp->st_nchunk > 0 ? sp->st_nchunk : 1), s);
+    sp->st_gchunk = dev_alloc(ctx, sizeof(u32) * 3 * (sp->st_gnchunk > 0 ? sp->st_gnchunk : 1), s);
+    HCI_LAUNCH(ctx, "st_meta", s, st_chunk_table_kernel, ceil_div(nua, 256), 256, 0, sp->st_cptr.as<u32>(),
+               sp->aoff.as<u32>(), nua, (u32)ST_CHUNK, sp->st_chunk.as<u32>());
+    HCI_LAUNCH(ctx, "st_meta", s, st_chunk_table_kernel, ceil_div(nub, 256), 256, 0, sp->st_gcptr.as<u32>(),
+               sp->boff.as<u32>(), nub, (u32)GT_CHUNK, sp->st_gchunk.as<u32>());
     // segment slots per row
     DevMem rn = dev_alloc(ctx, sizeof(u32) * (N + 1), s);
     HCI_LAUNCH(ctx, "st_row_nseg", s, st_row_nseg_kernel, ceil_div(N + 1, 256), 256, 0,
