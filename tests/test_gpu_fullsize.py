@@ -6,7 +6,9 @@ V1 + C(1e-4) by the definition of the criterion.  The GPU selection from
 the same (V1, c1) must give the identical 1,138,281-determinant list.  On
 V2 the GPU products (stored float64 and float32-mixed, the benchmark's
 launch configuration) are compared with the oracle's on sampled rows, and
-the density matrices are checked against identities that hold at any size.
+the density matrices are checked against identities that hold at any size;
+the sampled second-order estimates are compared batch by batch and the
+extrapolation levels checked for nesting and the variational bound.
 
 (44e,44o) porphyrin-shaped integrals: two-level hash keys and 64-bit words
 with bits above 32 in use; selection bit-exact and sampled-row products."""
@@ -76,6 +78,39 @@ def test_full_size_variational_and_rdm_identities(P, cas16_v2):
     e_rdm = float(np.sum(h * r1) + 0.5 * np.sum(g * r2))
     assert abs(e_rdm - e) < 1e-7
 
+
+
+def test_pt2_sampled_batches_full_size(P, cas16_v2):
+    """Sampled second-order estimates (eq. semistoc) on the full space: every
+    batch against the oracle on the same draws (a seeded coefficient vector,
+    E0 10 Ha below the V1 energy so no denominator comes near zero), and the
+    semistochastic total with eps2_d = eps2 equal to the deterministic E2."""
+    h, g, V1, c1, e1, V2 = cas16_v2
+    ctx = P.HCIContext(h, g, 8, 8)
+    c = hs.random_coeffs(len(V2), 29)
+    e0 = e1 - 10.0
+    u = np.random.default_rng(30).random((2, 64))
+    a, b = ctx.pt2_stochastic(V2, c, e0, 1e-6, 1e-4, u)
+    for k in range(2):
+        ra, rb = O.pt2_stochastic(h, g, V2, c, e0, 1e-6, 1e-4, u[k])
+        print(f"[pt2s full batch {k}] gpu {a[k]:.12e} {b[k]:.12e} oracle {ra:.12e} {rb:.12e}", flush=True)
+        assert abs(a[k] - ra) <= 1e-10 * abs(ra) and abs(b[k] - rb) <= 1e-10 * abs(rb)
+    e2, err, e2d = ctx.pt2_semistochastic(V2, c, e0, 1e-4, 1e-4, u)
+    assert e2 == e2d and err == 0.0
+
+
+def test_extrapolation_full_size_levels(P, cas16_v2):
+    """Extrapolation levels on the full space: nested sizes, variational
+    energies that never decrease as determinants go, negative E2."""
+    h, g, V1, c1, e1, V2 = cas16_v2
+    ctx = P.HCIContext(h, g, 8, 8)
+    e, c, _ = ctx.davidson(V2, ctx.embed(V1, c1, V2), tol=1e-6, precision="fp32_mixed")
+    res = ctx.extrapolate(V2, c, fraction=0.33, levels=3, eps2=1e-3, tol=1e-6, precision="fp32_mixed")
+    print(f"[extrap full] {res['sizes']} {res['evar']} {res['e2']}", flush=True)
+    assert res["sizes"] == O.extrapolation_sizes(len(V2), 0.33, 3)
+    assert abs(res["evar"][0] - e) < 1e-8
+    assert all(y >= x - 1e-8 for x, y in zip(res["evar"], res["evar"][1:]))
+    assert all(x < 0 for x in res["e2"])
 
 @pytest.fixture(scope="module")
 def cas44():
