@@ -223,7 +223,7 @@ struct Space {
     DevMem st_cptr;       // u32 [nua + 1]: first workgroup of each bucket
     DevMem st_gcptr;      // u32 [nub + 1]: first workgroup of each beta group
     DevMem st_chunk;      // u32 [st_nchunk][3]: bucket, first row, end row of each workgroup
-    DevMem st_gchunk;     // u32 [st_gnchunk][3]: beta group, first, end beta-major position
+    DevMem st_gchunk;     // u32 [st_gnchunk][4]: rows [k0, k1), c slice [s0, s1) (beta-major)
     i64 st_gnchunk = 0;   // workgroups of the beta-group product
     i64 st_gmax = 0;      // largest beta group
     DevMem st_rsb;        // i64 [N + 1]: first segment slot of each row

@@ -26,6 +26,7 @@
 // separate element pass per precision.
 #include <algorithm>
 #include <cstdlib>
+#include <vector>
 
 #include "slater.h"
 
@@ -57,7 +58,7 @@ struct StView {
     const u32* segcnt;  // entries of every (row, segment) before padding
     const u16* cols;
     const u32* chunk;   // [workgroups][3]: bucket, first row, end row
-    const u32* gchunk;  // [beta-group workgroups][3]: group, first, end position (beta-major)
+    const u32* gchunk;  // [beta-group workgroups][4]: rows [k0, k1) and c slice [s0, s1), beta-major
 };
 
 StView st_view(const Space& s) {
@@ -703,8 +704,8 @@ __global__ void __launch_bounds__(ST_BLOCK) st_spmv_kernel(SpaceView S, StView T
 // adds each row's G segment to sigma (after the staged kernel).
 template <class VT, class CT, int SUB, bool LDS>
 __device__ __forceinline__ double g_rows(const StView& T, const VT* __restrict__ vals,
-                                         const CT* __restrict__ src, i64 mk0, i64 mk1, int nrw,
-                                         int lane) {
+                                         const CT* __restrict__ src, i64 mk0, i64 mk1, u32 base,
+                                         int nrw, int lane) {
     constexpr int GROUPS = HCI_WAVE / SUB;
     double acc = 0.0;
     for (int qb = 0; qb < nrw; qb += GROUPS) {
@@ -713,6 +714,8 @@ __device__ __forceinline__ double g_rows(const StView& T, const VT* __restrict__
         const i64 k0 = __shfl(mk0, q, HCI_WAVE);
         const i64 k1s = __shfl(mk1, q, HCI_WAVE);
         const i64 k1 = q < nrw ? k1s : k0;
+        // the row's group starts base entries into the slice
+        const CT* __restrict__ rsrc = src + (u32)__shfl((int)base, q, HCI_WAVE);
         double t = 0.0;
         for (i64 k = k0 + ST_VEC * sl; k < k1; k += 2 * ST_VEC * SUB) {
             Entries8<VT> e1, e2;
@@ -720,8 +723,8 @@ __device__ __forceinline__ double g_rows(const StView& T, const VT* __restrict__
             const bool two = k2 < k1;
             e1.load(T.cols + k, vals + k);
             if (two) e2.load(T.cols + k2, vals + k2);
-            t = e1.dot(src, t);
-            if (two) t = e2.dot(src, t);
+            t = e1.dot(rsrc, t);
+            if (two) t = e2.dot(rsrc, t);
         }
         t = group_sum_f64<SUB>(t);
         const double v = __shfl(t, ((lane - qb) * SUB) & (HCI_WAVE - 1), HCI_WAVE);
@@ -740,14 +743,15 @@ __global__ void __launch_bounds__(GT_BLOCK) st_spmv_g_kernel(SpaceView S, StView
     const u32 tid = threadIdx.x;
     const int lane = lane_id();
     const u32 wave = tid / HCI_WAVE;
-    // beta group and positions (beta-major order) of this workgroup's chunk
-    const u32* ce = T.gchunk + 3 * (i64)blockIdx.x;
-    const u32 b = ce[0], k0 = ce[1], k1 = ce[2];
-    const u32 gb = S.boff[b];
-    const u32 gsz = S.boff[b + 1] - gb;
-    const bool in_lds = gsz <= cap;
+    // rows [k0, k1) (beta-major order) of this workgroup and the slice
+    // [s0, s1) of the beta-major c they read: whole small groups packed
+    // together, or part of a large group with the whole group's slice
+    const u32* ce = T.gchunk + 4 * (i64)blockIdx.x;
+    const u32 k0 = ce[0], k1 = ce[1], s0 = ce[2], s1 = ce[3];
+    const u32 slen = s1 - s0;
+    const bool in_lds = slen <= cap;
     if (in_lds) {
-        for (u32 p = tid; p < gsz; p += GT_BLOCK) stage[p] = cpb[gb + p];
+        for (u32 p = tid; p < slen; p += GT_BLOCK) stage[p] = cpb[s0 + p];
     }
     __syncthreads();
     const u32 nrows = k1 - k0;
@@ -755,13 +759,15 @@ __global__ void __launch_bounds__(GT_BLOCK) st_spmv_g_kernel(SpaceView S, StView
     const bool has = lane < nrw;
     const u32 i = has ? S.permb[k0 + wave + GT_WAVES * (u32)lane] : 0u;
     i64 mk0 = 0, mk1 = 0;
+    u32 base = 0;
     if (has) {
         const i64 slot = T.rsb[i] + T.nseg[S.ia[i]] - 1;
         mk0 = T.sstart[slot];
         mk1 = mk0 + pad_vec(T.segcnt[slot]);
+        base = S.boff[S.ib[i]] - s0;
     }
-    const double acc = in_lds ? g_rows<VT, CT, SUB, true>(T, vals, stage, mk0, mk1, nrw, lane)
-                              : g_rows<VT, CT, SUB, false>(T, vals, cpb + gb, mk0, mk1, nrw, lane);
+    const double acc = in_lds ? g_rows<VT, CT, SUB, true>(T, vals, stage, mk0, mk1, base, nrw, lane)
+                              : g_rows<VT, CT, SUB, false>(T, vals, cpb + s0, mk0, mk1, base, nrw, lane);
     if (has) sigma[i] += acc;
 }
 
@@ -773,7 +779,7 @@ void launch_spmv(hci_ctx_s* ctx, Space* sp, const char* name, const char* gname,
     const size_t shmem = sizeof(CT) << sp->st_wlog;
     // the beta-group kernel stages whole groups up to the largest one (groups
     // beyond the window gather from global memory)
-    const u32 cap = (u32)std::min<i64>((i64)1 << sp->st_wlog, sp->st_gmax);
+    const u32 cap = (u32)std::min<i64>((i64)1 << sp->st_wlog, std::max<i64>(sp->st_gmax, GT_CHUNK));
     const size_t gshmem = sizeof(CT) * (cap > 0 ? cap : 1);
     auto kern = st_spmv_kernel<VT, CT, ST_SUB>;
     // beta-group rows are short (a few hundred entries): 16 lanes per row
@@ -832,11 +838,36 @@ bool staged_prepare(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
     scan_u32_to_u32(ctx, gnchunk.as<u32>(), sp->st_gcptr.as<u32>(), nub + 1, s);
     sp->st_gnchunk = read_scalar(sp->st_gcptr.as<u32>() + nub, s);
     sp->st_chunk = dev_alloc(ctx, sizeof(u32) * 3 * (sp->st_nchunk > 0 ? sp->st_nchunk : 1), s);
-    sp->st_gchunk = dev_alloc(ctx, sizeof(u32) * 3 * (sp->st_gnchunk > 0 ? sp->st_gnchunk : 1), s);
     HCI_LAUNCH(ctx, "st_meta", s, st_chunk_table_kernel, ceil_div(nua, 256), 256, 0, sp->st_cptr.as<u32>(),
                sp->aoff.as<u32>(), nua, (u32)ST_CHUNK, sp->st_chunk.as<u32>());
-    HCI_LAUNCH(ctx, "st_meta", s, st_chunk_table_kernel, ceil_div(nub, 256), 256, 0, sp->st_gcptr.as<u32>(),
-               sp->boff.as<u32>(), nub, (u32)GT_CHUNK, sp->st_gchunk.as<u32>());
+    {
+        // beta-group workgroups, in beta-major order: consecutive groups of at
+        // most GT_CHUNK rows together packed into one workgroup (their slices
+        // of the beta-major c are contiguous); a larger group in parts of
+        // GT_CHUNK rows, each with the whole group's slice
+        std::vector<u32> boff((size_t)nub + 1);
+        HIP_CHECK(hipMemcpyAsync(boff.data(), sp->boff.ptr, sizeof(u32) * (nub + 1), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        std::vector<u32> tab;
+        for (i64 b = 0; b < nub;) {
+            if (boff[b + 1] - boff[b] > GT_CHUNK) {
+                for (u32 k0 = boff[b]; k0 < boff[b + 1]; k0 += GT_CHUNK)
+                    tab.insert(tab.end(), {k0, std::min<u32>(k0 + GT_CHUNK, boff[b + 1]), boff[b], boff[b + 1]});
+                ++b;
+                continue;
+            }
+            i64 e = b + 1;
+            while (e < nub && boff[e + 1] - boff[b] <= GT_CHUNK) ++e;
+            tab.insert(tab.end(), {boff[b], boff[e], boff[b], boff[e]});
+            b = e;
+        }
+        sp->st_gnchunk = (i64)(tab.size() / 4);
+        sp->st_gchunk = dev_alloc(ctx, sizeof(u32) * (tab.empty() ? 4 : tab.size()), s);
+        if (!tab.empty())
+            HIP_CHECK(hipMemcpyAsync(sp->st_gchunk.ptr, tab.data(), sizeof(u32) * tab.size(),
+                                     hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));  // tab leaves scope
+    }
     // segment slots per row
     DevMem rn = dev_alloc(ctx, sizeof(u32) * (N + 1), s);
     HCI_LAUNCH(ctx, "st_row_nseg", s, st_row_nseg_kernel, ceil_div(N + 1, 256), 256, 0,
