@@ -116,7 +116,13 @@ int hci_ctx_set_stored_budget(hci_ctx ctx, int64_t bytes);
  * columns are stored as 16-bit offsets (6 bytes per float32 entry).  0
  * selects the plain CSR layout (32-bit columns).  Valid values: 0 or 6..16
  * (default 14); spaces outside the staged layout's limits use plain CSR.
- * Changing the layout releases the cached structure.  HCI_E_ARG otherwise. */
+ * Changing the layout releases the cached structure.  HCI_E_ARG otherwise.
+ * The alpha single x beta single connections of the staged layout (and of
+ * the density matrices) are found through on-chip bitmaps of the beta
+ * strings of each neighbour bucket when the space has at most 65535 unique
+ * beta strings, else by searching the bucket; the environment variable
+ * HCI_AB_SEARCH=1, read when a layout is built, forces the search (both give
+ * the same entries in the same order). */
 int hci_ctx_set_stage_window(hci_ctx ctx, int log2_window);
 
 /* Per-kernel timing with HIP events on the launch stream (off by default).
