@@ -64,3 +64,24 @@ def test_extrapolation_rejects_bad_arguments(P):
             ctx.extrapolate(V, c, **kw)
         assert ei.value.code == -1, kw
     ctx.close()
+
+
+def test_extrapolation_down_to_one_determinant(P):
+    """Levels that shrink to a single determinant (sizes 4, 2, 1, 1): each
+    level against the oracle; the repeated last point leaves the fit defined."""
+    w = hs.WORKLOADS["cas8"]
+    h, g = hs.workload_integrals(w)
+    V0 = hs.aufbau_det(4, 4)
+    C = O.select(h, g, V0, np.array([1.0]), 0.0)
+    hv = np.array([abs(O.hij(h, g, V0[0], x)) for x in C])
+    V = O.merge(V0, C[np.argsort(-hv)[:3]])
+    e, c = O.lowest_eigenpair(h, g, V)
+    ref = O.extrapolation(h, g, V, c, 0.5, 4, 1e-4)
+    assert ref["sizes"] == [4, 2, 1, 1]
+    ctx = P.HCIContext(h, g, 4, 4)
+    res = ctx.extrapolate(V, c, fraction=0.5, levels=4, eps2=1e-4, tol=1e-10)
+    ctx.close()
+    assert res["sizes"] == ref["sizes"]
+    assert np.abs(res["evar"] - ref["evar"]).max() < 1e-9
+    assert np.all(np.abs(res["e2"] - ref["e2"]) <= 1e-9 * np.abs(ref["e2"]) + 1e-12)
+    assert abs(res["e_extrap"] - ref["e_extrap"]) < 1e-8

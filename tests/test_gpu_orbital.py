@@ -1,10 +1,10 @@
 """Orbital step (active-active rotations) on the matrix cores against the oracle.
 
-* Gradient dE/dkappa and rotated integrals at n = 8, 16, 30, 44 (ragged
-  against the 16-wide tiles except n = 16), the density matrices of a
-  selected state (n <= 16) or random tensors with the index symmetries of a
-  real state (n = 30, 44); contractions of n^3 terms in another order:
-  1e-12 of the largest entry.
+* Gradient dE/dkappa and rotated integrals at n = 3, 8, 16, 30, 44 and the
+  largest supported n = 64 (ragged against the 16-wide tiles except n = 16
+  and 64), the density matrices of a selected state (n = 8, 16) or random
+  tensors with the index symmetries of a real state (other n);
+  contractions of n^3 terms in another order: 1e-12 of the largest entry.
 * Through the library end to end: the full-CI energy of (8e,8o) with
   rotated integrals equals the unrotated one, and the orbital gradient of
   the full-CI state vanishes.
@@ -47,15 +47,15 @@ def _case(n):
         na = nb = 8
     else:
         h, g = hs.make_integrals(n, 3 * n, n)
-        na = nb = n // 2
+        na = nb = max(1, n // 2)
     return h, g, na, nb
 
 
-@pytest.mark.parametrize("n", [8, 16, 30, 44])
+@pytest.mark.parametrize("n", [3, 8, 16, 30, 44, 64])
 def test_gradient_and_rotation_match_oracle(P, n):
     h, g, na, nb = _case(n)
     ctx = P.HCIContext(h, g, na, nb)
-    if n <= 16:  # density matrices of a selected state
+    if n in (8, 16):  # density matrices of a selected state
         V0 = hs.aufbau_det(na, nb)
         V = O.merge(V0, O.select(h, g, V0, np.array([1.0]), 5e-2 if n == 16 else 1e-2))
         e, c, _ = ctx.davidson(V, None, tol=1e-9)

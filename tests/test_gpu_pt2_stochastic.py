@@ -127,3 +127,35 @@ def test_stochastic_rejects_bad_arguments(case, lib_mod):
     assert bad == [-1, -1, -1, -1]
     with pytest.raises(lib_mod.HCIError):
         ctx.pt2_stochastic(V, np.zeros(len(V)), e0, 1e-4, 1e-3, u)
+
+
+def test_stochastic_edge_draws(lib_mod):
+    """Two draws on the same row (w = 2, the off-diagonal part vanishes) and a
+    one-determinant space, against the oracle."""
+    w = hs.WORKLOADS["cas8"]
+    h, g = hs.workload_integrals(w)
+    V0 = hs.aufbau_det(4, 4)
+    V = O.merge(V0, O.select(h, g, V0, np.array([1.0]), 0.05))
+    e0, c = O.lowest_eigenpair(h, g, V)
+    ctx = lib_mod.HCIContext(h, g, 4, 4)
+    # both uniforms in the first row's cumulative range
+    _, q, Q = O.pt2_sample(c, np.array([0.0]))
+    first = int(np.nonzero(q)[0][0])
+    hi = q[first] / Q
+    u = np.array([[0.0, 0.5 * hi]])
+    wref, _, _ = O.pt2_sample(c, u[0])
+    assert wref[first] == 2 and wref.sum() == 2
+    a, b = ctx.pt2_stochastic(V, c, e0, 1e-5, 1e-3, u)
+    ra, rb = O.pt2_stochastic(h, g, V, c, e0, 1e-5, 1e-3, u[0])
+    assert abs(a[0] - ra) <= 1e-10 * abs(ra) and abs(b[0] - rb) <= 1e-10 * max(abs(rb), 1e-300)
+    # a single determinant: every draw picks it
+    V1 = V0
+    c1 = np.array([1.0])
+    e1 = O.diag(h, g, V1[0])
+    u1 = np.array([[0.3, 0.9, 0.1]])
+    a1, b1 = ctx.pt2_stochastic(V1, c1, e1, 1e-5, 1e-3, u1)
+    ra1, rb1 = O.pt2_stochastic(h, g, V1, c1, e1, 1e-5, 1e-3, u1[0])
+    assert abs(a1[0] - ra1) <= 1e-10 * abs(ra1) and abs(b1[0] - rb1) <= 1e-10 * abs(rb1)
+    # with every draw on the one row the estimate is the deterministic E2
+    assert abs(ra1 - O.pt2(h, g, V1, c1, e1, 1e-5)["E2"]) <= 1e-12 * abs(ra1)
+    ctx.close()
