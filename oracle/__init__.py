@@ -19,6 +19,11 @@ Where each function comes from (paper sections/equations):
   evaluated), not as the heat-bath walk.
 * ``select_bruteforce`` -- the same criterion evaluated over the whole
   determinant space with the operator-built H (tiny spaces).
+* ``select_roots`` / ``lowest_eigenpairs`` -- several states of one
+  calculation (the paper's excited states are the lowest states of other
+  spin projections, N_alpha != N_beta, which every function here accepts):
+  the k lowest eigenpairs by a library eigensolver, and the union of the
+  single-state selections (a reading: the paper selects for one state).
 * ``hci`` -- the variational macro-iteration V <- V + C(eps1) followed by
   re-diagonalisation (Sec. "Variational Stage", Fig. 1a), with a library
   eigensolver standing in for Davidson (eq. variational).
@@ -283,16 +288,29 @@ def select(h, g, V, c, eps) -> np.ndarray:
     return sort_unique(out[:total])
 
 
+def select_roots(h, g, V, C, eps) -> np.ndarray:
+    """Selection for several states at once: the union over the rows c of C
+    of C(eps) (a determinant enters when it passes the criterion of eq.
+    criteria for at least one state).  The paper computes each state it
+    reports separately; the union is the reading taken for several roots of
+    one calculation."""
+    C = np.atleast_2d(np.asarray(C, dtype=np.float64))
+    parts = [select(h, g, V, c, eps) for c in C]
+    return sort_unique(np.concatenate([p.reshape(-1, 2) for p in parts]))
+
+
 def select_bruteforce(h, g, V, c, eps, space) -> np.ndarray:
     """The same criterion over a whole determinant space with the
-    operator-built H: keep a outside V when max_i |H_ai c_i| > eps."""
+    operator-built H: keep a outside V when max_i |H_ai c_i| > eps; c may
+    hold several states as rows (then the maximum runs over them too)."""
     space = np.asarray(space, dtype=np.uint64)
     Hs = hamiltonian_by_operators(h, g, space)
     index = {(int(a), int(b)): k for k, (a, b) in enumerate(space)}
     vi = np.array([index[(int(a), int(b))] for a, b in V], dtype=np.int64)
     inV = np.zeros(len(space), dtype=bool)
     inV[vi] = True
-    f = np.max(np.abs(Hs[:, vi]) * np.abs(np.asarray(c))[None, :], axis=1)
+    C = np.atleast_2d(np.abs(np.asarray(c, dtype=np.float64)))
+    f = np.max(np.abs(Hs[:, vi])[None, :, :] * C[:, None, :], axis=(0, 2))
     keep = (f > eps) & ~inV
     return sort_unique(space[keep])
 
@@ -315,6 +333,31 @@ def lowest_eigenpair(h, g, V, tol=1e-12, v0=None, dense_max=3000):
     if c[k] < 0:
         c = -c
     return e, c
+
+
+def _fix_sign(c):
+    k = int(np.argmax(np.abs(c)))
+    return -c if c[k] < 0 else c
+
+
+def lowest_eigenpairs(h, g, V, k, tol=1e-12, dense_max=3000):
+    """The k lowest eigenpairs of H on V in ascending order (several states
+    of one determinant space): dense LAPACK below dense_max, else Lanczos
+    (scipy eigsh).  Each vector's largest |c_i| (first index on ties) is made
+    positive.  Returns (e [k], C [k, m])."""
+    m = len(V)
+    if not 1 <= k <= m:
+        raise ValueError("need 1 <= k <= len(V)")
+    if m <= dense_max:
+        w, U = np.linalg.eigh(hamiltonian_csr(h, g, V).toarray())
+        e, C = w[:k].copy(), U[:, :k].T.copy()
+    else:
+        import scipy.sparse.linalg as sla
+        w, U = sla.eigsh(hamiltonian_csr(h, g, V), k=k, which="SA", tol=tol)
+        o = np.argsort(w)
+        e, C = w[o].copy(), U[:, o].T.copy()
+    C = np.array([_fix_sign(c) for c in C])
+    return e, C
 
 
 def hci(h, g, nalpha, nbeta, eps1, max_iter=20, V0=None, tol=1e-12, dense_max=3000):

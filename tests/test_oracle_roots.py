@@ -1,0 +1,103 @@
+"""Pins of the oracle's several-state functions (no GPU).
+
+* The k lowest eigenvalues of a Hamiltonian without two-electron terms are
+  the k smallest sums of one-electron eigenvalues over N_alpha and N_beta
+  distinct orbitals (closed form).
+* The spectrum of a spin projection M_s = (N_alpha - N_beta)/2 > 0 is
+  contained in that of every smaller |M_s| with the same electron count
+  (every spin multiplet has a component in each sector): pins the two-electron
+  terms between unequal alpha and beta counts, the paper's triplet and
+  quintet states.
+* Both eigensolver routes (dense and Lanczos) against the eigenvalues of the
+  operator-built Hamiltonian.
+* The union selection against brute force over the whole space with the
+  criterion maximised over states, and against the single-state selection.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import hci_synth as hs
+import oracle as O
+
+
+@pytest.mark.parametrize("n,na,nb,k,seed", [(6, 3, 2, 10, 1), (7, 2, 2, 12, 2), (5, 4, 1, 5, 3)])
+def test_noninteracting_spectrum(n, na, nb, k, seed):
+    rng = np.random.default_rng(seed)
+    h = rng.normal(size=(n, n))
+    h = h + h.T
+    g = np.zeros((n, n, n, n))
+    eps = np.linalg.eigvalsh(h)
+    sums = sorted(sum(eps[list(A)]) + sum(eps[list(B)])
+                  for A in itertools.combinations(range(n), na)
+                  for B in itertools.combinations(range(n), nb))
+    V = hs.full_space(n, na, nb)
+    e, C = O.lowest_eigenpairs(h, g, V, k)
+    assert np.abs(e - np.array(sums[:k])).max() < 1e-10
+    assert np.all(np.diff(e) >= 0)
+
+
+@pytest.mark.parametrize("n,N,seed", [(6, 6, 4), (6, 5, 5), (7, 4, 6)])
+def test_spin_sector_spectra_nested(n, N, seed):
+    h, g = hs.make_integrals(n, 3 * n, seed)
+    spectra = {}
+    for na in range((N + 1) // 2, min(n, N) + 1):
+        nb = N - na
+        V = hs.full_space(n, na, nb)
+        spectra[na] = np.linalg.eigvalsh(O.hamiltonian_csr(h, g, V).toarray())
+    keys = sorted(spectra)
+    for lo, hi in zip(keys, keys[1:]):
+        a, b = spectra[hi], spectra[lo]
+        assert len(a) < len(b)
+        # every level of the higher projection appears in the lower one
+        d = np.abs(a[:, None] - b[None, :]).min(axis=1)
+        assert d.max() < 1e-9, (lo, hi, d.max())
+    # the sectors are not all the same: the lowest state is a low-spin one
+    assert spectra[keys[0]][0] < spectra[keys[-1]][0] - 1e-6
+
+
+@pytest.mark.parametrize("route", ["dense", "lanczos"])
+def test_lowest_eigenpairs_both_routes(route):
+    n, na, nb = 7, 3, 3
+    h, g = hs.make_integrals(n, 21, 9)
+    V = hs.random_dets(n, na, nb, 300, seed=9, bias=0.2)
+    H_op = O.hamiltonian_by_operators(h, g, V)
+    ref = np.linalg.eigvalsh(H_op)
+    k = 6
+    e, C = O.lowest_eigenpairs(h, g, V, k, dense_max=3000 if route == "dense" else 0)
+    assert np.abs(e - ref[:k]).max() < 1e-9
+    # eigenvectors: orthonormal, residuals small, sign convention
+    assert np.abs(C @ C.T - np.eye(k)).max() < 1e-9
+    assert np.abs(C @ H_op - e[:, None] * C).max() < 1e-7
+    for c in C:
+        j = int(np.argmax(np.abs(c)))
+        assert c[j] > 0
+
+
+def test_lowest_eigenpairs_rejects_bad_k():
+    h, g = hs.make_integrals(4, 12, 1)
+    V = hs.full_space(4, 1, 1)
+    with pytest.raises(ValueError):
+        O.lowest_eigenpairs(h, g, V, 0)
+    with pytest.raises(ValueError):
+        O.lowest_eigenpairs(h, g, V, len(V) + 1)
+
+
+@pytest.mark.parametrize("eps", [1e-3, 2e-2, 1e-1])
+def test_select_roots_union_matches_bruteforce(eps):
+    n, na, nb = 6, 3, 2
+    h, g = hs.make_integrals(n, 18, 11)
+    space = hs.full_space(n, na, nb)
+    V = hs.random_dets(n, na, nb, 12, seed=11, bias=0.3)
+    C = np.stack([hs.random_coeffs(len(V), 20 + r) for r in range(3)])
+    got = O.select_roots(h, g, V, C, eps)
+    ref = O.select_bruteforce(h, g, V, C, eps, space)
+    assert np.array_equal(got, ref)
+    # one state is the single-state selection; the union holds each state's
+    single = [O.select(h, g, V, c, eps) for c in C]
+    assert np.array_equal(O.select_roots(h, g, V, C[:1], eps), single[0])
+    have = {tuple(x) for x in got.tolist()}
+    for s in single:
+        assert {tuple(x) for x in s.tolist()} <= have
+    assert len(got) <= sum(len(s) for s in single)
