@@ -65,6 +65,10 @@ typedef enum {
 
 typedef enum { HCI_FP64 = 0, HCI_FP32_MIXED = 1 } hci_precision;
 
+/* Largest number of states of one determinant space (hci_select_roots,
+ * hci_davidson_roots). */
+#define HCI_MAX_ROOTS 31
+
 typedef enum {
     HCI_SIGMA_AUTO = 0,      /* stored when the Hamiltonian fits the memory budget */
     HCI_SIGMA_STORED = 1,    /* build the sparse Hamiltonian once, then stream it */
@@ -155,6 +159,21 @@ const char* hci_last_error(void);
 int hci_select(hci_ctx ctx, const uint64_t* dets, const double* c, int64_t n_var,
                double eps1, uint64_t* out_dets, int64_t cap, int64_t* n_out, void* stream);
 
+/* Selection for several states of one space at once.  The paper selects
+ * for one state per calculation (its excited states are the lowest states of
+ * other spin projections, N_alpha != N_beta, which every entry point here
+ * accepts); for several states of one space the set taken is the union of
+ * the single-state sets: D_a enters when fl(|H_ai| * |c_i|) > eps1 for some
+ * D_i in V and some state.  One walk with the weights max over the states of
+ * |c_i| gives exactly that union (the float64 product is non-decreasing in
+ * its second factor).
+ *   c: device float64 [nroots][n_var] (state r in row r), 1 <= nroots <=
+ *   HCI_MAX_ROOTS.  Every other argument, the output and the errors as in
+ *   hci_select. */
+int hci_select_roots(hci_ctx ctx, const uint64_t* dets, const double* c, int nroots,
+                     int64_t n_var, double eps1, uint64_t* out_dets, int64_t cap,
+                     int64_t* n_out, void* stream);
+
 /* Carry a vector from V to a superset V' (both sorted unique lists), as the
  * warm start of the next Davidson solve after V' = V + C (Fig. 1a):
  * c_new[k'] = c[k] where V'[k'] == V[k], and 0 on the determinants of V'
@@ -214,6 +233,28 @@ int hci_diagonal(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* hdiag
 int hci_davidson(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* c_inout,
                  double* e_out, double tol, int max_iter, int precision, int mode,
                  int* iters_out, void* stream);
+
+/* The nroots lowest eigenpairs of H on V (several states of one space; the
+ * paper's stationarity condition eq. variational for each state), by
+ * deflation: state r is the lowest eigenpair of Q H Q on the complement of
+ * states 0..r-1 (Q = 1 - sum_l c_l c_l^T), found by the solver of
+ * hci_davidson with every new direction orthogonalised against the earlier
+ * states and every product projected by Q.  States come out in ascending
+ * order when each solve reaches the lowest state of its complement, the
+ * case unless a start vector has no overlap with it.
+ *   c_inout: device float64 [nroots][n_var]: row r is the start of state r
+ *   (a zero row, or one inside the span of the earlier states, selects the
+ *   lowest-diagonal determinant that the earlier states hold less than half
+ *   of); on return the orthonormal eigenvectors, each with its
+ *   largest-magnitude entry > 0.  e_out: host float64 [nroots], eigenvalues
+ *   + ecore.  iters_out: host int [nroots] (may be NULL), products per
+ *   state.  1 <= nroots <= min(HCI_MAX_ROOTS, n_var).  tol, max_iter (per
+ *   state), precision and mode as in hci_davidson.  HCI_E_NOCONV when some
+ *   state missed tol (every state is still written).  Synchronises the
+ *   stream. */
+int hci_davidson_roots(hci_ctx ctx, const uint64_t* dets, int64_t n_var, int nroots,
+                       double* c_inout, double* e_out, double tol, int max_iter,
+                       int precision, int mode, int* iters_out, void* stream);
 
 /* ---------------------------------------------------------------------- RDMs
  * Spin-traced transition density matrices between bra and ket on V (the

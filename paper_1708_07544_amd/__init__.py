@@ -106,17 +106,25 @@ class HCIContext:
         return d
 
     def select(self, dets, c, eps1: float, cap: Optional[int] = None) -> torch.Tensor:
-        """V + C(eps1), sorted and unique (int64 [m,2] on the device)."""
+        """V + C(eps1), sorted and unique (int64 [m,2] on the device).  A 2-D c
+        holds several states as rows: the union of their selections."""
         d = self._dets(dets)
         c = torch.as_tensor(c, dtype=torch.float64).to(self.device).contiguous()
         n = d.shape[0]
+        if c.dim() == 2 and c.shape[1] != n or c.dim() == 1 and c.shape[0] != n or c.dim() > 2:
+            raise ValueError("c must be [n] or [nroots, n]")
         cap = int(cap) if cap is not None else max(4 * n, 1 << 16)
         n_out = ctypes.c_int64()
         for _ in range(2):
             out = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=self.device)
-            code = check(lib().hci_select(self.handle, _lib._ptr(d), _lib._ptr(c), n, float(eps1),
-                                          _lib._ptr(out), cap, ctypes.byref(n_out), _lib._stream()),
-                         allow=(_lib.HCI_E_CAPACITY,))
+            if c.dim() == 2:
+                call = lib().hci_select_roots(self.handle, _lib._ptr(d), _lib._ptr(c), c.shape[0], n,
+                                              float(eps1), _lib._ptr(out), cap, ctypes.byref(n_out),
+                                              _lib._stream())
+            else:
+                call = lib().hci_select(self.handle, _lib._ptr(d), _lib._ptr(c), n, float(eps1),
+                                        _lib._ptr(out), cap, ctypes.byref(n_out), _lib._stream())
+            code = check(call, allow=(_lib.HCI_E_CAPACITY,))
             if code == _lib.HCI_OK:
                 return out[: n_out.value].contiguous()
             cap = int(n_out.value)
@@ -181,6 +189,27 @@ class HCIContext:
                                  float(tol), int(max_iter), _PREC[precision], _MODE[mode],
                                  ctypes.byref(iters), _lib._stream()), allow=allow)
         return float(e.value), c, int(iters.value)
+
+    def davidson_roots(self, dets, nroots: int, c0=None, tol: float = 1e-8, max_iter: int = 500,
+                       precision="fp64", mode="auto", allow_noconv: bool = False):
+        """The nroots lowest eigenpairs on V: returns (E [nroots] numpy,
+        C [nroots, n] orthonormal rows, products per state)."""
+        d = self._dets(dets)
+        n = d.shape[0]
+        if c0 is None:
+            c = torch.zeros((nroots, n), dtype=torch.float64, device=self.device)
+        else:
+            c = torch.as_tensor(c0, dtype=torch.float64).to(self.device).clone().contiguous()
+            if c.shape != (nroots, n):
+                raise ValueError("c0 must be [nroots, n]")
+        e = (ctypes.c_double * max(nroots, 1))()
+        iters = (ctypes.c_int * max(nroots, 1))()
+        allow = (_lib.HCI_E_NOCONV,) if allow_noconv else ()
+        check(lib().hci_davidson_roots(self.handle, _lib._ptr(d), n, int(nroots), _lib._ptr(c),
+                                       ctypes.cast(e, ctypes.c_void_p), float(tol), int(max_iter),
+                                       _PREC[precision], _MODE[mode], ctypes.cast(iters, ctypes.c_void_p),
+                                       _lib._stream()), allow=allow)
+        return np.array(e[:nroots]), c, [int(x) for x in iters[:nroots]]
 
     def rdm12(self, dets, bra, ket=None, two_body: bool = True):
         d = self._dets(dets)

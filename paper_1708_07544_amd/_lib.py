@@ -66,11 +66,13 @@ _SIGNATURES = {
     "hci_ctx_set_timing": [_vp, _i32],
     "hci_ctx_kernel_time": [_vp, ctypes.c_char_p, _vp, _vp, _i32],
     "hci_select": [_vp, _vp, _vp, _i64, _f64, _vp, _i64, _vp, _vp],
+    "hci_select_roots": [_vp, _vp, _vp, _i32, _i64, _f64, _vp, _i64, _vp, _vp],
     "hci_embed": [_vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp],
     "hci_sigma": [_vp, _vp, _i64, _vp, _vp, _i32, _i32, _vp],
     "hci_connections": [_vp, _vp, _i64, _vp, _vp],
     "hci_diagonal": [_vp, _vp, _i64, _vp, _vp],
     "hci_davidson": [_vp, _vp, _i64, _vp, _vp, _f64, _i32, _i32, _i32, _vp, _vp],
+    "hci_davidson_roots": [_vp, _vp, _i64, _i32, _vp, _vp, _f64, _i32, _i32, _i32, _vp, _vp],
     "hci_rdm12": [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp],
     "hci_energy_backward": [_vp, _vp, _i64, _vp, _f64, _f64, _vp, _f64, _f64, _i32, _vp, _vp,
                             _vp, _vp, _vp],

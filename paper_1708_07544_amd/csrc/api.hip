@@ -305,6 +305,27 @@ int hci_select(hci_ctx ctx, const uint64_t* dets, const double* c, int64_t n_var
     });
 }
 
+int hci_select_roots(hci_ctx ctx, const uint64_t* dets, const double* c, int nroots, int64_t n_var,
+                     double eps1, uint64_t* out_dets, int64_t cap, int64_t* n_out, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && c && out_dets && n_out, HCI_E_ARG, "null argument");
+        HCI_REQUIRE(n_var > 0 && cap >= 0, HCI_E_ARG, "bad sizes");
+        HCI_REQUIRE(nroots >= 1 && nroots <= HCI_MAX_ROOTS, HCI_E_ARG, "nroots must be in [1, 31]");
+        HCI_REQUIRE(eps1 >= 0.0, HCI_E_ARG, "eps1 must be >= 0");
+        HCI_REQUIRE((const void*)out_dets != (const void*)dets, HCI_E_ARG, "out_dets aliases dets");
+        hipStream_t s = as_stream(stream);
+        get_space(ctx, dets, n_var, s);
+        const i64 m = select_roots_run(ctx, dets, c, nroots, n_var, eps1, out_dets, cap, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        *n_out = m;
+        if (m > cap) {
+            g_last_error = "capacity " + std::to_string(cap) + " < required " + std::to_string(m);
+            return HCI_E_CAPACITY;
+        }
+        return HCI_OK;
+    });
+}
+
 int hci_embed(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c,
               const uint64_t* dets_new, int64_t n_new, double* c_new, void* stream) {
     return guarded([&]() -> int {
@@ -380,6 +401,30 @@ int hci_davidson(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* c_ino
                                     iters_out, s);
         if (rc == HCI_E_NOCONV) g_last_error = "Davidson did not reach tol within max_iter products";
         return rc;
+    });
+}
+
+int hci_davidson_roots(hci_ctx ctx, const uint64_t* dets, int64_t n_var, int nroots, double* c_inout,
+                       double* e_out, double tol, int max_iter, int precision, int mode, int* iters_out,
+                       void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && c_inout && e_out, HCI_E_ARG, "null argument");
+        HCI_REQUIRE(nroots >= 1 && nroots <= HCI_MAX_ROOTS, HCI_E_ARG, "nroots must be in [1, 31]");
+        HCI_REQUIRE(nroots <= n_var, HCI_E_ARG, "nroots exceeds the number of determinants");
+        HCI_REQUIRE(tol > 0.0 && max_iter > 0, HCI_E_ARG, "tol and max_iter must be positive");
+        HCI_REQUIRE(precision == HCI_FP64 || precision == HCI_FP32_MIXED, HCI_E_ARG, "bad precision");
+        HCI_REQUIRE(mode >= 0 && mode <= 2, HCI_E_ARG, "bad mode");
+        hipStream_t s = as_stream(stream);
+        Space* sp = get_space(ctx, dets, n_var, s);
+        int worst = HCI_OK;
+        for (int r = 0; r < nroots; ++r) {
+            // state r: the lowest eigenpair in the complement of states 0..r-1
+            const int rc = davidson_run(ctx, sp, c_inout + (i64)r * n_var, e_out + r, tol, max_iter, precision,
+                                        mode, iters_out ? iters_out + r : nullptr, s, c_inout, r);
+            if (rc != HCI_OK) worst = rc;
+        }
+        if (worst == HCI_E_NOCONV) g_last_error = "Davidson did not reach tol within max_iter products for a state";
+        return worst;
     });
 }
 

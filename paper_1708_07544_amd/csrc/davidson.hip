@@ -14,6 +14,12 @@
 // that), then restart from the Ritz vector with float64 products until the
 // float64 residual meets tol.  Restarts keep the current and the previous
 // Ritz vectors.
+//
+// Several states (deflation): with nlock converged orthonormal vectors L
+// given, the solver works on Q H Q restricted to the complement of L
+// (Q = 1 - L L^T): every new basis vector is orthogonalised against L before
+// the basis, and every product H v is projected by Q.  Its lowest eigenpair
+// there is the next state, and its residual is orthogonal to L.
 #include <cfloat>
 
 #include "common.h"
@@ -346,6 +352,55 @@ __global__ void argmin_seed_kernel(const double* __restrict__ hd, i64 N, double*
     for (i64 i = threadIdx.x; i < N; i += 256) x[i] = (i == bi[0]) ? 1.0 : 0.0;
 }
 
+// Start vector for a deflated solve: e_j for the determinant of lowest
+// diagonal among those that the locked vectors hold less than half of
+// (w_j = sum_l L_lj^2 <= 1/2), else the one they hold least (first index on
+// ties).  At most 2 nlock determinants have w_j > 1/2, so with N >= 2 nlock
+// the first rule always applies; e_j is never inside the span of L.
+__device__ __forceinline__ bool seed_less(int fa, double va, i64 ia, int fb, double vb, i64 ib) {
+    if (fa != fb) return fa < fb;
+    if (va != vb) return va < vb;
+    return ia < ib;
+}
+
+__global__ void __launch_bounds__(256) deflated_seed_kernel(const double* __restrict__ hd, i64 N,
+                                                            const double* __restrict__ L, int nlock,
+                                                            double* __restrict__ x) {
+    __shared__ int bf[256];
+    __shared__ double bv[256];
+    __shared__ i64 bi[256];
+    int f = 2;
+    double v = 0.0;
+    i64 idx = 0;
+    for (i64 i = threadIdx.x; i < N; i += 256) {
+        double w = 0.0;
+        for (int l = 0; l < nlock; ++l) w += L[(i64)l * N + i] * L[(i64)l * N + i];
+        const int fi = w > 0.5 ? 1 : 0;
+        const double vi = fi ? w : hd[i];
+        if (seed_less(fi, vi, i, f, v, idx)) {
+            f = fi;
+            v = vi;
+            idx = i;
+        }
+    }
+    bf[threadIdx.x] = f;
+    bv[threadIdx.x] = v;
+    bi[threadIdx.x] = idx;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            const int o = threadIdx.x + st;
+            if (seed_less(bf[o], bv[o], bi[o], bf[threadIdx.x], bv[threadIdx.x], bi[threadIdx.x])) {
+                bf[threadIdx.x] = bf[o];
+                bv[threadIdx.x] = bv[o];
+                bi[threadIdx.x] = bi[o];
+            }
+        }
+        __syncthreads();
+    }
+    for (i64 i = threadIdx.x; i < N; i += 256) x[i] = (i == bi[0]) ? 1.0 : 0.0;
+}
+
 // sign convention: largest-|c| entry positive (first index on ties)
 // Sign convention: the entry of largest magnitude (first index on ties) is
 // made positive.  Block partials of (|x_i|, i), a one-block decision, then a
@@ -437,16 +492,26 @@ struct Workspace {
                    (const double*)coef, t, N, partial.as<double>(), nblk);
         reduce(1, nrm2);
     }
+    // w -= L L^T w (one sweep: w is H v with v orthogonal to L, so its
+    // component along L is of the order of the locked residuals)
+    void project(const double* L, int nl, double* w, double* coef) {
+        if (nl == 0) return;
+        dots(L, N, nl, w, coef);
+        HCI_LAUNCH(ctx, "dv_deflate", s, sub_dots_kernel<true>, nblk, DV_BLOCK, 0, L, N, nl,
+                   (const double*)coef, w, N, partial.as<double>(), nblk);
+    }
 };
 
 }  // namespace
 
 int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol, int max_iter,
-                 int precision, int mode, int* iters_out, hipStream_t s) {
+                 int precision, int mode, int* iters_out, hipStream_t s, const double* lock, int nlock) {
     const i64 N = sp->N;
+    HCI_REQUIRE(nlock >= 0 && nlock < DV_MAXK && nlock < N && (nlock == 0 || lock != nullptr), HCI_E_ARG,
+                "bad number of locked vectors");
     ensure_diag(ctx, sp, s);
     const double* hd = sp->hdiag.as<double>();
-    const int kmax = (int)std::min<i64>(DV_KMAX, N);
+    const int kmax = (int)std::min<i64>(DV_KMAX, N - nlock);
     Workspace ws(ctx, N, s);
     DevMem Vb = dev_alloc(ctx, sizeof(double) * kmax * N, s);
     DevMem Wb = dev_alloc(ctx, sizeof(double) * kmax * N, s);
@@ -470,11 +535,22 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
     HIP_CHECK(hipMemsetAsync(dead, 0, sizeof(double), s));
     const i64 g1 = ceil_div(N, 256);
 
-    // start vector (a zero vector selects the lowest diagonal determinant)
+    // start vector (a zero vector selects the lowest diagonal determinant);
+    // deflated: its part outside the locked vectors, or a seed when nothing
+    // of it is left
     HIP_CHECK(hipMemcpyAsync(xc, c, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     ws.dots(xc, N, 1, xc, nrm_x);
-    if (read_scalar(nrm_x, s) <= 0.0)
-        HCI_LAUNCH(ctx, "dv_seed", s, argmin_seed_kernel, 1, 256, 0, hd, N, xc);
+    if (nlock == 0) {
+        if (read_scalar(nrm_x, s) <= 0.0)
+            HCI_LAUNCH(ctx, "dv_seed", s, argmin_seed_kernel, 1, 256, 0, hd, N, xc);
+    } else {
+        const double n0 = read_scalar(nrm_x, s);
+        ws.cgs2(lock, N, nlock, xc, sc, nrm_x);
+        if (!(read_scalar(nrm_x, s) > 1e-12 * n0) || n0 <= 0.0) {
+            HCI_LAUNCH(ctx, "dv_seed", s, deflated_seed_kernel, 1, 256, 0, hd, N, lock, nlock, xc);
+            ws.cgs2(lock, N, nlock, xc, sc, nrm_x);
+        }
+    }
 
     const bool mixed = precision == HCI_FP32_MIXED;
     int phase_prec = mixed ? HCI_FP32_MIXED : HCI_FP64;
@@ -491,6 +567,7 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
         HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, xc, nrm_x, V, N);
         if (need_sigma) {
             sigma_apply(ctx, sp, V, W, phase_prec, phase_mode, s);
+            ws.project(lock, nlock, W, sc);
             ++products;
             have_prev = false;
         } else {
@@ -508,6 +585,7 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
             if (read_scalar(nrm_t, s) > 1e-24) {
                 HCI_LAUNCH(ctx, "dv_normalize", s, normalize_kernel, g1, 256, 0, t, nrm_t, V + N, N);
                 sigma_apply(ctx, sp, V + N, W + N, phase_prec, phase_mode, s);
+                ws.project(lock, nlock, W + N, sc);
                 ++products;
                 k = 2;
             }
@@ -542,11 +620,14 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
             }
             if (products >= max_iter) break;
             if (k == kmax) break;  // thick restart
-            // orthogonalise the preconditioned residual against the basis (CGS2)
+            // orthogonalise the preconditioned residual against the locked
+            // vectors and the basis (CGS2)
+            if (nlock > 0) ws.cgs2(lock, N, nlock, t, sc, nrm_t);
             ws.cgs2(V, N, k, t, sc, nrm_t);
             HCI_LAUNCH(ctx, "dv_normalize", s, normalize_guard_kernel, g1, 256, 0, t, nrm_t,
                        V + (i64)k * N, N, dead);
             sigma_apply(ctx, sp, V + (i64)k * N, W + (i64)k * N, phase_prec, phase_mode, s);
+            ws.project(lock, nlock, W + (i64)k * N, sc);
             ++products;
             // new Gram column: G[j][k] = V_j . W_k, j <= k
             ws.dots(V, N, k + 1, W + (i64)k * N, G.as<double>() + k, DV_MAXK);

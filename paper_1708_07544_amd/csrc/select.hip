@@ -127,7 +127,26 @@ i64 pow2_at_least(i64 x) {
     return p;
 }
 
+// w_i = max_r |C_r,i| over the states r (rows of C): fl(|H_ai| x) is
+// non-decreasing in x, so fl(|H_ai| w_i) > eps exactly when some state
+// passes, and one walk with w selects the union of the states' sets.
+__global__ void roots_weight_kernel(const double* __restrict__ C, int nroots, i64 N, double* __restrict__ w) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double m = 0.0;
+    for (int r = 0; r < nroots; ++r) m = fmax(m, fabs(C[(i64)r * N + i]));
+    w[i] = m;
+}
+
 }  // namespace
+
+i64 select_roots_run(hci_ctx_s* ctx, const u64* dets, const double* C, int nroots, i64 N, double eps,
+                     u64* out, i64 cap, hipStream_t s) {
+    DevMem w = dev_alloc(ctx, sizeof(double) * N, s);
+    HCI_LAUNCH(ctx, "select_roots", s, roots_weight_kernel, ceil_div(N, 256), 256, 0, C, nroots, N,
+               w.as<double>());
+    return select_run(ctx, dets, w.as<double>(), N, eps, out, cap, s);
+}
 
 void embed_run(hci_ctx_s* ctx, const u64* dets, i64 n, const double* c, const u64* dn, i64 nn,
                double* out, hipStream_t s) {

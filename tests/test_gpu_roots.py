@@ -1,0 +1,166 @@
+"""Several states of one space, and unequal spin projections, against the oracle.
+
+* hci_davidson_roots: energies of the lowest states (1e-9 Ha, residual
+  tolerance 1e-10) and eigenvectors (1e-6 per entry, the residual over the
+  gap to the neighbouring states) of (8e,8o) and (5a,3b) full spaces and a
+  (16e,16o) HCI space, in both precisions, from zero and from warm starts;
+  the whole spectrum of a four-determinant space; one state equals
+  hci_davidson; argument errors.
+* A spin check through the library: the lowest M_s = 1 energies are
+  M_s = 0 states (other components of the same multiplets).
+* hci_select_roots: identical bit for bit to the oracle's union of
+  single-state selections.
+"""
+import numpy as np
+import pytest
+
+import hci_synth as hs
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P(gpu_available):
+    import paper_1708_07544_amd as P
+    return P
+
+
+def _space(name):
+    if name == "cas8":
+        h, g = hs.workload_integrals(hs.WORKLOADS["cas8"])
+        return h, g, 4, 4, hs.full_space(8, 4, 4)
+    if name == "ms1":
+        h, g = hs.workload_integrals(hs.WORKLOADS["cas8"])
+        return h, g, 5, 3, hs.full_space(8, 5, 3)
+    h, g = hs.workload_integrals(hs.WORKLOADS["cas16"])
+    V0 = hs.aufbau_det(8, 8)
+    return h, g, 8, 8, O.merge(V0, O.select(h, g, V0, np.array([1.0]), 5e-2))
+
+
+def _check_states(e, C, eref, Cref, tol_e=1e-9, tol_c=1e-6):
+    """Energies; vectors up to sign (in states odd under the exchange of alpha
+    and beta strings the two largest |c_i| are equal and opposite, so rounding
+    picks the entry that fixes the sign); the sign convention on the
+    library's own vectors (largest |c_i|, first on ties, positive)."""
+    k = len(eref)
+    assert np.abs(e - eref).max() < tol_e, (e, eref)
+    assert np.abs(C @ C.T - np.eye(k)).max() < 1e-10
+    for r in range(k):
+        d = min(np.abs(C[r] - Cref[r]).max(), np.abs(C[r] + Cref[r]).max())
+        assert d < tol_c, (r, d)
+        assert C[r][int(np.argmax(np.abs(C[r])))] > 0
+
+
+@pytest.mark.parametrize("name,k,precision", [("cas8", 4, "fp64"), ("cas8", 4, "fp32_mixed"),
+                                              ("ms1", 3, "fp64"), ("ms1", 3, "fp32_mixed"),
+                                              ("cas16", 3, "fp32_mixed")])
+def test_roots_match_oracle(P, name, k, precision):
+    h, g, na, nb, V = _space(name)
+    eref, Cref = O.lowest_eigenpairs(h, g, V, k + 1)
+    assert np.diff(eref).min() > 1e-4  # states separated: vectors compare one by one
+    eref, Cref = eref[:k], Cref[:k]
+    print(f"[roots {name} |V|={len(V)} k={k} {precision}]", flush=True)
+    ctx = P.HCIContext(h, g, na, nb)
+    e, C, its = ctx.davidson_roots(V, k, tol=1e-10, precision=precision)
+    print(f"  E={e} products={its}", flush=True)
+    _check_states(e, C.cpu().numpy(), eref, Cref)
+    # warm start from perturbed reference vectors: same states, fewer products
+    rng = np.random.default_rng(5)
+    C0 = Cref + 1e-4 * rng.normal(size=Cref.shape)
+    e2, C2, its2 = ctx.davidson_roots(V, k, c0=C0, tol=1e-10, precision=precision)
+    _check_states(e2, C2.cpu().numpy(), eref, Cref)
+    assert sum(its2) <= sum(its)
+    ctx.close()
+
+
+def test_ms1_states_are_ms0_states(P):
+    """Spin symmetry through the library: each of the three lowest M_s = 1
+    energies equals one of the M_s = 0 states (the other component of the
+    same multiplet; which one is read from the oracle's full spectrum)."""
+    h, g = hs.workload_integrals(hs.WORKLOADS["cas8"])
+    V1 = hs.full_space(8, 5, 3)
+    V0 = hs.full_space(8, 4, 4)
+    full0 = np.linalg.eigvalsh(O.hamiltonian_csr(h, g, V0).toarray())
+    e1ref, _ = O.lowest_eigenpairs(h, g, V1, 3)
+    idx = [int(np.argmin(np.abs(full0 - x))) for x in e1ref]
+    assert max(abs(full0[i] - x) for i, x in zip(idx, e1ref)) < 1e-9 and max(idx) < 8
+    c1 = P.HCIContext(h, g, 5, 3)
+    e1, _, _ = c1.davidson_roots(V1, 3, tol=1e-10)
+    c1.close()
+    c0 = P.HCIContext(h, g, 4, 4)
+    e0, _, _ = c0.davidson_roots(V0, max(idx) + 1, tol=1e-10)
+    c0.close()
+    print(f"[Ms=1 in Ms=0] {e1} at {idx} of {e0}", flush=True)
+    for i, x in zip(idx, e1):
+        assert abs(e0[i] - x) < 1e-9
+
+
+def test_roots_whole_spectrum_and_single_state(P):
+    h, g = hs.make_integrals(4, 12, 3)
+    V = hs.full_space(4, 1, 1)[:4]  # four determinants
+    eref = np.linalg.eigvalsh(O.hamiltonian_by_operators(h, g, V))
+    ctx = P.HCIContext(h, g, 1, 1)
+    e, C, _ = ctx.davidson_roots(V, 4, tol=1e-12)
+    assert np.abs(e - eref).max() < 1e-12
+    Cn = C.cpu().numpy()
+    assert np.abs(Cn @ Cn.T - np.eye(4)).max() < 1e-12
+    # one state is hci_davidson, also from the same start vector
+    hb, gb = hs.workload_integrals(hs.WORKLOADS["cas8"])
+    Vb = hs.full_space(8, 4, 4)
+    cb = P.HCIContext(hb, gb, 4, 4)
+    e1, c1, it1 = cb.davidson(Vb, None, tol=1e-10)
+    er, Cr, itr = cb.davidson_roots(Vb, 1, tol=1e-10)
+    assert er[0] == e1 and itr[0] == it1
+    assert torch_equal(Cr[0], c1)
+    # a start row inside the span of the earlier states falls back to a seed
+    C0 = np.zeros((2, len(Vb)))
+    C0[0] = c1.cpu().numpy()
+    C0[1] = c1.cpu().numpy()
+    eref2, Cref2 = O.lowest_eigenpairs(hb, gb, Vb, 2)
+    e2, C2, _ = cb.davidson_roots(Vb, 2, c0=C0, tol=1e-10)
+    _check_states(e2, C2.cpu().numpy(), eref2, Cref2)
+    cb.close()
+    ctx.close()
+
+
+def torch_equal(a, b):
+    return bool((a == b).all())
+
+
+def test_roots_rejects_bad_arguments(P):
+    h, g = hs.make_integrals(4, 12, 3)
+    V = hs.full_space(4, 1, 1)[:4]
+    ctx = P.HCIContext(h, g, 1, 1)
+    for k in (0, 5):
+        with pytest.raises(P.HCIError) as ei:
+            ctx.davidson_roots(V, k)
+        assert ei.value.code == -1, k
+    h8, g8 = hs.workload_integrals(hs.WORKLOADS["cas8"])
+    c8 = P.HCIContext(h8, g8, 4, 4)
+    with pytest.raises(P.HCIError) as ei:
+        c8.davidson_roots(hs.full_space(8, 4, 4), 32)
+    assert ei.value.code == -1
+    with pytest.raises(P.HCIError) as ei:
+        c8.select(hs.full_space(8, 4, 4)[:40], np.ones((32, 40)), 1e-3)
+    assert ei.value.code == -1
+    c8.close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("n,na,nb,m,nroots,seed", [(10, 3, 5, 500, 3, 2), (12, 6, 6, 1200, 4, 3),
+                                                   (14, 7, 6, 64, 2, 5)])
+@pytest.mark.parametrize("eps", [1e-4, 1e-2])
+def test_select_roots_bit_exact(P, n, na, nb, m, nroots, seed, eps):
+    h, g = hs.make_integrals(n, 3 * n, seed)
+    V = hs.random_dets(n, na, nb, m, seed=seed, bias=0.2)
+    C = np.stack([hs.random_coeffs(len(V), seed + 100 + r) for r in range(nroots)])
+    C[-1] = C[0]  # a repeated state changes nothing
+    ref = O.merge(V, O.select_roots(h, g, V, C, eps))
+    ctx = P.HCIContext(h, g, na, nb)
+    out = P.dets_to_numpy(ctx.select(V, C, eps))
+    print(f"[select_roots n={n} m={len(V)} k={nroots} eps={eps}] ref={len(ref)} gpu={len(out)}", flush=True)
+    assert np.array_equal(out, ref)
+    one = P.dets_to_numpy(ctx.select(V, C[:1], eps))
+    assert np.array_equal(one, P.dets_to_numpy(ctx.select(V, C[0], eps)))
+    ctx.close()
