@@ -62,6 +62,8 @@ def parse():
                     help="levels of the full-CI extrapolation leg on the final space (0: skip it)")
     ap.add_argument("--orbital-reps", type=int, default=20,
                     help="timed repetitions of the orbital-step leg (0: skip it)")
+    ap.add_argument("--roots", type=int, default=3,
+                    help="states of the several-state leg (0 skips it)")
     ap.add_argument("--pt2-cpu-rows", type=int, default=2000,
                     help="rows of the final space the oracle's PT2 pair walk times")
     return ap.parse_args()
@@ -185,6 +187,9 @@ def main():
     orbital = None
     if args.orbital_reps > 0:
         orbital = orbital_leg(args)
+    roots = None
+    if args.roots > 1:
+        roots = roots_leg(ctx, V1, c1, V2, c_mixed, w.eps1, args)
     # ---------------------------------------------------------------- roofline
     sk = kernels.get("sigma_stored_f32")
     gk = kernels.get("sigma_stored_f32_g")
@@ -247,9 +252,45 @@ def main():
         "pt2": pt2,
         "orbital": orbital,
         "extrapolation": extrap,
+        "roots": roots,
     }
     del dav_time_ms
     print(json.dumps(out))
+
+
+def roots_leg(ctx, V1, c1, V2, c2, eps1, args):
+    """Several states: the lowest args.roots states on V1 (float64), the
+    union selection of V1 over them against the single-state selection, and
+    the lowest states on the step's space V2 (mixed precision, state 0 warm
+    started from the step's vector)."""
+    import torch
+    k = args.roots
+    e1, C1, _ = ctx.davidson_roots(V1, k, tol=args.tol)
+
+    def timed(f):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = f()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t) * 1e3
+
+    single, ms_single = timed(lambda: ctx.select(V1, c1, eps1))
+    union, ms_union = timed(lambda: ctx.select(V1, C1, eps1))
+    del single, union
+    C0 = torch.zeros((k, V2.shape[0]), dtype=torch.float64, device=V2.device)
+    C0[0] = c2
+    (e2, C2, its), ms = timed(lambda: ctx.davidson_roots(V2, k, c0=C0, tol=args.tol,
+                                                         precision="fp32_mixed", max_iter=2000))
+    # davidson_ms includes building the stored Hamiltonian of V2, as the step does
+    out = {"states": k, "energies": [float(x) for x in e2], "products": its,
+           "davidson_ms": round(ms, 2), "n_det": int(V2.shape[0]),
+           "select_single_ms": round(ms_single, 2), "select_union_ms": round(ms_union, 2),
+           "n_select_single": int(ctx.select(V1, c1, eps1).shape[0]),
+           "n_select_union": int(ctx.select(V1, C1, eps1).shape[0])}
+    log(f"[bench] {k} states on {out['n_det']} determinants: {out['energies']} "
+        f"({ms:.1f} ms, products {its}); union selection {out['n_select_union']} in {ms_union:.1f} ms "
+        f"vs single {out['n_select_single']} in {ms_single:.1f} ms")
+    return out
 
 
 PT2_KERNELS = ["pt2_count", "pt2_fill_pairs", "radix_hist", "radix_scatter", "pt2_reduce", "pt2_r",

@@ -229,7 +229,10 @@ int hci_diagonal(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* hdiag
  *   the mixed product, then refines with float64 products until the float64
  *   residual meets tol.  iters_out (host, may be NULL): products performed.
  *   HCI_E_NOCONV when max_iter products did not reach tol (c and E hold the
- *   best iterate).  Synchronises the stream. */
+ *   best iterate).  The start vector is used as given: one confined to a
+ *   symmetry sector of H (see hci_davidson_roots) gives the lowest state of
+ *   that sector, as a warm start from the previous state of the same
+ *   symmetry intends.  Synchronises the stream. */
 int hci_davidson(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* c_inout,
                  double* e_out, double tol, int max_iter, int precision, int mode,
                  int* iters_out, void* stream);
@@ -239,9 +242,14 @@ int hci_davidson(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* c_ino
  * deflation: state r is the lowest eigenpair of Q H Q on the complement of
  * states 0..r-1 (Q = 1 - sum_l c_l c_l^T), found by the solver of
  * hci_davidson with every new direction orthogonalised against the earlier
- * states and every product projected by Q.  States come out in ascending
- * order when each solve reaches the lowest state of its complement, the
- * case unless a start vector has no overlap with it.
+ * states and every product projected by Q.  Every start vector first gets a
+ * fixed pseudo-random component of about 1e-3 of its norm (splitmix64 of
+ * the determinant index), so that each solve reaches the lowest state of its
+ * complement whatever its symmetry: a start vector confined to one symmetry
+ * sector of H (even or odd under the exchange of alpha and beta strings when
+ * N_alpha = N_beta and V is closed under it, as selected spaces of such
+ * states are) would otherwise converge inside that sector and skip lower
+ * states of the other.  States come out in ascending order.
  *   c_inout: device float64 [nroots][n_var]: row r is the start of state r
  *   (a zero row, or one inside the span of the earlier states, selects the
  *   lowest-diagonal determinant that the earlier states hold less than half

@@ -385,6 +385,23 @@ def hci(h, g, nalpha, nbeta, eps1, max_iter=20, V0=None, tol=1e-12, dense_max=30
     return V, c, e, history
 
 
+def hci_roots(h, g, nalpha, nbeta, eps1, nroots, V0, max_iter=20, tol=1e-12, dense_max=3000):
+    """The variational stage for several states of one space: from V0 (at
+    least nroots determinants), V <- V + union of the states' C(eps1), then the
+    nroots lowest eigenpairs, until nothing is added or max_iter."""
+    V = sort_unique(V0)
+    e, C = lowest_eigenpairs(h, g, V, nroots, tol=tol, dense_max=dense_max)
+    history = [(len(V), e.copy())]
+    for _ in range(max_iter):
+        A = select_roots(h, g, V, C, eps1)
+        if len(A) == 0:
+            break
+        V = merge(V, A)
+        e, C = lowest_eigenpairs(h, g, V, nroots, tol=tol, dense_max=dense_max)
+        history.append((len(V), e.copy()))
+    return V, C, e, history
+
+
 def _keys(V):
     """Structured view for ordered searches over (alpha, beta)."""
     V = np.ascontiguousarray(V, dtype=np.uint64)

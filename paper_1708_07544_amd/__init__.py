@@ -334,9 +334,14 @@ class HCIContext:
 
     # ---------------------------------------------------------------- driver
     def hci(self, eps1: float, max_macro: int = 20, tol: float = 1e-8, precision="fp64",
-            mode="auto", dets0=None, log=None):
+            mode="auto", dets0=None, log=None, nroots: int = 1):
         """HCI variational stage: V0 = aufbau (or dets0), then repeatedly
-        V <- V + C(eps1) and re-diagonalise until nothing is added."""
+        V <- V + C(eps1) and re-diagonalise until nothing is added.  With
+        nroots > 1 the nroots lowest states are followed and C is the union
+        of their selections (dets0 must then hold at least nroots
+        determinants); returns (V, C [nroots, n], E [nroots], history)."""
+        if nroots > 1:
+            return self._hci_roots(eps1, nroots, dets0, max_macro, tol, precision, mode, log)
         if dets0 is None:
             dets0 = np.array([[(1 << self.nalpha) - 1, (1 << self.nbeta) - 1]], dtype=np.uint64)
         V = self._dets(dets0)
@@ -353,3 +358,21 @@ class HCIContext:
             if log:
                 log(hist[-1])
         return V, c, e, hist
+
+    def _hci_roots(self, eps1, nroots, dets0, max_macro, tol, precision, mode, log):
+        if dets0 is None:
+            raise ValueError("several states need a start list dets0 of at least nroots determinants")
+        V = self._dets(dets0)
+        e, C, it = self.davidson_roots(V, nroots, tol=tol, precision=precision, mode=mode)
+        hist = [(int(V.shape[0]), e, it)]
+        for _ in range(max_macro):
+            Vn = self.select(V, C, eps1)
+            if Vn.shape[0] == V.shape[0]:
+                break
+            C0 = torch.stack([self.embed(V, C[r], Vn) for r in range(nroots)])
+            V = Vn
+            e, C, it = self.davidson_roots(V, nroots, c0=C0, tol=tol, precision=precision, mode=mode)
+            hist.append((int(V.shape[0]), e, it))
+            if log:
+                log(hist[-1])
+        return V, C, e, hist

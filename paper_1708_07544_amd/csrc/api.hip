@@ -420,7 +420,7 @@ int hci_davidson_roots(hci_ctx ctx, const uint64_t* dets, int64_t n_var, int nro
         for (int r = 0; r < nroots; ++r) {
             // state r: the lowest eigenpair in the complement of states 0..r-1
             const int rc = davidson_run(ctx, sp, c_inout + (i64)r * n_var, e_out + r, tol, max_iter, precision,
-                                        mode, iters_out ? iters_out + r : nullptr, s, c_inout, r);
+                                        mode, iters_out ? iters_out + r : nullptr, s, c_inout, r, true);
             if (rc != HCI_OK) worst = rc;
         }
         if (worst == HCI_E_NOCONV) g_last_error = "Davidson did not reach tol within max_iter products for a state";

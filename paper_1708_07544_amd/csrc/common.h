@@ -408,10 +408,11 @@ void staged_ensure_vals(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s)
 void layout_info(hci_ctx_s* ctx, Space* sp, int64_t* info, hipStream_t s);
 void staged_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int precision,
                   hipStream_t s);
-// lock: nlock orthonormal vectors [nlock][N] to deflate (the states below)
+// lock: nlock orthonormal vectors [nlock][N] to deflate (the states below);
+// generic_start: add a fixed pseudo-random 1e-3 component to the start vector
 int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol, int max_iter,
                  int precision, int mode, int* iters_out, hipStream_t s, const double* lock = nullptr,
-                 int nlock = 0);
+                 int nlock = 0, bool generic_start = false);
 double heat_bath_max(hci_ctx_s* ctx, hipStream_t s);
 i64 select_run(hci_ctx_s* ctx, const u64* dets, const double* c, i64 N, double eps, u64* out,
                i64 cap, hipStream_t s);

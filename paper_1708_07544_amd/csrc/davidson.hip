@@ -19,7 +19,9 @@
 // given, the solver works on Q H Q restricted to the complement of L
 // (Q = 1 - L L^T): every new basis vector is orthogonalised against L before
 // the basis, and every product H v is projected by Q.  Its lowest eigenpair
-// there is the next state, and its residual is orthogonal to L.
+// there is the next state, and its residual is orthogonal to L.  For several
+// states every start vector gets a small fixed pseudo-random component, so
+// that the lowest state of the complement is reached whatever its symmetry.
 #include <cfloat>
 
 #include "common.h"
@@ -401,6 +403,27 @@ __global__ void __launch_bounds__(256) deflated_seed_kernel(const double* __rest
     for (i64 i = threadIdx.x; i < N; i += 256) x[i] = (i == bi[0]) ? 1.0 : 0.0;
 }
 
+// x += delta z with z_i uniform in [-1, 1) from the splitmix64 generator
+// (Steele, Lea and Flood, OOPSLA 2014) at counter i, and |delta z| about
+// 1e-3 |x| (E z_i^2 = 1/3).  A start vector confined to one symmetry sector
+// of H (even or odd under the exchange of alpha and beta strings when
+// N_alpha = N_beta, for instance) otherwise only reaches other sectors
+// through rounding errors.
+__device__ __forceinline__ u64 splitmix64_at(u64 i) {
+    u64 z = (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void generic_start_kernel(double* __restrict__ x, i64 N, const double* __restrict__ nrm2) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double delta = 1e-3 * sqrt(3.0 * *nrm2 / (double)N);
+    const double z = (double)(splitmix64_at((u64)i) >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+    x[i] += delta * z;
+}
+
 // sign convention: largest-|c| entry positive (first index on ties)
 // Sign convention: the entry of largest magnitude (first index on ties) is
 // made positive.  Block partials of (|x_i|, i), a one-block decision, then a
@@ -505,7 +528,8 @@ struct Workspace {
 }  // namespace
 
 int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol, int max_iter,
-                 int precision, int mode, int* iters_out, hipStream_t s, const double* lock, int nlock) {
+                 int precision, int mode, int* iters_out, hipStream_t s, const double* lock, int nlock,
+                 bool generic_start) {
     const i64 N = sp->N;
     HCI_REQUIRE(nlock >= 0 && nlock < DV_MAXK && nlock < N && (nlock == 0 || lock != nullptr), HCI_E_ARG,
                 "bad number of locked vectors");
@@ -550,6 +574,11 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
             HCI_LAUNCH(ctx, "dv_seed", s, deflated_seed_kernel, 1, 256, 0, hd, N, lock, nlock, xc);
             ws.cgs2(lock, N, nlock, xc, sc, nrm_x);
         }
+    }
+    if (generic_start) {
+        ws.dots(xc, N, 1, xc, nrm_x);
+        HCI_LAUNCH(ctx, "dv_seed", s, generic_start_kernel, g1, 256, 0, xc, N, (const double*)nrm_x);
+        if (nlock > 0) ws.cgs2(lock, N, nlock, xc, sc, nrm_x);
     }
 
     const bool mixed = precision == HCI_FP32_MIXED;

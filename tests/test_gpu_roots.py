@@ -105,14 +105,14 @@ def test_roots_whole_spectrum_and_single_state(P):
     assert np.abs(e - eref).max() < 1e-12
     Cn = C.cpu().numpy()
     assert np.abs(Cn @ Cn.T - np.eye(4)).max() < 1e-12
-    # one state is hci_davidson, also from the same start vector
+    # one state is the state of hci_davidson
     hb, gb = hs.workload_integrals(hs.WORKLOADS["cas8"])
     Vb = hs.full_space(8, 4, 4)
     cb = P.HCIContext(hb, gb, 4, 4)
     e1, c1, it1 = cb.davidson(Vb, None, tol=1e-10)
     er, Cr, itr = cb.davidson_roots(Vb, 1, tol=1e-10)
-    assert er[0] == e1 and itr[0] == it1
-    assert torch_equal(Cr[0], c1)
+    assert abs(er[0] - e1) < 1e-10
+    assert float((Cr[0] - c1).abs().max()) < 1e-7
     # a start row inside the span of the earlier states falls back to a seed
     C0 = np.zeros((2, len(Vb)))
     C0[0] = c1.cpu().numpy()
@@ -122,10 +122,6 @@ def test_roots_whole_spectrum_and_single_state(P):
     _check_states(e2, C2.cpu().numpy(), eref2, Cref2)
     cb.close()
     ctx.close()
-
-
-def torch_equal(a, b):
-    return bool((a == b).all())
 
 
 def test_roots_rejects_bad_arguments(P):
@@ -164,3 +160,27 @@ def test_select_roots_bit_exact(P, n, na, nb, m, nroots, seed, eps):
     one = P.dets_to_numpy(ctx.select(V, C[:1], eps))
     assert np.array_equal(one, P.dets_to_numpy(ctx.select(V, C[0], eps)))
     ctx.close()
+
+
+@pytest.mark.parametrize("na,nb", [(4, 4), (5, 3)])
+def test_hci_several_states_matches_oracle(P, na, nb):
+    """The several-state variational stage (union selection, deflated
+    Davidson, warm starts carried by hci_embed) against the oracle's loop:
+    the same determinant lists at every step and the same energies.  With
+    N_alpha = N_beta the selected spaces are closed under the exchange of
+    alpha and beta strings and the warm starts have a definite parity under
+    it that the next space's states do not share (at 1927 determinants the
+    starts are odd, even, even and the lowest states even, odd, odd): the
+    case that needs the symmetry-breaking start of the several-state
+    solver."""
+    h, g = hs.workload_integrals(hs.WORKLOADS["cas8"])
+    a = hs.aufbau_det(na, nb)
+    V0 = O.merge(a, O.select(h, g, a, np.array([1.0]), 0.2))
+    Vr, Cr, er, hr = O.hci_roots(h, g, na, nb, 3e-2, 3, V0)
+    ctx = P.HCIContext(h, g, na, nb)
+    V, C, e, hist = ctx.hci(3e-2, nroots=3, dets0=V0, tol=1e-10)
+    ctx.close()
+    print(f"[hci roots {na},{nb}] sizes {[x[0] for x in hist]} vs {[x[0] for x in hr]}: {e} vs {er}", flush=True)
+    assert [x[0] for x in hist] == [x[0] for x in hr]
+    assert np.array_equal(P.dets_to_numpy(V), Vr)
+    assert np.abs(e - er).max() < 1e-9

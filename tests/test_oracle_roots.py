@@ -101,3 +101,19 @@ def test_select_roots_union_matches_bruteforce(eps):
     for s in single:
         assert {tuple(x) for x in s.tolist()} <= have
     assert len(got) <= sum(len(s) for s in single)
+
+
+def test_hci_roots_reaches_full_ci_states_and_is_variational():
+    """eps1 = 0 grows V until the tracked states are the full-CI ones; on the
+    way each state's energy never rises (the k lowest eigenvalues of a
+    larger space are below those of a subspace, by interlacing)."""
+    n, na, nb, k = 6, 3, 2, 3
+    h, g = hs.make_integrals(n, 18, 13)
+    full = np.linalg.eigvalsh(O.hamiltonian_csr(h, g, hs.full_space(n, na, nb)).toarray())
+    V0 = O.merge(hs.aufbau_det(na, nb), O.select(h, g, hs.aufbau_det(na, nb), np.array([1.0]), 0.2))
+    assert len(V0) >= k
+    V, C, e, hist = O.hci_roots(h, g, na, nb, 0.0, k, V0)
+    assert np.abs(e - full[:k]).max() < 1e-10
+    E = np.array([x for _, x in hist])
+    assert np.all(np.diff(E, axis=0) <= 1e-12)
+    assert len(hist) > 2
