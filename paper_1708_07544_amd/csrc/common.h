@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <memory>
 #include <string>
@@ -323,14 +324,44 @@ struct ScopedTimer {
     }
 };
 
+// The dispatch packet counts a grid in work-items as a 32-bit number: a
+// larger grid would silently run only part of its workgroups, so it is an
+// error here.  Kernels that may see more rows than one launch can cover loop
+// over them (row_grid below).
+inline bool launch_fits(i64 grid, i64 block) { return grid >= 0 && grid * block < ((i64)1 << 32); }
+inline bool launch_fits(const dim3& grid, i64 block) {
+    return (i64)grid.x * block < ((i64)1 << 32) && (i64)grid.y < ((i64)1 << 32) && (i64)grid.z < ((i64)1 << 32);
+}
+inline dim3 launch_dim(i64 grid) { return dim3((unsigned)grid); }
+inline dim3 launch_dim(const dim3& grid) { return grid; }
+
 #define HCI_LAUNCH(ctx, name, stream, kernel, grid, block, shmem, ...)             \
     do {                                                                          \
+        const auto _grid = (grid);                                                \
+        const i64 _block = (i64)(block);                                          \
+        HCI_REQUIRE(launch_fits(_grid, _block), HCI_E_UNSUPPORTED,                \
+                    std::string("launch of ") + (name) + " would exceed 2^32 work-items"); \
         ScopedTimer _st((ctx), (name), (stream));                                 \
-        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), (shmem), (stream), __VA_ARGS__); \
+        hipLaunchKernelGGL(kernel, launch_dim(_grid), dim3((unsigned)_block), (shmem), (stream), \
+                           __VA_ARGS__);                                          \
         HIP_CHECK(hipGetLastError());                                             \
     } while (0)
 
 inline i64 ceil_div(i64 a, i64 b) { return (a + b - 1) / b; }
+
+// Workgroups for `rows` rows at `rows_per_block` per workgroup of `block`
+// work-items, clamped below the 2^32 work-item limit of one launch (the
+// kernel then strides over the rest).  HCI_ROW_GRID_CAP=<k> clamps to k
+// workgroups instead, so that tests exercise the striding on small lists.
+inline i64 row_grid(i64 rows, i64 rows_per_block, i64 block) {
+    i64 cap = (((i64)1 << 32) - 1) / block;
+    if (const char* e = std::getenv("HCI_ROW_GRID_CAP")) {
+        const long long k = std::atoll(e);
+        if (k > 0 && k < cap) cap = (i64)k;
+    }
+    const i64 g = ceil_div(rows, rows_per_block);
+    return g < cap ? g : cap;
+}
 
 inline SpaceView space_view(const Space& s, int n) {
     SpaceView v;

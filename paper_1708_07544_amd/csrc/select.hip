@@ -22,42 +22,57 @@ constexpr int WALK_BLOCK = 256;
 constexpr int WALK_ROWS = WALK_BLOCK / HCI_WAVE;
 using namespace hset;
 
+// Inserts the visited candidates.  Once the set holds `limit` new
+// determinants (its load factor would pass 1/2) or an insert fails, the
+// overflow flag is raised and the wave stops inserting: the host grows the
+// set and walks again, so the rest of this walk would be wasted probing of
+// an ever fuller table.  Every lane of a wave calls the visitor together,
+// so `stop` stays uniform.
 struct InsertVis {
     HashSet H;
     u64* out;
     unsigned long long* counter;
     i64 cap;
+    i64 limit;
+    bool stop;
     __device__ __forceinline__ void operator()(bool ok, u64 aa, u64 ab) {
-        bool fresh = false;
+        if (stop) return;
+        bool fresh = false, failed = false;
         u64 key = 0;
         if (ok) {
             if (!det_key(H, aa, ab, key) || hash_insert(H.det, H.det_mask, key, fresh) < 0) {
-                atomicOr(H.overflow, 1ull);
+                failed = true;
                 fresh = false;
             }
         }
         const u64 m = ballot(fresh);
-        if (!m) return;
         unsigned long long base = 0;
-        if (lane_id() == 0) base = atomicAdd(counter, (unsigned long long)__popcll(m));
+        if (m && lane_id() == 0) base = atomicAdd(counter, (unsigned long long)__popcll(m));
         base = __shfl(base, 0, 64);
         if (fresh) {
             const i64 at = (i64)base + rank_in(m);
             if (at < cap) out[at] = key;
+        }
+        if (ballot(failed) != 0 || (m && (i64)base + __popcll(m) > limit)) {
+            if (lane_id() == 0) atomicOr(H.overflow, 1ull);
+            stop = true;
         }
     }
 };
 
 __global__ void __launch_bounds__(WALK_BLOCK) select_walk_kernel(
     HBView T, IntView I, const u64* __restrict__ dets, const double* __restrict__ c, i64 N,
-    double eps, double hb_max, HashSet H, u64* __restrict__ out, i64 cap,
+    double eps, double hb_max, HashSet H, u64* __restrict__ out, i64 cap, i64 limit,
     unsigned long long* __restrict__ counter) {
-    const i64 i = (i64)blockIdx.x * WALK_ROWS + threadIdx.x / HCI_WAVE;
-    if (i >= N) return;
-    const double ci = fabs(c[i]);
-    if (!(hb_max * ci > eps)) return;  // nothing can pass from this determinant
-    InsertVis v{H, out, counter, cap};
-    heat_bath_walk(T, I, dets[2 * i], dets[2 * i + 1], ci, eps, v);
+    // one wavefront per row, striding over the rows beyond one launch's grid
+    for (i64 i = (i64)blockIdx.x * WALK_ROWS + threadIdx.x / HCI_WAVE; i < N;
+         i += (i64)gridDim.x * WALK_ROWS) {
+        const double ci = fabs(c[i]);
+        if (!(hb_max * ci > eps)) continue;  // nothing can pass from this determinant
+        if (*(volatile unsigned long long*)H.overflow != 0ull) return;  // the set is being regrown
+        InsertVis v{H, out, counter, cap, limit, false};
+        heat_bath_walk(T, I, dets[2 * i], dets[2 * i + 1], ci, eps, v);
+    }
 }
 
 // V followed by the decoded new determinants, split into (alpha, beta) words
@@ -218,8 +233,10 @@ i64 select_run(hci_ctx_s* ctx, const u64* dets, const double* c, i64 N, double e
         // new determinants can never exceed the free slots
         const i64 kcap = det_slots / 2;
         keys = dev_alloc(ctx, sizeof(u64) * kcap, s);
-        HCI_LAUNCH(ctx, "select_walk", s, select_walk_kernel, ceil_div(N, WALK_ROWS), WALK_BLOCK, 0, T,
-                   I, dets, c, N, eps, hbm, H, keys.as<u64>(), kcap, counter);
+        // stop the walk once the new determinants would take the load factor past 1/2
+        const i64 limit = std::max<i64>(0, std::min<i64>(kcap, det_slots / 2 - N));
+        HCI_LAUNCH(ctx, "select_walk", s, select_walk_kernel, row_grid(N, WALK_ROWS, WALK_BLOCK), WALK_BLOCK, 0, T,
+                   I, dets, c, N, eps, hbm, H, keys.as<u64>(), kcap, limit, counter);
         u64 hv[4];
         HIP_CHECK(hipMemcpyAsync(hv, flags.ptr, sizeof(hv), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));

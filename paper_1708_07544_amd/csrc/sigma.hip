@@ -27,12 +27,14 @@ struct CountVis {
     }
 };
 
+// one wavefront per row, striding over the rows beyond one launch's grid
 __global__ void __launch_bounds__(ROW_BLOCK) count_kernel(SpaceView S, u32* __restrict__ counts) {
-    const i64 i = (i64)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
-    if (i >= S.N) return;
-    CountVis v;
-    enumerate_row(S, (u32)i, v);
-    if (lane_id() == 0) counts[i] = v.cnt;
+    for (i64 i = (i64)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE; i < S.N;
+         i += (i64)gridDim.x * ROWS_PER_BLOCK) {
+        CountVis v;
+        enumerate_row(S, (u32)i, v);
+        if (lane_id() == 0) counts[i] = v.cnt;
+    }
 }
 
 // Connectivity pass of the stored matrix: column indices only (integer work).
@@ -132,12 +134,13 @@ __global__ void __launch_bounds__(ROW_BLOCK) sigma_recompute_kernel(SpaceView S,
                                                                     const float* __restrict__ c32,
                                                                     const double* __restrict__ hd,
                                                                     double* __restrict__ sigma) {
-    const i64 i = (i64)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
-    if (i >= S.N) return;
-    SigmaVis<F32> v{&I, c, c32, S.alpha[i], S.beta[i]};
-    enumerate_row(S, (u32)i, v);
-    const double acc = wave_sum_f64(v.acc);
-    if (lane_id() == 0) sigma[i] = hd[i] * c[i] + acc;
+    for (i64 i = (i64)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE; i < S.N;
+         i += (i64)gridDim.x * ROWS_PER_BLOCK) {
+        SigmaVis<F32> v{&I, c, c32, S.alpha[i], S.beta[i]};
+        enumerate_row(S, (u32)i, v);
+        const double acc = wave_sum_f64(v.acc);
+        if (lane_id() == 0) sigma[i] = hd[i] * c[i] + acc;
+    }
 }
 
 __global__ void f64_to_f32_kernel(const double* __restrict__ x, float* __restrict__ y, i64 n) {
@@ -157,7 +160,7 @@ void ensure_rowptr(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
     const i64 N = sp->N;
     SpaceView S = space_view(*sp, ctx->n);
     DevMem counts = dev_alloc(ctx, sizeof(u32) * (N + 1), s);
-    HCI_LAUNCH(ctx, "conn_count", s, count_kernel, ceil_div(N, ROWS_PER_BLOCK), ROW_BLOCK, 0, S,
+    HCI_LAUNCH(ctx, "conn_count", s, count_kernel, row_grid(N, ROWS_PER_BLOCK, ROW_BLOCK), ROW_BLOCK, 0, S,
                counts.as<u32>());
     HIP_CHECK(hipMemsetAsync(counts.as<u32>() + N, 0, sizeof(u32), s));
     DevMem total = dev_alloc(ctx, sizeof(u64), s);
@@ -233,6 +236,9 @@ void ensure_csr(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s) {
 
 int choose_mode(hci_ctx_s* ctx, Space* sp, int precision, int mode, hipStream_t s) {
     if (mode == HCI_SIGMA_STORED || mode == HCI_SIGMA_RECOMPUTE) return mode;
+    // the stored builds and the plain product take one wavefront per row in
+    // one launch; more rows than that are recomputed (striding kernels)
+    if (ceil_div(sp->N, ROWS_PER_BLOCK) * ROW_BLOCK >= ((i64)1 << 32)) return HCI_SIGMA_RECOMPUTE;
     ensure_layout(ctx, sp, s);
     const bool f32 = precision == HCI_FP32_MIXED;
     // bytes per stored entry: value + column (u16 staged, u32 plain)
@@ -274,11 +280,12 @@ void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int 
     } else {
         SpaceView S = space_view(*sp, ctx->n);
         IntView I = int_view(ctx->ints);
+        const i64 rgrid = row_grid(N, ROWS_PER_BLOCK, ROW_BLOCK);
         if (f32) {
-            HCI_LAUNCH(ctx, "sigma_recompute_f32", s, sigma_recompute_kernel<true>, grid, ROW_BLOCK, 0,
+            HCI_LAUNCH(ctx, "sigma_recompute_f32", s, sigma_recompute_kernel<true>, rgrid, ROW_BLOCK, 0,
                        S, I, c, c32.as<float>(), sp->hdiag.as<double>(), sigma);
         } else {
-            HCI_LAUNCH(ctx, "sigma_recompute_f64", s, sigma_recompute_kernel<false>, grid, ROW_BLOCK, 0,
+            HCI_LAUNCH(ctx, "sigma_recompute_f64", s, sigma_recompute_kernel<false>, rgrid, ROW_BLOCK, 0,
                        S, I, c, (const float*)nullptr, sp->hdiag.as<double>(), sigma);
         }
     }

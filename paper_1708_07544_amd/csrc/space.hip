@@ -159,6 +159,17 @@ void build_adjacency(hci_ctx_s* ctx, const DevMem& uniq, i64 m, int n, DevMem& p
     HCI_LAUNCH(ctx, "adjacency_count", s, adjacency_kernel<false>, ceil_div(m, 128), 128, 0,
                uniq.as<u64>(), m, n, (const u32*)nullptr, cnt.as<u32>());
     HIP_CHECK(hipMemsetAsync(cnt.as<u32>() + m, 0, sizeof(u32), s));
+    {
+        // the offsets below and the per-bucket position tables of the stored
+        // layout (one entry per link and per string) are 32-bit: refuse a
+        // space whose links would wrap them, before anything is written
+        DevMem wide = dev_alloc(ctx, sizeof(i64) * (m + 1), s);
+        scan_u32_to_i64(ctx, cnt.as<u32>(), wide.as<i64>(), m + 1, s);
+        const i64 links = read_scalar(wide.as<i64>() + m, s);
+        HCI_REQUIRE(links + m < ((i64)1 << 32) - 1, HCI_E_UNSUPPORTED,
+                    "the unique strings of this list have " + std::to_string(links) +
+                        " single-excitation links; at most 2^32 - 2 minus the string count are supported");
+    }
     scan_u32_to_u32(ctx, cnt.as<u32>(), ptr.as<u32>(), m + 1, s);
     total = read_scalar(ptr.as<u32>() + m, s);
     idx = dev_alloc(ctx, sizeof(u32) * (total > 0 ? total : 1), s);
@@ -167,6 +178,33 @@ void build_adjacency(hci_ctx_s* ctx, const DevMem& uniq, i64 m, int n, DevMem& p
 }
 
 }  // namespace
+
+// Strings, groups, the beta-major permutation and the single-excitation
+// adjacency of a validated list.
+static void build_structure(hci_ctx_s* ctx, Space* sp, int n, hipStream_t s) {
+    const i64 N = sp->N;
+    // alpha-major groups
+    build_groups(ctx, sp->alpha.as<u64>(), N, sp->ia, sp->ua, sp->aoff, sp->nua, s);
+    // beta-major order: stable sort of beta with det index as payload
+    {
+        DevMem khi = dev_alloc(ctx, sizeof(u64) * N, s), klo = dev_alloc(ctx, sizeof(u64) * N, s);
+        DevMem thi = dev_alloc(ctx, sizeof(u64) * N, s), tlo = dev_alloc(ctx, sizeof(u64) * N, s);
+        DevMem tv = dev_alloc(ctx, sizeof(u32) * N, s);
+        sp->permb = dev_alloc(ctx, sizeof(u32) * N, s);
+        HCI_LAUNCH(ctx, "zero_u64", s, zero_u64_kernel, ceil_div(N, 256), 256, 0, khi.as<u64>(), N);
+        HIP_CHECK(hipMemcpyAsync(klo.ptr, sp->beta.ptr, sizeof(u64) * N, hipMemcpyDeviceToDevice, s));
+        HCI_LAUNCH(ctx, "iota", s, iota_kernel, ceil_div(N, 256), 256, 0, sp->permb.as<u32>(), N);
+        radix_sort128(ctx, khi.as<u64>(), klo.as<u64>(), sp->permb.as<u32>(), thi.as<u64>(),
+                      tlo.as<u64>(), tv.as<u32>(), N, 0, n, s);
+        DevMem ib_sorted;
+        build_groups(ctx, klo.as<u64>(), N, ib_sorted, sp->ub, sp->boff, sp->nub, s);
+        sp->ib = dev_alloc(ctx, sizeof(u32) * N, s);
+        HCI_LAUNCH(ctx, "scatter_u32", s, scatter_u32_kernel, ceil_div(N, 256), 256, 0,
+                   ib_sorted.as<u32>(), sp->permb.as<u32>(), N, sp->ib.as<u32>());
+    }
+    build_adjacency(ctx, sp->ua, sp->nua, n, sp->as_ptr, sp->as_idx, sp->n_as, s);
+    build_adjacency(ctx, sp->ub, sp->nub, n, sp->bs_ptr, sp->bs_idx, sp->n_bs, s);
+}
 
 Space* get_space(hci_ctx_s* ctx, const u64* dets, i64 N, hipStream_t s) {
     HCI_REQUIRE(dets != nullptr && N > 0, HCI_E_ARG, "empty or null determinant list");
@@ -197,26 +235,11 @@ Space* get_space(hci_ctx_s* ctx, const u64* dets, i64 N, hipStream_t s) {
     sp->hash = hv[0];
     sp->alpha = std::move(alpha);
     sp->beta = std::move(beta);
-    // alpha-major groups
-    build_groups(ctx, sp->alpha.as<u64>(), N, sp->ia, sp->ua, sp->aoff, sp->nua, s);
-    // beta-major order: stable sort of beta with det index as payload
-    {
-        DevMem khi = dev_alloc(ctx, sizeof(u64) * N, s), klo = dev_alloc(ctx, sizeof(u64) * N, s);
-        DevMem thi = dev_alloc(ctx, sizeof(u64) * N, s), tlo = dev_alloc(ctx, sizeof(u64) * N, s);
-        DevMem tv = dev_alloc(ctx, sizeof(u32) * N, s);
-        sp->permb = dev_alloc(ctx, sizeof(u32) * N, s);
-        HCI_LAUNCH(ctx, "zero_u64", s, zero_u64_kernel, ceil_div(N, 256), 256, 0, khi.as<u64>(), N);
-        HIP_CHECK(hipMemcpyAsync(klo.ptr, sp->beta.ptr, sizeof(u64) * N, hipMemcpyDeviceToDevice, s));
-        HCI_LAUNCH(ctx, "iota", s, iota_kernel, ceil_div(N, 256), 256, 0, sp->permb.as<u32>(), N);
-        radix_sort128(ctx, khi.as<u64>(), klo.as<u64>(), sp->permb.as<u32>(), thi.as<u64>(),
-                      tlo.as<u64>(), tv.as<u32>(), N, 0, n, s);
-        DevMem ib_sorted;
-        build_groups(ctx, klo.as<u64>(), N, ib_sorted, sp->ub, sp->boff, sp->nub, s);
-        sp->ib = dev_alloc(ctx, sizeof(u32) * N, s);
-        HCI_LAUNCH(ctx, "scatter_u32", s, scatter_u32_kernel, ceil_div(N, 256), 256, 0,
-                   ib_sorted.as<u32>(), sp->permb.as<u32>(), N, sp->ib.as<u32>());
+    try {
+        build_structure(ctx, sp, n, s);
+    } catch (...) {
+        drop_space(ctx);  // never leave a half-built entry under this list's key
+        throw;
     }
-    build_adjacency(ctx, sp->ua, sp->nua, n, sp->as_ptr, sp->as_idx, sp->n_as, s);
-    build_adjacency(ctx, sp->ub, sp->nub, n, sp->bs_ptr, sp->bs_idx, sp->n_bs, s);
     return sp;
 }

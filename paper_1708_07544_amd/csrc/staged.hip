@@ -806,6 +806,8 @@ bool staged_prepare(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
     HIP_CHECK(hipDeviceGetAttribute(&max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     if ((i64)sizeof(double) << wlog > (i64)max_shared) return false;
     const i64 N = sp->N, nua = sp->nua, nub = sp->nub;
+    // the build passes take one wavefront per row in one launch
+    if (ceil_div(N, ST_ROWS_PER_BLOCK) * ST_ROW_BLOCK >= ((i64)1 << 32)) return false;
     SpaceView S = space_view(*sp, ctx->n);
     sp->st_wlog = (u32)wlog;
     sp->st_xpos = dev_alloc(ctx, sizeof(u32) * (nua + sp->n_as), s);

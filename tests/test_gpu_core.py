@@ -207,6 +207,30 @@ def test_ragged_sizes(lib_mod, m):
     assert np.abs(r2.cpu().numpy() - o2).max() < 1e-12
 
 
+@pytest.mark.parametrize("cap", [1, 3])
+def test_row_kernels_stride_over_a_clamped_grid(lib_mod, monkeypatch, cap):
+    """One launch covers at most 2^32 work-items, so the row kernels of the
+    selection walk, the connection count and the recomputed product stride
+    over the rows of a clamped grid.  HCI_ROW_GRID_CAP forces the grid down
+    to `cap` workgroups: every row is then reached through the stride."""
+    monkeypatch.setenv("HCI_ROW_GRID_CAP", str(cap))
+    n, na, nb = 12, 6, 5
+    h, g = hs.make_integrals(n, 36, 12)
+    V = hs.random_dets(n, na, nb, 3000, seed=12, bias=0.15)
+    c = hs.random_coeffs(len(V), 77)
+    ctx = lib_mod.HCIContext(h, g, na, nb)
+    ref = O.sigma(h, g, V, c)
+    for precision, tol in (("fp64", 1e-12), ("fp32_mixed", 1e-6)):
+        out = ctx.sigma(V, c, precision=precision, mode="recompute").cpu().numpy()
+        assert rel_err(out, ref) < tol, precision
+    ctx.set_stage_window(0)  # plain layout: its count pass is a row kernel
+    ctx.release_cache()
+    assert ctx.connections(V) == int(O.row_counts(n, V).sum())
+    sel = lib_mod.dets_to_numpy(ctx.select(V, c, 1e-3))
+    assert np.array_equal(sel, O.merge(V, O.select(h, g, V, c, 1e-3)))
+    ctx.close()
+
+
 def _layout_space(name):
     if name == "cas8":
         w = hs.WORKLOADS["cas8"]
