@@ -39,6 +39,18 @@
  *   - All work is enqueued on `stream` (a hipStream_t; NULL = default
  *     stream).  Calls that return host scalars synchronise that stream.
  *
+ * Sizes: a list holds at most 2^32 - 2 determinants, and the
+ * single-excitation links between its unique alpha (beta) strings plus their
+ * number stay below 2^32 (HCI_E_UNSUPPORTED otherwise, before any work).
+ * One launch covers at most 2^32 work-items: the row kernels of the
+ * selection walk, the connection count and the recomputed product stride
+ * over the rows of a clamped grid (so any list size works there); the
+ * stored-Hamiltonian builds take one wavefront per row in one launch, so
+ * HCI_SIGMA_AUTO recomputes lists of more than about 67 million
+ * determinants, and any launch that would exceed the limit fails with
+ * HCI_E_UNSUPPORTED instead of running in part.  HCI_ROW_GRID_CAP=<k> in the
+ * environment clamps the striding kernels to k workgroups (for tests).
+ *
  * Errors: every entry point returns an hci_status.  No C++ exception crosses
  * the ABI.  hci_last_error() returns a thread-local message for the last
  * failing call.  A context must not be used by two threads at once.
