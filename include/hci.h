@@ -34,8 +34,9 @@
  *     allocator (or hipMalloc when none is given) and released by
  *     hci_ctx_destroy.  The context caches, for the most recently used
  *     determinant list, its bucket/adjacency structure and the stored
- *     Hamiltonian; the cache is keyed by the list's address, length and a
- *     content hash computed on the GPU, so editing a list in place is safe.
+ *     Hamiltonian; the cache is keyed by the list's length and a content
+ *     hash computed on the GPU (not its address), so editing a list in place
+ *     is safe and an equal list in another buffer reuses the structure.
  *   - All work is enqueued on `stream` (a hipStream_t; NULL = default
  *     stream).  Calls that return host scalars synchronise that stream.
  *
