@@ -62,6 +62,8 @@ def parse():
                     help="levels of the full-CI extrapolation leg on the final space (0: skip it)")
     ap.add_argument("--orbital-reps", type=int, default=20,
                     help="timed repetitions of the orbital-step leg (0: skip it)")
+    ap.add_argument("--recompute-reps", type=int, default=2,
+                    help="products timed in recompute mode on the final space (0 skips it)")
     ap.add_argument("--roots", type=int, default=3,
                     help="states of the several-state leg (0 skips it)")
     ap.add_argument("--pt2-cpu-rows", type=int, default=2000,
@@ -187,6 +189,9 @@ def main():
     orbital = None
     if args.orbital_reps > 0:
         orbital = orbital_leg(args)
+    recompute = None
+    if args.recompute_reps > 0:
+        recompute = recompute_leg(ctx, V2, c_mixed, pairs, args)
     roots = None
     if args.roots > 1:
         roots = roots_leg(ctx, V1, c1, V2, c_mixed, w.eps1, args)
@@ -253,9 +258,30 @@ def main():
         "orbital": orbital,
         "extrapolation": extrap,
         "roots": roots,
+        "recompute": recompute,
     }
     del dav_time_ms
     print(json.dumps(out))
+
+
+def recompute_leg(ctx, V2, c, pairs, args):
+    """The product with connections and elements regenerated in every call
+    (the mode of spaces whose Hamiltonian exceeds the memory budget), timed
+    on the final space after one untimed call."""
+    import torch
+    out = {"reps": args.recompute_reps, "det_pairs": pairs}
+    for precision in ("fp32_mixed", "fp64"):
+        ctx.sigma(V2, c, precision=precision, mode="recompute")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.recompute_reps):
+            ctx.sigma(V2, c, precision=precision, mode="recompute")
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / args.recompute_reps
+        out[precision] = {"ms": round(ms, 2), "det_pairs_per_s": pairs / (ms * 1e-3)}
+    log(f"[bench] recomputed product on {V2.shape[0]} determinants: "
+        f"{out['fp32_mixed']['ms']:.1f} ms mixed, {out['fp64']['ms']:.1f} ms f64")
+    return out
 
 
 def roots_leg(ctx, V1, c1, V2, c2, eps1, args):
