@@ -19,6 +19,8 @@ Where each function comes from (paper sections/equations):
   evaluated), not as the heat-bath walk.
 * ``select_bruteforce`` -- the same criterion evaluated over the whole
   determinant space with the operator-built H (tiny spaces).
+* ``spin_square`` -- <S^2> = S_z (S_z + 1) + |S_+ c|^2 of a state, by the
+  definition of the spin raising operator on the determinants.
 * ``select_roots`` / ``lowest_eigenpairs`` -- several states of one
   calculation (the paper's excited states are the lowest states of other
   spin projections, N_alpha != N_beta, which every function here accepts):
@@ -333,6 +335,44 @@ def lowest_eigenpair(h, g, V, tol=1e-12, v0=None, dense_max=3000):
     if c[k] < 0:
         c = -c
     return e, c
+
+
+def spin_square(V, c) -> float:
+    """<S^2> of the state c on V, for characterising the states (the paper
+    reports states of given spin: the pentacene triplet, the Fe-porphyrin
+    triplet and quintet).  S^2 = S_z (S_z + 1) + S_- S_+, so
+    <S^2> = S_z (S_z + 1) + |S_+ c|^2 / |c|^2 with S_+ = sum_p a+_pa a_pb.
+    a+_pa a_pb acts on D = (alpha, beta) with p in beta and not in alpha and
+    gives D' = (alpha + p, beta - p) with the sign (-1)^(N_alpha + #beta
+    below p + #alpha below p) (alpha creators left of beta creators,
+    ascending orbitals).  Written out per orbital over the whole list."""
+    V = np.asarray(V, dtype=np.uint64).reshape(-1, 2)
+    c = np.asarray(c, dtype=np.float64)
+    a, b = V[:, 0], V[:, 1]
+    na = int(np.bitwise_count(a[0])) if len(V) else 0
+    nb = int(np.bitwise_count(b[0])) if len(V) else 0
+    keys, vals = [], []
+    for p in range(64):
+        bit = np.uint64(1) << np.uint64(p)
+        below = bit - np.uint64(1)
+        sel = ((b & bit) != 0) & ((a & bit) == 0)
+        if not sel.any():
+            continue
+        nbelow = np.bitwise_count(b[sel] & below).astype(np.int64) + np.bitwise_count(a[sel] & below).astype(np.int64)
+        sign = np.where((na + nbelow) % 2 == 0, 1.0, -1.0)
+        keys.append(np.stack([a[sel] | bit, b[sel] & ~bit], axis=1))
+        vals.append(sign * c[sel])
+    sz = 0.5 * (na - nb)
+    norm2 = float(c @ c)
+    if not keys:
+        return sz * (sz + 1.0)
+    K = np.concatenate(keys)
+    X = np.concatenate(vals)
+    kv = np.ascontiguousarray(K).view([("a", np.uint64), ("b", np.uint64)]).ravel()
+    _, inv = np.unique(kv, return_inverse=True)
+    amp = np.zeros(inv.max() + 1)
+    np.add.at(amp, inv, X)
+    return sz * (sz + 1.0) + float(amp @ amp) / norm2
 
 
 def _fix_sign(c):

@@ -117,3 +117,42 @@ def test_hci_roots_reaches_full_ci_states_and_is_variational():
     E = np.array([x for _, x in hist])
     assert np.all(np.diff(E, axis=0) <= 1e-12)
     assert len(hist) > 2
+
+
+def _det(alpha_orbs, beta_orbs):
+    return [hs.det_bits(alpha_orbs), hs.det_bits(beta_orbs)]
+
+
+def test_spin_square_hand_cases():
+    """Closed shell 0; one alpha and one beta electron in different orbitals
+    1 (half singlet, half triplet); their two combinations 0 and 2; a
+    high-spin determinant S_z (S_z + 1)."""
+    assert abs(O.spin_square(np.array([_det([0, 1], [0, 1])]), [1.0])) < 1e-15
+    assert abs(O.spin_square(np.array([_det([0], [1])]), [1.0]) - 1.0) < 1e-15
+    V = O.sort_unique(np.array([_det([0], [1]), _det([1], [0])], dtype=np.uint64))
+    got = sorted(O.spin_square(V, np.array([1.0, s]) / np.sqrt(2.0)) for s in (1.0, -1.0))
+    assert abs(got[0]) < 1e-15 and abs(got[1] - 2.0) < 1e-15
+    assert abs(O.spin_square(np.array([_det([0, 1, 3], [])]), [1.0]) - 1.5 * 2.5) < 1e-15
+
+
+@pytest.mark.parametrize("n,na,nb,seed", [(6, 3, 3, 4), (6, 4, 2, 5), (5, 3, 2, 6)])
+def test_spin_square_of_eigenstates_matches_the_spin_sectors(n, na, nb, seed):
+    """Every eigenstate of a full space has <S^2> = S(S+1) with S integer or
+    half-integer as N; and S is also what the spectra say: the state's energy
+    appears in the M_s = S sector and not in M_s = S + 1."""
+    h, g = hs.make_integrals(n, 3 * n, seed)
+    N = na + nb
+    spectra = {}
+    for a in range((N + 1) // 2, min(n, N) + 1):
+        spectra[a] = np.linalg.eigvalsh(O.hamiltonian_csr(h, g, hs.full_space(n, a, N - a)).toarray())
+    V = hs.full_space(n, na, nb)
+    w, U = np.linalg.eigh(O.hamiltonian_csr(h, g, V).toarray())
+    for k in range(10):
+        s2 = O.spin_square(V, U[:, k])
+        S = (np.sqrt(1.0 + 4.0 * s2) - 1.0) / 2.0
+        assert abs(2 * S - round(2 * S)) < 1e-8 and round(2 * S) % 2 == N % 2, (k, s2)
+        S = round(2 * S) / 2
+        a_top = int(round((N + 2 * S) / 2))  # the sector with M_s = S
+        assert np.abs(spectra[a_top] - w[k]).min() < 1e-9, (k, S)
+        if a_top + 1 in spectra:
+            assert np.abs(spectra[a_top + 1] - w[k]).min() > 1e-7, (k, S)
