@@ -222,6 +222,11 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(h, g, P.dets_to_numpy(V2), c_mixed.cpu().numpy(), args.cpu_seconds, nv)
+    torch.cuda.synchronize()
+    t6 = time.perf_counter()
+    s2 = ctx.spin_square(V2, c_mixed)
+    s2_ms = (time.perf_counter() - t6) * 1e3
+    log(f"[bench] <S^2> of the final state: {s2:.6f} ({s2_ms:.1f} ms)")
     dav_time_ms = None
     out = {
         "metric": METRIC,
@@ -248,6 +253,7 @@ def main():
         if (fp64 and product_ms) else None,
         "layout": layout,
         "energy": e_mixed,
+        "spin_square": {"value": s2, "ms": round(s2_ms, 2)},
         "fp64": fp64,
         "energy_error_vs_fp64": abs(e_mixed - fp64["energy"]) if fp64 else None,
         "speedup_vs_fp64": (fp64["ms_per_step"] / ms_step) if fp64 else None,
@@ -309,6 +315,7 @@ def roots_leg(ctx, V1, c1, V2, c2, eps1, args):
                                                          precision="fp32_mixed", max_iter=2000))
     # davidson_ms includes building the stored Hamiltonian of V2, as the step does
     out = {"states": k, "energies": [float(x) for x in e2], "products": its,
+           "spin_square": [round(ctx.spin_square(V2, C2[r]), 8) for r in range(k)],
            "davidson_ms": round(ms, 2), "n_det": int(V2.shape[0]),
            "select_single_ms": round(ms_single, 2), "select_union_ms": round(ms_union, 2),
            "n_select_single": int(ctx.select(V1, c1, eps1).shape[0]),

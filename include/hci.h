@@ -277,6 +277,17 @@ int hci_davidson_roots(hci_ctx ctx, const uint64_t* dets, int64_t n_var, int nro
                        double* c_inout, double* e_out, double tol, int max_iter,
                        int precision, int mode, int* iters_out, void* stream);
 
+/* <S^2> of the state c on V, to tell which spin state a solve found (the
+ * paper's excited states are the lowest of given spin; the determinant space
+ * fixes only S_z = (N_alpha - N_beta)/2, so a state of any S >= |S_z| can be
+ * the lowest): <S^2> = S_z (S_z + 1) + |S_+ c|^2 / |c|^2 with the spin
+ * raising operator S_+ = sum_p a+_{p,alpha} a_{p,beta}, whose images are
+ * summed per target determinant in a fixed order.
+ *   c: device float64 [n_var], need not be normalised (HCI_E_ARG if zero).
+ *   s2_out: host.  Synchronises the stream. */
+int hci_spin_square(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c,
+                    double* s2_out, void* stream);
+
 /* ---------------------------------------------------------------------- RDMs
  * Spin-traced transition density matrices between bra and ket on V (the
  * Gamma^{x,y} of Sec. "Computational Details"; accumulated by looping over

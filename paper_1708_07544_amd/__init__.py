@@ -211,6 +211,15 @@ class HCIContext:
                                        _lib._stream()), allow=allow)
         return np.array(e[:nroots]), c, [int(x) for x in iters[:nroots]]
 
+    def spin_square(self, dets, c) -> float:
+        """<S^2> of the state c on V."""
+        d = self._dets(dets)
+        c = torch.as_tensor(c, dtype=torch.float64).to(self.device).contiguous()
+        s2 = ctypes.c_double()
+        check(lib().hci_spin_square(self.handle, _lib._ptr(d), d.shape[0], _lib._ptr(c), ctypes.byref(s2),
+                                    _lib._stream()))
+        return float(s2.value)
+
     def rdm12(self, dets, bra, ket=None, two_body: bool = True):
         d = self._dets(dets)
         bra = torch.as_tensor(bra, dtype=torch.float64).to(self.device).contiguous()

@@ -73,6 +73,7 @@ _SIGNATURES = {
     "hci_diagonal": [_vp, _vp, _i64, _vp, _vp],
     "hci_davidson": [_vp, _vp, _i64, _vp, _vp, _f64, _i32, _i32, _i32, _vp, _vp],
     "hci_davidson_roots": [_vp, _vp, _i64, _i32, _vp, _vp, _f64, _i32, _i32, _i32, _vp, _vp],
+    "hci_spin_square": [_vp, _vp, _i64, _vp, _vp, _vp],
     "hci_rdm12": [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp],
     "hci_energy_backward": [_vp, _vp, _i64, _vp, _f64, _f64, _vp, _f64, _f64, _i32, _vp, _vp,
                             _vp, _vp, _vp],

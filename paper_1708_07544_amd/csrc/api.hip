@@ -428,6 +428,17 @@ int hci_davidson_roots(hci_ctx ctx, const uint64_t* dets, int64_t n_var, int nro
     });
 }
 
+int hci_spin_square(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double* s2_out,
+                    void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && c && s2_out, HCI_E_ARG, "null argument");
+        hipStream_t s = as_stream(stream);
+        get_space(ctx, dets, n_var, s);  // validates the list
+        *s2_out = spin_square(ctx, dets, n_var, c, s);
+        return HCI_OK;
+    });
+}
+
 int hci_rdm12(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* bra, const double* ket,
               double* rdm1, double* rdm2, void* stream) {
     return guarded([&]() -> int {

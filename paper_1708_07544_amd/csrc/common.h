@@ -447,6 +447,8 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
 double heat_bath_max(hci_ctx_s* ctx, hipStream_t s);
 i64 select_run(hci_ctx_s* ctx, const u64* dets, const double* c, i64 N, double eps, u64* out,
                i64 cap, hipStream_t s);
+// <S^2> of c on the list (ecore-free, normalised by |c|^2)
+double spin_square(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, hipStream_t s);
 // union over the states (rows of C [nroots][N]) of the selected sets
 i64 select_roots_run(hci_ctx_s* ctx, const u64* dets, const double* C, int nroots, i64 N, double eps,
                      u64* out, i64 cap, hipStream_t s);

@@ -184,3 +184,41 @@ def test_hci_several_states_matches_oracle(P, na, nb):
     assert [x[0] for x in hist] == [x[0] for x in hr]
     assert np.array_equal(P.dets_to_numpy(V), Vr)
     assert np.abs(e - er).max() < 1e-9
+
+
+@pytest.mark.parametrize("case", ["cas8", "ms1", "random12", "random20", "hand"])
+def test_spin_square_matches_oracle(P, case):
+    """<S^2> through the library against the oracle on the same vectors:
+    eigenstates of full spaces (where it is S(S+1) exactly), random lists
+    with random vectors (N_alpha != N_beta included, 50,000 determinants of
+    20 orbitals), hand cases; a zero vector is an argument error."""
+    if case in ("cas8", "ms1"):
+        h, g, na, nb, V = _space(case)
+        e, C = O.lowest_eigenpairs(h, g, V, 4)
+        vecs = list(C)
+    elif case == "hand":
+        h, g = hs.make_integrals(4, 12, 1)
+        na, nb = 1, 1
+        V = O.sort_unique(np.array([[hs.det_bits([0]), hs.det_bits([1])],
+                                    [hs.det_bits([1]), hs.det_bits([0])],
+                                    [hs.det_bits([2]), hs.det_bits([2])]], dtype=np.uint64))
+        vecs = [np.array([1.0, 1.0, 0.0]), np.array([1.0, -1.0, 0.0]), np.array([0.0, 0.0, 2.0]),
+                np.array([0.3, -0.2, 0.9])]
+    else:
+        n, na, nb, m = (12, 6, 5, 3000) if case == "random12" else (20, 10, 10, 50_000)
+        h, g = hs.make_integrals(n, 3 * n, n)
+        V = hs.random_dets(n, na, nb, m, seed=n, bias=0.1)
+        vecs = [hs.random_coeffs(len(V), 90 + k) for k in range(2)]
+    ctx = P.HCIContext(h, g, na, nb)
+    for k, c in enumerate(vecs):
+        got = ctx.spin_square(V, c)
+        ref = O.spin_square(V, c)
+        print(f"[S^2 {case} {k}] {got:.12f} oracle {ref:.12f}", flush=True)
+        assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (got, ref)
+        if case in ("cas8", "ms1"):
+            S = (np.sqrt(1.0 + 4.0 * got) - 1.0) / 2.0
+            assert abs(S - round(S)) < 1e-8
+    with pytest.raises(P.HCIError) as ei:
+        ctx.spin_square(V, np.zeros(len(V)))
+    assert ei.value.code == -1
+    ctx.close()
