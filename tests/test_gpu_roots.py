@@ -222,3 +222,31 @@ def test_spin_square_matches_oracle(P, case):
         ctx.spin_square(V, np.zeros(len(V)))
     assert ei.value.code == -1
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_roots_at_the_largest_count(P, precision):
+    """HCI_MAX_ROOTS = 31 states of a 60-determinant space: the last solves
+    deflate 30 locked vectors and work in complements of a few dimensions."""
+    n, na, nb = 6, 2, 2
+    h, g = hs.make_integrals(n, 18, 21)
+    V = hs.random_dets(n, na, nb, 60, seed=21, bias=0.0)
+    ref = np.linalg.eigvalsh(O.hamiltonian_by_operators(h, g, V))
+    ctx = P.HCIContext(h, g, na, nb)
+    e, C, its = ctx.davidson_roots(V, 31, tol=1e-10, precision=precision)
+    ctx.close()
+    Cn = C.cpu().numpy()
+    print(f"[31 roots {precision}] |V|={len(V)} max dE {np.abs(e - ref[:31]).max():.2e}", flush=True)
+    assert np.abs(e - ref[:31]).max() < 1e-9
+    assert np.abs(Cn @ Cn.T - np.eye(31)).max() < 1e-9
+
+
+def test_spin_square_without_beta_electrons(P):
+    """N_beta = 0: S_+ has no images and <S^2> = S_z (S_z + 1) exactly."""
+    n, na, nb = 7, 3, 0
+    h, g = hs.make_integrals(n, 21, 4)
+    V = hs.full_space(n, na, nb)
+    c = hs.random_coeffs(len(V), 5)
+    ctx = P.HCIContext(h, g, na, nb)
+    assert ctx.spin_square(V, c) == 1.5 * 2.5 == O.spin_square(V, c)
+    ctx.close()
