@@ -120,10 +120,22 @@ struct SigmaVis {
     const float* c32;
     u64 ai, bi;
     double acc = 0.0;
+    SinglesQueue q;  // single excitations, evaluated 64 at a time
+    __device__ __forceinline__ void term(u32 j, u64 aj, u64 bj) {
+        if (F32) acc += (double)hij_f32(*I, ai, bi, aj, bj) * (double)c32[j];
+        else acc += hij_f64(*I, ai, bi, aj, bj) * c[j];
+    }
+    __device__ __forceinline__ void flush() {
+        if (lane_id() < q.n) term((u32)q.k, q.a, q.b);
+        q.n = 0;
+    }
     __device__ __forceinline__ void operator()(bool ok, u32 j, u64 aj, u64 bj) {
-        if (ok) {
-            if (F32) acc += (double)hij_f32(*I, ai, bi, aj, bj) * (double)c32[j];
-            else acc += hij_f64(*I, ai, bi, aj, bj) * c[j];
+        const bool single = ok && popc64(ai ^ aj) + popc64(bi ^ bj) == 2;
+        if (ok && !single) term(j, aj, bj);
+        const u64 m = ballot(single);
+        if (m) {
+            if (q.full_for(m)) flush();
+            q.push(m, (i64)j, aj, bj);
         }
     }
 };
@@ -138,6 +150,7 @@ __global__ void __launch_bounds__(ROW_BLOCK) sigma_recompute_kernel(SpaceView S,
          i += (i64)gridDim.x * ROWS_PER_BLOCK) {
         SigmaVis<F32> v{&I, c, c32, S.alpha[i], S.beta[i]};
         enumerate_row(S, (u32)i, v);
+        if (v.q.n) v.flush();
         const double acc = wave_sum_f64(v.acc);
         if (lane_id() == 0) sigma[i] = hd[i] * c[i] + acc;
     }

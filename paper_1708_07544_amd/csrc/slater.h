@@ -153,6 +153,58 @@ __device__ __forceinline__ u32 upper_bound_u32(const u32* __restrict__ arr, u32 
     return lo;
 }
 
+// Index of the n-th (from 0) set bit of m (32-bit halves, no 64-bit
+// variable shifts).
+__device__ __forceinline__ int nth_set_bit(u64 m, int n) {
+    u32 w = lo32(m);
+    int base = 0;
+    const int c = __popc(w);
+    if (n >= c) {
+        n -= c;
+        w = hi32(m);
+        base = 32;
+    }
+#pragma unroll
+    for (int s = 16; s > 0; s >>= 1) {
+        const int cl = __popc(w & ((1u << s) - 1u));
+        if (n >= cl) {
+            n -= cl;
+            w >>= s;
+            base += s;
+        }
+    }
+    return base;
+}
+
+// Single excitations of one row, deferred.  Their element sums over every
+// occupied orbital; they are a few percent of a row's connections, but
+// nearly every wavefront of 64 holds one and would run that path for all
+// lanes.  The wavefront queues them instead (slot l in lane l) and evaluates
+// up to 64 at once.  Every lane calls push together; the caller flushes
+// (lanes below n evaluate their slot) when full_for says so and at the end
+// of the row.
+struct SinglesQueue {
+    int n = 0;  // queued, wave-uniform
+    i64 k = 0;  // this lane's slot: caller's index and the determinant
+    u64 a = 0, b = 0;
+    __device__ __forceinline__ bool full_for(u64 m) const { return n + popc64(m) > HCI_WAVE; }
+    __device__ __forceinline__ void push(u64 m, i64 kk, u64 aa, u64 bb) {
+        const int cnt = popc64(m);
+        const int l = lane_id();
+        const bool mine = l >= n && l < n + cnt;
+        const int src = mine ? nth_set_bit(m, l - n) : l;
+        const i64 sk = __shfl(kk, src, HCI_WAVE);
+        const u64 sa = __shfl(aa, src, HCI_WAVE);
+        const u64 sb = __shfl(bb, src, HCI_WAVE);
+        if (mine) {
+            k = sk;
+            a = sa;
+            b = sb;
+        }
+        n += cnt;
+    }
+};
+
 // Enumerate every j != i in V with excitation degree <= 2 from row i.  The
 // whole wavefront calls this for one row; `vis(ok, j, aj, bj)` is invoked
 // wave-uniformly, each lane carrying its own candidate (ok = it is one).

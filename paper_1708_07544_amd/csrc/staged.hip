@@ -497,16 +497,28 @@ __global__ void __launch_bounds__(ST_BLOCK) st_vals_kernel(SpaceView S, IntView 
         const u64 bi = S.beta[i];
         const i64 sb = T.rsb[i];
         const u32 gb = S.boff[S.ib[i]];
+        SinglesQueue q;
+        auto flush = [&]() {
+            if (lane_id() < q.n) {
+                const double v = hij_f64(I, ai, bi, q.a, q.b);
+                if constexpr ((OUT & 1) != 0) v32[q.k] = (float)v;
+                if constexpr ((OUT & 2) != 0) v64[q.k] = v;
+            }
+            q.n = 0;
+        };
         for (u32 sg = 0; sg < ns; ++sg) {
             const i64 k0 = T.sstart[sb + sg];
             const u32 cnt = T.segcnt[sb + sg];
             const i64 k1 = k0 + pad_vec(cnt);
             const i64 kr = k0 + cnt;
-            for (i64 k = k0 + lane_id(); k < k1; k += HCI_WAVE) {
+            // uniform trip count: the queue's ballots and shuffles need every lane
+            for (i64 kb = k0; kb < k1; kb += HCI_WAVE) {
+                const i64 k = kb + lane_id();
                 double v = 0.0;
+                bool single = false;
+                u64 aj = 0, bj = 0;
                 if (k < kr) {
                     const u32 col = T.cols[k];
-                    u64 aj, bj;
                     if (sg + 1 < ns) {
                         const u32 P = (sg << T.wlog) + col;
                         u32 lo = 0, hi = nr - 1u;  // last range starting at or before P
@@ -521,12 +533,21 @@ __global__ void __launch_bounds__(ST_BLOCK) st_vals_kernel(SpaceView S, IntView 
                         aj = S.alpha[S.permb[gb + col]];
                         bj = bi;
                     }
-                    v = hij_f64(I, ai, bi, aj, bj);
+                    single = popc64(ai ^ aj) + popc64(bi ^ bj) == 2;
+                    if (!single) v = hij_f64(I, ai, bi, aj, bj);
                 }
-                if constexpr ((OUT & 1) != 0) v32[k] = (float)v;
-                if constexpr ((OUT & 2) != 0) v64[k] = v;
+                if (!single && k < k1) {
+                    if constexpr ((OUT & 1) != 0) v32[k] = (float)v;
+                    if constexpr ((OUT & 2) != 0) v64[k] = v;
+                }
+                const u64 m = ballot(single);
+                if (m) {
+                    if (q.full_for(m)) flush();
+                    q.push(m, k, aj, bj);
+                }
             }
         }
+        if (q.n) flush();
     }
 }
 
