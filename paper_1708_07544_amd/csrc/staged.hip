@@ -33,10 +33,17 @@
 namespace {
 
 
+constexpr int ST_CPY = 8;          // window copy: gathers in flight per thread
 constexpr int ST_ROW_BLOCK = 256;  // build passes: one wavefront per row
 constexpr int ST_ROWS_PER_BLOCK = ST_ROW_BLOCK / HCI_WAVE;
 constexpr int ST_BLOCK = 1024;     // product: 16 wavefronts
 constexpr int ST_WAVES = ST_BLOCK / HCI_WAVE;
+
+// LDS for a bucket's stage ranges in the product (two u32 per range; a
+// bucket has at most N_alpha (n - N_alpha) alpha-single neighbours)
+inline size_t st_range_lds(const hci_ctx_s* ctx) {
+    return sizeof(u32) * 2 * (size_t)(1 + ctx->na * (ctx->n - ctx->na));
+}
 constexpr u32 ST_CHUNK = 64 * ST_WAVES;  // rows per workgroup (64 per wavefront)
 constexpr int GT_BLOCK = 512;      // beta-group product: 8 wavefronts
 constexpr int GT_WAVES = GT_BLOCK / HCI_WAVE;
@@ -671,23 +678,45 @@ __global__ void __launch_bounds__(ST_BLOCK) st_spmv_kernel(SpaceView S, StView T
     const u32 row = r0 + wave + ST_WAVES * (u32)lane;
     const bool has = lane < nrw;
     const i64 sb = has ? T.rsb[row] : 0;
+    // the bucket's stage ranges (start within the slice, first row of the
+    // range's bucket) in LDS after the window, read once per workgroup
+    u32* rx = reinterpret_cast<u32*>(st_smem + (sizeof(CT) << T.wlog));
+    u32* rsrc = rx + nr;
+    for (u32 e = tid; e < nr; e += ST_BLOCK) {
+        rx[e] = xs[e];
+        rsrc[e] = S.aoff[e == 0 ? a : S.as_idx[t0 + e - 1]];
+    }
     double acc = 0.0;
     for (u32 g = 0; g + 1 < ns; ++g) {
-        __syncthreads();  // the previous window is consumed
+        __syncthreads();  // the previous window is consumed (and the ranges are in)
         const u32 wstart = g << T.wlog;
         const u32 wend = min(wstart + wsize, slen);
         u32 p = wstart + tid;
         if (p < wend) {
-            u32 e = upper_bound_u32(xs, nr, p) - 1u;
-            u32 src = S.aoff[e == 0 ? a : S.as_idx[t0 + e - 1]];
-            u32 xe = xs[e];
-            for (; p < wend; p += ST_BLOCK) {
-                while (e + 1 < nr && xs[e + 1] <= p) {
-                    ++e;
-                    src = S.aoff[S.as_idx[t0 + e - 1]];
-                    xe = xs[e];
+            // last range starting at or before p
+            u32 e = 0, hi = nr - 1u;
+            while (e < hi) {
+                const u32 mid = (e + hi + 1u) >> 1;
+                if (rx[mid] <= p) e = mid;
+                else hi = mid - 1u;
+            }
+            // ST_CPY independent gathers in flight per thread, then the stores
+            for (; p < wend; p += ST_CPY * ST_BLOCK) {
+                u32 sidx[ST_CPY];
+#pragma unroll
+                for (int j = 0; j < ST_CPY; ++j) {
+                    const u32 pj = p + (u32)j * ST_BLOCK;
+                    while (e + 1 < nr && rx[e + 1] <= pj) ++e;
+                    sidx[j] = rsrc[e] + (pj - rx[e]);
                 }
-                stage[p - wstart] = cx[src + (p - xe)];
+                CT v[ST_CPY];
+#pragma unroll
+                for (int j = 0; j < ST_CPY; ++j) v[j] = p + (u32)j * ST_BLOCK < wend ? cx[sidx[j]] : (CT)0;
+#pragma unroll
+                for (int j = 0; j < ST_CPY; ++j) {
+                    const u32 pj = p + (u32)j * ST_BLOCK;
+                    if (pj < wend) stage[pj - wstart] = v[j];
+                }
             }
         }
         __syncthreads();
@@ -797,7 +826,7 @@ constexpr int ST_SUB = 32;
 template <class VT, class CT>
 void launch_spmv(hci_ctx_s* ctx, Space* sp, const char* name, const char* gname, const VT* vals,
                  const CT* cx, const CT* cpb, const double* c, double* sigma, hipStream_t s) {
-    const size_t shmem = sizeof(CT) << sp->st_wlog;
+    const size_t shmem = (sizeof(CT) << sp->st_wlog) + st_range_lds(ctx);
     // the beta-group kernel stages whole groups up to the largest one (groups
     // beyond the window gather from global memory)
     const u32 cap = (u32)std::min<i64>((i64)1 << sp->st_wlog, std::max<i64>(sp->st_gmax, GT_CHUNK));
@@ -825,7 +854,7 @@ bool staged_prepare(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
     int dev = 0, max_shared = 0;
     HIP_CHECK(hipGetDevice(&dev));
     HIP_CHECK(hipDeviceGetAttribute(&max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    if ((i64)sizeof(double) << wlog > (i64)max_shared) return false;
+    if (((i64)sizeof(double) << wlog) + (i64)st_range_lds(ctx) > (i64)max_shared) return false;
     const i64 N = sp->N, nua = sp->nua, nub = sp->nub;
     // the build passes take one wavefront per row in one launch
     if (ceil_div(N, ST_ROWS_PER_BLOCK) * ST_ROW_BLOCK >= ((i64)1 << 32)) return false;
