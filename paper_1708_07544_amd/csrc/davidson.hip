@@ -30,7 +30,7 @@ namespace {
 
 constexpr int DV_BLOCK = 256;
 constexpr int DV_MAXK = 32;   // capacity of the small dense arrays
-constexpr int DV_KMAX = 24;   // subspace size before a thick restart
+constexpr int DV_KMAX = 32;   // subspace size before a thick restart
 
 // partial[j * nblk + b] = sum over the block's rows of X_j[i] * t[i], j < k
 __global__ void __launch_bounds__(DV_BLOCK) dots_kernel(const double* __restrict__ X, i64 ld, int k,
