@@ -649,15 +649,31 @@ def pt2_stochastic(h, g, V, c, e0, eps2, eps2_d, u):
     return tuple(pt2_stochastic_counts(h, g, V, c, e0, [eps2, eps2_d], w, p, len(u)))
 
 
+def semistochastic_combine(e2d, per):
+    """eq. semistoc from its pieces: E2^D(eps2_d) plus the mean over batches
+    of the bracket [E2^S(eps2) - E2^S(eps2_d)] (both terms of a batch from
+    the same draws), and the standard error of that mean, i.e. the sample
+    standard deviation of the brackets (n_b - 1 in the denominator) over
+    sqrt(n_b); nan for one batch.  per: [(E2^S(eps2), E2^S(eps2_d)), ...]."""
+    diff = np.array([x - y for x, y in per], dtype=np.float64)
+    nb = len(diff)
+    mean = float(np.sum(diff) / nb)
+    if nb > 1:
+        var = float(np.sum((diff - mean) ** 2) / (nb - 1))
+        err = float(np.sqrt(var) / np.sqrt(nb))
+    else:
+        err = float("nan")
+    return e2d + mean, err
+
+
 def pt2_semistochastic(h, g, V, c, e0, eps2, eps2_d, u_batches):
     """eq. semistoc: E2^D(eps2_d) + mean over batches of
     [E2^S(eps2) - E2^S(eps2_d)]; returns (E2, standard error of the mean
     (nan for one batch), E2^D(eps2_d), per-batch pairs)."""
     e2d = pt2(h, g, V, c, e0, eps2_d)["E2"]
     per = [pt2_stochastic(h, g, V, c, e0, eps2, eps2_d, u) for u in u_batches]
-    diff = np.array([x - y for x, y in per])
-    err = float(np.std(diff, ddof=1) / np.sqrt(len(diff))) if len(diff) > 1 else float("nan")
-    return e2d + float(np.mean(diff)), err, e2d, per
+    e2, err = semistochastic_combine(e2d, per)
+    return e2, err, e2d, per
 
 
 def orbital_gradient(h, g, rdm1, rdm2):
@@ -714,7 +730,20 @@ def extrapolation(h, g, V, c, fraction, levels, eps2):
         e, ck = lowest_eigenpair(h, g, Vk)
         evar.append(e)
         e2.append(pt2(h, g, Vk, ck, e, eps2)["E2"])
-    etot = np.array(evar) + np.array(e2)
-    a, b = extrapolation_fit(e2, etot)
+    a, b, err = extrapolation_assemble(evar, e2)
     return dict(sizes=sizes, evar=np.array(evar), e2=np.array(e2), e_extrap=a, slope=b,
-                error=0.25 * abs(a - etot[0]))
+                error=err)
+
+
+def extrapolation_assemble(evar, e2):
+    """The extrapolation from the levels' energies (Sec. "Results and
+    discussion": the total energy E_var + E2 of each level against its E2,
+    a straight line taken to E2 = 0; the Fe-porphyrin table's error bar is a
+    quarter of the distance from the extrapolated energy to the most accurate
+    total energy, that of level 0).  Returns (a, b, error) of the
+    least-squares line E_var + E2 = a + b E2."""
+    evar = np.asarray(evar, dtype=np.float64)
+    e2 = np.asarray(e2, dtype=np.float64)
+    etot = evar + e2
+    a, b = extrapolation_fit(e2, etot)
+    return a, b, 0.25 * abs(a - float(etot[0]))

@@ -45,3 +45,36 @@ def test_levels_are_nested_and_variational():
     efci, cf = O.lowest_eigenpair(h, g, F)
     full = O.extrapolation(h, g, F, cf, 0.33, 2, 1e-5)
     assert full["e2"][0] == 0.0 and abs(full["evar"][0] - efci) < 1e-10
+
+
+def test_assembly_fits_total_energy_against_e2():
+    """Hand-made levels: E2 = (-0.3, -0.2, -0.1) and totals E_var + E2 =
+    (1, 3, 2).  By hand: mean E2 = -0.2, mean total 2, S_xx = 0.02,
+    S_xy = 0.1, so the line is 3 + 5 E2; the error bar is a quarter of
+    |3 - 1| = 0.5 (level 0 is the most accurate total energy).  A fit of
+    E_var instead of the total gives slope 4; an error taken from E_var_0
+    gives 0.425; an error from the last level gives 0.25."""
+    e2 = np.array([-0.3, -0.2, -0.1])
+    etot = np.array([1.0, 3.0, 2.0])
+    evar = etot - e2
+    a, b, err = O.extrapolation_assemble(evar, e2)
+    assert abs(a - 3.0) < 1e-12 and abs(b - 5.0) < 1e-12
+    assert abs(err - 0.5) < 1e-12
+    # the planted alternatives give other numbers
+    a_v, b_v = O.extrapolation_fit(e2, evar)
+    assert abs(b_v - 4.0) < 1e-12
+    assert abs(0.25 * abs(a - evar[0]) - 0.425) < 1e-12
+    assert abs(0.25 * abs(a - etot[-1]) - 0.25) < 1e-12
+
+
+def test_assembly_two_levels_is_the_line_through_them():
+    """Two levels: the line through (E2_0, T_0), (E2_1, T_1) evaluated at
+    E2 = 0 is (T_1 E2_0 - T_0 E2_1) / (E2_0 - E2_1)."""
+    e2 = np.array([-0.02, -0.05])
+    evar = np.array([-100.10, -100.04])
+    t = evar + e2
+    a, b, err = O.extrapolation_assemble(evar, e2)
+    a_ref = (t[1] * e2[0] - t[0] * e2[1]) / (e2[0] - e2[1])
+    assert abs(a - a_ref) < 1e-12
+    assert abs(b - (t[0] - t[1]) / (e2[0] - e2[1])) < 1e-12
+    assert abs(err - 0.25 * abs(a_ref - t[0])) < 1e-13
