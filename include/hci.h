@@ -369,6 +369,20 @@ int hci_extrapolate(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const doub
  *   Asynchronous on the stream. */
 int hci_orbital_gradient(hci_ctx ctx, const double* rdm1, const double* rdm2, double* grad, void* stream);
 
+/* hci_orbital_gradient for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result, bit for bit, with the partial sums held in a
+ * fixed device array of 16 MiB per GPU (512 tiles of 64 x 64 float64, enough
+ * for every norb <= 64), whose address the library resolves once per device
+ * in hci_ctx_create; the array stays allocated until the process ends.  The
+ * call allocates nothing (no hipMalloc, no allocator callback).  Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (two
+ * streams, two threads, two contexts) race and must be serialised by the
+ * caller.  Arguments as hci_orbital_gradient; HCI_E_UNSUPPORTED if the split
+ * would need more tiles than the array holds.  Asynchronous on the stream. */
+int hci_orbital_gradient_noalloc(hci_ctx ctx, const double* rdm1, const double* rdm2, double* grad,
+                                 void* stream);
+
 /* Integrals of the context's h, g in rotated orbitals phi'_p = sum_a phi_a U_ap:
  * h_out = U^T h U, g_out_pqrs = sum_abcd U_ap U_bq U_cr U_ds (ab|cd) (the
  * active-space integral transformation of the orbital step).  U: device

@@ -291,6 +291,19 @@ class HCIContext:
                                          _lib._stream()))
         return grad
 
+    def orbital_gradient_noalloc(self, rdm1, rdm2, grad) -> torch.Tensor:
+        """The same gradient written into the caller's grad ([n][n] float64 on
+        this device) by the entry point that allocates nothing."""
+        n = self.norb
+        for t, shape in ((rdm1, (n, n)), (rdm2, (n, n, n, n)), (grad, (n, n))):
+            if (not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda
+                    or tuple(t.shape) != shape or not t.is_contiguous()):
+                raise ValueError("rdm1, rdm2, grad must be contiguous float64 tensors of shapes "
+                                 "[n,n], [n,n,n,n], [n,n] on the context's device")
+        check(lib().hci_orbital_gradient_noalloc(self.handle, _lib._ptr(rdm1), _lib._ptr(rdm2),
+                                                 _lib._ptr(grad), _lib._stream()))
+        return grad
+
     def rotate_integrals(self, U) -> Tuple[torch.Tensor, torch.Tensor]:
         """(U^T h U, (U x U x U x U)^T g) of this context's integrals."""
         n = self.norb

@@ -80,6 +80,7 @@ _SIGNATURES = {
     "hci_pt2": [_vp, _vp, _i64, _vp, _f64, _f64, _vp, _vp, _vp, _vp],
     "hci_ctx_set_pt2_budget": [_vp, _i64],
     "hci_orbital_gradient": [_vp, _vp, _vp, _vp, _vp],
+    "hci_orbital_gradient_noalloc": [_vp, _vp, _vp, _vp, _vp],
     "hci_extrapolate": [_vp, _vp, _i64, _vp, _f64, _i32, _f64, _f64, _i32, _vp, _vp, _vp, _vp, _vp],
     "hci_rotate_integrals": [_vp, _vp, _vp, _vp, _vp],
     "hci_pt2_stochastic": [_vp, _vp, _i64, _vp, _f64, _f64, _f64, _vp, _i64, _i64, _vp, _vp, _vp],

@@ -191,6 +191,7 @@ int hci_ctx_create(int norb, int nalpha, int nbeta, const double* h, const doubl
         }
         HIP_CHECK(hipGetDevice(&ctx->device));
         try {
+            orbital_scratch_setup(ctx->device);
             integrals_stage(ctx, h, g, as_stream(stream));
             HIP_CHECK(hipStreamSynchronize(as_stream(stream)));
         } catch (...) {
@@ -566,6 +567,15 @@ int hci_orbital_gradient(hci_ctx ctx, const double* rdm1, const double* rdm2, do
     return guarded([&]() -> int {
         HCI_REQUIRE(ctx != nullptr && rdm1 && rdm2 && grad, HCI_E_ARG, "null argument");
         orbital_gradient(ctx, rdm1, rdm2, grad, as_stream(stream));
+        return HCI_OK;
+    });
+}
+
+int hci_orbital_gradient_noalloc(hci_ctx ctx, const double* rdm1, const double* rdm2, double* grad,
+                                 void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && rdm1 && rdm2 && grad, HCI_E_ARG, "null argument");
+        orbital_gradient_noalloc(ctx, rdm1, rdm2, grad, as_stream(stream));
         return HCI_OK;
     });
 }

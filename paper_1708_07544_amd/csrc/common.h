@@ -481,6 +481,12 @@ void extrapolate(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double
 // orbital step (active-active rotations): grad = dE/dkappa (n x n), and the
 // rotated integrals of the context's h, g under U
 void orbital_gradient(hci_ctx_s* ctx, const double* rdm1, const double* rdm2, double* grad, hipStream_t s);
+// the same gradient with its partial sums in a fixed device array (no
+// allocation); orbital_scratch_setup resolves that array's address on a
+// device (called once per device, with the device current, at set-up)
+void orbital_gradient_noalloc(hci_ctx_s* ctx, const double* rdm1, const double* rdm2, double* grad,
+                              hipStream_t s);
+void orbital_scratch_setup(int device);
 void rotate_integrals(hci_ctx_s* ctx, const double* U, double* h_out, double* g_out, hipStream_t s);
 // device bytes per screened pair while a pass is processed (pairs, sort, segments)
 constexpr i64 PT2_BYTES_PER_PAIR = 128;

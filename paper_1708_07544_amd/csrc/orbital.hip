@@ -9,6 +9,9 @@
 // (v_mfma_f64_16x16x4): G as an n x n^3 by n^3 x n product split over
 // workgroups, the rotation as four quarter transforms, each an n^3 x n by
 // n x n product that moves the transformed index to the back.
+#include <map>
+#include <mutex>
+
 #include "common.h"
 
 namespace {
@@ -147,6 +150,25 @@ __global__ void gfock_finish_kernel(const double* __restrict__ part, int nblk, c
     grad[x * n + y] = 2.0 * (fxy - fyx);
 }
 
+// Partial-sum scratch of the allocation-free gradient entry point: one
+// 64 x 64 float64 tile per workgroup of gfock_partial_kernel, at most
+// ORB_SCRATCH_BLOCKS workgroups (the most that orbital_gradient's split uses
+// for any n <= 64), 16 MiB per GPU, held until the process ends.  Host code
+// never passes this name to a kernel: it is only the stand-in of the device
+// symbol; the device address comes from hipGetSymbolAddress, per device.
+constexpr i64 ORB_SCRATCH_BLOCKS = 512;
+static __device__ __align__(256) double scratch[ORB_SCRATCH_BLOCKS * 4096];
+
+// Workgroups of the gradient's K split: about 2 chunks of 32 K per
+// workgroup, at most 512 workgroups (so the scratch above always suffices).
+i64 gradient_split(int n, i64* per_out) {
+    const i64 K = (i64)n * n * n;
+    const i64 nchunk = ceil_div(K, GK);
+    const i64 per = std::max<i64>(2, ceil_div(nchunk, 512));
+    *per_out = per;
+    return ceil_div(nchunk, per);
+}
+
 void quarter(hci_ctx_s* ctx, const double* A, i64 J, int n, const double* U, double* out, hipStream_t s) {
     const i64 waves = ceil_div(J, 16);
     HCI_LAUNCH(ctx, "orb_rotate", s, quarter_kernel, ceil_div(waves, OB_WAVES), OB_BLOCK, 0, A, J, n, U, out);
@@ -154,18 +176,61 @@ void quarter(hci_ctx_s* ctx, const double* A, i64 J, int n, const double* U, dou
 
 }  // namespace
 
-void orbital_gradient(hci_ctx_s* ctx, const double* rdm1, const double* rdm2, double* grad, hipStream_t s) {
+namespace {
+
+// The two launches of the gradient with the partial sums in `part`
+// (nblk x 4096 float64, every entry the finish kernel reads is written by
+// the partial kernel first, so nothing needs clearing).
+void gradient_launch(hci_ctx_s* ctx, const double* rdm1, const double* rdm2, double* grad, double* part,
+                     i64 nblk, i64 per, hipStream_t s) {
     const int n = ctx->n;
     const i64 K = (i64)n * n * n;
-    const i64 nchunk = ceil_div(K, GK);
-    // about 2 chunks per workgroup, at most 512 workgroups
-    const i64 per = std::max<i64>(2, ceil_div(nchunk, 512));
-    const i64 nblk = ceil_div(nchunk, per);
-    DevMem part = dev_alloc(ctx, sizeof(double) * 4096 * nblk, s);
     HCI_LAUNCH(ctx, "orb_gradient", s, gfock_partial_kernel, nblk, OB_BLOCK, 0, ctx->ints.g.as<double>(), rdm2,
-               n, K, per, part.as<double>());
+               n, K, per, part);
     HCI_LAUNCH(ctx, "orb_gradient", s, gfock_finish_kernel, ceil_div((i64)n * n, 256), 256, 0,
-               (const double*)part.as<double>(), (int)nblk, ctx->ints.h.as<double>(), rdm1, n, grad);
+               (const double*)part, (int)nblk, ctx->ints.h.as<double>(), rdm1, n, grad);
+}
+
+// Device address of `scratch` on each device (resolved once per device).
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;
+
+}  // namespace
+
+void orbital_gradient(hci_ctx_s* ctx, const double* rdm1, const double* rdm2, double* grad, hipStream_t s) {
+    i64 per = 0;
+    const i64 nblk = gradient_split(ctx->n, &per);
+    DevMem part = dev_alloc(ctx, sizeof(double) * 4096 * nblk, s);
+    gradient_launch(ctx, rdm1, rdm2, grad, part.as<double>(), nblk, per, s);
+}
+
+void orbital_scratch_setup(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr.count(device)) return;
+    int cur = 0;
+    HIP_CHECK(hipGetDevice(&cur));
+    HCI_REQUIRE(cur == device, HCI_E_HIP, "scratch set-up: the context's device is not current");
+    void* ptr = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    HCI_REQUIRE(ptr != nullptr, HCI_E_HIP, "scratch set-up: no device address for the gradient scratch");
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+}
+
+void orbital_gradient_noalloc(hci_ctx_s* ctx, const double* rdm1, const double* rdm2, double* grad,
+                              hipStream_t s) {
+    i64 per = 0;
+    const i64 nblk = gradient_split(ctx->n, &per);
+    HCI_REQUIRE(nblk <= ORB_SCRATCH_BLOCKS, HCI_E_UNSUPPORTED,
+                "the gradient needs " + std::to_string(nblk) + " partial tiles; the fixed scratch holds " +
+                    std::to_string(ORB_SCRATCH_BLOCKS));
+    double* part = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        auto it = g_scratch_ptr.find(ctx->device);
+        HCI_REQUIRE(it != g_scratch_ptr.end(), HCI_E_HIP, "scratch of this device was not set up");
+        part = it->second;
+    }
+    gradient_launch(ctx, rdm1, rdm2, grad, part, nblk, per, s);
 }
 
 void rotate_integrals(hci_ctx_s* ctx, const double* U, double* h_out, double* g_out, hipStream_t s) {
