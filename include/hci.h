@@ -333,6 +333,32 @@ int hci_energy_backward(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const 
 int hci_pt2(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double e0,
             double eps2, double* e2_out, double* r_out, int64_t* n_conn_out, void* stream);
 
+/* Freeze the screened pair set of the second-order energy at the current
+ * integrals: M = {(i, a): D_a outside V, one excitation from D_i,
+ * fl(|H_ai| |c_i|) > eps2} (eq. pt_hci's screening), kept in the context
+ * for hci_energy(..., frozen = 1).  The energy E_var + E2 is then a smooth
+ * function of the integrals on the frozen V and M, whose derivative is the
+ * relaxed density matrix of hci_energy_backward at the same point (eq.
+ * lambda); re-screening at perturbed integrals would make it jump.  The set
+ * survives hci_ctx_update_integrals and is replaced by the next freeze.
+ *   dets, c: device, as hci_pt2.  n_pairs_out (host, may be NULL): |M|.
+ *   HCI_E_NOMEM if the pairs exceed the pt2 budget (a frozen set is held in
+ *   one pass).  Synchronises the stream. */
+int hci_pt2_freeze(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double eps2,
+                   int64_t* n_pairs_out, void* stream);
+
+/* The energy E = E_var + E2 of a frozen determinant list (eq. variational,
+ * eq. pt_hci): the lowest eigenpair by hci_davidson from c_inout (tol,
+ * max_iter, precision, mode as there), then E2 of that eigenpair: over the
+ * pair set of hci_pt2_freeze (frozen != 0; HCI_E_ARG if the set belongs to
+ * another list or none exists), else re-screened at eps2 (eps2 = 0: E2 = 0).
+ *   c_inout: device float64 [n_var], start vector in, eigenvector out.
+ *   e_out: host [3] = {E_var, E2, E_var + E2} (ecore included).
+ *   iters_out: host or NULL.  HCI_E_NOCONV as hci_davidson (energies of the
+ *   best iterate written).  Synchronises the stream. */
+int hci_energy(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* c_inout, double tol, int max_iter,
+               int precision, int mode, double eps2, int frozen, double* e_out, int* iters_out, void* stream);
+
 /* Extrapolation to the full-CI limit (Sec. "Results and discussion": the
  * procedure of the butadiene calculations).  Starting from the largest
  * calculation (dets, c), level k keeps the m_k most important determinants
@@ -396,8 +422,10 @@ int hci_rotate_integrals(hci_ctx ctx, const double* U, double* h_out, double* g_
  * 64 GiB, about 128 B per pair).  hci_pt2 and the deterministic part of
  * hci_pt2_semistochastic take the pairs in several passes over a hash
  * partition of the connected determinants when they exceed it (the memory
- * bottleneck of eq. pt_hci); hci_energy_backward with eps2 > 0 keeps all
- * pairs and returns HCI_E_NOMEM beyond it.  bytes <= 0: HCI_E_ARG. */
+ * bottleneck of eq. pt_hci); so does hci_energy_backward with eps2 > 0,
+ * which accumulates r, Gamma^{dc} and Gamma^{dd} pass by pass.  The passes
+ * are sized from a count pass before any pair is stored.  bytes <= 0:
+ * HCI_E_ARG. */
 int hci_ctx_set_pt2_budget(hci_ctx ctx, int64_t bytes);
 
 /* Sampled estimates of the screened second-order energy of eq. pt_hci, the

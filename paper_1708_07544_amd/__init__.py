@@ -190,6 +190,34 @@ class HCIContext:
                                  ctypes.byref(iters), _lib._stream()), allow=allow)
         return float(e.value), c, int(iters.value)
 
+    def energy(self, dets, c0=None, tol: float = 1e-10, max_iter: int = 500, precision="fp64",
+               mode="auto", eps2: float = 0.0, frozen: bool = False, allow_noconv: bool = False):
+        """E_var + E2 of the list (E2 over the frozen pair set when frozen,
+        else re-screened at eps2): returns ((E_var, E2, E_var + E2), c, products)."""
+        d = self._dets(dets)
+        n = d.shape[0]
+        if c0 is None:
+            c = torch.zeros(n, dtype=torch.float64, device=self.device)
+        else:
+            c = torch.as_tensor(c0, dtype=torch.float64).to(self.device).clone().contiguous()
+        e = (ctypes.c_double * 3)()
+        iters = ctypes.c_int()
+        allow = (_lib.HCI_E_NOCONV,) if allow_noconv else ()
+        check(lib().hci_energy(self.handle, _lib._ptr(d), n, _lib._ptr(c), float(tol), int(max_iter),
+                               _PREC[precision], _MODE[mode], float(eps2), int(bool(frozen)),
+                               ctypes.cast(e, ctypes.c_void_p), ctypes.byref(iters), _lib._stream()),
+              allow=allow)
+        return (float(e[0]), float(e[1]), float(e[2])), c, int(iters.value)
+
+    def pt2_freeze(self, dets, c, eps2: float) -> int:
+        """Freeze the screened pair set of (dets, c) at eps2 for energy(..., frozen=True); returns |M|."""
+        d = self._dets(dets)
+        c = torch.as_tensor(c, dtype=torch.float64).to(self.device).contiguous()
+        m = ctypes.c_int64()
+        check(lib().hci_pt2_freeze(self.handle, _lib._ptr(d), d.shape[0], _lib._ptr(c), float(eps2),
+                                   ctypes.byref(m), _lib._stream()))
+        return int(m.value)
+
     def davidson_roots(self, dets, nroots: int, c0=None, tol: float = 1e-8, max_iter: int = 500,
                        precision="fp64", mode="auto", allow_noconv: bool = False):
         """The nroots lowest eigenpairs on V: returns (E [nroots] numpy,

@@ -78,6 +78,8 @@ _SIGNATURES = {
     "hci_energy_backward": [_vp, _vp, _i64, _vp, _f64, _f64, _vp, _f64, _f64, _i32, _vp, _vp,
                             _vp, _vp, _vp],
     "hci_pt2": [_vp, _vp, _i64, _vp, _f64, _f64, _vp, _vp, _vp, _vp],
+    "hci_pt2_freeze": [_vp, _vp, _i64, _vp, _f64, _vp, _vp],
+    "hci_energy": [_vp, _vp, _i64, _vp, _f64, _i32, _i32, _i32, _f64, _i32, _vp, _vp, _vp],
     "hci_ctx_set_pt2_budget": [_vp, _i64],
     "hci_orbital_gradient": [_vp, _vp, _vp, _vp, _vp],
     "hci_orbital_gradient_noalloc": [_vp, _vp, _vp, _vp, _vp],

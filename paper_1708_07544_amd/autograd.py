@@ -1,13 +1,20 @@
 """The HCI energy as a differentiable function of the active-space integrals.
 
-Forward: E(h, g) on a frozen determinant list V (the lowest eigenvalue of H
-on V, found by the library's Davidson solver).  Backward: the library's
-density matrices, dE/dh = gamma and dE/dg = 1/2 Gamma averaged over the
-8-fold integral symmetry (Hellmann-Feynman; eq. vdedk2 of the paper).  With
-eps2 > 0 the energy is E_var + E2(eps2) with V, C(eps2) and the screening
-mask frozen, and the backward is the Lagrangian-relaxed density matrix
-(eq. lambda).  V is held fixed so that finite differences of the energy are
-well defined (re-selecting at perturbed integrals would jump).
+Forward: E(h, g) on a frozen determinant list V: the lowest eigenvalue of H
+on V (the library's Davidson solver), plus, with eps2 > 0, the screened
+second-order energy E2(eps2), both summed by the library (hci_energy).
+Backward: the library's density matrices, dE/dh = gamma and dE/dg = 1/2
+Gamma averaged over the 8-fold integral symmetry (Hellmann-Feynman;
+eq. vdedk2 of the paper), or with eps2 > 0 the Lagrangian-relaxed density
+matrices (eq. lambda).  V is held fixed so that finite differences of the
+energy are defined (re-selecting at perturbed integrals would jump); with
+``frozen=True`` the screened pair set of E2 is frozen too (hci_pt2_freeze
+at the first evaluation, or by the caller), so E_var + E2 is smooth in the
+integrals.
+
+A context passed as ``context`` is reused across calls (its integrals are
+replaced by hci_ctx_update_integrals), so repeated evaluations do not create
+a context each; otherwise one is created per forward.
 """
 from __future__ import annotations
 
@@ -27,13 +34,18 @@ class HCIEnergy(torch.autograd.Function):
         tol = opts.get("tol", 1e-10)
         precision = opts.get("precision", "fp64")
         eps2 = float(opts.get("eps2", 0.0))
-        ctx = HCIContext(h.detach(), g.detach(), nalpha, nbeta)
+        frozen = bool(opts.get("frozen", False))
+        ctx = opts.get("context")
+        if ctx is None:
+            ctx = HCIContext(h.detach(), g.detach(), nalpha, nbeta)
+        else:
+            ctx.update_integrals(h.detach(), g.detach(), ctx.ecore)
         c0 = opts.get("c0")
-        e, c, _ = ctx.davidson(dets, c0, tol=tol, precision=precision)
-        e_tot = e
-        if eps2 > 0.0:
-            e2, _, _ = ctx.pt2(dets, c, e, eps2, want_r=False)
-            e_tot = e + e2
+        if frozen and not opts.get("keep_frozen", False):
+            # freeze the pair set at these integrals from this point's eigenvector
+            (ev, _, _), c0, _ = ctx.energy(dets, c0, tol=tol, precision=precision)
+            ctx.pt2_freeze(dets, c0, eps2)
+        (e, e2, e_tot), c, _ = ctx.energy(dets, c0, tol=tol, precision=precision, eps2=eps2, frozen=frozen)
         fctx.hci = ctx
         fctx.dets = dets
         fctx.c = c

@@ -222,6 +222,7 @@ int hci_ctx_destroy(hci_ctx ctx) {
         if (!ctx) return HCI_OK;
         (void)hipDeviceSynchronize();
         drop_space(ctx);
+        drop_frozen(ctx);
         ctx->ints = Integrals();
         for (auto& p : ctx->pending) {
             (void)hipEventDestroy(p.start);
@@ -477,14 +478,21 @@ int hci_energy_backward(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const 
         HCI_REQUIRE(z_tol > 0.0, HCI_E_ARG, "z_tol must be positive");
         // relaxed gradient (eq. lambda with lambda_c = z/2 - (d.d) c/2):
         // (1 - d.d) G^cc + G^zc + 2 G^dc + G^dd
-        std::unique_ptr<Pt2State> st;
+        DevMem p1 = dev_alloc(ctx, sizeof(double) * n2, s), p2 = dev_alloc(ctx, sizeof(double) * n4, s);
+        DevMem q1 = dev_alloc(ctx, sizeof(double) * n2, s), q2 = dev_alloc(ctx, sizeof(double) * n4, s);
+        HIP_CHECK(hipMemsetAsync(p1.ptr, 0, sizeof(double) * n2, s));
+        HIP_CHECK(hipMemsetAsync(p2.ptr, 0, sizeof(double) * n4, s));
+        HIP_CHECK(hipMemsetAsync(q1.ptr, 0, sizeof(double) * n2, s));
+        HIP_CHECK(hipMemsetAsync(q2.ptr, 0, sizeof(double) * n4, s));
         const double* rr = r;
         double dd = 0.0, e2 = 0.0;
+        DevMem rbuf;
         if (eps2 > 0.0) {
-            st = pt2_run(ctx, dets, n_var, c, e - ctx->ecore, eps2, s);
-            rr = st->r.as<double>();
-            dd = st->dd;
-            e2 = st->e2;
+            // r, E2, d.d, Gamma^{dc} and Gamma^{dd} in the budgeted passes of the PT2
+            rbuf = dev_alloc(ctx, sizeof(double) * n_var, s);
+            pt2_relaxed_pieces(ctx, dets, n_var, c, e - ctx->ecore, eps2, rbuf.as<double>(), p1.as<double>(),
+                               p2.as<double>(), q1.as<double>(), q2.as<double>(), &e2, &dd, nullptr, nullptr, s);
+            rr = rbuf.as<double>();
         }
         DevMem zbuf;
         double* z = z_out;
@@ -495,17 +503,6 @@ int hci_energy_backward(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const 
         const int prod = zvector_solve(ctx, sp, c, e, rr, z, z_tol, precision, 100000, s);
         DevMem t1 = dev_alloc(ctx, sizeof(double) * n2, s), t2 = dev_alloc(ctx, sizeof(double) * n4, s);
         rdm_compute(ctx, sp, z, c, t1.as<double>(), t2.as<double>(), s);
-        DevMem p1 = dev_alloc(ctx, sizeof(double) * n2, s), p2 = dev_alloc(ctx, sizeof(double) * n4, s);
-        DevMem q1 = dev_alloc(ctx, sizeof(double) * n2, s), q2 = dev_alloc(ctx, sizeof(double) * n4, s);
-        HIP_CHECK(hipMemsetAsync(p1.ptr, 0, sizeof(double) * n2, s));
-        HIP_CHECK(hipMemsetAsync(p2.ptr, 0, sizeof(double) * n4, s));
-        HIP_CHECK(hipMemsetAsync(q1.ptr, 0, sizeof(double) * n2, s));
-        HIP_CHECK(hipMemsetAsync(q2.ptr, 0, sizeof(double) * n4, s));
-        if (st) {
-            rdm_add_pt2_pairs(ctx, *st, dets, c, p1.as<double>(), p2.as<double>(), s);
-            rdm_add_diag(ctx, st->ca.as<u64>(), st->cb.as<u64>(), st->d.as<double>(), st->d.as<double>(),
-                         st->nC, q1.as<double>(), q2.as<double>(), s);
-        }
         HCI_LAUNCH(ctx, "bw_combine", s, combine4_kernel, ceil_div(n2, 256), 256, 0, 1.0 - dd,
                    g1.as<double>(), 1.0, t1.as<double>(), 2.0, p1.as<double>(), 1.0, q1.as<double>(),
                    g1.as<double>(), n2);
@@ -523,6 +520,48 @@ int hci_energy_backward(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const 
             return HCI_E_NOCONV;
         }
         return HCI_OK;
+    });
+}
+
+int hci_pt2_freeze(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* c, double eps2,
+                   int64_t* n_pairs_out, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && c, HCI_E_ARG, "null argument");
+        HCI_REQUIRE(eps2 >= 0.0, HCI_E_ARG, "eps2 must be >= 0");
+        hipStream_t s = as_stream(stream);
+        Space* sp = get_space(ctx, dets, n_var, s);
+        const i64 M = pt2_freeze(ctx, dets, n_var, sp->hash, c, eps2, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (n_pairs_out) *n_pairs_out = M;
+        return HCI_OK;
+    });
+}
+
+int hci_energy(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* c_inout, double tol, int max_iter,
+               int precision, int mode, double eps2, int frozen, double* e_out, int* iters_out, void* stream) {
+    return guarded([&]() -> int {
+        HCI_REQUIRE(ctx != nullptr && dets && c_inout && e_out, HCI_E_ARG, "null argument");
+        HCI_REQUIRE(tol > 0.0 && max_iter > 0, HCI_E_ARG, "tol and max_iter must be positive");
+        HCI_REQUIRE(precision == HCI_FP64 || precision == HCI_FP32_MIXED, HCI_E_ARG, "bad precision");
+        HCI_REQUIRE(mode >= 0 && mode <= 2, HCI_E_ARG, "bad mode");
+        HCI_REQUIRE(eps2 >= 0.0, HCI_E_ARG, "eps2 must be >= 0");
+        hipStream_t s = as_stream(stream);
+        Space* sp = get_space(ctx, dets, n_var, s);
+        const u64 hash = sp->hash;
+        double evar = 0.0;
+        const int rc = davidson_run(ctx, sp, c_inout, &evar, tol, max_iter, precision, mode, iters_out, s);
+        double e2 = 0.0;
+        if (frozen) {
+            e2 = pt2_frozen_energy(ctx, dets, n_var, hash, c_inout, evar - ctx->ecore, s);
+        } else if (eps2 > 0.0) {
+            e2 = pt2_energy(ctx, dets, n_var, c_inout, evar - ctx->ecore, eps2, nullptr, nullptr, nullptr, s);
+        }
+        HIP_CHECK(hipStreamSynchronize(s));
+        e_out[0] = evar;
+        e_out[1] = e2;
+        e_out[2] = evar + e2;
+        if (rc == HCI_E_NOCONV) g_last_error = "Davidson did not reach tol within max_iter products";
+        return rc;
     });
 }
 

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/hci.h"
+#include "phase.h"
 
 typedef uint64_t u64;
 typedef uint32_t u32;
@@ -45,19 +46,18 @@ void hci_set_error(const std::string& msg);
 // ---------------------------------------------------------------- device helpers
 __device__ __forceinline__ int popc64(u64 x) { return __popcll(x); }
 __device__ __forceinline__ int ctz64(u64 x) { return __builtin_ctzll(x); }
-// Bit manipulation on 64-bit occupation words goes through 32-bit halves:
-// variable-amount 64-bit shifts are avoided everywhere in device code (they
-// produced sporadic wrong results on gfx950 in the element kernels).
+// Bit manipulation on 64-bit occupation words goes through 32-bit halves
+// and shifts by less than 32 (well defined for every orbital index; the
+// phase helpers in phase.h are checked against brute force on the CPU).
 __device__ __forceinline__ u64 join32(u32 hi, u32 lo) { return ((u64)hi << 32) | (u64)lo; }
 __device__ __forceinline__ u32 lo32(u64 x) { return (u32)x; }
 __device__ __forceinline__ u32 hi32(u64 x) { return (u32)(x >> 32); }
 
 // word with only bit p set (0 <= p < 64)
-// (single-bit words come from a table: the compiler would otherwise fold a
-// select of shifted halves back into a 64-bit variable shift)
-static __constant__ u64 kBit64[64] = {0x1ull, 0x2ull, 0x4ull, 0x8ull, 0x10ull, 0x20ull, 0x40ull, 0x80ull, 0x100ull, 0x200ull, 0x400ull, 0x800ull, 0x1000ull, 0x2000ull, 0x4000ull, 0x8000ull, 0x10000ull, 0x20000ull, 0x40000ull, 0x80000ull, 0x100000ull, 0x200000ull, 0x400000ull, 0x800000ull, 0x1000000ull, 0x2000000ull, 0x4000000ull, 0x8000000ull, 0x10000000ull, 0x20000000ull, 0x40000000ull, 0x80000000ull, 0x100000000ull, 0x200000000ull, 0x400000000ull, 0x800000000ull, 0x1000000000ull, 0x2000000000ull, 0x4000000000ull, 0x8000000000ull, 0x10000000000ull, 0x20000000000ull, 0x40000000000ull, 0x80000000000ull, 0x100000000000ull, 0x200000000000ull, 0x400000000000ull, 0x800000000000ull, 0x1000000000000ull, 0x2000000000000ull, 0x4000000000000ull, 0x8000000000000ull, 0x10000000000000ull, 0x20000000000000ull, 0x40000000000000ull, 0x80000000000000ull, 0x100000000000000ull, 0x200000000000000ull, 0x400000000000000ull, 0x800000000000000ull, 0x1000000000000000ull, 0x2000000000000000ull, 0x4000000000000000ull, 0x8000000000000000ull};
-
-__device__ __forceinline__ u64 bit(int p) { return kBit64[p]; }
+__device__ __forceinline__ u64 bit(int p) {
+    const u32 one = 1u << (p & 31);
+    return join32(p >= 32 ? one : 0u, p < 32 ? one : 0u);
+}
 
 // bit p of s (0 <= p < 64)
 __device__ __forceinline__ bool test_bit(u64 s, int p) {
@@ -66,7 +66,9 @@ __device__ __forceinline__ bool test_bit(u64 s, int p) {
 }
 
 // bits [0, k) set (0 <= k <= 64)
-__device__ __forceinline__ u64 low_mask(int k) { return k >= 64 ? ~0ull : kBit64[k] - 1ull; }
+__device__ __forceinline__ u64 low_mask(int k) {
+    return join32(phase_mask32(k > 32 ? k - 32 : 0), phase_mask32(k < 32 ? k : 32));
+}
 
 // byte b (0..7) of x
 __device__ __forceinline__ u32 byte_of(u64 x, int b) {
@@ -74,35 +76,13 @@ __device__ __forceinline__ u32 byte_of(u64 x, int b) {
     return (w >> (8 * (b & 3))) & 0xffu;
 }
 
-// Number of set bits of s below position k (0 <= k <= 64), from 32-bit
-// halves: phase factors are built from these counts only, with no 64-bit
-// variable shifts (shift-built 64-bit masks gave sporadic wrong parities on
-// gfx950 in the element kernels).
-__device__ __forceinline__ int rank_below(u64 s, int k) {
-    const u64 m = low_mask(k);
-    return __popc(lo32(s) & lo32(m)) + __popc(hi32(s) & hi32(m));
-}
-
-// number of set bits of s strictly between orbitals p and q (p != q)
-__device__ __forceinline__ int count_between(u64 s, int p, int q) {
-    const int lo = p < q ? p : q, hi = p < q ? q : p;
-    return rank_below(s, hi) - rank_below(s, lo + 1);
-}
-
-// (-1)^(number of set bits of s strictly between orbitals p and q)
-__device__ __forceinline__ double sign_between(u64 s, int p, int q) {
-    return (count_between(s, p, q) & 1) ? -1.0 : 1.0;
-}
-
-// Phase of the same-spin double p -> r then q -> s applied to string si
-// (p, q occupied; r, s empty): the second count is taken on si with p
-// removed and r added, i.e. it changes by one for each of p, r that lies
-// strictly between q and s.
+// Phases of excitations (host and device, checked on the CPU against a
+// brute-force count of the bits between two orbitals).
+__device__ __forceinline__ int rank_below(u64 s, int k) { return phase_rank_below(s, k); }
+__device__ __forceinline__ int count_between(u64 s, int p, int q) { return phase_count_between(s, p, q); }
+__device__ __forceinline__ double sign_between(u64 s, int p, int q) { return phase_sign_between(s, p, q); }
 __device__ __forceinline__ double sign_double(u64 si, int p, int r, int q, int s) {
-    const int lo = q < s ? q : s, hi = q < s ? s : q;
-    const int n = count_between(si, p, r) + count_between(si, q, s) + (p > lo && p < hi) +
-                  (r > lo && r < hi);
-    return (n & 1) ? -1.0 : 1.0;
+    return phase_sign_double(si, p, r, q, s);
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -237,6 +217,10 @@ struct Space {
     i64 st_nnz = 0;       // stored entries (segments padded to multiples of 4)
     DevMem st_vals32, st_vals64;
     DevMem cpb32, cpb64;  // c in beta-major order
+    DevMem rc_chunk_a;    // u32 [rc_nch_a][3]: recomputed product, alpha-bucket chunks
+    DevMem rc_chunk_b;    // u32 [rc_nch_b][3]: beta-bucket chunks (beta-major positions)
+    i64 rc_nch_a = 0, rc_nch_b = 0;
+    i64 rc_maxdeg = 0;    // largest alpha-single degree of a unique alpha string
     DevMem rdm_cptr;      // u32 [nua + 1]: first workgroup of each bucket (density matrices)
     i64 rdm_nchunk = 0;
     bool st_have32 = false, st_have64 = false;
@@ -293,6 +277,7 @@ struct hci_ctx_s {
     bool has_alloc = false;
     Integrals ints;
     Space* space = nullptr;
+    struct Pt2Frozen* frozen = nullptr;  // screened PT2 pairs frozen by hci_pt2_freeze
     i64 stored_budget = (i64)64 << 30;
     i64 pt2_budget = (i64)64 << 30;  // screened PT2 pairs held at once
     int stage_wlog = 14;  // log2 of the staged layout's window; 0 = plain CSR
@@ -306,6 +291,8 @@ struct hci_ctx_s {
 DevMem dev_alloc(hci_ctx_s* ctx, size_t bytes, hipStream_t stream);
 // release a cached space
 void drop_space(hci_ctx_s* ctx);
+// release the frozen PT2 pair set
+void drop_frozen(hci_ctx_s* ctx);
 
 // kernel timing hooks (no-ops unless timing is on)
 void timer_begin(hci_ctx_s* ctx, const char* name, hipStream_t s, PendingEvent* ev);
@@ -439,6 +426,8 @@ void staged_ensure_vals(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s)
 void layout_info(hci_ctx_s* ctx, Space* sp, int64_t* info, hipStream_t s);
 void staged_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int precision,
                   hipStream_t s);
+// product with connections and elements regenerated on the fly (no storage)
+void recompute_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int precision, hipStream_t s);
 // lock: nlock orthonormal vectors [nlock][N] to deflate (the states below);
 // generic_start: add a fixed pseudo-random 1e-3 component to the start vector
 int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol, int max_iter,
@@ -455,24 +444,21 @@ i64 select_roots_run(hci_ctx_s* ctx, const u64* dets, const double* C, int nroot
 void embed_run(hci_ctx_s* ctx, const u64* dets, i64 n, const double* c, const u64* dn, i64 nn,
                double* out, hipStream_t s);
 
-// eps2-screened PT2 pieces on a frozen (V, c, E0).
-struct Pt2State {
-    i64 N = 0;       // |V|
-    i64 M = 0;       // screened (i, a) pairs, in i order
-    DevMem off;      // i64 [N+1] pair range of each i
-    DevMem a_hi, a_lo;  // u64 [M] alpha / beta of a
-    DevMem idx;      // u32 [M] i
-    DevMem hai;      // f64 [M] H_ai
-    DevMem dpair;    // f64 [M] d_a of the pair's a
-    DevMem r;        // f64 [N] dE2/dc at fixed E0
-    i64 nC = 0;      // |C(eps2)|
-    DevMem ca, cb;   // u64 [nC] the connected determinants (sorted)
-    DevMem d;        // f64 [nC] first-order coefficients
-    double e2 = 0.0, dd = 0.0;
-    ~Pt2State();
-};
-std::unique_ptr<Pt2State> pt2_run(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double e0,
-                                  double eps2, hipStream_t s);
+// eps2-screened PT2 pieces of the relaxed gradient on a frozen (V, c, E0),
+// in the same budgeted passes as pt2_energy: r = dE2/dc (device [N],
+// overwritten), Gamma^{dc} added to dc1/dc2 (bra D_a weighted d_a, ket D_i
+// weighted c_i, over the screened pairs) and Gamma^{dd} added to dd1/dd2
+// (diagonal of the connected determinants, weights d_a^2); E2 and d.d on the
+// host.
+void pt2_relaxed_pieces(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double e0, double eps2,
+                        double* r, double* dc1, double* dc2, double* dd1, double* dd2, double* e2_out,
+                        double* dd_out, i64* nconn, int* npasses, hipStream_t s);
+// Freeze the screened pairs M = {(i, a): fl(|H_ai| |c_i|) > eps2} of (V, c) at
+// the current integrals (one pass within the pt2 budget); returns |M|.
+i64 pt2_freeze(hci_ctx_s* ctx, const u64* dets, i64 N, u64 hash, const double* c, double eps2, hipStream_t s);
+// E2 over the frozen pairs with the current integrals, c and E0 (ecore-free)
+double pt2_frozen_energy(hci_ctx_s* ctx, const u64* dets, i64 N, u64 hash, const double* c, double e0,
+                         hipStream_t s);
 // extrapolation to the full-CI limit: per level (host arrays) the determinant
 // count, E_var (ecore included) and E2; fit = {E at E2 = 0, slope, error}
 void extrapolate(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double fraction, int levels,
@@ -503,9 +489,10 @@ void pt2_stochastic(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, dou
 // returns the number of Hamiltonian products.
 int zvector_solve(hci_ctx_s* ctx, Space* sp, const double* c, double e, const double* r, double* z,
                   double tol, int precision, int max_products, hipStream_t s);
-// rdm1/rdm2 += sum_pairs w <D_a| ops |D_i> with w = dpair * c_i (Gamma^{dc})
-void rdm_add_pt2_pairs(hci_ctx_s* ctx, const Pt2State& st, const u64* dets, const double* c,
-                       double* rdm1, double* rdm2, hipStream_t s);
+// rdm1/rdm2 += sum over M pairs t of w_t <D_a(t)| ops |D_i(t)>, w_t = wa_t c_i(t)
+// (Gamma^{dc} of the screened PT2 pairs: D_a = (a_hi, a_lo), i = idx)
+void rdm_add_pairs(hci_ctx_s* ctx, const u64* a_hi, const u64* a_lo, const u32* idx, const double* wa, i64 M,
+                   const u64* dets, const double* c, double* rdm1, double* rdm2, hipStream_t s);
 // rdm1/rdm2 += sum_k wa_k wb_k <D_k| ops |D_k> over the listed determinants
 void rdm_add_diag(hci_ctx_s* ctx, const u64* alpha, const u64* beta, const double* wa,
                   const double* wb, i64 M, double* rdm1, double* rdm2, hipStream_t s);

@@ -111,6 +111,16 @@ __global__ void __launch_bounds__(PT_BLOCK) pt_fill_kernel(HBView T, IntView I, 
     if (lane_id() == 0 && v.pos != off[i + 1]) atomicAdd(bad, 1ull);
 }
 
+// H_ai of stored pairs with the current integrals
+__global__ void pair_elems(IntView I, const u64* __restrict__ dets, const u32* __restrict__ idx,
+                           const u64* __restrict__ a_hi, const u64* __restrict__ a_lo, i64 M,
+                           double* __restrict__ hai) {
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M) return;
+    const i64 i = idx[t];
+    hai[t] = hij_f64(I, dets[2 * i], dets[2 * i + 1], a_hi[t], a_lo[t]);
+}
+
 __global__ void iota_u32(u32* __restrict__ x, i64 n) {
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] = (u32)i;
@@ -329,8 +339,6 @@ i64 p2(i64 x) {
 
 }  // namespace
 
-Pt2State::~Pt2State() = default;
-
 namespace {
 
 // Hash set of V for the "outside V" test of the walk.
@@ -450,95 +458,149 @@ double sum_to_host(hci_ctx_s* ctx, const double* x, i64 n, hipStream_t s) {
 
 }  // namespace
 
-std::unique_ptr<Pt2State> pt2_run(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double e0,
-                                  double eps2, hipStream_t s) {
-    auto st = std::make_unique<Pt2State>();
-    const double hbm = heat_bath_max(ctx, s);
-    IntView I = int_view(ctx->ints);
-    VSet v;
-    vset_build(ctx, dets, N, v, s);
-    Pairs P;
-    walk_pairs(ctx, v, dets, c, N, eps2, hbm, 1, 0, P, s);
-    const i64 M = P.M;
-    HCI_REQUIRE(M * PT2_BYTES_PER_PAIR <= ctx->pt2_budget, HCI_E_NOMEM,
-                "pt2: the screened pairs of the relaxed gradient exceed the pt2 memory budget");
-    st->M = M;
-    st->N = N;
-    st->off = std::move(P.off);
-    st->a_hi = std::move(P.a_hi);
-    st->a_lo = std::move(P.a_lo);
-    st->idx = std::move(P.idx);
-    st->hai = std::move(P.hai);
-    st->dpair = dev_alloc(ctx, sizeof(double) * (M > 0 ? M : 1), s);
-    st->r = dev_alloc(ctx, sizeof(double) * N, s);
-    if (M == 0) {
-        HIP_CHECK(hipMemsetAsync(st->r.ptr, 0, sizeof(double) * N, s));
-        st->e2 = 0.0;
-        st->nC = 0;
-        st->dd = 0.0;
-        return st;
-    }
-    Segs G;
-    sort_segments(ctx, st->a_hi.as<u64>(), st->a_lo.as<u64>(), M, G, s);
-    const i64 nseg = G.nseg;
-    st->nC = nseg;
-    st->ca = std::move(G.ca);
-    st->cb = std::move(G.cb);
-    st->d = dev_alloc(ctx, sizeof(double) * nseg, s);
-    DevMem term = dev_alloc(ctx, sizeof(double) * nseg, s);
-    HCI_LAUNCH(ctx, "pt2_reduce", s, seg_reduce, ceil_div(nseg, 256), 256, 0, I, G.start.as<i64>(), nseg,
-               M, G.perm.as<u32>(), st->hai.as<double>(), st->idx.as<u32>(), c, st->ca.as<u64>(),
-               st->cb.as<u64>(), e0, st->d.as<double>(), term.as<double>(), st->dpair.as<double>());
-    HCI_LAUNCH(ctx, "pt2_r", s, r_rows<false>, ceil_div(N, 256), 256, 0, st->off.as<i64>(), N,
-               st->hai.as<double>(), st->dpair.as<double>(), st->r.as<double>());
-    st->e2 = sum_to_host(ctx, term.as<double>(), nseg, s);
-    // d.d for the relaxed density matrix
-    HCI_LAUNCH(ctx, "pt2_dd_sq", s, sq_kernel_pt, ceil_div(nseg, 256), 256, 0, st->d.as<double>(), nseg,
-               term.as<double>());
-    st->dd = sum_to_host(ctx, term.as<double>(), nseg, s);
-    return st;
-}
+namespace {
 
-double pt2_energy(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double e0, double eps2,
-                  double* r, i64* nconn, int* npasses, hipStream_t s) {
+// One pass of the screened pairs: the pairs (i, a) with D_a in hash
+// partition `part` of `nparts`, sorted into segments of equal a, with the
+// first-order amplitudes d_a of the segments and their copy on every pair.
+struct Pt2Pass {
+    Pairs P;
+    Segs G;
+    DevMem d, term, dpair;
+};
+
+// Run the screened pairs in passes over hash partitions of D_a sized to the
+// pt2 memory budget: a count pass over all rows comes first (it allocates
+// only the row offsets), so the number of passes is fixed before any pair
+// is stored.  `each(Pt2Pass&)` sees every nonempty pass in order; the
+// passes' sums are added in that order (fixed).
+template <class F>
+void pt2_passes(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double e0, double eps2,
+                int* npasses, hipStream_t s, F&& each) {
     const double hbm = heat_bath_max(ctx, s);
     IntView I = int_view(ctx->ints);
     VSet v;
     vset_build(ctx, dets, N, v, s);
-    // passes over hash partitions of a sized to the pt2 memory budget
     DevMem off_all;
     const i64 Mall = count_pairs(ctx, v, dets, c, N, eps2, hbm, 1, 0, off_all, s);
     const i64 budget = std::max<i64>(ctx->pt2_budget, PT2_BYTES_PER_PAIR);
     const i64 nparts = std::max<i64>(1, ceil_div(Mall * PT2_BYTES_PER_PAIR, budget));
     HCI_REQUIRE(nparts <= 65536, HCI_E_NOMEM, "pt2: more than 65536 passes needed for the memory budget");
     if (nparts > 1) off_all = DevMem();
+    if (npasses) *npasses = (int)nparts;
+    for (i64 part = 0; part < nparts; ++part) {
+        Pt2Pass X;
+        if (nparts == 1) {  // the sizing count is this pass's count
+            X.P.M = Mall;
+            X.P.off = std::move(off_all);
+        }
+        walk_pairs(ctx, v, dets, c, N, eps2, hbm, (u32)nparts, (u32)part, X.P, s);
+        if (X.P.M == 0) continue;
+        sort_segments(ctx, X.P.a_hi.as<u64>(), X.P.a_lo.as<u64>(), X.P.M, X.G, s);
+        X.d = dev_alloc(ctx, sizeof(double) * X.G.nseg, s);
+        X.term = dev_alloc(ctx, sizeof(double) * X.G.nseg, s);
+        X.dpair = dev_alloc(ctx, sizeof(double) * X.P.M, s);
+        HCI_LAUNCH(ctx, "pt2_reduce", s, seg_reduce, ceil_div(X.G.nseg, 256), 256, 0, I, X.G.start.as<i64>(),
+                   X.G.nseg, X.P.M, X.G.perm.as<u32>(), X.P.hai.as<double>(), X.P.idx.as<u32>(), c,
+                   X.G.ca.as<u64>(), X.G.cb.as<u64>(), e0, X.d.as<double>(), X.term.as<double>(),
+                   X.dpair.as<double>());
+        each(X);
+    }
+}
+
+}  // namespace
+
+// The screened pairs frozen at some integrals: the set M (pairs and their
+// segments of equal a) is kept, the elements are recomputed at every use.
+struct Pt2Frozen {
+    i64 N = 0;
+    u64 hash = 0;
+    Pairs P;
+    Segs G;
+};
+
+i64 pt2_freeze(hci_ctx_s* ctx, const u64* dets, i64 N, u64 hash, const double* c, double eps2, hipStream_t s) {
+    drop_frozen(ctx);
+    auto F = std::make_unique<Pt2Frozen>();
+    F->N = N;
+    F->hash = hash;
+    const double hbm = heat_bath_max(ctx, s);
+    VSet v;
+    vset_build(ctx, dets, N, v, s);
+    F->P.M = count_pairs(ctx, v, dets, c, N, eps2, hbm, 1, 0, F->P.off, s);
+    HCI_REQUIRE(F->P.M * PT2_BYTES_PER_PAIR <= std::max<i64>(ctx->pt2_budget, PT2_BYTES_PER_PAIR), HCI_E_NOMEM,
+                "pt2: the screened pairs to freeze (" + std::to_string(F->P.M) +
+                    ") exceed the pt2 memory budget; a frozen set is held in one pass");
+    walk_pairs(ctx, v, dets, c, N, eps2, hbm, 1, 0, F->P, s);
+    if (F->P.M > 0) sort_segments(ctx, F->P.a_hi.as<u64>(), F->P.a_lo.as<u64>(), F->P.M, F->G, s);
+    const i64 M = F->P.M;
+    ctx->frozen = F.release();
+    return M;
+}
+
+double pt2_frozen_energy(hci_ctx_s* ctx, const u64* dets, i64 N, u64 hash, const double* c, double e0,
+                         hipStream_t s) {
+    Pt2Frozen* F = ctx->frozen;
+    HCI_REQUIRE(F != nullptr, HCI_E_ARG, "no frozen pt2 pair set (call hci_pt2_freeze first)");
+    HCI_REQUIRE(F->N == N && F->hash == hash, HCI_E_ARG, "the frozen pt2 pair set belongs to another list");
+    const i64 M = F->P.M;
+    if (M == 0) return 0.0;
+    IntView I = int_view(ctx->ints);
+    HCI_LAUNCH(ctx, "pt2_frozen_elems", s, pair_elems, ceil_div(M, 256), 256, 0, I, dets, F->P.idx.as<u32>(),
+               F->P.a_hi.as<u64>(), F->P.a_lo.as<u64>(), M, F->P.hai.as<double>());
+    const i64 nseg = F->G.nseg;
+    DevMem d = dev_alloc(ctx, sizeof(double) * nseg, s), term = dev_alloc(ctx, sizeof(double) * nseg, s);
+    DevMem dpair = dev_alloc(ctx, sizeof(double) * M, s);
+    HCI_LAUNCH(ctx, "pt2_reduce", s, seg_reduce, ceil_div(nseg, 256), 256, 0, I, F->G.start.as<i64>(), nseg, M,
+               F->G.perm.as<u32>(), F->P.hai.as<double>(), F->P.idx.as<u32>(), c, F->G.ca.as<u64>(),
+               F->G.cb.as<u64>(), e0, d.as<double>(), term.as<double>(), dpair.as<double>());
+    return sum_to_host(ctx, term.as<double>(), nseg, s);
+}
+
+void drop_frozen(hci_ctx_s* ctx) {
+    delete ctx->frozen;
+    ctx->frozen = nullptr;
+}
+
+void pt2_relaxed_pieces(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double e0, double eps2,
+                        double* r, double* dc1, double* dc2, double* dd1, double* dd2, double* e2_out,
+                        double* dd_out, i64* nconn, int* npasses, hipStream_t s) {
+    HIP_CHECK(hipMemsetAsync(r, 0, sizeof(double) * N, s));
+    double e2 = 0.0, dd = 0.0;
+    i64 nc = 0;
+    pt2_passes(ctx, dets, N, c, e0, eps2, npasses, s, [&](Pt2Pass& X) {
+        HCI_LAUNCH(ctx, "pt2_r", s, r_rows<true>, ceil_div(N, 256), 256, 0, X.P.off.as<i64>(), N,
+                   X.P.hai.as<double>(), X.dpair.as<double>(), r);
+        e2 += sum_to_host(ctx, X.term.as<double>(), X.G.nseg, s);
+        HCI_LAUNCH(ctx, "pt2_dd_sq", s, sq_kernel_pt, ceil_div(X.G.nseg, 256), 256, 0, X.d.as<double>(),
+                   X.G.nseg, X.term.as<double>());
+        dd += sum_to_host(ctx, X.term.as<double>(), X.G.nseg, s);
+        nc += X.G.nseg;
+        // Gamma^{dc}: bra D_a (weight d_a), ket D_i (weight c_i) over the pass's pairs
+        rdm_add_pairs(ctx, X.P.a_hi.as<u64>(), X.P.a_lo.as<u64>(), X.P.idx.as<u32>(), X.dpair.as<double>(),
+                      X.P.M, dets, c, dc1, dc2, s);
+        // Gamma^{dd}: the diagonal of the connected determinants, weights d_a^2
+        rdm_add_diag(ctx, X.G.ca.as<u64>(), X.G.cb.as<u64>(), X.d.as<double>(), X.d.as<double>(), X.G.nseg,
+                     dd1, dd2, s);
+    });
+    *e2_out = e2;
+    *dd_out = dd;
+    if (nconn) *nconn = nc;
+}
+
+double pt2_energy(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, double e0, double eps2,
+                  double* r, i64* nconn, int* npasses, hipStream_t s) {
     if (r) HIP_CHECK(hipMemsetAsync(r, 0, sizeof(double) * N, s));
     double e2 = 0.0;
     i64 nc = 0;
-    for (i64 part = 0; part < nparts; ++part) {
-        Pairs P;
-        if (nparts == 1) {  // the sizing count is this pass's count
-            P.M = Mall;
-            P.off = std::move(off_all);
-        }
-        walk_pairs(ctx, v, dets, c, N, eps2, hbm, (u32)nparts, (u32)part, P, s);
-        if (P.M == 0) continue;
-        Segs G;
-        sort_segments(ctx, P.a_hi.as<u64>(), P.a_lo.as<u64>(), P.M, G, s);
-        DevMem d = dev_alloc(ctx, sizeof(double) * G.nseg, s);
-        DevMem term = dev_alloc(ctx, sizeof(double) * G.nseg, s);
-        DevMem dpair = dev_alloc(ctx, sizeof(double) * P.M, s);
-        HCI_LAUNCH(ctx, "pt2_reduce", s, seg_reduce, ceil_div(G.nseg, 256), 256, 0, I, G.start.as<i64>(),
-                   G.nseg, P.M, G.perm.as<u32>(), P.hai.as<double>(), P.idx.as<u32>(), c, G.ca.as<u64>(),
-                   G.cb.as<u64>(), e0, d.as<double>(), term.as<double>(), dpair.as<double>());
+    pt2_passes(ctx, dets, N, c, e0, eps2, npasses, s, [&](Pt2Pass& X) {
         if (r)
-            HCI_LAUNCH(ctx, "pt2_r", s, r_rows<true>, ceil_div(N, 256), 256, 0, P.off.as<i64>(), N,
-                       P.hai.as<double>(), dpair.as<double>(), r);
-        e2 += sum_to_host(ctx, term.as<double>(), G.nseg, s);
-        nc += G.nseg;
-    }
+            HCI_LAUNCH(ctx, "pt2_r", s, r_rows<true>, ceil_div(N, 256), 256, 0, X.P.off.as<i64>(), N,
+                       X.P.hai.as<double>(), X.dpair.as<double>(), r);
+        e2 += sum_to_host(ctx, X.term.as<double>(), X.G.nseg, s);
+        nc += X.G.nseg;
+    });
     if (nconn) *nconn = nc;
-    if (npasses) *npasses = (int)nparts;
     return e2;
 }
 

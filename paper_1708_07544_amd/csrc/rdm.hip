@@ -647,10 +647,9 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
     rdm_add_diag(ctx, sp->alpha.as<u64>(), sp->beta.as<u64>(), bra, ket, N, rdm1, rdm2, s);
 }
 
-void rdm_add_pt2_pairs(hci_ctx_s* ctx, const Pt2State& st, const u64* dets, const double* c,
-                       double* rdm1, double* rdm2, hipStream_t s) {
-    if (st.M <= 0) return;
-    HCI_LAUNCH(ctx, "rdm_pt2_pairs", s, pt2_pairs_kernel, ceil_div(st.M, 256), 256, 0,
-               st.a_hi.as<u64>(), st.a_lo.as<u64>(), st.idx.as<u32>(), st.dpair.as<double>(), dets, c,
-               st.M, ctx->n, rdm1, rdm2);
+void rdm_add_pairs(hci_ctx_s* ctx, const u64* a_hi, const u64* a_lo, const u32* idx, const double* wa, i64 M,
+                   const u64* dets, const double* c, double* rdm1, double* rdm2, hipStream_t s) {
+    if (M <= 0) return;
+    HCI_LAUNCH(ctx, "rdm_pt2_pairs", s, pt2_pairs_kernel, ceil_div(M, 256), 256, 0, a_hi, a_lo, idx, wa, dets,
+               c, M, ctx->n, rdm1, rdm2);
 }

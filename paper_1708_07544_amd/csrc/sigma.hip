@@ -5,9 +5,9 @@
 // Stored mode: the off-diagonal connections of each row are enumerated once
 // (count pass, scan, fill pass) into CSR with u32 columns and float64 or
 // float32 values; each product then streams the CSR once (HBM-bound).
-// Recompute mode: every product re-enumerates the connections of each row
-// and evaluates the elements on the fly (integer/ALU-bound, no storage).
-// Both use one wavefront per row and fixed-order reductions (no atomics).
+// Recompute mode (recompute.hip): every product regenerates the connections
+// and elements on the fly (no storage).  The stored product uses one
+// wavefront per row and fixed-order reductions (no atomics).
 #include "slater.h"
 
 namespace {
@@ -111,49 +111,6 @@ __global__ void __launch_bounds__(SPMV_BLOCK) spmv_kernel(i64 N, const i64* __re
 __global__ void pad4_kernel(const u32* __restrict__ counts, i64 n, u32* __restrict__ padded) {
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) padded[i] = (counts[i] + 3u) & ~3u;
-}
-
-template <bool F32>
-struct SigmaVis {
-    const IntView* I;
-    const double* c;
-    const float* c32;
-    u64 ai, bi;
-    double acc = 0.0;
-    SinglesQueue q;  // single excitations, evaluated 64 at a time
-    __device__ __forceinline__ void term(u32 j, u64 aj, u64 bj) {
-        if (F32) acc += (double)hij_f32(*I, ai, bi, aj, bj) * (double)c32[j];
-        else acc += hij_f64(*I, ai, bi, aj, bj) * c[j];
-    }
-    __device__ __forceinline__ void flush() {
-        if (lane_id() < q.n) term((u32)q.k, q.a, q.b);
-        q.n = 0;
-    }
-    __device__ __forceinline__ void operator()(bool ok, u32 j, u64 aj, u64 bj) {
-        const bool single = ok && popc64(ai ^ aj) + popc64(bi ^ bj) == 2;
-        if (ok && !single) term(j, aj, bj);
-        const u64 m = ballot(single);
-        if (m) {
-            if (q.full_for(m)) flush();
-            q.push(m, (i64)j, aj, bj);
-        }
-    }
-};
-
-template <bool F32>
-__global__ void __launch_bounds__(ROW_BLOCK) sigma_recompute_kernel(SpaceView S, IntView I,
-                                                                    const double* __restrict__ c,
-                                                                    const float* __restrict__ c32,
-                                                                    const double* __restrict__ hd,
-                                                                    double* __restrict__ sigma) {
-    for (i64 i = (i64)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE; i < S.N;
-         i += (i64)gridDim.x * ROWS_PER_BLOCK) {
-        SigmaVis<F32> v{&I, c, c32, S.alpha[i], S.beta[i]};
-        enumerate_row(S, (u32)i, v);
-        if (v.q.n) v.flush();
-        const double acc = wave_sum_f64(v.acc);
-        if (lane_id() == 0) sigma[i] = hd[i] * c[i] + acc;
-    }
 }
 
 __global__ void f64_to_f32_kernel(const double* __restrict__ x, float* __restrict__ y, i64 n) {
@@ -264,7 +221,6 @@ void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int 
     ensure_diag(ctx, sp, s);
     const i64 N = sp->N;
     const bool f32 = precision == HCI_FP32_MIXED;
-    const i64 grid = ceil_div(N, ROWS_PER_BLOCK);
     const i64 gridp = ceil_div(N, SPMV_ROWS);
     DevMem& c32 = sp->c32;
     if (mode == HCI_SIGMA_STORED) {
@@ -274,12 +230,16 @@ void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int 
             return;
         }
     }
+    if (mode != HCI_SIGMA_STORED) {
+        recompute_apply(ctx, sp, c, sigma, precision, s);
+        return;
+    }
     if (f32) {
         if (!c32.ptr) c32 = dev_alloc(ctx, sizeof(float) * N, s);
         HCI_LAUNCH(ctx, "c_to_f32", s, f64_to_f32_kernel, ceil_div(N, 256), 256, 0, c,
                    c32.as<float>(), N);
     }
-    if (mode == HCI_SIGMA_STORED) {
+    {
         ensure_csr(ctx, sp, precision, s);
         if (f32) {
             HCI_LAUNCH(ctx, "sigma_stored_f32", s, (spmv_kernel<float, float>), gridp, SPMV_BLOCK, 0,
@@ -289,17 +249,6 @@ void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int 
             HCI_LAUNCH(ctx, "sigma_stored_f64", s, (spmv_kernel<double, double>), gridp, SPMV_BLOCK,
                        0, N, sp->rowptr.as<i64>(), sp->cols.as<u32>(), sp->vals64.as<double>(), c,
                        c, sp->hdiag.as<double>(), sigma);
-        }
-    } else {
-        SpaceView S = space_view(*sp, ctx->n);
-        IntView I = int_view(ctx->ints);
-        const i64 rgrid = row_grid(N, ROWS_PER_BLOCK, ROW_BLOCK);
-        if (f32) {
-            HCI_LAUNCH(ctx, "sigma_recompute_f32", s, sigma_recompute_kernel<true>, rgrid, ROW_BLOCK, 0,
-                       S, I, c, c32.as<float>(), sp->hdiag.as<double>(), sigma);
-        } else {
-            HCI_LAUNCH(ctx, "sigma_recompute_f64", s, sigma_recompute_kernel<false>, rgrid, ROW_BLOCK, 0,
-                       S, I, c, (const float*)nullptr, sp->hdiag.as<double>(), sigma);
         }
     }
 }
