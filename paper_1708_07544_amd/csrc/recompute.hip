@@ -29,6 +29,8 @@
 // kernels: the alpha-major kernel writes sigma_i = H_ii c_i + (its classes),
 // the beta-major kernel then adds the same-beta class.  No atomics; the
 // order of every sum is fixed by the data.
+#include <cstdlib>
+
 #include "slater.h"
 
 namespace {
@@ -36,9 +38,19 @@ namespace {
 constexpr int RC_BLOCK = 512;
 constexpr int RC_WAVES = RC_BLOCK / HCI_WAVE;
 constexpr u32 RC_ROWS = 256;    // rows per chunk (workgroup)
-constexpr u32 RC_TILE = 1024;   // candidate columns staged at a time
+constexpr u32 RC_TILE = 2048;   // candidate columns staged at a time
 constexpr u32 RC_UNROLL = 4;    // 64-column steps whose loads are in flight together
 constexpr u32 RC_OWN = 0xffffu; // column from the chunk's own bucket
+constexpr u32 RC_BM_BYTES = 28 * 1024;  // bitmaps of a neighbour group (aliases the column tile)
+
+// Neighbour lookup through LDS bitmaps of the beta strings present in each
+// neighbour bucket (when the space has at most 65535 unique beta strings):
+// W words per neighbour, G neighbours per group, nbs_avg the mean number of
+// beta singles of a beta string (to choose between lookup and scan per chunk).
+struct RcBitmaps {
+    u32 W, G;
+    float nbs_avg;
+};
 
 // Element arithmetic of one precision: float32 elements (rounded integrals,
 // float32 sums) for the mixed product, float64 otherwise.
@@ -63,38 +75,42 @@ struct RcLds {
     u32* lstart;   // [maxl] first row of each link's bucket
     u32* linfo;    // [maxl] p | r << 8 | (sign < 0) << 16 of each alpha-single link
     double* racc;  // [RC_ROWS]
-    u16* queue;    // [RC_WAVES][2][128] singles / doubles queues of each wavefront
+    u16* queue;    // [RC_WAVES][3][128] singles / same-string doubles / alpha x beta queues
     VT* ftab;      // [n*n]
 };
 
-// maxl: links of a chunk at most (its own bucket + the largest alpha degree)
+// maxl: links of a chunk at most (its own bucket + the largest alpha degree).
+// colw, colc, colk are contiguous (the tile region, at least RC_BM_BYTES,
+// which the neighbour bitmaps reuse).
 template <class VT>
 __device__ __forceinline__ RcLds<VT> rc_lds(char* smem, int n, u32 maxl) {
     RcLds<VT> L;
     L.colw = reinterpret_cast<u64*>(smem);
-    L.racc = reinterpret_cast<double*>(L.colw + RC_TILE);
-    L.colc = reinterpret_cast<VT*>(L.racc + RC_ROWS);
-    L.ftab = L.colc + RC_TILE;
+    L.colc = reinterpret_cast<VT*>(L.colw + RC_TILE);
+    L.colk = reinterpret_cast<u16*>(L.colc + RC_TILE);
+    L.ftab = reinterpret_cast<VT*>(L.colk + RC_TILE);
     L.loff = reinterpret_cast<u32*>(L.ftab + n * n);
     L.lstart = L.loff + maxl + 1;
     L.linfo = L.lstart + maxl;
-    L.colk = reinterpret_cast<u16*>(L.linfo + maxl);
-    L.queue = L.colk + RC_TILE;
+    L.racc = reinterpret_cast<double*>(smem + ((reinterpret_cast<char*>(L.linfo + maxl) - smem + 7) & ~(size_t)7));
+    L.queue = reinterpret_cast<u16*>(L.racc + RC_ROWS);
     return L;
 }
 
 template <class VT>
 size_t rc_lds_bytes(int n, u32 maxl) {
-    return sizeof(u64) * RC_TILE + sizeof(double) * RC_ROWS + sizeof(VT) * (RC_TILE + (size_t)n * n) +
-           sizeof(u32) * (3 * (size_t)maxl + 1) + sizeof(u16) * (RC_TILE + RC_WAVES * 256);
+    const size_t head = (sizeof(u64) + sizeof(VT) + sizeof(u16)) * RC_TILE + sizeof(VT) * (size_t)n * n +
+                        sizeof(u32) * (3 * (size_t)maxl + 1);
+    return ((head + 7) & ~(size_t)7) + sizeof(double) * RC_ROWS + sizeof(u16) * RC_WAVES * 384;
 }
+static_assert((sizeof(u64) + sizeof(float) + sizeof(u16)) * RC_TILE >= RC_BM_BYTES, "bitmaps fit the tile region");
 
 // Ftab[q][p] = sum over the occupied orbitals r of the chunk's fixed string F of (qp|rr)
 template <class VT>
 __device__ __forceinline__ void rc_fixed_table(const RcInts<VT>& T, u64 F, VT* Ftab) {
     const int n = T.n;
     for (int e = (int)threadIdx.x; e < n * n; e += RC_BLOCK) {
-        const i64 row = (i64)e * n;  // e = q * n + p
+        const int row = e * n;  // e = q * n + p
         VT v = (VT)0;
         for (u64 m = F; m; m &= m - 1) v += T.jj[row + ctz64(m)];
         Ftab[e] = v;
@@ -109,8 +125,8 @@ __device__ __forceinline__ double rc_single(const RcInts<VT>& T, const VT* Ftab,
     const int n = T.n;
     const u64 x = X ^ Y;
     const int p = ctz64(X & x), q = ctz64(Y & x);
-    const i64 row = ((i64)q * n + p) * n;
-    VT v = T.h[(i64)q * n + p];
+    const int row = (q * n + p) * n;  // n <= 64: every index below 2^31
+    VT v = T.h[q * n + p];
     for (u64 m = X; m; m &= m - 1) v += T.jk[row + ctz64(m)];
     v += Ftab[q * n + p];
     return (double)((VT)sign_between(X, p, q) * v);
@@ -129,7 +145,9 @@ __device__ __forceinline__ double rc_double(const RcInts<VT>& T, u64 X, u64 Y) {
     const int r = ctz64(parts);
     parts &= parts - 1;
     const int s = ctz64(parts);
-    return (double)((VT)sign_double(X, p, r, q, s) * (T.g[gidx(n, r, p, s, q)] - T.g[gidx(n, r, q, s, p)]));
+    const int rn = r * n;
+    return (double)((VT)sign_double(X, p, r, q, s) *
+                    (T.g[((rn + p) * n + s) * n + q] - T.g[((rn + q) * n + s) * n + p]));
 }
 
 // Alpha single (link: p -> r with its phase) times beta single X (row) ->
@@ -141,7 +159,7 @@ __device__ __forceinline__ double rc_cross(const RcInts<VT>& T, u32 info, u64 X,
     const int q = ctz64(X & x), s = ctz64(Y & x);
     const int p = (int)(info & 0xffu), r = (int)((info >> 8) & 0xffu);
     const VT sa = (info >> 16) ? (VT)-1 : (VT)1;
-    return (double)((sa * (VT)sign_between(X, q, s)) * T.g[gidx(n, r, p, s, q)]);
+    return (double)((sa * (VT)sign_between(X, q, s)) * T.g[((r * n + p) * n + s) * n + q]);
 }
 
 // Stage columns [P0, P0 + tlen) of the chunk's concatenated links: link t
@@ -179,10 +197,16 @@ __device__ __forceinline__ void rc_flush_d(const RcInts<VT>& T, const RcLds<VT>&
                                            double& acc) {
     if ((u32)lane_id() < cnt) {
         const u32 kk = qd[lane_id()];
-        const u16 t = L.colk[kk];
-        const u64 y = L.colw[kk];
-        const double v = t == (u16)RC_OWN ? rc_double<VT>(T, X, y) : rc_cross<VT>(T, L.linfo[t], X, y);
-        acc += v * (double)L.colc[kk];
+        acc += rc_double<VT>(T, X, L.colw[kk]) * (double)L.colc[kk];
+    }
+}
+
+template <class VT>
+__device__ __forceinline__ void rc_flush_x(const RcInts<VT>& T, const RcLds<VT>& L, const u16* qx, u32 cnt, u64 X,
+                                           double& acc) {
+    if ((u32)lane_id() < cnt) {
+        const u32 kk = qx[lane_id()];
+        acc += rc_cross<VT>(T, L.linfo[L.colk[kk]], X, L.colw[kk]) * (double)L.colc[kk];
     }
 }
 
@@ -206,14 +230,14 @@ __device__ __forceinline__ void rc_shift(u16* q, u32 cnt) {
 }
 
 // One row X against the staged tile (columns [0, own) are the chunk's own
-// bucket): hits are compacted into the wavefront's two queues (singles;
-// doubles and alpha x beta) and evaluated 64 at a time.
+// bucket): hits are compacted into the wavefront's three queues (singles,
+// same-string doubles, alpha x beta) and evaluated 64 at a time.
 template <class VT>
-__device__ __forceinline__ double rc_row(const RcInts<VT>& T, const RcLds<VT>& L, u16* qs, u16* qd, u32 tlen,
-                                         u32 own, u64 X) {
+__device__ __forceinline__ double rc_row(const RcInts<VT>& T, const RcLds<VT>& L, u16* qs, u16* qd, u16* qx,
+                                         u32 tlen, u32 own, u64 X) {
     const u32 lane = (u32)lane_id();
     double acc = 0.0;
-    u32 ns = 0, nd = 0;  // queued (wave-uniform)
+    u32 ns = 0, nd = 0, nx = 0;  // queued (wave-uniform)
     for (u32 k0 = 0; k0 < tlen; k0 += RC_UNROLL * HCI_WAVE) {
         int d[RC_UNROLL];
 #pragma unroll
@@ -226,13 +250,21 @@ __device__ __forceinline__ double rc_row(const RcInts<VT>& T, const RcLds<VT>& L
             const u32 k = k0 + u * HCI_WAVE + lane;
             const bool in_own = k < own;
             const bool sgl = in_own && d[u] == 2;
-            const bool dbl = in_own ? d[u] == 4 : d[u] == 2;
-            const u64 ms = ballot(sgl), md = ballot(dbl);
+            const bool dbl = in_own && d[u] == 4;
+            const bool crs = !in_own && d[u] == 2;
+            const u64 ms = ballot(sgl), md = ballot(dbl), mx = ballot(crs);
             if (sgl) qs[ns + rank_in(ms)] = (u16)k;
             if (dbl) qd[nd + rank_in(md)] = (u16)k;
+            if (crs) qx[nx + rank_in(mx)] = (u16)k;
             ns += (u32)popc64(ms);
             nd += (u32)popc64(md);
+            nx += (u32)popc64(mx);
             __builtin_amdgcn_wave_barrier();
+            if (nx >= HCI_WAVE) {
+                rc_flush_x<VT>(T, L, qx, HCI_WAVE, X, acc);
+                rc_shift(qx, nx);
+                nx -= HCI_WAVE;
+            }
             if (nd >= HCI_WAVE) {
                 rc_flush_d<VT>(T, L, qd, HCI_WAVE, X, acc);
                 rc_shift(qd, nd);
@@ -245,10 +277,76 @@ __device__ __forceinline__ double rc_row(const RcInts<VT>& T, const RcLds<VT>& L
             }
         }
     }
+    rc_flush_x<VT>(T, L, qx, nx, X, acc);
     rc_flush_d<VT>(T, L, qd, nd, X, acc);
     rc_flush_s<VT>(T, L, qs, ns, X, acc);
     __builtin_amdgcn_wave_barrier();
     return wave_sum_f64(acc);
+}
+
+// Alpha single x beta single connections of rows [r0, r1) of bucket A by
+// lookup: for a group of neighbours A' (links 1.. of the chunk), LDS bitmaps
+// of the beta strings present in each bucket A' (build_beta_maps); each row
+// probes its beta singles (the beta adjacency) in every bitmap of the group.
+// Hits are queued as (neighbour, single) and evaluated 64 at a time; c_j is
+// read from global memory at its position in bucket A'.  The bitmaps alias
+// the column tile.  Adds to racc; ends with a barrier.
+template <class VT>
+__device__ __forceinline__ void rc_cross_lookup(const SpaceView& S, const RcInts<VT>& T, const VT* __restrict__ cx,
+                                                const RcLds<VT>& L, u32 t_beg, u32 deg, u32 r0, u32 r1,
+                                                RcBitmaps M, u16* qx) {
+    const u32 tid = threadIdx.x;
+    const u32 wave = tid / HCI_WAVE;
+    const u32 lane = (u32)lane_id();
+    u32* bm = reinterpret_cast<u32*>(L.colw);
+    u16* pre = reinterpret_cast<u16*>(bm + (size_t)M.G * M.W);
+    for (u32 g0 = 0; g0 < deg; g0 += M.G) {
+        const u32 g1 = min(g0 + M.G, deg);
+        const u32 ng = g1 - g0;
+        build_beta_maps<RC_BLOCK>(S, t_beg, g0, g1, M.W, bm, pre, tid);
+        for (u32 r = r0 + wave; r < r1; r += RC_WAVES) {
+            const u64 X = S.beta[r];
+            const u32 bs = S.ib[r];
+            const u32 s0 = S.bs_ptr[bs], s1 = S.bs_ptr[bs + 1];
+            double acc = 0.0;
+            u32 nx = 0;
+            auto flush = [&](u32 cnt) {
+                if (lane < cnt) {
+                    const u32 e = qx[lane];
+                    const u32 q = e >> 10, kk = e & 1023u;
+                    const u32 bp = S.bs_idx[s0 + kk];
+                    const u32 w = bp >> 5, bt = bp & 31u;
+                    const u32 word = bm[q * M.W + w];
+                    const u32 j = L.lstart[1 + g0 + q] + (u32)pre[q * M.W + w] +
+                                  (u32)__builtin_popcount(word & ((1u << bt) - 1u));
+                    acc += rc_cross<VT>(T, L.linfo[g0 + q], X, S.ub[bp]) * (double)cx[j];
+                }
+            };
+            for (u32 k0 = s0; k0 < s1; k0 += HCI_WAVE) {
+                const u32 k = k0 + lane;
+                const bool valid = k < s1;
+                const u32 bp = valid ? S.bs_idx[k] : 0u;
+                const u32 w = bp >> 5, bt = bp & 31u;
+                for (u32 q = 0; q < ng; ++q) {
+                    const bool hit = valid && ((bm[q * M.W + w] >> bt) & 1u);
+                    const u64 m = ballot(hit);
+                    if (hit) qx[nx + rank_in(m)] = (u16)((q << 10) | (k - s0));
+                    nx += (u32)popc64(m);
+                    __builtin_amdgcn_wave_barrier();
+                    if (nx >= HCI_WAVE) {
+                        flush(HCI_WAVE);
+                        rc_shift(qx, nx);
+                        nx -= HCI_WAVE;
+                    }
+                }
+            }
+            flush(nx);
+            __builtin_amdgcn_wave_barrier();
+            acc = wave_sum_f64(acc);
+            if (lane == 0) L.racc[r - r0] += acc;
+        }
+        __syncthreads();  // the bitmaps are rebuilt for the next group
+    }
 }
 
 // One chunk: rows [r0, r1) of bucket `b` (alpha-major: determinant indices of
@@ -257,7 +355,7 @@ __device__ __forceinline__ double rc_row(const RcInts<VT>& T, const RcLds<VT>& L
 // Returns with racc[0, r1 - r0) holding the rows' sums (last barrier done).
 template <class VT, bool ALPHA_MAJOR>
 __device__ __forceinline__ void rc_chunk(const SpaceView& S, const RcInts<VT>& T, const VT* __restrict__ cx,
-                                         const RcLds<VT>& L, u32 b, u32 r0, u32 r1) {
+                                         const RcLds<VT>& L, u32 b, u32 r0, u32 r1, RcBitmaps M) {
     const u32 tid = threadIdx.x;
     const u32 wave = tid / HCI_WAVE;
     const u32 lane = (u32)lane_id();
@@ -270,6 +368,14 @@ __device__ __forceinline__ void rc_chunk(const SpaceView& S, const RcInts<VT>& T
     for (u32 x = tid; x < nr; x += RC_BLOCK) L.racc[x] = 0.0;
     rc_fixed_table<VT>(T, F, L.ftab);
     // link table: own bucket, then the alpha neighbours in adjacency order
+    // neighbour buckets by lookup when scanning them would cost more than
+    // probing every row's beta singles in them (uniform decision)
+    bool lookup = false;
+    if (ALPHA_MAJOR && M.W > 0 && deg > 0) {
+        const u32 own_len = off[b + 1] - off[b];
+        (void)own_len;
+        lookup = true;  // refined below once the link lengths are known
+    }
     if (wave == 0) {
         u32 run = 0;
         for (u32 base = 0; base < nlinks; base += HCI_WAVE) {
@@ -298,9 +404,16 @@ __device__ __forceinline__ void rc_chunk(const SpaceView& S, const RcInts<VT>& T
         if (lane == 0) L.loff[nlinks] = run;
     }
     __syncthreads();
-    const u32 total = L.loff[nlinks];
-    u16* qs = L.queue + wave * 256;
+    u32 total = L.loff[nlinks];
+    if (lookup) {
+        const u32 scan_cols = total - L.loff[1];
+        lookup = (float)scan_cols > 2.0f * (float)deg * M.nbs_avg;
+        if (lookup) total = L.loff[1];  // scan only the own bucket
+    }
+    u16* qs = L.queue + wave * 384;
     u16* qd = qs + 128;
+    u16* qx = qd + 128;
+    if (lookup) rc_cross_lookup<VT>(S, T, cx, L, t_beg, deg, r0, r1, M, qx);
     for (u32 P0 = 0; P0 < total; P0 += RC_TILE) {
         const u32 tlen = min(RC_TILE, total - P0);
         rc_stage<VT, ALPHA_MAJOR>(S, cx, L, nlinks, P0, tlen);
@@ -308,7 +421,7 @@ __device__ __forceinline__ void rc_chunk(const SpaceView& S, const RcInts<VT>& T
         const u32 own = L.loff[1] > P0 ? min(L.loff[1] - P0, tlen) : 0u;  // own-bucket columns of this tile
         for (u32 r = r0 + wave; r < r1; r += RC_WAVES) {
             const u64 X = ALPHA_MAJOR ? S.beta[r] : S.alpha[S.permb[r]];
-            const double v = rc_row<VT>(T, L, qs, qd, tlen, own, X);
+            const double v = rc_row<VT>(T, L, qs, qd, qx, tlen, own, X);
             if (lane == 0) L.racc[r - r0] += v;
         }
         __syncthreads();
@@ -323,12 +436,12 @@ __global__ void __launch_bounds__(RC_BLOCK) rc_alpha_kernel(SpaceView S, RcInts<
                                                             i64 nch, const VT* __restrict__ cx,
                                                             const double* __restrict__ c,
                                                             const double* __restrict__ hd,
-                                                            double* __restrict__ sigma, u32 maxl) {
+                                                            double* __restrict__ sigma, u32 maxl, RcBitmaps M) {
     extern __shared__ __align__(16) char smem[];
     const RcLds<VT> L = rc_lds<VT>(smem, T.n, maxl);
     for (i64 ch = blockIdx.x; ch < nch; ch += gridDim.x) {
         const u32 a = chunks[3 * ch], r0 = chunks[3 * ch + 1], r1 = chunks[3 * ch + 2];
-        rc_chunk<VT, true>(S, T, cx, L, a, r0, r1);
+        rc_chunk<VT, true>(S, T, cx, L, a, r0, r1, M);
         for (u32 r = r0 + threadIdx.x; r < r1; r += RC_BLOCK) sigma[r] = hd[r] * c[r] + L.racc[r - r0];
         __syncthreads();
     }
@@ -346,7 +459,7 @@ __global__ void __launch_bounds__(RC_BLOCK) rc_beta_kernel(SpaceView S, RcInts<V
     for (i64 ch = blockIdx.x; ch < nch; ch += gridDim.x) {
         const u32 b = chunks[3 * ch], k0 = chunks[3 * ch + 1], k1 = chunks[3 * ch + 2];
         if (S.boff[b + 1] - S.boff[b] < 2) continue;  // a lone determinant (uniform)
-        rc_chunk<VT, false>(S, T, cx, L, b, k0, k1);
+        rc_chunk<VT, false>(S, T, cx, L, b, k0, k1, RcBitmaps{0u, 0u, 0.0f});
         for (u32 k = k0 + threadIdx.x; k < k1; k += RC_BLOCK) sigma[S.permb[k]] += L.racc[k - k0];
         __syncthreads();
     }
@@ -395,8 +508,19 @@ void rc_launch(hci_ctx_s* ctx, Space* sp, RcInts<VT> T, const VT* cx, const doub
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_b));
     const i64 ga = row_grid(sp->rc_nch_a * RC_BLOCK, RC_BLOCK, RC_BLOCK);
     const i64 gb = row_grid(sp->rc_nch_b * RC_BLOCK, RC_BLOCK, RC_BLOCK);
+    // beta-string bitmaps of neighbour groups (as the stored build), within the tile's LDS
+    RcBitmaps M{0u, 0u, 0.0f};
+    const char* force_search = std::getenv("HCI_AB_SEARCH");  // "1": always scan (tests)
+    if (sp->nub <= 65535 && !(force_search && force_search[0] == '1')) {
+        const u32 W = (u32)ceil_div(sp->nub, 32);
+        const u32 G = (u32)std::min<i64>(64, RC_BM_BYTES / (6 * (i64)W));
+        if (G >= 1) M = RcBitmaps{W, G, (float)sp->n_bs / (float)sp->nub};
+        // "1": look every neighbour bucket up, whatever scanning it would cost (tests)
+        const char* force_lookup = std::getenv("HCI_RC_LOOKUP");
+        if (G >= 1 && force_lookup && force_lookup[0] == '1') M.nbs_avg = 0.0f;
+    }
     HCI_LAUNCH(ctx, na, s, rc_alpha_kernel<VT>, ga, RC_BLOCK, lds_a, S, T, sp->rc_chunk_a.as<u32>(), sp->rc_nch_a, cx,
-               c, sp->hdiag.as<double>(), sigma, maxl);
+               c, sp->hdiag.as<double>(), sigma, maxl, M);
     HCI_LAUNCH(ctx, nb, s, rc_beta_kernel<VT>, gb, RC_BLOCK, lds_b, S, T, sp->rc_chunk_b.as<u32>(), sp->rc_nch_b, cx,
                sigma);
 }

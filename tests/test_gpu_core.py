@@ -272,7 +272,11 @@ def test_stored_layout_beta_maps_match_search(lib_mod, monkeypatch, space, wlog)
     and for spaces with more than 65535 beta strings) by searching each
     neighbour bucket.  Both discover the same entries in the same order, so
     the stored layouts and the products agree bit for bit, and both match the
-    oracle; the density matrices (same choice of path) agree to rounding."""
+    oracle; the density matrices (same choice of path) agree to rounding.
+    The recomputed product scans neighbour buckets or looks the rows' beta
+    singles up in the same bitmaps (chosen per chunk by cost; HCI_AB_SEARCH=1
+    forces the scan, HCI_RC_LOOKUP=1 the lookup): every path against the
+    oracle."""
     if space == "cas16s":
         w = hs.WORKLOADS["cas16"]
         h, g = hs.workload_integrals(w)
@@ -291,11 +295,15 @@ def test_stored_layout_beta_maps_match_search(lib_mod, monkeypatch, space, wlog)
     c = hs.random_coeffs(len(V), 32)
     ref = O.sigma(h, g, V, c)
     outs = {}
-    for path in ["maps", "search"]:
+    for path in ["maps", "search", "lookup"]:
         if path == "search":
             monkeypatch.setenv("HCI_AB_SEARCH", "1")
         else:
             monkeypatch.delenv("HCI_AB_SEARCH", raising=False)
+        if path == "lookup":  # the recomputed product looks every neighbour bucket up
+            monkeypatch.setenv("HCI_RC_LOOKUP", "1")
+        else:
+            monkeypatch.delenv("HCI_RC_LOOKUP", raising=False)
         print(f"[beta maps {space} |V|={len(V)} wlog={wlog} {path}]", flush=True)
         ctx = lib_mod.HCIContext(h, g, na, nb)
         ctx.set_stage_window(wlog)
@@ -303,12 +311,18 @@ def test_stored_layout_beta_maps_match_search(lib_mod, monkeypatch, space, wlog)
         assert ctx.connections(V) == int(O.row_counts(n, V).sum())
         for prec in ["fp64", "fp32_mixed"]:
             outs[path, prec] = ctx.sigma(V, c, precision=prec, mode="stored").cpu().numpy()
+            outs[path, "rc", prec] = ctx.sigma(V, c, precision=prec, mode="recompute").cpu().numpy()
         r1, r2 = ctx.rdm12(V, c)
         outs[path, "rdm"] = (r1.cpu().numpy(), r2.cpu().numpy())
         ctx.close()
     for prec, tol in [("fp64", 1e-12), ("fp32_mixed", 1e-6)]:
         assert np.array_equal(outs["maps", prec], outs["search", prec]), prec
+        assert np.array_equal(outs["maps", prec], outs["lookup", prec]), prec
         assert rel_err(outs["maps", prec], ref) < tol, prec
+        # recomputed product: neighbour buckets scanned (search) or looked up
+        # (lookup), connections met in another order, so rounding only
+        for path in ["maps", "search", "lookup"]:
+            assert rel_err(outs[path, "rc", prec], ref) < tol, (path, prec)
     # density matrices: same pairs, float64 atomics in another order
     for k in range(2):
         a, b = outs["maps", "rdm"][k], outs["search", "rdm"][k]
