@@ -155,3 +155,97 @@ def test_cas44_relaxed_backward(cas44r):
     assert np.abs(zg.cpu().numpy() - z).max() <= 1e-8 * max(1.0, np.abs(z).max())
     assert np.abs(dh.cpu().numpy() - 0.5 * (r1 + r1.T)).max() < 1e-8
     assert np.abs(dg.cpu().numpy() - 0.5 * O.symmetrize8(r2)).max() < 1e-8
+
+
+# ---------------------------------------------------------------- (44e,44o) relaxed at size
+@pytest.fixture(scope="module")
+def cas44_v1(gpu_available):
+    """The porphyrin-shaped (44e,44o) integrals and the method's first space:
+    aufbau + C(1e-4) by the oracle's definition of the criterion (341,821
+    determinants), with the library's lowest eigenpair on it."""
+    import paper_1708_07544_amd as P
+    w = hs.WORKLOADS["cas44"]
+    h, g = hs.workload_integrals(w)
+    V0 = hs.aufbau_det(22, 22)
+    V = O.merge(V0, O.select(h, g, V0, np.array([1.0]), w.eps1))
+    ctx = P.HCIContext(h, g, 22, 22)
+    e, c, it = ctx.davidson(V, None, tol=1e-10, precision="fp32_mixed")
+    print(f"[cas44 V1] |V|={len(V)} E={e:.10f} products={it}", flush=True)
+    return h, g, V, ctx, e, c
+
+
+def test_cas44_relaxed_finite_differences_frozen(cas44_v1):
+    """(44e,44o) at eps2 = 1e-2 on the 341,821-determinant space: the relaxed
+    gradient (mixed-precision z-solve refined in float64 to 1e-8) against
+    central finite differences of E_var + E2 with V and the screened pair set
+    frozen at the unperturbed integrals (hci_pt2_freeze), on 5 one-electron
+    and 5 two-electron symmetry orbits.  Step 1e-4 (|E| ~ 1.6e3 Ha, so
+    rounding of E stays ~1e-6 of the quotient); tolerance 2e-5."""
+    from paper_1708_07544_amd.autograd import hci_energy
+    h, g, V, ctx, e1, c1 = cas44_v1
+    n, eps2 = 44, 1e-2
+    Vd = torch.as_tensor(V.view(np.int64)).cuda()
+    ht = torch.tensor(h, device="cuda", requires_grad=True)
+    gt = torch.tensor(g, device="cuda", requires_grad=True)
+    E = hci_energy(ht, gt, Vd, 22, 22, tol=1e-10, eps2=eps2, frozen=True, context=ctx, c0=c1,
+                   precision="fp32_mixed", z_tol=1e-8)
+    E.backward()
+    dh, dg = ht.grad.cpu().numpy(), gt.grad.cpu().numpy()
+    c_ref = ctx.davidson(V, c1, tol=1e-10)[1]
+
+    def energy(hh, gg):
+        return hci_energy(torch.tensor(hh, device="cuda"), torch.tensor(gg, device="cuda"), Vd, 22, 22,
+                          tol=1e-10, eps2=eps2, frozen=True, keep_frozen=True, context=ctx, c0=c_ref).item()
+
+    step = 1e-4
+    rng = np.random.default_rng(44)
+    for _ in range(5):
+        p, q = (int(x) for x in rng.integers(0, n, 2))
+        d = sym_delta(n, p, q, step)
+        fd = (energy(h + d, g) - energy(h - d, g)) / (2 * step)
+        ana = float(np.sum(dh * d)) / step
+        print(f"[cas44 relaxed h {p},{q}] fd={fd:.9f} ana={ana:.9f}", flush=True)
+        assert abs(fd - ana) < 2e-5, (p, q, fd, ana)
+    for _ in range(5):
+        idx = tuple(int(x) for x in rng.integers(0, n, 4))
+        d = orbit_delta(g.shape, idx, step)
+        fd = (energy(h, g + d) - energy(h, g - d)) / (2 * step)
+        ana = float(np.sum(dg * d)) / step
+        print(f"[cas44 relaxed g {idx}] fd={fd:.9f} ana={ana:.9f}", flush=True)
+        assert abs(fd - ana) < 2e-5, (idx, fd, ana)
+    ctx.update_integrals(h, g)
+
+
+def test_cas44_relaxed_density_at_scale(cas44_v1):
+    """(44e,44o) at eps2 = 1e-3 on the 341,821-determinant space (about 10^9
+    connected determinants, taken in budgeted passes): the relaxed density
+    matrices reproduce E_var + E2 (sum h dh + sum g dg, an identity of the
+    Lagrangian once d_a = N_a / (E - H_aa), z is orthogonal to c and c is an
+    eigenvector), trace N and partial trace (N - 1) gamma; the z-vector meets
+    the equation Q(H - E)Q z = -Q r on sampled rows, with the oracle's
+    products (H z)_i, to the solve's tolerance."""
+    h, g, V, ctx, e1, c1 = cas44_v1
+    eps2 = 1e-3
+    N = 44
+    dh, dg, z, e2 = ctx.energy_backward(V, c1, e1, eps2=eps2, z_tol=1e-8, precision="fp32_mixed", want_z=True)
+    dh, dg = dh.cpu().numpy(), dg.cpu().numpy()
+    e_rel = float(np.sum(h * dh) + np.sum(g * dg))
+    print(f"[cas44 relaxed eps2={eps2}] E_var={e1:.9f} E2={e2:.9f} sum h dh + g dg = {e_rel:.9f}", flush=True)
+    assert abs(e_rel - (e1 + e2)) < 1e-7
+    assert abs(np.trace(dh) - N) < 1e-8
+    G = 2.0 * dg  # Gamma_rel, 8-fold symmetrised
+    assert abs(np.einsum("pprr->", G) - N * (N - 1)) < 1e-7
+    assert np.abs(np.einsum("pqrr->pq", G) - (N - 1) * dh).max() < 1e-8
+    # the z-vector equation on sampled rows (float64 oracle products of z)
+    e2b, r, _ = ctx.pt2(V, c1, e1, eps2)
+    assert abs(e2b - e2) <= 1e-10 * abs(e2)
+    zc, cc, rc = z.cpu().numpy(), c1.cpu().numpy(), r.cpu().numpy()
+    hc = ctx.sigma(V, c1, precision="fp64").cpu().numpy()
+    assert abs(zc @ cc) < 1e-10 * np.linalg.norm(zc)
+    b = -(rc - cc * (cc @ rc))
+    rows = np.random.default_rng(45).choice(len(V), 200, replace=False)
+    hz = O.sigma(h, g, V, zc, rows=rows)
+    lhs = hz - e1 * zc[rows] - cc[rows] * ((hc - e1 * cc) @ zc)
+    res = np.abs(lhs - b[rows]).max()
+    print(f"[cas44 z] |b|={np.linalg.norm(b):.3e} max sampled residual {res:.3e}", flush=True)
+    assert res <= 1e-8 * np.linalg.norm(b) * 1.01

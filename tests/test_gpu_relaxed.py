@@ -16,6 +16,27 @@ import oracle as O
 pytestmark = pytest.mark.gpu
 
 
+PERMS = [(0, 1, 2, 3), (1, 0, 2, 3), (0, 1, 3, 2), (1, 0, 3, 2), (2, 3, 0, 1), (3, 2, 0, 1),
+         (2, 3, 1, 0), (3, 2, 1, 0)]
+
+
+def orbit_delta(shape, idx, step):
+    """A perturbation of one 8-fold symmetry orbit of (pq|rs)."""
+    d = np.zeros(shape)
+    for pm in PERMS:
+        d[tuple(np.array(idx)[list(pm)])] = step
+    return d
+
+
+def sym_delta(n, p, q, step):
+    """A perturbation of h_pq and h_qp together."""
+    d = np.zeros((n, n))
+    d[p, q] += step
+    if p != q:
+        d[q, p] += step
+    return d
+
+
 @pytest.fixture(scope="module")
 def P(gpu_available):
     import paper_1708_07544_amd as P
@@ -83,3 +104,91 @@ def test_relaxed_backward(P, n, na, nb, m, seed, eps2, precision):
     assert np.abs(zg.cpu().numpy() - z).max() <= 1e-8 * max(1.0, np.abs(z).max())
     assert np.abs(dh.cpu().numpy() - grad * 0.5 * (r1 + r1.T)).max() < 1e-8
     assert np.abs(dg.cpu().numpy() - grad * 0.5 * O.symmetrize8(r2)).max() < 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_relaxed_backward_in_passes(P, precision):
+    """The relaxed gradient with eps2 > 0 accumulates r, E2, d.d, Gamma^{dc}
+    and Gamma^{dd} over the budgeted passes of the PT2 (a hash partition of
+    the connected determinants): with the budget forced to a fifth of the
+    pairs (several passes) it agrees with one pass and with the oracle."""
+    n, na, nb, m, seed, eps2 = CASES[1]
+    h, g, V, e0, c, pt = setup_case(n, na, nb, m, seed, eps2)
+    H = O.hamiltonian_csr(h, g, V).toarray()
+    z = O.zvector_dense(H, c, e0, pt["r"])
+    r1, r2 = O.relaxed_rdms(n, V, c, e0, z, pt)
+    npairs = len(pt["pairs"][1])
+    outs = []
+    for budget in (None, max(1, npairs // 5) * 128):
+        ctx = P.HCIContext(h, g, na, nb)
+        if budget is not None:
+            ctx.set_pt2_budget(budget)
+        dh, dg, zg, e2 = ctx.energy_backward(V, c, e0, eps2=eps2, z_tol=1e-11, precision=precision, want_z=True)
+        outs.append((dh.cpu().numpy(), dg.cpu().numpy(), e2))
+        assert abs(e2 - pt["E2"]) <= 1e-12 * abs(pt["E2"])
+        assert np.abs(outs[-1][0] - 0.5 * (r1 + r1.T)).max() < 1e-8
+        assert np.abs(outs[-1][1] - 0.5 * O.symmetrize8(r2)).max() < 1e-8
+        ctx.close()
+    assert np.abs(outs[0][0] - outs[1][0]).max() < 1e-10
+    assert np.abs(outs[0][1] - outs[1][1]).max() < 1e-10
+
+
+def test_energy_entry_point_and_frozen_pairs(P):
+    """hci_energy returns E_var (the Davidson eigenvalue), E2 (as hci_pt2 at
+    eps2) and their sum, computed in the library; over the pair set frozen by
+    hci_pt2_freeze at the same integrals and vector, E2 is the same."""
+    n, na, nb, m, seed, eps2 = CASES[0]
+    h, g, V, e0, c, pt = setup_case(n, na, nb, m, seed, eps2)
+    ctx = P.HCIContext(h, g, na, nb)
+    (ev, e2, et), cv, it = ctx.energy(V, None, tol=1e-11, eps2=eps2)
+    assert abs(ev - e0) < 1e-9
+    e2_ref, _, _ = ctx.pt2(V, cv, ev, eps2, want_r=False)
+    assert e2 == e2_ref and et == ev + e2
+    assert abs(e2 - pt["E2"]) <= 1e-9 * abs(pt["E2"])
+    assert ctx.pt2_freeze(V, cv, eps2) == len(pt["pairs"][1])
+    (ev2, e2f, etf), _, _ = ctx.energy(V, cv, tol=1e-11, eps2=eps2, frozen=True)
+    assert abs(e2f - e2) <= 1e-12 * abs(e2) and abs(etf - (ev2 + e2f)) == 0.0
+    # a frozen set belongs to its list
+    with pytest.raises(Exception):
+        ctx.energy(V[:-1], None, tol=1e-9, eps2=eps2, frozen=True)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_frozen_energy_finite_differences(P, precision):
+    """E_var + E2 on a frozen list V and a frozen pair set (hci_pt2_freeze at
+    the unperturbed integrals) is smooth in the integrals; its central finite
+    differences (step 1e-5) on 6 one-electron and 6 two-electron symmetry
+    orbits equal the relaxed gradient (eq. lambda) of hci_energy_backward,
+    through HCIEnergy with a reused context."""
+    import torch
+    from paper_1708_07544_amd.autograd import hci_energy
+    n, na, nb, m, seed, eps2 = CASES[1]
+    h, g = hs.make_integrals(n, 3 * n, seed)
+    V = hs.random_dets(n, na, nb, m, seed=seed, bias=0.25)
+    Vd = torch.as_tensor(V.view(np.int64)).cuda()
+    ctx = P.HCIContext(h, g, na, nb)
+    ht = torch.tensor(h, device="cuda", requires_grad=True)
+    gt = torch.tensor(g, device="cuda", requires_grad=True)
+    E = hci_energy(ht, gt, Vd, na, nb, tol=1e-12, eps2=eps2, frozen=True, context=ctx, precision=precision,
+                   z_tol=1e-11)
+    E.backward()
+    dh, dg = ht.grad.cpu().numpy(), gt.grad.cpu().numpy()
+
+    def energy(hh, gg):
+        return hci_energy(torch.tensor(hh, device="cuda"), torch.tensor(gg, device="cuda"), Vd, na, nb,
+                          tol=1e-12, eps2=eps2, frozen=True, keep_frozen=True, context=ctx).item()
+
+    step = 1e-5
+    rng = np.random.default_rng(7)
+    for _ in range(6):
+        p, q = (int(x) for x in rng.integers(0, n, 2))
+        d = sym_delta(n, p, q, step)
+        fd = (energy(h + d, g) - energy(h - d, g)) / (2 * step)
+        ana = float(np.sum(dh * d)) / step
+        assert abs(fd - ana) < 1e-6 * max(1.0, abs(ana)), (p, q, fd, ana)
+    for _ in range(6):
+        idx = tuple(int(x) for x in rng.integers(0, n, 4))
+        d = orbit_delta(g.shape, idx, step)
+        fd = (energy(h, g + d) - energy(h, g - d)) / (2 * step)
+        ana = float(np.sum(dg * d)) / step
+        assert abs(fd - ana) < 1e-6 * max(1.0, abs(ana)), (idx, fd, ana)
