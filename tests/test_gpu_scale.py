@@ -1,0 +1,152 @@
+"""The (30e,30o) and (44e,44o) workloads at their configured sizes, through
+the method's own loop: the oracle's first space V1 = aufbau + C(eps1), the
+library's lowest eigenpair on it, the library's selection of V2 from that
+eigenvector, and the lowest eigenpair on V2.  These runs take minutes (the
+Hamiltonians of V2 do not fit in memory, so every product is recomputed),
+so they are run on demand: HCI_SCALE_TESTS=1.  Their measured output is
+kept in profiles/config_scale_runs.md.
+
+(30e,30o): V2 at eps1 = 5e-3 (the configured 3e-5 selects 2.2e8
+determinants from this state); the energy backward (gamma, Gamma of V2)
+against central finite differences of the energy on 3 one-electron and 3
+two-electron symmetry orbits, V frozen.
+
+(44e,44o) porphyrin-shaped: eps1 = 1e-4 .. 1.6e-3 make the selection from
+V1's eigenvector overflow its 2^32-slot set (more than 2^31 new
+determinants), which is checked; V2 at eps1 = 1e-2 (about 1.1e7
+determinants) is solved in float32-mixed precision with float64
+refinement, recomputed products, and its residual is checked row by row
+against the oracle's float64 products on sampled rows.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import hci_synth as hs
+import oracle as O
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow,
+              pytest.mark.skipif(os.environ.get("HCI_SCALE_TESTS") != "1",
+                                 reason="config-size runs take minutes; HCI_SCALE_TESTS=1 runs them")]
+
+PERMS = [(0, 1, 2, 3), (1, 0, 2, 3), (0, 1, 3, 2), (1, 0, 3, 2), (2, 3, 0, 1), (3, 2, 0, 1),
+         (2, 3, 1, 0), (3, 2, 1, 0)]
+
+
+def orbit_delta(shape, idx, step):
+    d = np.zeros(shape)
+    for pm in PERMS:
+        d[tuple(np.array(idx)[list(pm)])] = step
+    return d
+
+
+def sym_delta(n, p, q, step):
+    d = np.zeros((n, n))
+    d[p, q] += step
+    if p != q:
+        d[q, p] += step
+    return d
+
+
+def _solve(ctx, V, c0, tol, precision, chunk, label):
+    """Lowest eigenpair by restarted solves of `chunk` products each (a
+    progress line per restart)."""
+    c = c0
+    total = 0
+    t0 = time.perf_counter()
+    for k in range(60):
+        e, c, it = ctx.davidson(V, c, tol=tol, max_iter=chunk, precision=precision, mode="recompute",
+                                allow_noconv=True)
+        total += it
+        res = ctx.sigma(V, c, precision="fp64", mode="recompute") - e * c
+        rn = float(torch.linalg.vector_norm(res))
+        print(f"{label} restart {k}: E={e:.12f} products={total} residual={rn:.3e} "
+              f"({time.perf_counter() - t0:.1f} s)", flush=True)
+        if rn <= tol:
+            return e, c, total
+    raise AssertionError("no convergence")
+
+
+def test_cas30_config_size_backward_finite_differences(gpu_available):
+    import paper_1708_07544_amd as P
+    w = hs.WORKLOADS["cas30"]
+    h, g = hs.workload_integrals(w)
+    n, na, nb = 30, 15, 15
+    V0 = hs.aufbau_det(na, nb)
+    V1 = O.merge(V0, O.select(h, g, V0, np.array([1.0]), w.eps1))
+    ctx = P.HCIContext(h, g, na, nb)
+    e1, c1, it1 = ctx.davidson(V1, None, tol=1e-8, precision="fp32_mixed")
+    print(f"[cas30] |V1|={len(V1)} E1={e1:.10f} products={it1}", flush=True)
+    V2 = P.dets_to_numpy(ctx.select(V1, c1, 5e-3))
+    print(f"[cas30] |V2|={len(V2)} at eps1=5e-3", flush=True)
+    assert len(V2) >= 5_000_000
+    e2, c2, it2 = _solve(ctx, V2, ctx.embed(V1, c1, V2), 1e-7, "fp32_mixed", 24, "[cas30 V2]")
+    assert e2 < e1
+    t = time.perf_counter()
+    dh, dg, _, _ = ctx.energy_backward(V2, c2, e2)
+    dh, dg = dh.cpu().numpy(), dg.cpu().numpy()
+    print(f"[cas30] energy backward on V2: {time.perf_counter() - t:.1f} s; "
+          f"tr gamma={np.trace(dh):.10f}", flush=True)
+    assert abs(np.trace(dh) - 30) < 1e-8
+    assert abs(float(np.sum(h * dh) + np.sum(g * dg)) - e2) < 1e-6
+
+    def energy(hh, gg):
+        ctx.update_integrals(hh, gg)
+        e, _, _ = _solve(ctx, V2, c2, 1e-7, "fp32_mixed", 24, "  [fd]")
+        return e
+
+    step = 1e-5
+    rng = np.random.default_rng(300)
+    for _ in range(3):
+        p, q = (int(x) for x in rng.integers(0, n, 2))
+        d = sym_delta(n, p, q, step)
+        fd = (energy(h + d, g) - energy(h - d, g)) / (2 * step)
+        ana = float(np.sum(dh * d)) / step
+        print(f"[cas30 V2 h {p},{q}] fd={fd:.9f} ana={ana:.9f}", flush=True)
+        assert abs(fd - ana) < 2e-5, (p, q, fd, ana)
+    for _ in range(3):
+        idx = tuple(int(x) for x in rng.integers(0, n, 4))
+        d = orbit_delta(g.shape, idx, step)
+        fd = (energy(h, g + d) - energy(h, g - d)) / (2 * step)
+        ana = float(np.sum(dg * d)) / step
+        print(f"[cas30 V2 g {idx}] fd={fd:.9f} ana={ana:.9f}", flush=True)
+        assert abs(fd - ana) < 2e-5, (idx, fd, ana)
+
+
+def test_cas44_config_loop(gpu_available):
+    import paper_1708_07544_amd as P
+    from paper_1708_07544_amd import _lib
+    w = hs.WORKLOADS["cas44"]
+    h, g = hs.workload_integrals(w)
+    V0 = hs.aufbau_det(22, 22)
+    V1 = O.merge(V0, O.select(h, g, V0, np.array([1.0]), w.eps1))
+    ctx = P.HCIContext(h, g, 22, 22)
+    e1, c1, it1 = ctx.davidson(V1, None, tol=1e-8, precision="fp32_mixed")
+    print(f"[cas44] |V1|={len(V1)} E1={e1:.10f} products={it1}", flush=True)
+    for eps in (1e-4, 1.6e-3):
+        with pytest.raises(_lib.HCIError) as err:
+            ctx.select(V1, c1, eps)
+        assert err.value.code == _lib.HCI_E_NOMEM
+        print(f"[cas44] eps1={eps}: {err.value}", flush=True)
+    t = time.perf_counter()
+    V2 = P.dets_to_numpy(ctx.select(V1, c1, 1e-2))
+    print(f"[cas44] |V2|={len(V2)} at eps1=1e-2 ({time.perf_counter() - t:.1f} s)", flush=True)
+    assert len(V2) >= 10_000_000
+    t = time.perf_counter()
+    e2, c2, it2 = _solve(ctx, V2, ctx.embed(V1, c1, V2), 1e-4, "fp32_mixed", 10, "[cas44 V2]")
+    print(f"[cas44] V2 solve: E2={e2:.10f} products={it2} {time.perf_counter() - t:.1f} s", flush=True)
+    assert e2 < e1
+    # residual rows against the oracle's float64 products
+    cv = c2.cpu().numpy()
+    rows = np.random.default_rng(440).choice(len(V2), 64, replace=False)
+    rows = np.concatenate([rows, [int(np.argmax(np.abs(cv)))]])
+    hc = O.sigma(h, g, V2, cv, rows=rows)
+    res = np.abs(hc - e2 * cv[rows])
+    lib_res = (ctx.sigma(V2, c2, precision="fp64", mode="recompute") - e2 * c2).cpu().numpy()[rows]
+    print(f"[cas44] sampled residual rows: oracle max {res.max():.3e}, library max {np.abs(lib_res).max():.3e}, "
+          f"max diff {np.abs(res - np.abs(lib_res)).max():.3e}", flush=True)
+    assert res.max() <= 1e-4
+    assert np.abs(hc - e2 * cv[rows] - lib_res).max() <= 1e-10 * np.abs(hc).max()
