@@ -5,19 +5,19 @@
 // the Hamiltonian product (Sec. "Computational Details").
 //
 // Diagonal pairs (i = j) only involve occupation numbers, so they are
-// reduced without atomics: D[x][y] = sum_i bra_i ket_i n_x(i) n_y(i) over
-// spin orbitals x, y, block partials then a fixed-order sum.  Each
-// off-diagonal pair (row i, connection j) adds bra_i ket_j times the
-// operator matrix element of the excitation D_j -> D_i to the few
-// rdm entries it touches, with float64 atomics.
+// reduced as an occupation-correlation product: D[x][y] = sum_i bra_i ket_i
+// n_x(i) n_y(i) over spin orbitals x, y, block partials then a fixed-order
+// sum.  Off-diagonal pairs go through rdm_det_kernel (below): per-chunk
+// owners, private copies per workgroup, fixed-order sums; no atomics, so the
+// result is the same bit for bit from run to run.  The screened PT2 pairs of
+// the relaxed gradient (Gamma^{dc}) are still added with float64 atomics
+// (pt2_pairs_kernel).
 #include <cstdlib>
 
 #include "slater.h"
 
 namespace {
 
-constexpr int ROW_BLOCK = 256;
-constexpr int ROWS_PER_BLOCK = ROW_BLOCK / HCI_WAVE;
 constexpr int OCC_CHUNK = 256;
 
 __device__ __forceinline__ void add64(double* p, double v) { unsafeAtomicAdd(p, v); }
@@ -92,34 +92,6 @@ __device__ __forceinline__ void pair_contrib(int n, double w, u64 ai, u64 bi, u6
         add64(&r2[r2idx(n, u2, v2, u1, v1)], x);
         add64(&r2[r2idx(n, u2, v1, u1, v2)], -x);
     }
-}
-
-struct RdmVis {
-    const double* ket;
-    double bra_i;
-    u64 ai, bi;
-    int n;
-    double* r1;
-    double* r2;
-    __device__ __forceinline__ void operator()(bool ok, u32 j, u64 aj, u64 bj) {
-        if (!ok) return;
-        const double w = bra_i * ket[j];
-        if (w == 0.0) return;
-        pair_contrib<true>(n, w, ai, bi, aj, bj, r1, r2);
-    }
-};
-
-__global__ void __launch_bounds__(ROW_BLOCK) rdm_offdiag_kernel(SpaceView S,
-                                                                const double* __restrict__ bra,
-                                                                const double* __restrict__ ket,
-                                                                double* __restrict__ r1,
-                                                                double* __restrict__ r2) {
-    const i64 i = (i64)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x / HCI_WAVE;
-    if (i >= S.N) return;
-    const double bi_ = bra[i];
-    if (bi_ == 0.0) return;  // wave-uniform
-    RdmVis v{ket, bi_, S.alpha[i], S.beta[i], S.n, r1, r2};
-    enumerate_row(S, (u32)i, v);
 }
 
 // Occupation correlation D[x][y] = sum_i w_i n_x(i) n_y(i) over spin
@@ -242,38 +214,43 @@ __global__ void swap_sym_kernel(double* __restrict__ r2, int n) {
     r2[R * n2 + P] = v;
 }
 
-// ---------------------------------------------------------------- bucket kernel
-// One workgroup owns up to RDM_CHUNK rows of one alpha bucket A (all rows
-// share the alpha string).  Every contribution whose orbital indices are fixed
-// by A up to a small set goes to a workgroup-private float64 accumulator in
-// LDS and reaches global memory once per workgroup:
-//   alpha single x beta single: per alpha neighbour t of A, [t][u2][v2]
-//     (processed G neighbours at a time);
-//   alpha single (same beta): per neighbour, the sum and its beta-occupation
-//     moments (opposite-spin spectators);
-//   beta single (same alpha): [u][v] and, when it fits, [u][v][k] for the
-//     same-spin spectators k;
-//   alpha double (same beta): one slot per (occupied pair, empty pair) of A.
-// Beta doubles (same alpha) go to global memory directly.  All rdm2 terms are
-// the canonical half T (see single_contrib).
+// ---------------------------------------------------------------- off-diagonal kernel
+// Off-diagonal pairs (row i = bra determinant, j = ket determinant) without
+// atomics.  A persistent grid of P workgroups: workgroup p takes the chunks
+// c = p, p + P, ... (up to RDM_CHUNK rows of one alpha bucket A each) in that
+// order and owns a private copy of the output in global memory -- the
+// canonical half T of rdm2 (one entry of each (pq|rs), (rs|pq) pair, see
+// single_contrib) and rdm1; the P copies are then summed in a fixed order.
+// Inside a workgroup every accumulator has one writer at a time:
+//   * wavefront 0 takes the chunk's rows one after another and finds their
+//     same-alpha connections (beta single or double: the rows of bucket A)
+//     and same-beta connections (alpha single or double: the rows of the
+//     row's beta bucket).  One row's contributions fall on distinct entries
+//     (distinct excitations), so each lane adds to its own: beta singles
+//     into the chunk's LDS sums [u][v] (and [u][v][k] for the same-spin
+//     spectators when they fit), alpha singles into one LDS slot per alpha
+//     neighbour of A with the beta-occupation moments (when they fit), the
+//     rest straight into the private copy;
+//   * wavefronts 1.. own the alpha neighbours A' of A (neighbour q goes to
+//     wavefront 1 + q mod (waves - 1)) and accumulate the alpha single x beta
+//     single pairs of every row of the chunk with A' in an LDS tile [u2][v2]
+//     per neighbour, found through bitmaps of the beta strings present in
+//     each neighbour bucket (build_beta_maps) or by scanning the bucket;
+//   * the LDS sums reach the private copy class by class, separated by
+//     barriers (different classes can share an entry of the spin-traced
+//     output).
 constexpr int RDM_BLOCK = 1024;
 constexpr int RDM_WAVES = RDM_BLOCK / HCI_WAVE;
 constexpr u32 RDM_CHUNK = 1024;
 
 struct RdmPlan {
     int n, G;
-    int npo, npv;                // occupied / empty orbital pairs of an alpha string
-    int o_p11, o_s1a, o_s1b2, o_s1b3, o_d2a, total;  // offsets in doubles
-    bool b3, d2;
-    int W;        // beta-string bitmap words per neighbour (0: search the buckets)
-    int o_bm;     // byte offset of the bitmaps (after the doubles)
-    int bytes;    // LDS of the workgroup
+    bool s1a, b3;           // alpha-single slots / beta-single spectator block in LDS
+    int o_p11, o_s1a, o_s1b2, o_s1b3, total;  // offsets in doubles
+    int W;                  // beta-string bitmap words per neighbour (0: scan the buckets)
+    int o_bm;               // byte offset of the bitmaps (after the doubles)
+    int bytes;              // LDS of the workgroup
 };
-
-__device__ __forceinline__ void lds_add(double* p, double v) { unsafeAtomicAdd(p, v); }
-
-// index of the unordered pair x < y
-__device__ __forceinline__ int pair_index(int x, int y) { return y * (y - 1) / 2 + x; }
 
 // position of the k-th set bit (k from 0) of s
 __device__ __forceinline__ int select_bit(u64 s, int k) {
@@ -281,16 +258,15 @@ __device__ __forceinline__ int select_bit(u64 s, int k) {
     return ctz64(s);
 }
 
-// 8 waves per SIMD: two workgroups share a CU (the kernel is latency bound).
-// BM: alpha single x beta single pairs through the LDS beta-string maps of
-// build_beta_maps; otherwise by scanning or searching each neighbour bucket.
+// non-atomic update of an entry this thread alone writes at this moment
+__device__ __forceinline__ void own_add(double* p, double v) { *p += v; }
+
 template <bool BM>
-__global__ void __launch_bounds__(RDM_BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8))) rdm_bucket_kernel(SpaceView S, RdmPlan P, i64 nua,
-                                                               const u32* __restrict__ cptr,
-                                                               const double* __restrict__ bra,
-                                                               const double* __restrict__ ket,
-                                                               double* __restrict__ r1,
-                                                               double* __restrict__ r2) {
+__global__ void __launch_bounds__(RDM_BLOCK) rdm_det_kernel(SpaceView S, RdmPlan P, i64 nua, i64 nchunk,
+                                                            const u32* __restrict__ cptr,
+                                                            const double* __restrict__ bra,
+                                                            const double* __restrict__ ket,
+                                                            double* __restrict__ priv) {
     extern __shared__ double lds[];
     __shared__ u32 sh[3];
     const u32 tid = threadIdx.x;
@@ -298,248 +274,227 @@ __global__ void __launch_bounds__(RDM_BLOCK) __attribute__((amdgpu_waves_per_eu(
     const u32 wave = tid / HCI_WAVE;
     const int n = P.n;
     const int nn = n * n;
-    if (tid == 0) {
-        // bucket of this workgroup: the last a with cptr[a] <= blockIdx.x
-        const u32 w = blockIdx.x;
-        u32 lo = 0, hi = (u32)nua - 1u;
-        while (lo < hi) {
-            const u32 mid = (lo + hi + 1u) >> 1;
-            if (cptr[mid] <= w) lo = mid;
-            else hi = mid - 1u;
-        }
-        const u32 r0 = S.aoff[lo] + (w - cptr[lo]) * RDM_CHUNK;
-        sh[0] = lo;
-        sh[1] = r0;
-        sh[2] = min(r0 + RDM_CHUNK, S.aoff[lo + 1]);
-    }
-    for (int x = (int)tid; x < P.total; x += RDM_BLOCK) lds[x] = 0.0;
-    __syncthreads();
-    const u32 a = sh[0], row0 = sh[1], row1 = sh[2];
-    const u64 A = S.ua[a];
-    const u64 full = low_mask(n);
-    const u64 E = ~A & full;  // empty alpha orbitals
-    const u32 t0 = S.as_ptr[a];
-    const u32 deg = S.as_ptr[a + 1] - t0;
-    const int nocc = popc64(A), nvir = n - nocc;
+    const i64 n4 = (i64)nn * nn;
+    double* r2 = priv + (i64)blockIdx.x * (n4 + nn);  // this workgroup's copy: T, then rdm1
+    double* r1 = r2 + n4;
     double* p11 = lds + P.o_p11;
     double* s1a = lds + P.o_s1a;
     double* s1b2 = lds + P.o_s1b2;
     double* s1b3 = lds + P.o_s1b3;
-    double* d2a = lds + P.o_d2a;
     u32* bm = reinterpret_cast<u32*>(reinterpret_cast<unsigned char*>(lds) + P.o_bm);
     u16* pre = reinterpret_cast<u16*>(bm + (i64)P.G * P.W);
-    const u32 ngroups = deg == 0 ? 1u : (deg + (u32)P.G - 1u) / (u32)P.G;
-    for (u32 g = 0; g < ngroups; ++g) {
-        const u32 tg0 = g * (u32)P.G;
-        const u32 tg1 = min(tg0 + (u32)P.G, deg);
-        if constexpr (BM) build_beta_maps<RDM_BLOCK>(S, t0, tg0, tg1, (u32)P.W, bm, pre, tid);
-        for (u32 row = row0 + wave; row < row1; row += RDM_WAVES) {
-            const double wb = bra[row];
-            if (wb == 0.0) continue;  // wave-uniform
-            const u64 B = S.beta[row];
-            const u32 b = S.ib[row];
-            if (g == 0) {
-                {  // same alpha: beta single (LDS) or beta double (global)
-                    const u32 lo = S.aoff[a], hi = S.aoff[a + 1];
-                    for (u32 base = lo; base < hi; base += HCI_WAVE) {
-                        const u32 j = base + lane;
-                        if (j >= hi || j == row) continue;
-                        const u64 bj = S.beta[j];
-                        const u64 xb = B ^ bj;
-                        const int d = popc64(xb);
-                        if (d == 2) {
-                            const int v = ctz64(bj & xb), u = ctz64(B & xb);
-                            const double x = wb * ket[j] * sign_between(bj, v, u);
-                            lds_add(&s1b2[u * n + v], x);
-                            for (u64 m = B & bj; m; m &= m - 1) {  // same-spin spectators
-                                const int k = ctz64(m);
-                                if (P.b3) {
-                                    lds_add(&s1b3[(u * n + v) * n + k], x);
-                                } else {
-                                    add64(&r2[r2idx(n, u, v, k, k)], x);
-                                    add64(&r2[r2idx(n, u, k, k, v)], -x);
+    for (i64 ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        if (tid == 0) {
+            // bucket of this chunk: the last a with cptr[a] <= ch
+            u32 lo = 0, hi = (u32)nua - 1u;
+            while (lo < hi) {
+                const u32 mid = (lo + hi + 1u) >> 1;
+                if (cptr[mid] <= (u32)ch) lo = mid;
+                else hi = mid - 1u;
+            }
+            const u32 r0 = S.aoff[lo] + ((u32)ch - cptr[lo]) * RDM_CHUNK;
+            sh[0] = lo;
+            sh[1] = r0;
+            sh[2] = min(r0 + RDM_CHUNK, S.aoff[lo + 1]);
+        }
+        for (int x = (int)tid; x < P.total; x += RDM_BLOCK) lds[x] = 0.0;
+        __syncthreads();
+        const u32 a = sh[0], row0 = sh[1], row1 = sh[2];
+        const u64 A = S.ua[a];
+        const u64 E = ~A & low_mask(n);  // empty alpha orbitals
+        const u32 t0 = S.as_ptr[a];
+        const u32 deg = S.as_ptr[a + 1] - t0;
+        const int nocc = popc64(A), nvir = n - nocc;
+        const u32 ngroups = deg == 0 ? 1u : (deg + (u32)P.G - 1u) / (u32)P.G;
+        for (u32 gi = 0; gi < ngroups; ++gi) {
+            const u32 tg0 = gi * (u32)P.G;
+            const u32 tg1 = min(tg0 + (u32)P.G, deg);
+            if constexpr (BM) build_beta_maps<RDM_BLOCK>(S, t0, tg0, tg1, (u32)P.W, bm, pre, tid);
+            if (wave == 0 && gi == 0) {
+                // same-string classes, one row at a time
+                for (u32 row = row0; row < row1; ++row) {
+                    const double wb = bra[row];
+                    if (wb == 0.0) continue;  // wave-uniform
+                    const u64 B = S.beta[row];
+                    const u32 b = S.ib[row];
+                    {  // same alpha: beta single or double
+                        const u32 lo = S.aoff[a], hi = S.aoff[a + 1];
+                        for (u32 base = lo; base < hi; base += HCI_WAVE) {
+                            const u32 j = base + lane;
+                            if (j >= hi || j == row) continue;
+                            const u64 bj = S.beta[j];
+                            const u64 xb = B ^ bj;
+                            const int d = popc64(xb);
+                            if (d == 2) {
+                                const int v = ctz64(bj & xb), u = ctz64(B & xb);
+                                const double x = wb * ket[j] * sign_between(bj, v, u);
+                                own_add(&s1b2[u * n + v], x);
+                                for (u64 m = B & bj; m; m &= m - 1) {  // same-spin spectators
+                                    const int k = ctz64(m);
+                                    if (P.b3) {
+                                        own_add(&s1b3[(u * n + v) * n + k], x);
+                                    } else {
+                                        own_add(&r2[r2idx(n, u, v, k, k)], x);
+                                        own_add(&r2[r2idx(n, u, k, k, v)], -x);
+                                    }
                                 }
+                            } else if (d == 4) {
+                                u64 holes = bj & xb, parts = B & xb;
+                                const int v1 = ctz64(holes);
+                                holes &= holes - 1;
+                                const int v2 = ctz64(holes);
+                                const int u1 = ctz64(parts);
+                                parts &= parts - 1;
+                                const int u2 = ctz64(parts);
+                                const double x = wb * ket[j] * sign_double(bj, v1, u1, v2, u2);
+                                own_add(&r2[r2idx(n, u1, v1, u2, v2)], x);
+                                own_add(&r2[r2idx(n, u1, v2, u2, v1)], -x);
                             }
-                        } else if (d == 4) {
-                            u64 holes = bj & xb, parts = B & xb;
-                            const int v1 = ctz64(holes);
-                            holes &= holes - 1;
-                            const int v2 = ctz64(holes);
-                            const int u1 = ctz64(parts);
-                            parts &= parts - 1;
-                            const int u2 = ctz64(parts);
-                            const double x = wb * ket[j] * sign_double(bj, v1, u1, v2, u2);
-                            add64(&r2[r2idx(n, u1, v1, u2, v2)], x);
-                            add64(&r2[r2idx(n, u1, v2, u2, v1)], -x);
                         }
                     }
-                }
-                {  // same beta: alpha single (LDS per neighbour) or alpha double
-                    const u32 lo = S.boff[b], hi = S.boff[b + 1];
-                    for (u32 base = lo; base < hi; base += HCI_WAVE) {
-                        const u32 k = base + lane;
-                        if (k >= hi) continue;
-                        const u32 j = S.permb[k];
-                        if (j == row) continue;
-                        const u64 aj = S.alpha[j];
-                        const u64 xa = A ^ aj;
-                        const int d = popc64(xa);
-                        if (d == 2) {
-                            const int v = ctz64(aj & xa), u = ctz64(A & xa);
-                            const double x = wb * ket[j] * sign_between(aj, v, u);
-                            double* slot = s1a + (i64)(rank_below(A, u) * nvir + rank_below(E, v)) * (1 + n);
-                            lds_add(&slot[0], x);
-                            for (u64 m = B; m; m &= m - 1) lds_add(&slot[1 + ctz64(m)], x);
-                        } else if (d == 4) {
-                            u64 holes = aj & xa, parts = A & xa;
-                            const int v1 = ctz64(holes);
-                            holes &= holes - 1;
-                            const int v2 = ctz64(holes);
-                            const int u1 = ctz64(parts);
-                            parts &= parts - 1;
-                            const int u2 = ctz64(parts);
-                            const double x = wb * ket[j] * sign_double(aj, v1, u1, v2, u2);
-                            if (P.d2) {
-                                const int po = pair_index(rank_below(A, u1), rank_below(A, u2));
-                                const int pv = pair_index(rank_below(E, v1), rank_below(E, v2));
-                                lds_add(&d2a[po * P.npv + pv], x);
-                            } else {
-                                add64(&r2[r2idx(n, u1, v1, u2, v2)], x);
-                                add64(&r2[r2idx(n, u1, v2, u2, v1)], -x);
+                    {  // same beta: alpha single or double
+                        const u32 lo = S.boff[b], hi = S.boff[b + 1];
+                        for (u32 base = lo; base < hi; base += HCI_WAVE) {
+                            const u32 k = base + lane;
+                            if (k >= hi) continue;
+                            const u32 j = S.permb[k];
+                            if (j == row) continue;
+                            const u64 aj = S.alpha[j];
+                            const u64 xa = A ^ aj;
+                            const int d = popc64(xa);
+                            if (d == 2) {
+                                const int v = ctz64(aj & xa), u = ctz64(A & xa);
+                                const double x = wb * ket[j] * sign_between(aj, v, u);
+                                if (P.s1a) {
+                                    double* slot = s1a + (i64)(rank_below(A, u) * nvir + rank_below(E, v)) * (1 + n);
+                                    own_add(&slot[0], x);
+                                    for (u64 m = B; m; m &= m - 1) own_add(&slot[1 + ctz64(m)], x);
+                                } else {
+                                    own_add(&r1[u * n + v], x);
+                                    for (u64 m = A & aj; m; m &= m - 1) {  // same-spin spectators
+                                        const int kk = ctz64(m);
+                                        own_add(&r2[r2idx(n, u, v, kk, kk)], x);
+                                        own_add(&r2[r2idx(n, u, kk, kk, v)], -x);
+                                    }
+                                    for (u64 m = B; m; m &= m - 1) own_add(&r2[r2idx(n, u, v, ctz64(m), ctz64(m))], x);
+                                }
+                            } else if (d == 4) {
+                                u64 holes = aj & xa, parts = A & xa;
+                                const int v1 = ctz64(holes);
+                                holes &= holes - 1;
+                                const int v2 = ctz64(holes);
+                                const int u1 = ctz64(parts);
+                                parts &= parts - 1;
+                                const int u2 = ctz64(parts);
+                                const double x = wb * ket[j] * sign_double(aj, v1, u1, v2, u2);
+                                own_add(&r2[r2idx(n, u1, v1, u2, v2)], x);
+                                own_add(&r2[r2idx(n, u1, v2, u2, v1)], -x);
                             }
                         }
                     }
                 }
             }
-            // alpha single x beta single for neighbours [tg0, tg1)
-            const u32 s0 = S.bs_ptr[b], s1 = S.bs_ptr[b + 1];
-            const u32 nbs = s1 - s0;
-            if constexpr (BM) {
-                for (u32 base = s0; base < s1; base += HCI_WAVE) {
-                    const u32 k = base + lane;
-                    if (k >= s1) continue;
-                    const u32 bp = S.bs_idx[k];
-                    const u64 bj = S.ub[bp];
-                    const u64 xb = B ^ bj;
-                    const int v2 = ctz64(bj & xb), u2 = ctz64(B & xb);
-                    const double wsb = wb * sign_between(bj, v2, u2);
-                    const u32 w = bp >> 5, bit = bp & 31u;
-                    for (u32 t = tg0; t < tg1; ++t) {
-                        const u32 q = t - tg0;
-                        const u32 word = bm[q * (u32)P.W + w];
-                        if (((word >> bit) & 1u) == 0u) continue;
-                        const u32 a2 = S.as_idx[t0 + t];
-                        const u64 A2 = S.ua[a2];
-                        const u64 xa = A ^ A2;
-                        const double sa = sign_between(A2, ctz64(A2 & xa), ctz64(A & xa));
-                        const u32 j = S.aoff[a2] + (u32)pre[q * (u32)P.W + w] +
-                                      (u32)__popc(word & ((1u << bit) - 1u));
-                        lds_add(&p11[(i64)q * nn + u2 * n + v2], wsb * ket[j] * sa);
+            if (wave > 0) {
+                // alpha single x beta single for the neighbours of this group owned by this wavefront
+                for (u32 t = tg0 + (wave - 1u); t < tg1; t += RDM_WAVES - 1) {
+                    const u32 q = t - tg0;
+                    const u32 a2 = S.as_idx[t0 + t];
+                    const u64 A2 = S.ua[a2];
+                    const u64 xa = A ^ A2;
+                    const double sa = sign_between(A2, ctz64(A2 & xa), ctz64(A & xa));
+                    double* tile = p11 + (i64)q * nn;
+                    const u32 lo2 = S.aoff[a2], hi2 = S.aoff[a2 + 1];
+                    for (u32 row = row0; row < row1; ++row) {
+                        const double wb = bra[row];
+                        if (wb == 0.0) continue;  // wave-uniform
+                        const u64 B = S.beta[row];
+                        if constexpr (BM) {
+                            const u32 b = S.ib[row];
+                            const u32 s0 = S.bs_ptr[b], s1 = S.bs_ptr[b + 1];
+                            for (u32 base = s0; base < s1; base += HCI_WAVE) {
+                                const u32 k = base + lane;
+                                if (k >= s1) continue;
+                                const u32 bp = S.bs_idx[k];
+                                const u32 w = bp >> 5, bit = bp & 31u;
+                                const u32 word = bm[q * (u32)P.W + w];
+                                if (((word >> bit) & 1u) == 0u) continue;
+                                const u64 bj = S.ub[bp];
+                                const u64 xb = B ^ bj;
+                                const int v2 = ctz64(bj & xb), u2 = ctz64(B & xb);
+                                const u32 j = lo2 + (u32)pre[q * (u32)P.W + w] + (u32)__popc(word & ((1u << bit) - 1u));
+                                own_add(&tile[u2 * n + v2], wb * ket[j] * sa * sign_between(bj, v2, u2));
+                            }
+                        } else {
+                            for (u32 base = lo2; base < hi2; base += HCI_WAVE) {
+                                const u32 j = base + lane;
+                                if (j >= hi2) continue;
+                                const u64 bj = S.beta[j];
+                                const u64 xb = B ^ bj;
+                                if (popc64(xb) != 2) continue;
+                                const int v2 = ctz64(bj & xb), u2 = ctz64(B & xb);
+                                own_add(&tile[u2 * n + v2], wb * ket[j] * sa * sign_between(bj, v2, u2));
+                            }
+                        }
                     }
                 }
             }
-            for (u32 t = tg0; t < (BM ? tg0 : tg1); ++t) {
-                const u32 a2 = S.as_idx[t0 + t];
-                const u64 A2 = S.ua[a2];
+            __syncthreads();
+            // flush this group's tiles: neighbour q fixes (u1, v1)
+            for (int x = (int)tid; x < (int)(tg1 - tg0) * nn; x += RDM_BLOCK) {
+                const double val = p11[x];
+                if (val == 0.0) continue;
+                p11[x] = 0.0;
+                const u32 t = tg0 + (u32)(x / nn);
+                const int u2 = (x % nn) / n, v2 = x % n;
+                const u64 A2 = S.ua[S.as_idx[t0 + t]];
                 const u64 xa = A ^ A2;
-                const int v1 = ctz64(A2 & xa), u1 = ctz64(A & xa);
-                const double sa = sign_between(A2, v1, u1);
-                double* slot = p11 + (i64)(t - tg0) * nn;
-                const u32 lo = S.aoff[a2], hi = S.aoff[a2 + 1];
-                const u32 len = hi - lo;
-                if (len <= 4u * nbs) {
-                    for (u32 base = lo; base < hi; base += HCI_WAVE) {
-                        const u32 j = base + lane;
-                        if (j >= hi) continue;
-                        const u64 bj = S.beta[j];
-                        const u64 xb = B ^ bj;
-                        if (popc64(xb) != 2) continue;
-                        const int v2 = ctz64(bj & xb), u2 = ctz64(B & xb);
-                        lds_add(&slot[u2 * n + v2], wb * ket[j] * sa * sign_between(bj, v2, u2));
-                    }
-                } else {
-                    for (u32 base = s0; base < s1; base += HCI_WAVE) {
-                        const u32 k = base + lane;
-                        if (k >= s1) continue;
-                        const u64 bj = S.ub[S.bs_idx[k]];
-                        const u32 pos = lower_bound_u64(S.beta + lo, len, bj);
-                        if (pos >= len || S.beta[lo + pos] != bj) continue;
-                        const u32 j = lo + pos;
-                        const u64 xb = B ^ bj;
-                        const int v2 = ctz64(bj & xb), u2 = ctz64(B & xb);
-                        lds_add(&slot[u2 * n + v2], wb * ket[j] * sa * sign_between(bj, v2, u2));
+                own_add(&r2[r2idx(n, ctz64(A & xa), ctz64(A2 & xa), u2, v2)], val);
+            }
+            __syncthreads();
+        }
+        // alpha singles (slot of the occupied orbital u and the empty orbital v
+        // of A): rdm1 and same-spin spectators from the sum, opposite-spin
+        // spectators from the beta-occupation moments
+        if (P.s1a) {
+            for (int q = (int)tid; q < nocc * nvir; q += RDM_BLOCK) {
+                const int u = select_bit(A, q / nvir), v = select_bit(E, q % nvir);
+                const double* slot = s1a + (i64)q * (1 + n);
+                const double X = slot[0];
+                if (X != 0.0) {
+                    own_add(&r1[u * n + v], X);
+                    for (u64 m = A; m; m &= m - 1) {
+                        const int k = ctz64(m);
+                        if (k == u) continue;
+                        own_add(&r2[r2idx(n, u, v, k, k)], X);
+                        own_add(&r2[r2idx(n, u, k, k, v)], -X);
                     }
                 }
+                for (int k = 0; k < n; ++k) {
+                    const double Y = slot[1 + k];
+                    if (Y != 0.0) own_add(&r2[r2idx(n, u, v, k, k)], Y);
+                }
+            }
+            __syncthreads();
+        }
+        // beta singles: rdm1 and the alpha spectators from the sum
+        for (int x = (int)tid; x < nn; x += RDM_BLOCK) {
+            const double X = s1b2[x];
+            if (X == 0.0) continue;
+            const int u = x / n, v = x % n;
+            own_add(&r1[x], X);
+            for (u64 m = A; m; m &= m - 1) own_add(&r2[r2idx(n, u, v, ctz64(m), ctz64(m))], X);
+        }
+        __syncthreads();
+        if (P.b3) {
+            for (int x = (int)tid; x < nn * n; x += RDM_BLOCK) {
+                const double X = s1b3[x];
+                if (X == 0.0) continue;
+                const int u = x / nn, v = (x / n) % n, k = x % n;
+                own_add(&r2[r2idx(n, u, v, k, k)], X);
+                own_add(&r2[r2idx(n, u, k, k, v)], -X);
             }
         }
         __syncthreads();
-        // flush this group's alpha single x beta single slots
-        for (int x = (int)tid; x < (int)(tg1 - tg0) * nn; x += RDM_BLOCK) {
-            const double val = p11[x];
-            if (val == 0.0) continue;
-            p11[x] = 0.0;
-            const u32 t = tg0 + (u32)(x / nn);
-            const int u2 = (x % nn) / n, v2 = x % n;
-            const u64 A2 = S.ua[S.as_idx[t0 + t]];
-            const u64 xa = A ^ A2;
-            add64(&r2[r2idx(n, ctz64(A & xa), ctz64(A2 & xa), u2, v2)], val);
-        }
-        __syncthreads();
-    }
-    // alpha singles (slot of the occupied orbital u and the empty orbital v of
-    // A): r1 and same-spin spectators from the sum, opposite-spin spectators
-    // from the beta-occupation moments
-    for (int q = (int)tid; q < nocc * nvir; q += RDM_BLOCK) {
-        const int u = select_bit(A, q / nvir), v = select_bit(E, q % nvir);
-        const double* slot = s1a + (i64)q * (1 + n);
-        const double X = slot[0];
-        if (X != 0.0) {
-            add64(&r1[u * n + v], X);
-            for (u64 m = A; m; m &= m - 1) {
-                const int k = ctz64(m);
-                if (k == u) continue;
-                add64(&r2[r2idx(n, u, v, k, k)], X);
-                add64(&r2[r2idx(n, u, k, k, v)], -X);
-            }
-        }
-        for (int k = 0; k < n; ++k) {
-            const double Y = slot[1 + k];
-            if (Y != 0.0) add64(&r2[r2idx(n, u, v, k, k)], Y);
-        }
-    }
-    // beta singles: r1 and the alpha spectators from the sum
-    for (int x = (int)tid; x < nn; x += RDM_BLOCK) {
-        const double X = s1b2[x];
-        if (X == 0.0) continue;
-        const int u = x / n, v = x % n;
-        add64(&r1[x], X);
-        for (u64 m = A; m; m &= m - 1) add64(&r2[r2idx(n, u, v, ctz64(m), ctz64(m))], X);
-    }
-    if (P.b3) {
-        for (int x = (int)tid; x < nn * n; x += RDM_BLOCK) {
-            const double X = s1b3[x];
-            if (X == 0.0) continue;
-            const int u = x / nn, v = (x / n) % n, k = x % n;
-            add64(&r2[r2idx(n, u, v, k, k)], X);
-            add64(&r2[r2idx(n, u, k, k, v)], -X);
-        }
-    }
-    if (P.d2) {
-        for (int x = (int)tid; x < P.npo * P.npv; x += RDM_BLOCK) {
-            const double X = d2a[x];
-            if (X == 0.0) continue;
-            const int po = x / P.npv, pv = x % P.npv;
-            int y = 1;
-            while ((y + 1) * y / 2 <= po) ++y;
-            const int ru2 = y, ru1 = po - y * (y - 1) / 2;
-            y = 1;
-            while ((y + 1) * y / 2 <= pv) ++y;
-            const int rv2 = y, rv1 = pv - y * (y - 1) / 2;
-            const int u1 = select_bit(A, ru1), u2 = select_bit(A, ru2);
-            const int v1 = select_bit(E, rv1), v2 = select_bit(E, rv2);
-            add64(&r2[r2idx(n, u1, v1, u2, v2)], X);
-            add64(&r2[r2idx(n, u1, v2, u2, v1)], -X);
-        }
     }
 }
 
@@ -549,22 +504,33 @@ __global__ void rdm_nchunk_kernel(const u32* __restrict__ aoff, i64 nua, u32* __
     if (a == nua) out[a] = 0;
 }
 
-// LDS layout of the bucket kernel for this context, within `budget` bytes,
-// with W bitmap words per neighbour (0: no bitmaps); false when even one
-// alpha neighbour per pass does not fit.
+__global__ void rdm_zero_kernel(double* __restrict__ x, i64 m) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (i64)gridDim.x * blockDim.x) x[i] = 0.0;
+}
+
+// out[e] = sum over the P private copies of entry e, in copy order
+__global__ void rdm_sum_copies_kernel(const double* __restrict__ priv, int P, i64 stride, i64 m,
+                                      double* __restrict__ out) {
+    const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    double s = 0.0;
+    for (int p = 0; p < P; ++p) s += priv[(i64)p * stride + e];
+    out[e] = s;
+}
+
+// LDS layout of the kernel for this context within `budget` bytes, with W
+// bitmap words per neighbour (0: scan the neighbour buckets); false when even
+// one neighbour tile per group does not fit.
 bool rdm_plan(int n, int na, int budget, int W, RdmPlan& P) {
     const int dmax = na * (n - na);
     const int nn = n * n;
     P.n = n;
-    P.npo = na * (na - 1) / 2;
-    P.npv = (n - na) * (n - na - 1) / 2;
     for (int variant = 0; variant < 3; ++variant) {
+        P.s1a = variant <= 1;
         P.b3 = variant == 0;
-        P.d2 = variant <= 1;
-        const int s1a = dmax * (1 + n);
+        const int s1a = P.s1a ? dmax * (1 + n) : 0;
         const int s1b3 = P.b3 ? nn * n : 0;
-        const int d2 = P.d2 ? P.npo * P.npv : 0;
-        const int rest = s1a + nn + s1b3 + d2;
+        const int rest = s1a + nn + s1b3;
         int G = (budget - 8 * rest) / (8 * nn + 6 * W);
         if (G < 1) continue;
         if (G > dmax) G = dmax > 0 ? dmax : 1;
@@ -573,8 +539,7 @@ bool rdm_plan(int n, int na, int budget, int W, RdmPlan& P) {
         P.o_s1a = G * nn;
         P.o_s1b2 = P.o_s1a + s1a;
         P.o_s1b3 = P.o_s1b2 + nn;
-        P.o_d2a = P.o_s1b3 + s1b3;
-        P.total = P.o_d2a + d2;
+        P.total = P.o_s1b3 + s1b3;
         P.W = W;
         P.o_bm = 8 * P.total;
         P.bytes = P.o_bm + ((6 * G * W + 15) & ~15);
@@ -608,41 +573,47 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
                  double* rdm2, hipStream_t s) {
     const int n = ctx->n;
     const i64 N = sp->N;
-    const i64 n2 = (i64)n * n;
-    HIP_CHECK(hipMemsetAsync(rdm1, 0, sizeof(double) * n2, s));
-    if (rdm2) HIP_CHECK(hipMemsetAsync(rdm2, 0, sizeof(double) * n2 * n2, s));
+    const i64 n2 = (i64)n * n, n4 = n2 * n2;
     SpaceView S = space_view(*sp, n);
-    // two workgroups per CU: up to 79 KB of LDS each
     int dev = 0, max_shared = 0;
     HIP_CHECK(hipGetDevice(&dev));
     HIP_CHECK(hipDeviceGetAttribute(&max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const int budget = std::min(79 * 1024, max_shared);
+    const int budget = std::min(79 * 1024, max_shared);  // two workgroups per CU
     const char* force_search = std::getenv("HCI_AB_SEARCH");  // "1": always search (tests)
     const int W = sp->nub <= 65535 && !(force_search && force_search[0] == '1') ? (int)ceil_div(sp->nub, 32) : 0;
     RdmPlan P;
-    bool planned = false;
-    if (rdm2) planned = (W > 0 && rdm_plan(n, ctx->na, budget, W, P)) || rdm_plan(n, ctx->na, budget, 0, P);
-    if (planned) {
-        if (!sp->rdm_cptr.ptr) {
-            DevMem cnt = dev_alloc(ctx, sizeof(u32) * (sp->nua + 1), s);
-            HCI_LAUNCH(ctx, "rdm_nchunk", s, rdm_nchunk_kernel, ceil_div(sp->nua + 1, 256), 256, 0,
-                       sp->aoff.as<u32>(), sp->nua, cnt.as<u32>());
-            sp->rdm_cptr = dev_alloc(ctx, sizeof(u32) * (sp->nua + 1), s);
-            scan_u32_to_u32(ctx, cnt.as<u32>(), sp->rdm_cptr.as<u32>(), sp->nua + 1, s);
-            sp->rdm_nchunk = read_scalar(sp->rdm_cptr.as<u32>() + sp->nua, s);
-        }
-        auto kern = P.W ? rdm_bucket_kernel<true> : rdm_bucket_kernel<false>;
-        HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, P.bytes));
-        HCI_LAUNCH(ctx, "rdm_offdiag", s, kern, sp->rdm_nchunk, RDM_BLOCK, (size_t)P.bytes, S, P, sp->nua,
-                   sp->rdm_cptr.as<u32>(), bra, ket, rdm1, rdm2);
-    } else {
-        HCI_LAUNCH(ctx, "rdm_offdiag", s, rdm_offdiag_kernel, ceil_div(N, ROWS_PER_BLOCK), ROW_BLOCK,
-                   0, S, bra, ket, rdm1, rdm2);
+    const bool planned = (W > 0 && rdm_plan(n, ctx->na, budget, W, P)) || rdm_plan(n, ctx->na, budget, 0, P);
+    HCI_REQUIRE(planned, HCI_E_UNSUPPORTED, "density matrices: no on-chip plan fits this orbital count");
+    if (!sp->rdm_cptr.ptr) {
+        DevMem cnt = dev_alloc(ctx, sizeof(u32) * (sp->nua + 1), s);
+        HCI_LAUNCH(ctx, "rdm_nchunk", s, rdm_nchunk_kernel, ceil_div(sp->nua + 1, 256), 256, 0, sp->aoff.as<u32>(),
+                   sp->nua, cnt.as<u32>());
+        sp->rdm_cptr = dev_alloc(ctx, sizeof(u32) * (sp->nua + 1), s);
+        scan_u32_to_u32(ctx, cnt.as<u32>(), sp->rdm_cptr.as<u32>(), sp->nua + 1, s);
+        sp->rdm_nchunk = read_scalar(sp->rdm_cptr.as<u32>() + sp->nua, s);
     }
-    // the off-diagonal passes accumulate one entry of each (pq|rs), (rs|pq) pair
+    // private copies of T and rdm1, one per workgroup of the persistent grid:
+    // two workgroups per CU, within 8 GiB of copies
+    int cus = 0;
+    HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const i64 stride = n4 + n2;
+    const i64 by_mem = std::max<i64>(1, ((i64)8 << 30) / (stride * (i64)sizeof(double)));
+    const i64 Pw = std::max<i64>(1, std::min<i64>({(i64)2 * cus, by_mem, sp->rdm_nchunk}));
+    DevMem priv = dev_alloc(ctx, sizeof(double) * Pw * stride, s);
+    HCI_LAUNCH(ctx, "rdm_zero", s, rdm_zero_kernel, std::min<i64>(ceil_div(Pw * stride, 256), 65536), 256, 0,
+               priv.as<double>(), Pw * stride);
+    auto kern = P.W ? rdm_det_kernel<true> : rdm_det_kernel<false>;
+    HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  P.bytes));
+    HCI_LAUNCH(ctx, "rdm_offdiag", s, kern, Pw, RDM_BLOCK, (size_t)P.bytes, S, P, sp->nua, sp->rdm_nchunk,
+               sp->rdm_cptr.as<u32>(), bra, ket, priv.as<double>());
+    HCI_LAUNCH(ctx, "rdm_sum", s, rdm_sum_copies_kernel, ceil_div(n2, 256), 256, 0, priv.as<double>() + n4, (int)Pw,
+               stride, n2, rdm1);
     if (rdm2) {
-        HCI_LAUNCH(ctx, "rdm_swap_sym", s, swap_sym_kernel, ceil_div(n2 * n2, 256), 256, 0, rdm2, n);
+        HCI_LAUNCH(ctx, "rdm_sum", s, rdm_sum_copies_kernel, ceil_div(n4, 256), 256, 0, priv.as<double>(), (int)Pw,
+                   stride, n4, rdm2);
+        // the off-diagonal pass accumulates one entry of each (pq|rs), (rs|pq) pair
+        HCI_LAUNCH(ctx, "rdm_swap_sym", s, swap_sym_kernel, ceil_div(n4, 256), 256, 0, rdm2, n);
     }
     rdm_add_diag(ctx, sp->alpha.as<u64>(), sp->beta.as<u64>(), bra, ket, N, rdm1, rdm2, s);
 }

@@ -323,7 +323,7 @@ def test_stored_layout_beta_maps_match_search(lib_mod, monkeypatch, space, wlog)
         # (lookup), connections met in another order, so rounding only
         for path in ["maps", "search", "lookup"]:
             assert rel_err(outs[path, "rc", prec], ref) < tol, (path, prec)
-    # density matrices: same pairs, float64 atomics in another order
+    # density matrices: same pairs, met in another order (bitmap lookup or bucket scan)
     for k in range(2):
         a, b = outs["maps", "rdm"][k], outs["search", "rdm"][k]
         assert np.abs(a - b).max() <= 1e-12 * max(1.0, np.abs(b).max()), k

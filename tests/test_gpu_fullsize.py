@@ -124,6 +124,22 @@ def test_full_size_energy_and_rdms_against_oracle(P, cas16_v2, precision):
     assert abs(e_rdm - e) <= 1e-7
 
 
+def test_rdm_bitwise_reproducible_full_size(P, cas16_v2):
+    """The density matrices are accumulated without atomics (owners per
+    chunk, private copies per workgroup, fixed-order sums), so two runs on the
+    full space give the same bytes; so do two contexts."""
+    h, g, V1, c1, e1, V2 = cas16_v2
+    c = hs.random_coeffs(len(V2), 41)
+    outs = []
+    for k in range(3):
+        ctx = P.HCIContext(h, g, 8, 8)
+        for _ in range(1 if k < 2 else 2):
+            r1, r2 = ctx.rdm12(V2, c)
+        outs.append((r1.cpu().numpy().tobytes(), r2.cpu().numpy().tobytes()))
+        ctx.close()
+    assert outs[0] == outs[1] == outs[2]
+
+
 def test_pt2_sampled_batches_full_size(P, cas16_v2):
     """Sampled second-order estimates (eq. semistoc) on the full space: every
     batch against the oracle on the same draws (a seeded coefficient vector,
