@@ -222,6 +222,7 @@ struct Space {
     i64 rc_nch_a = 0, rc_nch_b = 0;
     i64 rc_maxdeg = 0;    // largest alpha-single degree of a unique alpha string
     DevMem rdm_cptr;      // u32 [nua + 1]: first workgroup of each bucket (density matrices)
+    DevMem alpha_b;       // u64 [N]: alpha word of each beta-major position (density matrices)
     i64 rdm_nchunk = 0;
     bool st_have32 = false, st_have64 = false;
 };

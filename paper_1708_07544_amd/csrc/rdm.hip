@@ -222,20 +222,22 @@ __global__ void swap_sym_kernel(double* __restrict__ r2, int n) {
 // canonical half T of rdm2 (one entry of each (pq|rs), (rs|pq) pair, see
 // single_contrib) and rdm1; the P copies are then summed in a fixed order.
 // Inside a workgroup every accumulator has one writer at a time:
-//   * wavefront 0 takes the chunk's rows one after another and finds their
-//     same-alpha connections (beta single or double: the rows of bucket A)
-//     and same-beta connections (alpha single or double: the rows of the
-//     row's beta bucket).  One row's contributions fall on distinct entries
-//     (distinct excitations), so each lane adds to its own: beta singles
+//   * the chunk's rows are taken one after another for their same-alpha
+//     connections (beta single or double: the rows of bucket A) and then
+//     their same-beta connections (alpha single or double: the rows of the
+//     row's beta bucket), each row's candidates spread over all threads of
+//     the workgroup, with a barrier between the two classes and after each
+//     row.  One row's contributions of one class fall on distinct entries
+//     (distinct excitations), so each thread adds to its own: beta singles
 //     into the chunk's LDS sums [u][v] (and [u][v][k] for the same-spin
 //     spectators when they fit), alpha singles into one LDS slot per alpha
 //     neighbour of A with the beta-occupation moments (when they fit), the
 //     rest straight into the private copy;
-//   * wavefronts 1.. own the alpha neighbours A' of A (neighbour q goes to
-//     wavefront 1 + q mod (waves - 1)) and accumulate the alpha single x beta
-//     single pairs of every row of the chunk with A' in an LDS tile [u2][v2]
-//     per neighbour, found through bitmaps of the beta strings present in
-//     each neighbour bucket (build_beta_maps) or by scanning the bucket;
+//   * then the wavefronts own the alpha neighbours A' of A (neighbour q goes
+//     to wavefront q mod waves) and accumulate the alpha single x beta single
+//     pairs of every row of the chunk with A' in an LDS tile [u2][v2] per
+//     neighbour, found through bitmaps of the beta strings present in each
+//     neighbour bucket (build_beta_maps) or by scanning the bucket;
 //   * the LDS sums reach the private copy class by class, separated by
 //     barriers (different classes can share an entry of the spin-traced
 //     output).
@@ -244,7 +246,8 @@ constexpr int RDM_WAVES = RDM_BLOCK / HCI_WAVE;
 constexpr u32 RDM_CHUNK = 1024;
 
 struct RdmPlan {
-    int n, G;
+    int n, G;               // G: alpha neighbours per group (bitmaps and tiles rebuilt per group)
+    bool tile;              // alpha single x beta single tiles in LDS (else straight into the copy)
     bool s1a, b3;           // alpha-single slots / beta-single spectator block in LDS
     int o_p11, o_s1a, o_s1b2, o_s1b3, total;  // offsets in doubles
     int W;                  // beta-string bitmap words per neighbour (0: scan the buckets)
@@ -266,6 +269,8 @@ __global__ void __launch_bounds__(RDM_BLOCK) rdm_det_kernel(SpaceView S, RdmPlan
                                                             const u32* __restrict__ cptr,
                                                             const double* __restrict__ bra,
                                                             const double* __restrict__ ket,
+                                                            const u64* __restrict__ alpha_b,
+                                                            const double* __restrict__ ket_b,
                                                             double* __restrict__ priv) {
     extern __shared__ double lds[];
     __shared__ u32 sh[3];
@@ -305,104 +310,104 @@ __global__ void __launch_bounds__(RDM_BLOCK) rdm_det_kernel(SpaceView S, RdmPlan
         const u32 t0 = S.as_ptr[a];
         const u32 deg = S.as_ptr[a + 1] - t0;
         const int nocc = popc64(A), nvir = n - nocc;
+        // same-string classes: one row at a time, its candidates spread over
+        // the whole workgroup (one row's contributions fall on distinct entries)
+        for (u32 row = row0; row < row1; ++row) {
+            const double wb = bra[row];
+            if (wb == 0.0) continue;  // wave-uniform
+            const u64 B = S.beta[row];
+            const u32 b = S.ib[row];
+            {  // same alpha: beta single or double
+                const u32 lo = S.aoff[a], hi = S.aoff[a + 1];
+                for (u32 j = lo + tid; j < hi; j += RDM_BLOCK) {
+                    const u64 bj = S.beta[j];
+                    const double kj = ket[j];
+                    const u64 xb = B ^ bj;  // 0 for the row itself
+                    const int d = popc64(xb);
+                    if (d == 2) {
+                        const int v = ctz64(bj & xb), u = ctz64(B & xb);
+                        const double x = wb * kj * sign_between(bj, v, u);
+                        own_add(&s1b2[u * n + v], x);
+                        for (u64 m = B & bj; m; m &= m - 1) {  // same-spin spectators
+                            const int k = ctz64(m);
+                            if (P.b3) {
+                                own_add(&s1b3[(u * n + v) * n + k], x);
+                            } else {
+                                own_add(&r2[r2idx(n, u, v, k, k)], x);
+                                own_add(&r2[r2idx(n, u, k, k, v)], -x);
+                            }
+                        }
+                    } else if (d == 4) {
+                        u64 holes = bj & xb, parts = B & xb;
+                        const int v1 = ctz64(holes);
+                        holes &= holes - 1;
+                        const int v2 = ctz64(holes);
+                        const int u1 = ctz64(parts);
+                        parts &= parts - 1;
+                        const int u2 = ctz64(parts);
+                        const double x = wb * kj * sign_double(bj, v1, u1, v2, u2);
+                        own_add(&r2[r2idx(n, u1, v1, u2, v2)], x);
+                        own_add(&r2[r2idx(n, u1, v2, u2, v1)], -x);
+                    }
+                }
+            }
+            __syncthreads();  // alpha and beta classes can meet on an entry
+            {  // same beta: alpha single or double
+                const u32 lo = S.boff[b], hi = S.boff[b + 1];
+                for (u32 k = lo + tid; k < hi; k += RDM_BLOCK) {
+                    // beta-major copies: the candidate's alpha word and ket coefficient
+                    const u64 aj = alpha_b[k];
+                    const double kj = ket_b[k];
+                    const u64 xa = A ^ aj;  // 0 for the row itself
+                    const int d = popc64(xa);
+                    if (d == 2) {
+                        const int v = ctz64(aj & xa), u = ctz64(A & xa);
+                        const double x = wb * kj * sign_between(aj, v, u);
+                        if (P.s1a) {
+                            double* slot = s1a + (i64)(rank_below(A, u) * nvir + rank_below(E, v)) * (1 + n);
+                            own_add(&slot[0], x);
+                            for (u64 m = B; m; m &= m - 1) own_add(&slot[1 + ctz64(m)], x);
+                        } else {
+                            own_add(&r1[u * n + v], x);
+                            for (u64 m = A & aj; m; m &= m - 1) {  // same-spin spectators
+                                const int kk = ctz64(m);
+                                own_add(&r2[r2idx(n, u, v, kk, kk)], x);
+                                own_add(&r2[r2idx(n, u, kk, kk, v)], -x);
+                            }
+                            for (u64 m = B; m; m &= m - 1) own_add(&r2[r2idx(n, u, v, ctz64(m), ctz64(m))], x);
+                        }
+                    } else if (d == 4) {
+                        u64 holes = aj & xa, parts = A & xa;
+                        const int v1 = ctz64(holes);
+                        holes &= holes - 1;
+                        const int v2 = ctz64(holes);
+                        const int u1 = ctz64(parts);
+                        parts &= parts - 1;
+                        const int u2 = ctz64(parts);
+                        const double x = wb * kj * sign_double(aj, v1, u1, v2, u2);
+                        own_add(&r2[r2idx(n, u1, v1, u2, v2)], x);
+                        own_add(&r2[r2idx(n, u1, v2, u2, v1)], -x);
+                    }
+                }
+            }
+            __syncthreads();  // the next row may add to the same entries
+        }
         const u32 ngroups = deg == 0 ? 1u : (deg + (u32)P.G - 1u) / (u32)P.G;
         for (u32 gi = 0; gi < ngroups; ++gi) {
             const u32 tg0 = gi * (u32)P.G;
             const u32 tg1 = min(tg0 + (u32)P.G, deg);
             if constexpr (BM) build_beta_maps<RDM_BLOCK>(S, t0, tg0, tg1, (u32)P.W, bm, pre, tid);
-            if (wave == 0 && gi == 0) {
-                // same-string classes, one row at a time
-                for (u32 row = row0; row < row1; ++row) {
-                    const double wb = bra[row];
-                    if (wb == 0.0) continue;  // wave-uniform
-                    const u64 B = S.beta[row];
-                    const u32 b = S.ib[row];
-                    {  // same alpha: beta single or double
-                        const u32 lo = S.aoff[a], hi = S.aoff[a + 1];
-                        for (u32 base = lo; base < hi; base += HCI_WAVE) {
-                            const u32 j = base + lane;
-                            if (j >= hi || j == row) continue;
-                            const u64 bj = S.beta[j];
-                            const u64 xb = B ^ bj;
-                            const int d = popc64(xb);
-                            if (d == 2) {
-                                const int v = ctz64(bj & xb), u = ctz64(B & xb);
-                                const double x = wb * ket[j] * sign_between(bj, v, u);
-                                own_add(&s1b2[u * n + v], x);
-                                for (u64 m = B & bj; m; m &= m - 1) {  // same-spin spectators
-                                    const int k = ctz64(m);
-                                    if (P.b3) {
-                                        own_add(&s1b3[(u * n + v) * n + k], x);
-                                    } else {
-                                        own_add(&r2[r2idx(n, u, v, k, k)], x);
-                                        own_add(&r2[r2idx(n, u, k, k, v)], -x);
-                                    }
-                                }
-                            } else if (d == 4) {
-                                u64 holes = bj & xb, parts = B & xb;
-                                const int v1 = ctz64(holes);
-                                holes &= holes - 1;
-                                const int v2 = ctz64(holes);
-                                const int u1 = ctz64(parts);
-                                parts &= parts - 1;
-                                const int u2 = ctz64(parts);
-                                const double x = wb * ket[j] * sign_double(bj, v1, u1, v2, u2);
-                                own_add(&r2[r2idx(n, u1, v1, u2, v2)], x);
-                                own_add(&r2[r2idx(n, u1, v2, u2, v1)], -x);
-                            }
-                        }
-                    }
-                    {  // same beta: alpha single or double
-                        const u32 lo = S.boff[b], hi = S.boff[b + 1];
-                        for (u32 base = lo; base < hi; base += HCI_WAVE) {
-                            const u32 k = base + lane;
-                            if (k >= hi) continue;
-                            const u32 j = S.permb[k];
-                            if (j == row) continue;
-                            const u64 aj = S.alpha[j];
-                            const u64 xa = A ^ aj;
-                            const int d = popc64(xa);
-                            if (d == 2) {
-                                const int v = ctz64(aj & xa), u = ctz64(A & xa);
-                                const double x = wb * ket[j] * sign_between(aj, v, u);
-                                if (P.s1a) {
-                                    double* slot = s1a + (i64)(rank_below(A, u) * nvir + rank_below(E, v)) * (1 + n);
-                                    own_add(&slot[0], x);
-                                    for (u64 m = B; m; m &= m - 1) own_add(&slot[1 + ctz64(m)], x);
-                                } else {
-                                    own_add(&r1[u * n + v], x);
-                                    for (u64 m = A & aj; m; m &= m - 1) {  // same-spin spectators
-                                        const int kk = ctz64(m);
-                                        own_add(&r2[r2idx(n, u, v, kk, kk)], x);
-                                        own_add(&r2[r2idx(n, u, kk, kk, v)], -x);
-                                    }
-                                    for (u64 m = B; m; m &= m - 1) own_add(&r2[r2idx(n, u, v, ctz64(m), ctz64(m))], x);
-                                }
-                            } else if (d == 4) {
-                                u64 holes = aj & xa, parts = A & xa;
-                                const int v1 = ctz64(holes);
-                                holes &= holes - 1;
-                                const int v2 = ctz64(holes);
-                                const int u1 = ctz64(parts);
-                                parts &= parts - 1;
-                                const int u2 = ctz64(parts);
-                                const double x = wb * ket[j] * sign_double(aj, v1, u1, v2, u2);
-                                own_add(&r2[r2idx(n, u1, v1, u2, v2)], x);
-                                own_add(&r2[r2idx(n, u1, v2, u2, v1)], -x);
-                            }
-                        }
-                    }
-                }
-            }
-            if (wave > 0) {
+            {
                 // alpha single x beta single for the neighbours of this group owned by this wavefront
-                for (u32 t = tg0 + (wave - 1u); t < tg1; t += RDM_WAVES - 1) {
+                for (u32 t = tg0 + wave; t < tg1; t += RDM_WAVES) {
                     const u32 q = t - tg0;
                     const u32 a2 = S.as_idx[t0 + t];
                     const u64 A2 = S.ua[a2];
                     const u64 xa = A ^ A2;
-                    const double sa = sign_between(A2, ctz64(A2 & xa), ctz64(A & xa));
-                    double* tile = p11 + (i64)q * nn;
+                    const int u1 = ctz64(A & xa), v1 = ctz64(A2 & xa);
+                    const double sa = sign_between(A2, v1, u1);
+                    // the tile [u2][v2] of this neighbour: in LDS, or its entries of the copy
+                    double* tile = P.tile ? p11 + (i64)q * nn : r2 + r2idx(n, u1, v1, 0, 0);
                     const u32 lo2 = S.aoff[a2], hi2 = S.aoff[a2 + 1];
                     for (u32 row = row0; row < row1; ++row) {
                         const double wb = bra[row];
@@ -440,7 +445,7 @@ __global__ void __launch_bounds__(RDM_BLOCK) rdm_det_kernel(SpaceView S, RdmPlan
             }
             __syncthreads();
             // flush this group's tiles: neighbour q fixes (u1, v1)
-            for (int x = (int)tid; x < (int)(tg1 - tg0) * nn; x += RDM_BLOCK) {
+            for (int x = (int)tid; P.tile && x < (int)(tg1 - tg0) * nn; x += RDM_BLOCK) {
                 const double val = p11[x];
                 if (val == 0.0) continue;
                 p11[x] = 0.0;
@@ -504,6 +509,14 @@ __global__ void rdm_nchunk_kernel(const u32* __restrict__ aoff, i64 nua, u32* __
     if (a == nua) out[a] = 0;
 }
 
+// beta-major copies: out[k] = in[permb[k]]
+template <class T>
+__global__ void rdm_permute_kernel(const T* __restrict__ in, const u32* __restrict__ permb, i64 N,
+                                   T* __restrict__ out) {
+    const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < N) out[k] = in[permb[k]];
+}
+
 __global__ void rdm_zero_kernel(double* __restrict__ x, i64 m) {
     for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (i64)gridDim.x * blockDim.x) x[i] = 0.0;
 }
@@ -519,32 +532,47 @@ __global__ void rdm_sum_copies_kernel(const double* __restrict__ priv, int P, i6
 }
 
 // LDS layout of the kernel for this context within `budget` bytes, with W
-// bitmap words per neighbour (0: scan the neighbour buckets); false when even
-// one neighbour tile per group does not fit.
+// bitmap words per neighbour (0: scan the neighbour buckets).  Neighbour
+// groups should keep every wavefront busy (G >= RDM_WAVES): the tiles stay
+// in LDS only when they allow that, else they go straight into the private
+// copy (each entry still has one owner, the neighbour's wavefront); bitmaps
+// only when at least RDM_WAVES of them fit (else the buckets are scanned and
+// one group holds every neighbour).  False when W > 0 and the bitmaps do not
+// fit (the caller retries with W = 0).
 bool rdm_plan(int n, int na, int budget, int W, RdmPlan& P) {
     const int dmax = na * (n - na);
     const int nn = n * n;
     P.n = n;
-    for (int variant = 0; variant < 3; ++variant) {
-        P.s1a = variant <= 1;
-        P.b3 = variant == 0;
-        const int s1a = P.s1a ? dmax * (1 + n) : 0;
-        const int s1b3 = P.b3 ? nn * n : 0;
+    P.W = W;
+    int want = std::min(RDM_WAVES / 2, std::max(dmax, 1));
+    if (const char* e = std::getenv("HCI_RDM_GROUP_MIN")) {  // smallest acceptable group (tuning)
+        const int k = std::atoi(e);
+        if (k >= 1) want = std::min(k, std::max(dmax, 1));
+    }
+    auto place = [&](bool tile, bool s1a_lds, bool b3) -> bool {
+        const int s1a = s1a_lds ? dmax * (1 + n) : 0;
+        const int s1b3 = b3 ? nn * n : 0;
         const int rest = s1a + nn + s1b3;
-        int G = (budget - 8 * rest) / (8 * nn + 6 * W);
-        if (G < 1) continue;
+        const int per = (tile ? 8 * nn : 0) + 6 * W;
+        int G = per > 0 ? (budget - 8 * rest) / per : (1 << 20);
+        if (G < want) return false;
         if (G > dmax) G = dmax > 0 ? dmax : 1;
         P.G = G;
+        P.tile = tile;
+        P.s1a = s1a_lds;
+        P.b3 = b3;
         P.o_p11 = 0;
-        P.o_s1a = G * nn;
+        P.o_s1a = tile ? G * nn : 0;
         P.o_s1b2 = P.o_s1a + s1a;
         P.o_s1b3 = P.o_s1b2 + nn;
         P.total = P.o_s1b3 + s1b3;
-        P.W = W;
         P.o_bm = 8 * P.total;
         P.bytes = P.o_bm + ((6 * G * W + 15) & ~15);
-        return true;
-    }
+        return 8 * rest <= budget;
+    };
+    for (int tile = 1; tile >= 0; --tile)
+        for (int variant = 0; variant < 3; ++variant)
+            if (place(tile != 0, variant <= 1, variant == 0)) return true;
     return false;
 }
 
@@ -599,6 +627,14 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
     const i64 stride = n4 + n2;
     const i64 by_mem = std::max<i64>(1, ((i64)8 << 30) / (stride * (i64)sizeof(double)));
     const i64 Pw = std::max<i64>(1, std::min<i64>({(i64)2 * cus, by_mem, sp->rdm_nchunk}));
+    if (!sp->alpha_b.ptr) {  // alpha word of each beta-major position (cached with the space)
+        sp->alpha_b = dev_alloc(ctx, sizeof(u64) * N, s);
+        HCI_LAUNCH(ctx, "rdm_permute", s, rdm_permute_kernel<u64>, ceil_div(N, 256), 256, 0, sp->alpha.as<u64>(),
+                   sp->permb.as<u32>(), N, sp->alpha_b.as<u64>());
+    }
+    DevMem ket_b = dev_alloc(ctx, sizeof(double) * N, s);
+    HCI_LAUNCH(ctx, "rdm_permute", s, rdm_permute_kernel<double>, ceil_div(N, 256), 256, 0, ket, sp->permb.as<u32>(),
+               N, ket_b.as<double>());
     DevMem priv = dev_alloc(ctx, sizeof(double) * Pw * stride, s);
     HCI_LAUNCH(ctx, "rdm_zero", s, rdm_zero_kernel, std::min<i64>(ceil_div(Pw * stride, 256), 65536), 256, 0,
                priv.as<double>(), Pw * stride);
@@ -606,7 +642,7 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
     HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   P.bytes));
     HCI_LAUNCH(ctx, "rdm_offdiag", s, kern, Pw, RDM_BLOCK, (size_t)P.bytes, S, P, sp->nua, sp->rdm_nchunk,
-               sp->rdm_cptr.as<u32>(), bra, ket, priv.as<double>());
+               sp->rdm_cptr.as<u32>(), bra, ket, sp->alpha_b.as<u64>(), ket_b.as<double>(), priv.as<double>());
     HCI_LAUNCH(ctx, "rdm_sum", s, rdm_sum_copies_kernel, ceil_div(n2, 256), 256, 0, priv.as<double>() + n4, (int)Pw,
                stride, n2, rdm1);
     if (rdm2) {
