@@ -236,7 +236,10 @@ int hci_diagonal(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* hdiag
  * <Psi|H|Psi> - E(<Psi|Psi> - 1) over the coefficients (eq. variational).
  *   c_inout: device float64 [n_var], the start vector (need not be
  *   normalised; a zero vector selects the lowest-diagonal determinant); on
- *   return the normalised eigenvector with its largest-magnitude entry > 0.
+ *   return the normalised eigenvector, signed so that its first entry whose
+ *   magnitude is within 1e-6 (relative) of the largest is > 0 (entries
+ *   equal by symmetry tie whatever rounding the solve leaves in them, so
+ *   the sign does not depend on rounding).
  *   e_out (host): eigenvalue + ecore.  tol: float64 residual norm
  *   ||H c - E c|| at which to stop.  precision HCI_FP32_MIXED iterates with
  *   the mixed product, then refines with float64 products until the float64
@@ -267,7 +270,7 @@ int hci_davidson(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* c_ino
  *   (a zero row, or one inside the span of the earlier states, selects the
  *   lowest-diagonal determinant that the earlier states hold less than half
  *   of); on return the orthonormal eigenvectors, each with its
- *   largest-magnitude entry > 0.  e_out: host float64 [nroots], eigenvalues
+ *   sign fixed as in hci_davidson.  e_out: host float64 [nroots], eigenvalues
  *   + ecore.  iters_out: host int [nroots] (may be NULL), products per
  *   state.  1 <= nroots <= min(HCI_MAX_ROOTS, n_var).  tol, max_iter (per
  *   state), precision and mode as in hci_davidson.  HCI_E_NOCONV when some

@@ -375,8 +375,16 @@ def spin_square(V, c) -> float:
     return sz * (sz + 1.0) + float(amp @ amp) / norm2
 
 
+SIGN_TIE = 1e-6
+
+
 def _fix_sign(c):
-    k = int(np.argmax(np.abs(c)))
+    """Sign convention of the eigenvectors (a reading: the paper fixes none):
+    the first entry whose magnitude is within SIGN_TIE (relative) of the
+    largest is positive, so entries equal by symmetry tie whatever rounding
+    a solver leaves in them."""
+    a = np.abs(c)
+    k = int(np.flatnonzero(a >= a.max() * (1.0 - SIGN_TIE))[0])
     return -c if c[k] < 0 else c
 
 

@@ -424,58 +424,69 @@ __global__ void generic_start_kernel(double* __restrict__ x, i64 N, const double
     x[i] += delta * z;
 }
 
-// sign convention: largest-|c| entry positive (first index on ties)
-// Sign convention: the entry of largest magnitude (first index on ties) is
-// made positive.  Block partials of (|x_i|, i), a one-block decision, then a
-// grid-wide multiply by +-1.
-__device__ __forceinline__ void absmax_merge(double& v, i64& idx, double ov, i64 oi) {
-    if (ov > v || (ov == v && oi < idx)) {
-        v = ov;
-        idx = oi;
-    }
-}
+// Sign convention: the first entry whose magnitude is within SIGN_TIE
+// (relative) of the largest is made positive.  Entries equal in exact
+// arithmetic (symmetry-related determinants) come out of a converged solve
+// equal only to about the solve's accuracy, so the band is wide enough that
+// they tie and the sign does not depend on rounding.  Block partials of
+// max |x_i|, a one-block maximum, block partials of the first index inside
+// the band, a one-block decision, then a grid-wide multiply by +-1.
+constexpr double SIGN_TIE = 1e-6;
 
 __global__ void __launch_bounds__(256) absmax_partial_kernel(const double* __restrict__ x, i64 N,
-                                                             double* __restrict__ pv,
-                                                             i64* __restrict__ pi) {
+                                                             double* __restrict__ pv) {
     __shared__ double bv[256];
-    __shared__ i64 bi[256];
-    double v = -1.0;
-    i64 idx = 0;
-    for (i64 i = (i64)blockIdx.x * 256 + threadIdx.x; i < N; i += (i64)gridDim.x * 256)
-        absmax_merge(v, idx, fabs(x[i]), i);
+    double v = 0.0;
+    for (i64 i = (i64)blockIdx.x * 256 + threadIdx.x; i < N; i += (i64)gridDim.x * 256) v = fmax(v, fabs(x[i]));
     bv[threadIdx.x] = v;
-    bi[threadIdx.x] = idx;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) absmax_merge(bv[threadIdx.x], bi[threadIdx.x], bv[threadIdx.x + st],
-                                                bi[threadIdx.x + st]);
+        if ((int)threadIdx.x < st) bv[threadIdx.x] = fmax(bv[threadIdx.x], bv[threadIdx.x + st]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        pv[blockIdx.x] = bv[0];
-        pi[blockIdx.x] = bi[0];
-    }
+    if (threadIdx.x == 0) pv[blockIdx.x] = bv[0];
 }
 
-__global__ void __launch_bounds__(256) sign_decide_kernel(const double* __restrict__ x,
-                                                          const double* __restrict__ pv,
-                                                          const i64* __restrict__ pi, int nblk,
-                                                          double* __restrict__ factor) {
-    __shared__ double bv[256];
+// first index i with |x_i| >= (1 - SIGN_TIE) max|x| (max from the partials)
+__global__ void __launch_bounds__(256) tie_index_partial_kernel(const double* __restrict__ x, i64 N,
+                                                                const double* __restrict__ pv, int nblk,
+                                                                i64* __restrict__ pi) {
+    __shared__ double bm[256];
     __shared__ i64 bi[256];
-    double v = -1.0;
-    i64 idx = 0;
-    for (int b = threadIdx.x; b < nblk; b += 256) absmax_merge(v, idx, pv[b], pi[b]);
-    bv[threadIdx.x] = v;
+    double m = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) m = fmax(m, pv[b]);
+    bm[threadIdx.x] = m;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) bm[threadIdx.x] = fmax(bm[threadIdx.x], bm[threadIdx.x + st]);
+        __syncthreads();
+    }
+    const double band = bm[0] * (1.0 - SIGN_TIE);
+    i64 idx = N;
+    for (i64 i = (i64)blockIdx.x * 256 + threadIdx.x; i < N && idx == N; i += (i64)gridDim.x * 256)
+        if (fabs(x[i]) >= band) idx = i;
     bi[threadIdx.x] = idx;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) absmax_merge(bv[threadIdx.x], bi[threadIdx.x], bv[threadIdx.x + st],
-                                                bi[threadIdx.x + st]);
+        if ((int)threadIdx.x < st) bi[threadIdx.x] = min(bi[threadIdx.x], bi[threadIdx.x + st]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *factor = x[bi[0]] < 0.0 ? -1.0 : 1.0;
+    if (threadIdx.x == 0) pi[blockIdx.x] = bi[0];
+}
+
+__global__ void __launch_bounds__(256) sign_decide_kernel(const double* __restrict__ x, i64 N,
+                                                          const i64* __restrict__ pi, int nblk,
+                                                          double* __restrict__ factor) {
+    __shared__ i64 bi[256];
+    i64 idx = N;
+    for (int b = threadIdx.x; b < nblk; b += 256) idx = min(idx, pi[b]);
+    bi[threadIdx.x] = idx;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) bi[threadIdx.x] = min(bi[threadIdx.x], bi[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *factor = (bi[0] < N && x[bi[0]] < 0.0) ? -1.0 : 1.0;
 }
 
 __global__ void scale_kernel(double* __restrict__ x, i64 N, const double* __restrict__ factor) {
@@ -681,10 +692,11 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
     {
         DevMem pv = dev_alloc(ctx, sizeof(double) * ws.nblk, s);
         DevMem pi = dev_alloc(ctx, sizeof(i64) * ws.nblk, s);
-        HCI_LAUNCH(ctx, "dv_signfix", s, absmax_partial_kernel, ws.nblk, 256, 0, c, N, pv.as<double>(),
-                   pi.as<i64>());
-        HCI_LAUNCH(ctx, "dv_signfix", s, sign_decide_kernel, 1, 256, 0, c, pv.as<double>(), pi.as<i64>(),
-                   ws.nblk, nrm_x);
+        HCI_LAUNCH(ctx, "dv_signfix", s, absmax_partial_kernel, ws.nblk, 256, 0, c, N, pv.as<double>());
+        HCI_LAUNCH(ctx, "dv_signfix", s, tie_index_partial_kernel, ws.nblk, 256, 0, c, N, (const double*)pv.as<double>(),
+                   ws.nblk, pi.as<i64>());
+        HCI_LAUNCH(ctx, "dv_signfix", s, sign_decide_kernel, 1, 256, 0, c, N, (const i64*)pi.as<i64>(), ws.nblk,
+                   nrm_x);
         HCI_LAUNCH(ctx, "dv_signfix", s, scale_kernel, g1, 256, 0, c, N, (const double*)nrm_x);
     }
     *e_out = theta + ctx->ecore;

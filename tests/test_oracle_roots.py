@@ -156,3 +156,13 @@ def test_spin_square_of_eigenstates_matches_the_spin_sectors(n, na, nb, seed):
         assert np.abs(spectra[a_top] - w[k]).min() < 1e-9, (k, S)
         if a_top + 1 in spectra:
             assert np.abs(spectra[a_top + 1] - w[k]).min() > 1e-7, (k, S)
+
+
+def test_sign_convention_ties():
+    """The first entry within 1e-6 (relative) of the largest magnitude is
+    made positive: a near-tie resolves to the first index, a clear maximum
+    decides by itself."""
+    c = np.array([0.1, -0.5, 0.5 * (1 - 1e-9), 0.2])
+    assert O._fix_sign(c)[1] > 0 and O._fix_sign(-c)[1] > 0
+    c = np.array([0.1, -0.5, 0.5 + 1e-3, 0.2])
+    assert O._fix_sign(c)[2] > 0 and O._fix_sign(-c)[2] > 0
