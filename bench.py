@@ -49,7 +49,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--fp64-steps", type=int, default=1)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cold-davidson", type=int, default=1,
+                    help="time a mixed-precision Davidson from a cold start on the final space (0 skips it)")
+    ap.add_argument("--cas8", type=int, default=1,
+                    help="time the (8e,8o) full-CI workload on the GPU and in the oracle (0 skips it)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy a 4 GiB buffer once (calibrates HBM byte counters)")
@@ -212,16 +215,39 @@ def main():
         else:
             # plain CSR: float32 value + u32 column per stored entry, 32 B per row
             alg_bytes = 8 * layout["stored_entries"] + 32 * nv
-        achieved = alg_bytes / (sk["avg_ms"] * 1e-3) / 1e9
+        # algorithmic bytes of the scope table: float32 value + u32 column =
+        # 8 B per connection, ~24 B per row (row pointer, c_i, sigma_i), over
+        # the connections of this kernel (all but the beta-group segments)
+        conns = nnz_off - layout["group_entries"]
+        survey_bytes = 8 * conns + 24 * nv
+        achieved = survey_bytes / (sk["avg_ms"] * 1e-3) / 1e9
+        achieved_fmt = alg_bytes / (sk["avg_ms"] * 1e-3) / 1e9
+        traffic = measured_traffic(nv)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(nv),
-                    "kernel": "sigma_stored_f32", "bytes_per_launch": alg_bytes,
+                    "traffic": traffic,
+                    "traffic_source": ("replayed from profiles/sigma_stored_f32_cas16_traffic.json "
+                                       "(FETCH_SIZE and WRITE_SIZE runs of the same kernel source on "
+                                       "this space; not counted in this run)") if traffic else None,
+                    "kernel": "sigma_stored_f32", "bytes_per_launch": survey_bytes,
+                    "bytes_rule": "8 B per connection + 24 B per row (connections = off-diagonal "
+                                  "pairs minus beta-group entries)",
+                    "format": {"bytes_per_launch": alg_bytes, "achieved": round(achieved_fmt, 1),
+                               "frac": round(achieved_fmt / HBM_PEAK_GBS, 4),
+                               "rule": "6 B per stored entry (f32 value + u16 column, padding "
+                                       "included) + 4 B per staged c entry + 48 B per row"},
                     "avg_launch_ms": round(sk["avg_ms"], 4)}
     # ---------------------------------------------------------------- CPU oracle
     cpu = None
+    oracle_check = None
     if not args.no_cpu:
-        cpu = cpu_baseline(h, g, P.dets_to_numpy(V2), c_mixed.cpu().numpy(), args.cpu_seconds, nv)
+        cpu, oracle_check = cpu_baseline(h, g, P.dets_to_numpy(V2), c_mixed.cpu().numpy(), e_mixed, nv, pairs)
+    cold = None
+    if args.cold_davidson:
+        cold = cold_leg(ctx, V2, pairs, args)
+    small = None
+    if args.cas8:
+        small = cas8_leg(args)
     torch.cuda.synchronize()
     t6 = time.perf_counter()
     s2 = ctx.spin_square(V2, c_mixed)
@@ -256,6 +282,10 @@ def main():
         "spin_square": {"value": s2, "ms": round(s2_ms, 2)},
         "fp64": fp64,
         "energy_error_vs_fp64": abs(e_mixed - fp64["energy"]) if fp64 else None,
+        "energy_vs_oracle": oracle_check,
+        "davidson_cold": cold,
+        "cas8": small,
+        "host_cpu": cpu_model(),
         "speedup_vs_fp64": (fp64["ms_per_step"] / ms_step) if fp64 else None,
         "kernels": kernels,
         "roofline": roofline,
@@ -479,30 +509,96 @@ def measured_traffic(nv):
     return round(rec["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(h, g, V, c, seconds, nv):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(h, g, V, c, e, nv, pairs):
     """The oracle's Hamiltonian product (every excitation of each row looked
-    up in V by binary search, Slater-Condon elements) on a bounded sample of
-    rows, timed on this host's cores."""
+    up in V by binary search, Slater-Condon elements) over every row of the
+    final space, timed on this host's cores (OpenMP threads); the same
+    product gives the Rayleigh quotient and residual of the library's
+    float32-mixed eigenvector in float64, i.e. its energy error against the
+    float64 oracle."""
     import numpy as np
 
     import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    rng = np.random.default_rng(0)
-    rows_done, pairs_done = 0, 0
-    chunk = 256
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        rows = rng.choice(len(V), chunk, replace=False)
-        _, pc = O.sigma(h, g, V, c, rows=rows, with_pairs=True)
-        rows_done += chunk
-        pairs_done += int(pc.sum())
+    sig = O.sigma(h, g, V, c)
     dt = time.perf_counter() - t0
-    log(f"[bench] cpu oracle: {rows_done} rows in {dt:.1f} s on {threads} threads")
-    return {"value": pairs_done / dt, "unit": "det-pairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"{rows_done} random rows of the {nv}-determinant space "
-                      f"({pairs_done} det-pairs), oracle sigma_i by full excitation "
-                      f"enumeration + binary search, {dt:.1f} s",
-            "rows_per_s": rows_done / dt}
+    rq = float(c @ sig / (c @ c))
+    res = float(np.linalg.norm(sig - rq * c))
+    log(f"[bench] cpu oracle: every row ({nv}) in {dt:.1f} s on {threads} threads; "
+        f"E_oracle(c) = {rq:.12f}, |E - E_oracle| = {abs(e - rq):.2e}, residual {res:.2e}")
+    base = {"value": pairs / dt, "unit": "det-pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"the whole {nv}-determinant final space ({pairs} det-pairs, one product), "
+                      f"oracle sigma_i by full excitation enumeration + binary search, {dt:.1f} s",
+            "rows_per_s": nv / dt, "cpu_model": cpu_model()}
+    check = {"energy_library": e, "energy_oracle_rayleigh": rq, "abs_error": abs(e - rq),
+             "oracle_residual_norm": res}
+    return base, check
+
+
+def cold_leg(ctx, V2, pairs, args):
+    """Davidson iterations per second from a cold start (zero start vector:
+    the lowest-diagonal determinant) on the final space, float32-mixed with
+    float64 refinement, the stored Hamiltonian already built."""
+    import torch
+    ctx.davidson(V2, None, tol=1e-2, precision="fp32_mixed", max_iter=2, allow_noconv=True)  # layout built, untimed
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    e, c, products = ctx.davidson(V2, None, tol=args.tol, precision="fp32_mixed", max_iter=4000)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    log(f"[bench] cold Davidson: {products} products in {dt:.2f} s, E = {e:.10f}")
+    return {"products": products, "seconds": round(dt, 3), "iter_per_s": products / dt,
+            "det_pairs_per_s": products * pairs / dt, "energy": e, "tol": args.tol}
+
+
+def cas8_leg(args):
+    """(8e,8o) at eps1 = 0 (the full 4,900-determinant space): the library's
+    HCI loop from the aufbau determinant in float64 (Davidson tol 1e-10)
+    against the oracle's whole HCI (selection by definition and dense LAPACK
+    eigensolves), both timed."""
+    import numpy as np
+    import torch
+
+    import hci_synth as hs
+    import oracle as O
+    import paper_1708_07544_amd as P
+    w = hs.WORKLOADS["cas8"]
+    h, g = hs.workload_integrals(w)
+    ctx = P.HCIContext(h, g, 4, 4)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    V = P.dets_to_device(hs.aufbau_det(4, 4))
+    e, c, _ = ctx.davidson(V, None, tol=1e-10)
+    for it in range(20):
+        Vn = ctx.select(V, c, 0.0)
+        if Vn.shape[0] == V.shape[0]:
+            break
+        e, c, _ = ctx.davidson(Vn, ctx.embed(V, c, Vn), tol=1e-10)
+        V = Vn
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - t
+    t = time.perf_counter()
+    Vo, _, eo, _ = O.hci(h, g, 4, 4, 0.0, dense_max=5000)
+    cpu_s = time.perf_counter() - t
+    ctx.close()
+    log(f"[bench] cas8: library {V.shape[0]} dets E = {e:.12f} in {gpu_s:.2f} s; "
+        f"oracle {len(Vo)} dets E = {eo:.12f} in {cpu_s:.2f} s")
+    return {"n_det": int(V.shape[0]), "energy": e, "energy_oracle": float(eo), "abs_error": abs(e - float(eo)),
+            "gpu_seconds": round(gpu_s, 3), "oracle_hci_seconds": round(cpu_s, 3),
+            "oracle": "selection by definition + dense LAPACK eigensolves, whole HCI loop",
+            "cpu_model": cpu_model()}
 
 
 if __name__ == "__main__":

@@ -39,17 +39,18 @@ def _space(name):
 
 
 def _check_states(e, C, eref, Cref, tol_e=1e-9, tol_c=1e-6):
-    """Energies; vectors up to sign (in states odd under the exchange of alpha
-    and beta strings the two largest |c_i| are equal and opposite, so rounding
-    picks the entry that fixes the sign); the sign convention on the
-    library's own vectors (largest |c_i|, first on ties, positive)."""
+    """Energies; vectors up to sign (against another solver, whose rounding
+    may place an entry just inside or outside the tie band); the sign
+    convention on the library's own vectors: the first entry within 1e-6
+    (relative) of the largest |c_i| is positive."""
     k = len(eref)
     assert np.abs(e - eref).max() < tol_e, (e, eref)
     assert np.abs(C @ C.T - np.eye(k)).max() < 1e-10
     for r in range(k):
         d = min(np.abs(C[r] - Cref[r]).max(), np.abs(C[r] + Cref[r]).max())
         assert d < tol_c, (r, d)
-        assert C[r][int(np.argmax(np.abs(C[r])))] > 0
+        a = np.abs(C[r])
+        assert C[r][int(np.flatnonzero(a >= a.max() * (1 - 1e-6))[0])] > 0
 
 
 @pytest.mark.parametrize("name,k,precision", [("cas8", 4, "fp64"), ("cas8", 4, "fp32_mixed"),
