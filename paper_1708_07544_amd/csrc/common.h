@@ -405,6 +405,10 @@ T read_scalar(const T* dptr, hipStream_t s) {
 // keys_hi/keys_lo/vals (the tmp buffers are scratch of the same size).
 void radix_sort128(hci_ctx_s* ctx, u64* hi, u64* lo, u32* vals, u64* thi, u64* tlo, u32* tvals,
                    i64 n, int bits_hi, int bits_lo, hipStream_t s);
+// Stable LSD radix sort of 64-bit keys by their bytes [byte_lo, byte_hi)
+// (the lower bytes keep their input order among equal sort bytes); tmp is
+// scratch of n words.
+void radix_sort64_bytes(hci_ctx_s* ctx, u64* keys, u64* tmp, i64 n, int byte_lo, int byte_hi, hipStream_t s);
 // Remove adjacent duplicates of sorted (hi, lo) keys; returns the unique
 // count m and writes out_pairs [m][2] = {hi, lo} only when m <= cap.
 i64 unique128_capped(hci_ctx_s* ctx, const u64* hi, const u64* lo, u64* out_pairs, i64 n, i64 cap,
@@ -490,10 +494,21 @@ void pt2_stochastic(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c, dou
 // returns the number of Hamiltonian products.
 int zvector_solve(hci_ctx_s* ctx, Space* sp, const double* c, double e, const double* r, double* z,
                   double tol, int precision, int max_products, hipStream_t s);
-// rdm1/rdm2 += sum over M pairs t of w_t <D_a(t)| ops |D_i(t)>, w_t = wa_t c_i(t)
-// (Gamma^{dc} of the screened PT2 pairs: D_a = (a_hi, a_lo), i = idx)
-void rdm_add_pairs(hci_ctx_s* ctx, const u64* a_hi, const u64* a_lo, const u32* idx, const double* wa, i64 M,
-                   const u64* dets, const double* c, double* rdm1, double* rdm2, hipStream_t s);
+// Density matrices of screened pairs (Gamma^{dc} of the PT2 pieces):
+// rdm1/rdm2 += sum over the pairs t of w_t <D_a(t)| ops |D_i(t)>, with
+// w_t = wa_t c_i(t), D_a = (a_hi, a_lo), i = idx.  The pairs of each pass are
+// sorted by excitation class (type and orbitals) and reduced segment by
+// segment in a fixed order into per-class tables, which one owner per
+// density-matrix entry adds to rdm1/rdm2 at the end: no atomics, the result
+// does not depend on scheduling.
+struct PairRdm {
+    DevMem dtab;  // [3][n^4]: alpha-beta, alpha-alpha, beta-beta doubles by orbitals
+    DevMem stab;  // [2][n][n][2n + 1]: singles by (spin, u, v): spectator sums, then the plain sum
+};
+void pair_rdm_init(hci_ctx_s* ctx, PairRdm& A, hipStream_t s);
+void pair_rdm_add(hci_ctx_s* ctx, PairRdm& A, const u64* a_hi, const u64* a_lo, const u32* idx, const double* wa,
+                  i64 M, const u64* dets, const double* c, hipStream_t s);
+void pair_rdm_finish(hci_ctx_s* ctx, PairRdm& A, double* rdm1, double* rdm2, hipStream_t s);
 // rdm1/rdm2 += sum_k wa_k wb_k <D_k| ops |D_k> over the listed determinants
 void rdm_add_diag(hci_ctx_s* ctx, const u64* alpha, const u64* beta, const double* wa,
                   const double* wb, i64 M, double* rdm1, double* rdm2, hipStream_t s);

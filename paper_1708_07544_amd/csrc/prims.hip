@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(RS_BLOCK) rs_hist_kernel(const u64* __restrict
     const i64 base = (i64)blockIdx.x * RS_TILE;
     for (int k = 0; k < RS_ITEMS; ++k) {
         i64 idx = base + (i64)k * RS_BLOCK + threadIdx.x;
-        if (idx < n) atomicAdd(&hist[digit_of(hi[idx], lo[idx], pass, passes_lo)], 1u);
+        if (idx < n) atomicAdd(&hist[digit_of(hi ? hi[idx] : 0ull, lo[idx], pass, passes_lo)], 1u);
     }
     __syncthreads();
     counts[(i64)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(RS_BLOCK) rs_scatter_kernel(
         u32 kv = 0;
         u32 d = 0;
         if (valid) {
-            khi = hi[idx];
+            khi = hi ? hi[idx] : 0ull;
             klo = lo[idx];
             if (HAS_VAL) kv = vals[idx];
             d = digit_of(khi, klo, pass, passes_lo);
@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(RS_BLOCK) rs_scatter_kernel(
         if (valid) {
             u32 pos = run[d] + rank;
             for (int q = 0; q < w; ++q) pos += wcnt[q][d];
-            ohi[pos] = khi;
+            if (ohi) ohi[pos] = khi;
             olo[pos] = klo;
             if (HAS_VAL) ovals[pos] = kv;
         }
@@ -212,6 +212,25 @@ void radix_sort128(hci_ctx_s* ctx, u64* hi, u64* lo, u32* vals, u64* thi, u64* t
         HIP_CHECK(hipMemcpyAsync(lo, slo, sizeof(u64) * n, hipMemcpyDeviceToDevice, s));
         if (vals) HIP_CHECK(hipMemcpyAsync(vals, sv, sizeof(u32) * n, hipMemcpyDeviceToDevice, s));
     }
+}
+
+void radix_sort64_bytes(hci_ctx_s* ctx, u64* keys, u64* tmp, i64 n, int byte_lo, int byte_hi, hipStream_t s) {
+    if (n <= 1 || byte_hi <= byte_lo) return;
+    HCI_REQUIRE(n < ((i64)1 << 32), HCI_E_UNSUPPORTED, "radix sort: more than 2^32 keys");
+    HCI_REQUIRE(byte_lo >= 0 && byte_hi <= 8, HCI_E_ARG, "radix sort: byte range outside a 64-bit key");
+    const i64 nb = ceil_div(n, RS_TILE);
+    DevMem counts = dev_alloc(ctx, sizeof(u32) * 256 * nb, s);
+    DevMem offs = dev_alloc(ctx, sizeof(u32) * 256 * nb, s);
+    u64 *src = keys, *dst = tmp;
+    for (int p = byte_lo; p < byte_hi; ++p) {  // passes_lo = 8: every digit is a byte of the one word
+        HCI_LAUNCH(ctx, "radix_hist", s, rs_hist_kernel, nb, RS_BLOCK, 0, (const u64*)nullptr, src, n, p, 8,
+                   counts.as<u32>(), nb);
+        scan_u32_to_u32(ctx, counts.as<u32>(), offs.as<u32>(), 256 * nb, s);
+        HCI_LAUNCH(ctx, "radix_scatter", s, rs_scatter_kernel<false>, nb, RS_BLOCK, 0, (const u64*)nullptr, src,
+                   (const u32*)nullptr, n, p, 8, offs.as<u32>(), nb, (u64*)nullptr, dst, (u32*)nullptr);
+        std::swap(src, dst);
+    }
+    if ((byte_hi - byte_lo) & 1) HIP_CHECK(hipMemcpyAsync(keys, src, sizeof(u64) * n, hipMemcpyDeviceToDevice, s));
 }
 
 i64 unique128_capped(hci_ctx_s* ctx, const u64* hi, const u64* lo, u64* out_pairs, i64 n, i64 cap,

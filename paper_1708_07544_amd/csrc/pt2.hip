@@ -568,6 +568,8 @@ void pt2_relaxed_pieces(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c,
     HIP_CHECK(hipMemsetAsync(r, 0, sizeof(double) * N, s));
     double e2 = 0.0, dd = 0.0;
     i64 nc = 0;
+    PairRdm acc;
+    pair_rdm_init(ctx, acc, s);
     pt2_passes(ctx, dets, N, c, e0, eps2, npasses, s, [&](Pt2Pass& X) {
         HCI_LAUNCH(ctx, "pt2_r", s, r_rows<true>, ceil_div(N, 256), 256, 0, X.P.off.as<i64>(), N,
                    X.P.hai.as<double>(), X.dpair.as<double>(), r);
@@ -577,12 +579,13 @@ void pt2_relaxed_pieces(hci_ctx_s* ctx, const u64* dets, i64 N, const double* c,
         dd += sum_to_host(ctx, X.term.as<double>(), X.G.nseg, s);
         nc += X.G.nseg;
         // Gamma^{dc}: bra D_a (weight d_a), ket D_i (weight c_i) over the pass's pairs
-        rdm_add_pairs(ctx, X.P.a_hi.as<u64>(), X.P.a_lo.as<u64>(), X.P.idx.as<u32>(), X.dpair.as<double>(),
-                      X.P.M, dets, c, dc1, dc2, s);
+        pair_rdm_add(ctx, acc, X.P.a_hi.as<u64>(), X.P.a_lo.as<u64>(), X.P.idx.as<u32>(), X.dpair.as<double>(),
+                     X.P.M, dets, c, s);
         // Gamma^{dd}: the diagonal of the connected determinants, weights d_a^2
         rdm_add_diag(ctx, X.G.ca.as<u64>(), X.G.cb.as<u64>(), X.d.as<double>(), X.d.as<double>(), X.G.nseg,
                      dd1, dd2, s);
     });
+    pair_rdm_finish(ctx, acc, dc1, dc2, s);
     *e2_out = e2;
     *dd_out = dd;
     if (nconn) *nconn = nc;

@@ -8,10 +8,10 @@
 // reduced as an occupation-correlation product: D[x][y] = sum_i bra_i ket_i
 // n_x(i) n_y(i) over spin orbitals x, y, block partials then a fixed-order
 // sum.  Off-diagonal pairs go through rdm_det_kernel (below): per-chunk
-// owners, private copies per workgroup, fixed-order sums; no atomics, so the
-// result is the same bit for bit from run to run.  The screened PT2 pairs of
-// the relaxed gradient (Gamma^{dc}) are still added with float64 atomics
-// (pt2_pairs_kernel).
+// owners, private copies per workgroup, fixed-order sums.  The screened PT2
+// pairs of the relaxed gradient (Gamma^{dc}) are sorted by excitation class
+// and reduced class by class.  No floating-point atomics anywhere, so the
+// result is the same bit for bit from run to run.
 #include <cstdlib>
 
 #include "slater.h"
@@ -20,78 +20,8 @@ namespace {
 
 constexpr int OCC_CHUNK = 256;
 
-__device__ __forceinline__ void add64(double* p, double v) { unsafeAtomicAdd(p, v); }
-
 __device__ __forceinline__ i64 r2idx(int n, int p, int q, int r, int s) {
     return (((i64)p * n + q) * n + r) * n + s;
-}
-
-// contributions of <D_i| ... |D_j> for a single excitation v -> u in the
-// string sj (spin s) of D_j, with `other` the opposite-spin string of D_j.
-// HALF adds only one entry of each pair (pq|rs), (rs|pq) of rdm2 (the two are
-// equal for any bra and ket); the caller then sets rdm2 = T + T^swap.
-template <bool HALF>
-__device__ __forceinline__ void single_contrib(int n, double x, u64 sj, u64 other, int v, int u,
-                                               double* r1, double* r2) {
-    add64(&r1[(i64)u * n + v], x);
-    if (!r2) return;
-    for (u64 m = sj & ~bit(v); m; m &= m - 1) {  // same-spin spectators
-        const int k = ctz64(m);
-        add64(&r2[r2idx(n, u, v, k, k)], x);
-        add64(&r2[r2idx(n, u, k, k, v)], -x);
-        if (!HALF) {
-            add64(&r2[r2idx(n, k, k, u, v)], x);
-            add64(&r2[r2idx(n, k, v, u, k)], -x);
-        }
-    }
-    for (u64 m = other; m; m &= m - 1) {  // opposite-spin spectators
-        const int k = ctz64(m);
-        add64(&r2[r2idx(n, u, v, k, k)], x);
-        if (!HALF) add64(&r2[r2idx(n, k, k, u, v)], x);
-    }
-}
-
-template <bool HALF>
-__device__ __forceinline__ void pair_contrib(int n, double w, u64 ai, u64 bi, u64 aj, u64 bj,
-                                             double* r1, double* r2) {
-    const u64 xa = ai ^ aj, xb = bi ^ bj;
-    const int da = popc64(xa) >> 1, db = popc64(xb) >> 1;
-    if (da == 1 && db == 0) {
-        const int v = ctz64(aj & xa), u = ctz64(ai & xa);
-        single_contrib<HALF>(n, w * sign_between(aj, v, u), aj, bj, v, u, r1, r2);
-        return;
-    }
-    if (da == 0 && db == 1) {
-        const int v = ctz64(bj & xb), u = ctz64(bi & xb);
-        single_contrib<HALF>(n, w * sign_between(bj, v, u), bj, aj, v, u, r1, r2);
-        return;
-    }
-    if (!r2) return;
-    if (da == 1 && db == 1) {
-        const int v1 = ctz64(aj & xa), u1 = ctz64(ai & xa);
-        const int v2 = ctz64(bj & xb), u2 = ctz64(bi & xb);
-        const double x = w * (sign_between(aj, v1, u1) * sign_between(bj, v2, u2));
-        add64(&r2[r2idx(n, u1, v1, u2, v2)], x);
-        if (!HALF) add64(&r2[r2idx(n, u2, v2, u1, v1)], x);
-        return;
-    }
-    const u64 sj = da == 2 ? aj : bj;
-    const u64 x2 = da == 2 ? xa : xb;
-    u64 holes = sj & x2, parts = x2 & ~sj;
-    const int v1 = ctz64(holes);
-    holes &= holes - 1;
-    const int v2 = ctz64(holes);
-    const int u1 = ctz64(parts);
-    parts &= parts - 1;
-    const int u2 = ctz64(parts);
-    const double sg = sign_double(sj, v1, u1, v2, u2);
-    const double x = w * sg;
-    add64(&r2[r2idx(n, u1, v1, u2, v2)], x);
-    add64(&r2[r2idx(n, u1, v2, u2, v1)], -x);
-    if (!HALF) {
-        add64(&r2[r2idx(n, u2, v2, u1, v1)], x);
-        add64(&r2[r2idx(n, u2, v1, u1, v2)], -x);
-    }
 }
 
 // Occupation correlation D[x][y] = sum_i w_i n_x(i) n_y(i) over spin
@@ -184,18 +114,189 @@ __global__ void diag_terms_kernel(const double* __restrict__ D, int n, double* _
     }
 }
 
-// Gamma^{dc}: one thread per screened pair (i, a), weight d_a c_i, bra D_a,
-// ket D_i (Sec. "Computational Details": the connection list of the PT2).
-__global__ void pt2_pairs_kernel(const u64* __restrict__ a_hi, const u64* __restrict__ a_lo,
-                                 const u32* __restrict__ idx, const double* __restrict__ dpair,
+// ---------------------------------------------------- screened pairs
+// Gamma^{dc} of the PT2 pieces: bra D_a (weight d_a), ket D_i (weight c_i)
+// over the screened connection list (Sec. "Computational Details").  Each
+// pair is one excitation class: a single v -> u of one spin, an
+// opposite-spin double, or a same-spin double with holes v1 < v2 and
+// particles u1 < u2.  The class and its orbitals form a 27-bit key
+// (type << 24 | four 6-bit orbitals); the pairs are sorted by key (stable, so
+// pairs of one class keep their list order) and each class is reduced by one
+// wavefront in a fixed order:
+//   doubles: X = sum of the signed weights, added to its table entry;
+//   singles: g = sum of x, A_k = sum x [k occupied in the ket's string of the
+//   excited spin, k != v], B_k = sum x [k occupied in the other string].
+// pair_table_kernel then gives every rdm entry one owner that adds the
+// entries of the tables it receives (the same terms an operator application
+// per pair gives: see the comments there).
+constexpr u32 PK_SKIP = 7u;  // type of a pair with zero weight (sorted last, ignored)
+
+struct PairClass {
+    u32 key;    // type << 24 | o0 << 18 | o1 << 12 | o2 << 6 | o3
+    double x;   // signed weight
+    u64 same;   // singles: ket string of the excited spin
+    u64 other;  // singles: ket string of the other spin
+};
+
+__device__ __forceinline__ u32 pk_pack(u32 type, int o0, int o1, int o2, int o3) {
+    return type << 24 | (u32)o0 << 18 | (u32)o1 << 12 | (u32)o2 << 6 | (u32)o3;
+}
+
+__device__ __forceinline__ PairClass pair_class(double w, u64 ai, u64 bi, u64 aj, u64 bj) {
+    PairClass P{pk_pack(PK_SKIP, 0, 0, 0, 0), 0.0, 0, 0};
+    if (w == 0.0) return P;
+    const u64 xa = ai ^ aj, xb = bi ^ bj;
+    const int da = popc64(xa) >> 1, db = popc64(xb) >> 1;
+    if (da + db == 1) {  // single v -> u (type 0 alpha, 1 beta)
+        const bool al = da == 1;
+        const u64 sj = al ? aj : bj, x = al ? xa : xb;
+        const int v = ctz64(sj & x), u = ctz64(x & ~sj);
+        P.key = pk_pack(al ? 0u : 1u, u, v, 0, 0);
+        P.x = w * sign_between(sj, v, u);
+        P.same = sj;
+        P.other = al ? bj : aj;
+        return P;
+    }
+    if (da == 1 && db == 1) {  // type 2: alpha v1 -> u1 with beta v2 -> u2
+        const int v1 = ctz64(aj & xa), u1 = ctz64(ai & xa);
+        const int v2 = ctz64(bj & xb), u2 = ctz64(bi & xb);
+        P.key = pk_pack(2u, u1, v1, u2, v2);
+        P.x = w * (sign_between(aj, v1, u1) * sign_between(bj, v2, u2));
+        return P;
+    }
+    // same-spin double (type 3 alpha, 4 beta); ctz order gives v1 < v2, u1 < u2
+    const bool al = da == 2;
+    const u64 sj = al ? aj : bj, x2 = al ? xa : xb;
+    u64 holes = sj & x2, parts = x2 & ~sj;
+    const int v1 = ctz64(holes);
+    holes &= holes - 1;
+    const int v2 = ctz64(holes);
+    const int u1 = ctz64(parts);
+    parts &= parts - 1;
+    const int u2 = ctz64(parts);
+    P.key = pk_pack(al ? 3u : 4u, u1, v1, u2, v2);
+    P.x = w * sign_double(sj, v1, u1, v2, u2);
+    return P;
+}
+
+__device__ __forceinline__ PairClass pair_class_at(i64 t, const u64* __restrict__ a_hi,
+                                                   const u64* __restrict__ a_lo, const u32* __restrict__ idx,
+                                                   const double* __restrict__ wa, const u64* __restrict__ dets,
+                                                   const double* __restrict__ c) {
+    const u32 i = idx[t];
+    return pair_class(wa[t] * c[i], a_hi[t], a_lo[t], dets[2 * (i64)i], dets[2 * (i64)i + 1]);
+}
+
+// key << 32 | t for every pair of the pass
+__global__ void pair_keys_kernel(const u64* __restrict__ a_hi, const u64* __restrict__ a_lo,
+                                 const u32* __restrict__ idx, const double* __restrict__ wa,
                                  const u64* __restrict__ dets, const double* __restrict__ c, i64 M,
-                                 int n, double* __restrict__ r1, double* __restrict__ r2) {
+                                 u64* __restrict__ keyed) {
     const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= M) return;
-    const u32 i = idx[t];
-    const double w = dpair[t] * c[i];
-    if (w == 0.0) return;
-    pair_contrib<false>(n, w, a_hi[t], a_lo[t], dets[2 * (i64)i], dets[2 * (i64)i + 1], r1, r2);
+    keyed[t] = (u64)pair_class_at(t, a_hi, a_lo, idx, wa, dets, c).key << 32 | (u64)t;
+}
+
+__global__ void pair_heads_kernel(const u64* __restrict__ keyed, i64 M, u32* __restrict__ flags) {
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M) return;
+    flags[t] = (t == 0 || (keyed[t] >> 32) != (keyed[t - 1] >> 32)) ? 1u : 0u;
+}
+
+__global__ void pair_starts_kernel(const u32* __restrict__ flags, const u32* __restrict__ pos, i64 M,
+                                   i64* __restrict__ start) {
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < M && flags[t]) start[pos[t]] = t;
+}
+
+// one wavefront per class segment [start[g], start[g + 1]) of the sorted pairs
+__global__ void __launch_bounds__(256) pair_segments_kernel(
+    const u64* __restrict__ keyed, const i64* __restrict__ start, i64 nseg, i64 M, const u64* __restrict__ a_hi,
+    const u64* __restrict__ a_lo, const u32* __restrict__ idx, const double* __restrict__ wa,
+    const u64* __restrict__ dets, const double* __restrict__ c, int n, double* __restrict__ dtab,
+    double* __restrict__ stab) {
+    const int lane = lane_id();
+    const i64 nw = (i64)gridDim.x * (blockDim.x / 64);
+    const i64 n4 = (i64)n * n * n * n;
+    for (i64 g = (i64)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; g < nseg; g += nw) {
+        const i64 b = start[g], e = g + 1 < nseg ? start[g + 1] : M;
+        const u32 key = (u32)(keyed[b] >> 32);
+        const u32 type = key >> 24;
+        if (type == PK_SKIP) continue;
+        const int o0 = (key >> 18) & 63, o1 = (key >> 12) & 63, o2 = (key >> 6) & 63, o3 = key & 63;
+        if (type >= 2) {
+            // lane-strided partial sums in list order, then a fixed butterfly
+            double acc = 0.0;
+            for (i64 t = b + lane; t < e; t += 64)
+                acc += pair_class_at((i64)(u32)keyed[t], a_hi, a_lo, idx, wa, dets, c).x;
+            acc = wave_sum_f64(acc);
+            if (lane == 0) dtab[(i64)(type - 2) * n4 + (((i64)o0 * n + o1) * n + o2) * n + o3] += acc;
+            continue;
+        }
+        // singles: lane k keeps A_k, B_k; the pairs go 64 at a time, each
+        // broadcast to every lane in list order
+        const int v = o1;
+        double A = 0.0, B = 0.0, gsum = 0.0;
+        for (i64 base = b; base < e; base += 64) {
+            PairClass mine{0u, 0.0, 0, 0};
+            if (base + lane < e) mine = pair_class_at((i64)(u32)keyed[base + lane], a_hi, a_lo, idx, wa, dets, c);
+            const int cnt = (int)min((i64)64, e - base);
+            for (int j = 0; j < cnt; ++j) {
+                const double xj = __shfl(mine.x, j, HCI_WAVE);
+                const u64 sj = __shfl(mine.same, j, HCI_WAVE), oj = __shfl(mine.other, j, HCI_WAVE);
+                gsum += xj;
+                if (lane < n) {
+                    if (lane != v && test_bit(sj, lane)) A += xj;
+                    if (test_bit(oj, lane)) B += xj;
+                }
+            }
+        }
+        double* row = stab + (((i64)type * n + o0) * n + v) * (2 * n + 1);
+        if (lane < n) {
+            row[lane] += A;
+            row[n + lane] += B;
+        }
+        if (lane == 0) row[2 * n] += gsum;
+    }
+}
+
+// Every rdm entry adds what the class tables give it:
+//   alpha-beta double (u1 v1 | u2 v2) with sum X: [u1 v1 u2 v2] and [u2 v2 u1 v1] += X;
+//   same-spin double (u1 < u2, v1 < v2), X: [u1 v1 u2 v2], [u2 v2 u1 v1] += X and
+//     [u1 v2 u2 v1], [u2 v1 u1 v2] -= X, so entry (p q r s) with p != r, q != s
+//     receives +-X(min(p,r), min(q,s), max(p,r), max(q,s)), + when p < r and
+//     q < s agree;
+//   single v -> u (spectator k): [u v k k] and [k k u v] += A_k + B_k,
+//     [u k k v] and [k v u k] -= A_k; rdm1[u][v] += g.
+__global__ void pair_table_kernel(const double* __restrict__ dtab, const double* __restrict__ stab, int n,
+                                  double* __restrict__ r1, double* __restrict__ r2) {
+    const i64 n2 = (i64)n * n, n4 = n2 * n2;
+    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n4 + n2) return;
+    const int w = 2 * n + 1;
+    auto S = [&](int sp, int u, int v, int k) { return stab[(((i64)sp * n + u) * n + v) * w + k]; };
+    if (t >= n4) {  // rdm1
+        const int p = (int)((t - n4) / n), q = (int)((t - n4) % n);
+        if (p != q) r1[(i64)p * n + q] += S(0, p, q, 2 * n) + S(1, p, q, 2 * n);
+        return;
+    }
+    const int p = (int)(t / (n2 * n)), q = (int)(t / n2 % n), r = (int)(t / n % n), s = (int)(t % n);
+    auto D = [&](int type, int a, int b2, int c2, int d) {
+        return dtab[(i64)type * n4 + (((i64)a * n + b2) * n + c2) * n + d];
+    };
+    double v = D(0, p, q, r, s) + D(0, r, s, p, q);
+    if (p != r && q != s) {
+        const double X = D(1, min(p, r), min(q, s), max(p, r), max(q, s)) +
+                         D(2, min(p, r), min(q, s), max(p, r), max(q, s));
+        v += ((p < r) == (q < s)) ? X : -X;
+    }
+    for (int sp = 0; sp < 2; ++sp) {
+        if (r == s && p != q) v += S(sp, p, q, r) + S(sp, p, q, n + r);
+        if (p == q && r != s) v += S(sp, r, s, p) + S(sp, r, s, n + p);
+        if (q == r && p != s) v -= S(sp, p, s, q);
+        if (p == s && r != q) v -= S(sp, r, q, p);
+    }
+    r2[t] += v;
 }
 
 // rdm2 = T + T^swap in place, T^swap[p][q][r][s] = T[r][s][p][q].
@@ -654,9 +755,44 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
     rdm_add_diag(ctx, sp->alpha.as<u64>(), sp->beta.as<u64>(), bra, ket, N, rdm1, rdm2, s);
 }
 
-void rdm_add_pairs(hci_ctx_s* ctx, const u64* a_hi, const u64* a_lo, const u32* idx, const double* wa, i64 M,
-                   const u64* dets, const double* c, double* rdm1, double* rdm2, hipStream_t s) {
+void pair_rdm_init(hci_ctx_s* ctx, PairRdm& A, hipStream_t s) {
+    const i64 n = ctx->n, n4 = n * n * n * n;
+    A.dtab = dev_alloc(ctx, sizeof(double) * 3 * n4, s);
+    A.stab = dev_alloc(ctx, sizeof(double) * 2 * n * n * (2 * n + 1), s);
+    HCI_LAUNCH(ctx, "rdm_zero", s, rdm_zero_kernel, std::min<i64>(ceil_div(3 * n4, 256), 65536), 256, 0,
+               A.dtab.as<double>(), 3 * n4);
+    HCI_LAUNCH(ctx, "rdm_zero", s, rdm_zero_kernel, ceil_div(2 * n * n * (2 * n + 1), 256), 256, 0,
+               A.stab.as<double>(), 2 * n * n * (2 * n + 1));
+}
+
+void pair_rdm_add(hci_ctx_s* ctx, PairRdm& A, const u64* a_hi, const u64* a_lo, const u32* idx, const double* wa,
+                  i64 M, const u64* dets, const double* c, hipStream_t s) {
     if (M <= 0) return;
-    HCI_LAUNCH(ctx, "rdm_pt2_pairs", s, pt2_pairs_kernel, ceil_div(M, 256), 256, 0, a_hi, a_lo, idx, wa, dets,
-               c, M, ctx->n, rdm1, rdm2);
+    HCI_REQUIRE(M < ((i64)1 << 32), HCI_E_UNSUPPORTED, "pt2 pairs: more than 2^32 pairs in one pass");
+    DevMem keyed = dev_alloc(ctx, sizeof(u64) * M, s);
+    HCI_LAUNCH(ctx, "rdm_pair_keys", s, pair_keys_kernel, ceil_div(M, 256), 256, 0, a_hi, a_lo, idx, wa, dets, c,
+               M, keyed.as<u64>());
+    {
+        DevMem tmp = dev_alloc(ctx, sizeof(u64) * M, s);
+        radix_sort64_bytes(ctx, keyed.as<u64>(), tmp.as<u64>(), M, 4, 8, s);  // by the key, bits 32..63
+    }
+    DevMem flags = dev_alloc(ctx, sizeof(u32) * (M + 1), s), pos = dev_alloc(ctx, sizeof(u32) * (M + 1), s);
+    HCI_LAUNCH(ctx, "rdm_pair_heads", s, pair_heads_kernel, ceil_div(M, 256), 256, 0, keyed.as<u64>(), M,
+               flags.as<u32>());
+    HIP_CHECK(hipMemsetAsync(flags.as<u32>() + M, 0, sizeof(u32), s));
+    scan_u32_to_u32(ctx, flags.as<u32>(), pos.as<u32>(), M + 1, s);
+    const i64 nseg = read_scalar(pos.as<u32>() + M, s);
+    DevMem start = dev_alloc(ctx, sizeof(i64) * nseg, s);
+    HCI_LAUNCH(ctx, "rdm_pair_starts", s, pair_starts_kernel, ceil_div(M, 256), 256, 0, flags.as<u32>(),
+               pos.as<u32>(), M, start.as<i64>());
+    const i64 blocks = std::min<i64>(ceil_div(nseg, 4), 16384);
+    HCI_LAUNCH(ctx, "rdm_pair_segments", s, pair_segments_kernel, blocks, 256, 0, keyed.as<u64>(),
+               start.as<i64>(), nseg, M, a_hi, a_lo, idx, wa, dets, c, ctx->n, A.dtab.as<double>(),
+               A.stab.as<double>());
+}
+
+void pair_rdm_finish(hci_ctx_s* ctx, PairRdm& A, double* rdm1, double* rdm2, hipStream_t s) {
+    const i64 n = ctx->n, n2 = n * n, n4 = n2 * n2;
+    HCI_LAUNCH(ctx, "rdm_pair_tables", s, pair_table_kernel, ceil_div(n4 + n2, 256), 256, 0, A.dtab.as<double>(),
+               A.stab.as<double>(), (int)n, rdm1, rdm2);
 }

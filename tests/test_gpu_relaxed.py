@@ -133,6 +133,26 @@ def test_relaxed_backward_in_passes(P, precision):
     assert np.abs(outs[0][1] - outs[1][1]).max() < 1e-10
 
 
+
+@pytest.mark.parametrize("passes", [1, 3])
+def test_relaxed_backward_bitwise_reproducible(P, passes):
+    """Gamma^{dc} is reduced class by class in a fixed order (no atomics), so
+    the relaxed gradient is the same bit for bit on a second call and in a
+    fresh context, in one pass and in several."""
+    n, na, nb, m, seed, eps2 = CASES[1]
+    h, g, V, e0, c, pt = setup_case(n, na, nb, m, seed, eps2)
+    npairs = len(pt["pairs"][1])
+    outs = []
+    for calls in (2, 1):  # two calls on one context, then one in a fresh context
+        ctx = P.HCIContext(h, g, na, nb)
+        if passes > 1:
+            ctx.set_pt2_budget(max(1, npairs // passes) * 128)
+        for _ in range(calls):
+            dh, dg, _, e2 = ctx.energy_backward(V, c, e0, eps2=eps2, z_tol=1e-11, precision="fp64", want_z=True)
+            outs.append((dh.cpu().numpy().tobytes(), dg.cpu().numpy().tobytes(), e2))
+        ctx.close()
+    assert outs[0] == outs[1] == outs[2]
+
 def test_energy_entry_point_and_frozen_pairs(P):
     """hci_energy returns E_var (the Davidson eigenvalue), E2 (as hci_pt2 at
     eps2) and their sum, computed in the library; over the pair set frozen by
