@@ -171,6 +171,15 @@ struct Integrals {
 };
 
 // Derived structure of one sorted determinant list V.
+// Row chunks (bucket, first row, end row) of a persistent grid of P
+// workgroups: workgroup p takes list[wptr[p] .. wptr[p + 1]) in that order.
+// The assignment balances an estimated cost and depends only on the space.
+struct RdmChunks {
+    DevMem list;  // u32 [n][3]
+    DevMem wptr;  // u32 [P + 1]
+    int P = 0;
+};
+
 struct Space {
     const u64* key_ptr = nullptr;  // caller's list address
     i64 N = 0;
@@ -221,9 +230,11 @@ struct Space {
     DevMem rc_chunk_b;    // u32 [rc_nch_b][3]: beta-bucket chunks (beta-major positions)
     i64 rc_nch_a = 0, rc_nch_b = 0;
     i64 rc_maxdeg = 0;    // largest alpha-single degree of a unique alpha string
-    DevMem rdm_cptr;      // u32 [nua + 1]: first workgroup of each bucket (density matrices)
+    // density matrices: row chunks of the alpha buckets (same alpha string,
+    // then alpha single x beta single) and of the beta buckets in beta-major
+    // order, each list assigned to the workgroups of a persistent grid
+    RdmChunks rdm_sa, rdm_nb, rdm_sb;
     DevMem alpha_b;       // u64 [N]: alpha word of each beta-major position (density matrices)
-    i64 rdm_nchunk = 0;
     bool st_have32 = false, st_have64 = false;
 };
 

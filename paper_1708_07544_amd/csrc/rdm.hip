@@ -12,7 +12,10 @@
 // pairs of the relaxed gradient (Gamma^{dc}) are sorted by excitation class
 // and reduced class by class.  No floating-point atomics anywhere, so the
 // result is the same bit for bit from run to run.
+#include <algorithm>
 #include <cstdlib>
+#include <queue>
+#include <vector>
 
 #include "slater.h"
 
@@ -315,230 +318,263 @@ __global__ void swap_sym_kernel(double* __restrict__ r2, int n) {
     r2[R * n2 + P] = v;
 }
 
-// ---------------------------------------------------------------- off-diagonal kernel
+// ---------------------------------------------------------------- off-diagonal kernels
 // Off-diagonal pairs (row i = bra determinant, j = ket determinant) without
-// atomics.  A persistent grid of P workgroups: workgroup p takes the chunks
-// c = p, p + P, ... (up to RDM_CHUNK rows of one alpha bucket A each) in that
-// order and owns a private copy of the output in global memory -- the
-// canonical half T of rdm2 (one entry of each (pq|rs), (rs|pq) pair, see
-// single_contrib) and rdm1; the P copies are then summed in a fixed order.
-// Inside a workgroup every accumulator has one writer at a time:
-//   * the chunk's rows are taken one after another for their same-alpha
-//     connections (beta single or double: the rows of bucket A) and then
-//     their same-beta connections (alpha single or double: the rows of the
-//     row's beta bucket), each row's candidates spread over all threads of
-//     the workgroup, with a barrier between the two classes and after each
-//     row.  One row's contributions of one class fall on distinct entries
-//     (distinct excitations), so each thread adds to its own: beta singles
-//     into the chunk's LDS sums [u][v] (and [u][v][k] for the same-spin
-//     spectators when they fit), alpha singles into one LDS slot per alpha
-//     neighbour of A with the beta-occupation moments (when they fit), the
-//     rest straight into the private copy;
-//   * then the wavefronts own the alpha neighbours A' of A (neighbour q goes
-//     to wavefront q mod waves) and accumulate the alpha single x beta single
-//     pairs of every row of the chunk with A' in an LDS tile [u2][v2] per
-//     neighbour, found through bitmaps of the beta strings present in each
-//     neighbour bucket (build_beta_maps) or by scanning the bucket;
-//   * the LDS sums reach the private copy class by class, separated by
-//     barriers (different classes can share an entry of the spin-traced
-//     output).
+// atomics.  Every kernel below runs a persistent grid of P workgroups over a
+// list of row chunks (up to RDM_CHUNK rows of one bucket each) that assigns
+// each chunk to one workgroup and balances an estimated cost (RdmChunks).
+// Workgroup p adds into its own private copy of the output in global memory
+// -- the canonical half T of rdm2 (one entry of each (pq|rs), (rs|pq) pair;
+// rdm2 = T + T^swap at the end) and rdm1 -- and the copies are summed in a
+// fixed order.  Inside a workgroup every entry has one writer at a time:
+//   * rdm_same_kernel, once over the alpha buckets (connections with the same
+//     alpha string: beta singles and doubles) and once over the beta buckets
+//     in beta-major order (the same beta string: alpha singles and doubles).
+//     The chunk's rows are staged in LDS and the bucket's candidates are read
+//     a piece at a time, one per thread; the rows are taken one after another, with a barrier after each row (one row's
+//     contributions fall on distinct entries, two rows' may not).  A single
+//     v -> u adds x to S2[u][v] (later rdm1[u][v] and the opposite-spin
+//     spectators, which the bucket's fixed string gives) and to S3[u][v][k]
+//     for the same-spin spectators k (in LDS when it fits, else straight into
+//     the copy); a double goes straight into the copy.
+//   * rdm_nb_kernel, over the alpha buckets: alpha single x beta single
+//     connections.  For a group of alpha neighbours A' of the chunk's bucket A
+//     the kernel keeps bitmaps of the beta strings present in each A'
+//     (build_beta_maps) and a tile [u2][v2] per A' (in LDS when it fits, else
+//     the entries of the copy that A' fixes); neighbour q is owned by
+//     wavefront q mod RDM_WAVES, whose memory operations take effect in
+//     program order.  The beta singles of a few rows at a time are staged in
+//     LDS, so the owner only tests its bitmap, gathers ket and adds.
 constexpr int RDM_BLOCK = 1024;
 constexpr int RDM_WAVES = RDM_BLOCK / HCI_WAVE;
 constexpr u32 RDM_CHUNK = 1024;
+constexpr u32 SS_PIECE = RDM_BLOCK;  // candidates of the bucket staged at a time: one per thread
 
-struct RdmPlan {
-    int n, G;               // G: alpha neighbours per group (bitmaps and tiles rebuilt per group)
-    bool tile;              // alpha single x beta single tiles in LDS (else straight into the copy)
-    bool s1a, b3;           // alpha-single slots / beta-single spectator block in LDS
-    int o_p11, o_s1a, o_s1b2, o_s1b3, total;  // offsets in doubles
-    int W;                  // beta-string bitmap words per neighbour (0: scan the buckets)
-    int o_bm;               // byte offset of the bitmaps (after the doubles)
-    int bytes;              // LDS of the workgroup
-};
-
-// position of the k-th set bit (k from 0) of s
-__device__ __forceinline__ int select_bit(u64 s, int k) {
-    for (int t = 0; t < k; ++t) s &= s - 1;
-    return ctz64(s);
-}
-
-// non-atomic update of an entry this thread alone writes at this moment
+// non-atomic update of an entry this thread (or wavefront) alone writes at this moment
 __device__ __forceinline__ void own_add(double* p, double v) { *p += v; }
 
-template <bool BM>
-__global__ void __launch_bounds__(RDM_BLOCK) rdm_det_kernel(SpaceView S, RdmPlan P, i64 nua, i64 nchunk,
-                                                            const u32* __restrict__ cptr,
-                                                            const double* __restrict__ bra,
-                                                            const double* __restrict__ ket,
-                                                            const u64* __restrict__ alpha_b,
-                                                            const double* __restrict__ ket_b,
-                                                            double* __restrict__ priv) {
+struct SameArgs {
+    int n;
+    const u32* list;    // chunks of this workgroup: list[wptr[p] .. wptr[p + 1])
+    const u32* wptr;
+    const u32* off;     // [nbuck + 1] first position of each bucket
+    const u64* xs;      // [nbuck] the fixed string of each bucket
+    const u64* ys;      // [N] the string of the excited spin at each position
+    const double* bra;  // [N] in the same order
+    const double* ket;
+    double* priv;
+    i64 stride;
+};
+
+// LDS: rows (string, bra) | S2 [n][n] | S3 [n][n][n]; a piece of candidates sits in
+// registers, one per thread
+template <bool S3>
+__global__ void __launch_bounds__(RDM_BLOCK) rdm_same_kernel(SameArgs G) {
     extern __shared__ double lds[];
-    __shared__ u32 sh[3];
+    const u32 tid = threadIdx.x;
+    const int n = G.n;
+    const int nn = n * n;
+    const i64 n4 = (i64)nn * nn;
+    u64* ry = reinterpret_cast<u64*>(lds);
+    double* rw = lds + RDM_CHUNK;
+    double* s2 = lds + 2 * RDM_CHUNK;
+    double* s3 = s2 + nn;
+    double* r2 = G.priv + (i64)blockIdx.x * G.stride;
+    double* r1 = r2 + n4;
+    const int nacc = nn + (S3 ? nn * n : 0);
+    for (u32 t = G.wptr[blockIdx.x]; t < G.wptr[blockIdx.x + 1]; ++t) {
+        const u32 bk = G.list[3 * (i64)t], row0 = G.list[3 * (i64)t + 1], row1 = G.list[3 * (i64)t + 2];
+        const u32 lo = G.off[bk], hi = G.off[bk + 1];
+        const u64 X = G.xs[bk];
+        const u32 nr = row1 - row0;
+        for (int x = (int)tid; x < nacc; x += RDM_BLOCK) s2[x] = 0.0;
+        for (u32 i = tid; i < nr; i += RDM_BLOCK) {
+            ry[i] = G.ys[row0 + i];
+            rw[i] = G.bra[row0 + i];
+        }
+        for (u32 p0 = lo; p0 < hi; p0 += SS_PIECE) {
+            const u32 np = min(SS_PIECE, hi - p0);
+            const bool have = tid < np;
+            u64 Yj = 0;
+            double kj = 0.0;
+            if (have) {
+                Yj = G.ys[p0 + tid];
+                kj = G.ket[p0 + tid];
+            }
+            __syncthreads();  // rows staged, accumulators cleared
+            for (u32 i = 0; i < nr; ++i) {
+                const double wb = rw[i];
+                if (wb == 0.0) continue;  // uniform
+                const u64 Yi = ry[i];
+                const u64 xy = Yi ^ Yj;  // 0 for the row itself
+                const int d = have ? popc64(xy) : 0;
+                if (d == 2) {
+                    const int u = ctz64(Yi & xy), v = ctz64(Yj & xy);
+                    const double x = wb * kj * sign_between(Yj, v, u);
+                    own_add(&s2[u * n + v], x);
+                    for (u64 m = Yi & Yj; m; m &= m - 1) {  // same-spin spectators
+                        const int k = ctz64(m);
+                        if constexpr (S3) {
+                            own_add(&s3[(u * n + v) * n + k], x);
+                        } else {
+                            own_add(&r2[r2idx(n, u, v, k, k)], x);
+                            own_add(&r2[r2idx(n, u, k, k, v)], -x);
+                        }
+                    }
+                } else if (d == 4) {
+                    u64 parts = Yi & xy, holes = Yj & xy;
+                    const int u1 = ctz64(parts);
+                    parts &= parts - 1;
+                    const int u2 = ctz64(parts);
+                    const int v1 = ctz64(holes);
+                    holes &= holes - 1;
+                    const int v2 = ctz64(holes);
+                    const double x = wb * kj * sign_double(Yj, v1, u1, v2, u2);
+                    own_add(&r2[r2idx(n, u1, v1, u2, v2)], x);
+                    own_add(&r2[r2idx(n, u1, v2, u2, v1)], -x);
+                }
+                __syncthreads();  // the next row may add to the same entries
+            }
+        }
+        // S2: rdm1 and the opposite-spin spectators (the bucket's fixed string)
+        for (int x = (int)tid; x < nn; x += RDM_BLOCK) {
+            const double val = s2[x];
+            if (val == 0.0) continue;
+            const int u = x / n, v = x % n;
+            own_add(&r1[x], val);
+            for (u64 m = X; m; m &= m - 1) own_add(&r2[r2idx(n, u, v, ctz64(m), ctz64(m))], val);
+        }
+        __syncthreads();  // S2 and S3 can meet on an entry
+        if constexpr (S3) {
+            for (int x = (int)tid; x < nn * n; x += RDM_BLOCK) {
+                const double val = s3[x];
+                if (val == 0.0) continue;  // (also every k = v entry)
+                const int u = x / nn, v = (x / n) % n, k = x % n;
+                own_add(&r2[r2idx(n, u, v, k, k)], val);
+                own_add(&r2[r2idx(n, u, k, k, v)], -val);
+            }
+        }
+        __syncthreads();  // LDS is reused by the next chunk
+    }
+}
+
+struct NbPlan {
+    int n, G;      // G: alpha neighbours per group (bitmaps and tiles rebuilt per group)
+    int W;         // beta-string bitmap words per neighbour (0: scan the neighbour buckets)
+    int R;         // rows whose beta singles are staged at a time
+    int ds;        // staged beta singles per row (the most a string has)
+    bool tile;     // tiles [u2][v2] in LDS (else straight into the copy)
+    int o_sing, o_row, o_nb, o_bm;  // byte offsets: singles, rows, neighbour info, bitmaps
+    int bytes;
+};
+
+constexpr u32 NB_NONE = 0xffffffffu;
+
+template <bool BM, bool TILE>
+__global__ void __launch_bounds__(RDM_BLOCK) rdm_nb_kernel(SpaceView S, NbPlan P, const u32* __restrict__ list,
+                                                           const u32* __restrict__ wptr,
+                                                           const double* __restrict__ bra,
+                                                           const double* __restrict__ ket, double* __restrict__ priv,
+                                                           i64 stride) {
+    extern __shared__ double lds[];
     const u32 tid = threadIdx.x;
     const int lane = lane_id();
     const u32 wave = tid / HCI_WAVE;
     const int n = P.n;
     const int nn = n * n;
     const i64 n4 = (i64)nn * nn;
-    double* r2 = priv + (i64)blockIdx.x * (n4 + nn);  // this workgroup's copy: T, then rdm1
-    double* r1 = r2 + n4;
-    double* p11 = lds + P.o_p11;
-    double* s1a = lds + P.o_s1a;
-    double* s1b2 = lds + P.o_s1b2;
-    double* s1b3 = lds + P.o_s1b3;
-    u32* bm = reinterpret_cast<u32*>(reinterpret_cast<unsigned char*>(lds) + P.o_bm);
+    unsigned char* base = reinterpret_cast<unsigned char*>(lds);
+    double* tiles = lds;  // [G][n][n] when TILE
+    uint2* sing = reinterpret_cast<uint2*>(base + P.o_sing);    // [R][ds]: (beta string, u2 * n + v2 | sign bit)
+    u64* rB = reinterpret_cast<u64*>(base + P.o_row);           // [R] beta string of the row
+    double* rW = reinterpret_cast<double*>(rB + P.R);            // [R] bra of the row
+    u32* nbl = reinterpret_cast<u32*>(base + P.o_nb);            // [G] first row of the neighbour bucket
+    u32* nbh = nbl + P.G;                                        // [G] end of it
+    u32* nbt = nbh + P.G;                                        // [G] u1 * n + v1
+    double* nbs = reinterpret_cast<double*>(nbt + ((P.G + 1) & ~1));  // [G] sign of the alpha single
+    u32* bm = reinterpret_cast<u32*>(base + P.o_bm);
     u16* pre = reinterpret_cast<u16*>(bm + (i64)P.G * P.W);
-    for (i64 ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-        if (tid == 0) {
-            // bucket of this chunk: the last a with cptr[a] <= ch
-            u32 lo = 0, hi = (u32)nua - 1u;
-            while (lo < hi) {
-                const u32 mid = (lo + hi + 1u) >> 1;
-                if (cptr[mid] <= (u32)ch) lo = mid;
-                else hi = mid - 1u;
-            }
-            const u32 r0 = S.aoff[lo] + ((u32)ch - cptr[lo]) * RDM_CHUNK;
-            sh[0] = lo;
-            sh[1] = r0;
-            sh[2] = min(r0 + RDM_CHUNK, S.aoff[lo + 1]);
-        }
-        for (int x = (int)tid; x < P.total; x += RDM_BLOCK) lds[x] = 0.0;
-        __syncthreads();
-        const u32 a = sh[0], row0 = sh[1], row1 = sh[2];
+    double* r2 = priv + (i64)blockIdx.x * stride;
+    if constexpr (TILE)
+        for (int x = (int)tid; x < P.G * nn; x += RDM_BLOCK) tiles[x] = 0.0;
+    for (u32 ct = wptr[blockIdx.x]; ct < wptr[blockIdx.x + 1]; ++ct) {
+        const u32 a = list[3 * (i64)ct], row0 = list[3 * (i64)ct + 1], row1 = list[3 * (i64)ct + 2];
         const u64 A = S.ua[a];
-        const u64 E = ~A & low_mask(n);  // empty alpha orbitals
         const u32 t0 = S.as_ptr[a];
         const u32 deg = S.as_ptr[a + 1] - t0;
-        const int nocc = popc64(A), nvir = n - nocc;
-        // same-string classes: one row at a time, its candidates spread over
-        // the whole workgroup (one row's contributions fall on distinct entries)
-        for (u32 row = row0; row < row1; ++row) {
-            const double wb = bra[row];
-            if (wb == 0.0) continue;  // wave-uniform
-            const u64 B = S.beta[row];
-            const u32 b = S.ib[row];
-            {  // same alpha: beta single or double
-                const u32 lo = S.aoff[a], hi = S.aoff[a + 1];
-                for (u32 j = lo + tid; j < hi; j += RDM_BLOCK) {
-                    const u64 bj = S.beta[j];
-                    const double kj = ket[j];
-                    const u64 xb = B ^ bj;  // 0 for the row itself
-                    const int d = popc64(xb);
-                    if (d == 2) {
-                        const int v = ctz64(bj & xb), u = ctz64(B & xb);
-                        const double x = wb * kj * sign_between(bj, v, u);
-                        own_add(&s1b2[u * n + v], x);
-                        for (u64 m = B & bj; m; m &= m - 1) {  // same-spin spectators
-                            const int k = ctz64(m);
-                            if (P.b3) {
-                                own_add(&s1b3[(u * n + v) * n + k], x);
-                            } else {
-                                own_add(&r2[r2idx(n, u, v, k, k)], x);
-                                own_add(&r2[r2idx(n, u, k, k, v)], -x);
-                            }
-                        }
-                    } else if (d == 4) {
-                        u64 holes = bj & xb, parts = B & xb;
-                        const int v1 = ctz64(holes);
-                        holes &= holes - 1;
-                        const int v2 = ctz64(holes);
-                        const int u1 = ctz64(parts);
-                        parts &= parts - 1;
-                        const int u2 = ctz64(parts);
-                        const double x = wb * kj * sign_double(bj, v1, u1, v2, u2);
-                        own_add(&r2[r2idx(n, u1, v1, u2, v2)], x);
-                        own_add(&r2[r2idx(n, u1, v2, u2, v1)], -x);
-                    }
-                }
-            }
-            __syncthreads();  // alpha and beta classes can meet on an entry
-            {  // same beta: alpha single or double
-                const u32 lo = S.boff[b], hi = S.boff[b + 1];
-                for (u32 k = lo + tid; k < hi; k += RDM_BLOCK) {
-                    // beta-major copies: the candidate's alpha word and ket coefficient
-                    const u64 aj = alpha_b[k];
-                    const double kj = ket_b[k];
-                    const u64 xa = A ^ aj;  // 0 for the row itself
-                    const int d = popc64(xa);
-                    if (d == 2) {
-                        const int v = ctz64(aj & xa), u = ctz64(A & xa);
-                        const double x = wb * kj * sign_between(aj, v, u);
-                        if (P.s1a) {
-                            double* slot = s1a + (i64)(rank_below(A, u) * nvir + rank_below(E, v)) * (1 + n);
-                            own_add(&slot[0], x);
-                            for (u64 m = B; m; m &= m - 1) own_add(&slot[1 + ctz64(m)], x);
-                        } else {
-                            own_add(&r1[u * n + v], x);
-                            for (u64 m = A & aj; m; m &= m - 1) {  // same-spin spectators
-                                const int kk = ctz64(m);
-                                own_add(&r2[r2idx(n, u, v, kk, kk)], x);
-                                own_add(&r2[r2idx(n, u, kk, kk, v)], -x);
-                            }
-                            for (u64 m = B; m; m &= m - 1) own_add(&r2[r2idx(n, u, v, ctz64(m), ctz64(m))], x);
-                        }
-                    } else if (d == 4) {
-                        u64 holes = aj & xa, parts = A & xa;
-                        const int v1 = ctz64(holes);
-                        holes &= holes - 1;
-                        const int v2 = ctz64(holes);
-                        const int u1 = ctz64(parts);
-                        parts &= parts - 1;
-                        const int u2 = ctz64(parts);
-                        const double x = wb * kj * sign_double(aj, v1, u1, v2, u2);
-                        own_add(&r2[r2idx(n, u1, v1, u2, v2)], x);
-                        own_add(&r2[r2idx(n, u1, v2, u2, v1)], -x);
-                    }
-                }
-            }
-            __syncthreads();  // the next row may add to the same entries
-        }
-        const u32 ngroups = deg == 0 ? 1u : (deg + (u32)P.G - 1u) / (u32)P.G;
-        for (u32 gi = 0; gi < ngroups; ++gi) {
-            const u32 tg0 = gi * (u32)P.G;
+        for (u32 tg0 = 0; tg0 < deg; tg0 += (u32)P.G) {
             const u32 tg1 = min(tg0 + (u32)P.G, deg);
+            const u32 nt = tg1 - tg0;
             if constexpr (BM) build_beta_maps<RDM_BLOCK>(S, t0, tg0, tg1, (u32)P.W, bm, pre, tid);
-            {
-                // alpha single x beta single for the neighbours of this group owned by this wavefront
-                for (u32 t = tg0 + wave; t < tg1; t += RDM_WAVES) {
-                    const u32 q = t - tg0;
-                    const u32 a2 = S.as_idx[t0 + t];
-                    const u64 A2 = S.ua[a2];
-                    const u64 xa = A ^ A2;
-                    const int u1 = ctz64(A & xa), v1 = ctz64(A2 & xa);
-                    const double sa = sign_between(A2, v1, u1);
-                    // the tile [u2][v2] of this neighbour: in LDS, or its entries of the copy
-                    double* tile = P.tile ? p11 + (i64)q * nn : r2 + r2idx(n, u1, v1, 0, 0);
-                    const u32 lo2 = S.aoff[a2], hi2 = S.aoff[a2 + 1];
-                    for (u32 row = row0; row < row1; ++row) {
-                        const double wb = bra[row];
-                        if (wb == 0.0) continue;  // wave-uniform
-                        const u64 B = S.beta[row];
-                        if constexpr (BM) {
-                            const u32 b = S.ib[row];
-                            const u32 s0 = S.bs_ptr[b], s1 = S.bs_ptr[b + 1];
-                            for (u32 base = s0; base < s1; base += HCI_WAVE) {
-                                const u32 k = base + lane;
-                                if (k >= s1) continue;
-                                const u32 bp = S.bs_idx[k];
-                                const u32 w = bp >> 5, bit = bp & 31u;
-                                const u32 word = bm[q * (u32)P.W + w];
+            for (u32 q = tid; q < nt; q += RDM_BLOCK) {
+                const u32 a2 = S.as_idx[t0 + tg0 + q];
+                const u64 A2 = S.ua[a2];
+                const u64 xa = A ^ A2;
+                const int u1 = ctz64(A & xa), v1 = ctz64(A2 & xa);
+                nbl[q] = S.aoff[a2];
+                nbh[q] = S.aoff[a2 + 1];
+                nbt[q] = (u32)(u1 * n + v1);
+                nbs[q] = sign_between(A2, v1, u1);
+            }
+            for (u32 s0 = row0; s0 < row1; s0 += (u32)P.R) {
+                const u32 nr = min((u32)P.R, row1 - s0);
+                __syncthreads();  // neighbour info written; the previous rows are done
+                for (u32 i = tid; i < nr; i += RDM_BLOCK) {
+                    rB[i] = S.beta[s0 + i];
+                    rW[i] = bra[s0 + i];
+                }
+                if constexpr (BM) {
+                    for (u32 x = tid; x < nr * (u32)P.ds; x += RDM_BLOCK) {
+                        const u32 i = x / (u32)P.ds, e = x % (u32)P.ds;
+                        const u32 b = S.ib[s0 + i];
+                        const u32 k = S.bs_ptr[b] + e;
+                        uint2 val = make_uint2(NB_NONE, 0u);
+                        if (k < S.bs_ptr[b + 1]) {
+                            const u32 bp = S.bs_idx[k];
+                            const u64 B = S.beta[s0 + i];
+                            const u64 bj = S.ub[bp];
+                            const u64 xb = B ^ bj;
+                            const int v2 = ctz64(bj & xb), u2 = ctz64(B & xb);
+                            const double sg = sign_between(bj, v2, u2);
+                            val = make_uint2(bp, (u32)(u2 * n + v2) | (sg < 0.0 ? 0x80000000u : 0u));
+                        }
+                        sing[x] = val;
+                    }
+                }
+                __syncthreads();
+                for (u32 q = wave; q < nt; q += RDM_WAVES) {
+                    const u32 lo2 = nbl[q];
+                    const double sa = nbs[q];
+                    const u32 t = nbt[q];
+                    double* tile = TILE ? tiles + (i64)q * nn : r2 + r2idx(n, (int)(t / (u32)n), (int)(t % (u32)n), 0, 0);
+                    if constexpr (BM) {
+                        const u32* bmq = bm + q * (u32)P.W;
+                        const u16* preq = pre + q * (u32)P.W;
+                        for (u32 i = 0; i < nr; ++i) {
+                            const double w = rW[i] * sa;
+                            if (w == 0.0) continue;  // uniform
+                            for (u32 e = (u32)lane; e < (u32)P.ds; e += HCI_WAVE) {
+                                const uint2 sv = sing[i * (u32)P.ds + e];
+                                if (sv.x == NB_NONE) continue;
+                                const u32 word = bmq[sv.x >> 5], bit = sv.x & 31u;
                                 if (((word >> bit) & 1u) == 0u) continue;
-                                const u64 bj = S.ub[bp];
-                                const u64 xb = B ^ bj;
-                                const int v2 = ctz64(bj & xb), u2 = ctz64(B & xb);
-                                const u32 j = lo2 + (u32)pre[q * (u32)P.W + w] + (u32)__popc(word & ((1u << bit) - 1u));
-                                own_add(&tile[u2 * n + v2], wb * ket[j] * sa * sign_between(bj, v2, u2));
+                                const u32 j = lo2 + (u32)preq[sv.x >> 5] + (u32)__popc(word & ((1u << bit) - 1u));
+                                const double x = w * ket[j];
+                                own_add(&tile[sv.y & 0x7fffffffu], (sv.y >> 31) ? -x : x);
                             }
-                        } else {
-                            for (u32 base = lo2; base < hi2; base += HCI_WAVE) {
-                                const u32 j = base + lane;
-                                if (j >= hi2) continue;
+                        }
+                    } else {  // scan the neighbour bucket
+                        const u32 hi2 = nbh[q];
+                        for (u32 i = 0; i < nr; ++i) {
+                            const double w = rW[i] * sa;
+                            if (w == 0.0) continue;  // uniform
+                            const u64 B = rB[i];
+                            for (u32 j = lo2 + (u32)lane; j < hi2; j += HCI_WAVE) {
                                 const u64 bj = S.beta[j];
                                 const u64 xb = B ^ bj;
                                 if (popc64(xb) != 2) continue;
                                 const int v2 = ctz64(bj & xb), u2 = ctz64(B & xb);
-                                own_add(&tile[u2 * n + v2], wb * ket[j] * sa * sign_between(bj, v2, u2));
+                                own_add(&tile[u2 * n + v2], w * ket[j] * sign_between(bj, v2, u2));
                             }
                         }
                     }
@@ -546,68 +582,18 @@ __global__ void __launch_bounds__(RDM_BLOCK) rdm_det_kernel(SpaceView S, RdmPlan
             }
             __syncthreads();
             // flush this group's tiles: neighbour q fixes (u1, v1)
-            for (int x = (int)tid; P.tile && x < (int)(tg1 - tg0) * nn; x += RDM_BLOCK) {
-                const double val = p11[x];
-                if (val == 0.0) continue;
-                p11[x] = 0.0;
-                const u32 t = tg0 + (u32)(x / nn);
-                const int u2 = (x % nn) / n, v2 = x % n;
-                const u64 A2 = S.ua[S.as_idx[t0 + t]];
-                const u64 xa = A ^ A2;
-                own_add(&r2[r2idx(n, ctz64(A & xa), ctz64(A2 & xa), u2, v2)], val);
-            }
-            __syncthreads();
-        }
-        // alpha singles (slot of the occupied orbital u and the empty orbital v
-        // of A): rdm1 and same-spin spectators from the sum, opposite-spin
-        // spectators from the beta-occupation moments
-        if (P.s1a) {
-            for (int q = (int)tid; q < nocc * nvir; q += RDM_BLOCK) {
-                const int u = select_bit(A, q / nvir), v = select_bit(E, q % nvir);
-                const double* slot = s1a + (i64)q * (1 + n);
-                const double X = slot[0];
-                if (X != 0.0) {
-                    own_add(&r1[u * n + v], X);
-                    for (u64 m = A; m; m &= m - 1) {
-                        const int k = ctz64(m);
-                        if (k == u) continue;
-                        own_add(&r2[r2idx(n, u, v, k, k)], X);
-                        own_add(&r2[r2idx(n, u, k, k, v)], -X);
-                    }
+            if constexpr (TILE) {
+                for (int x = (int)tid; x < (int)nt * nn; x += RDM_BLOCK) {
+                    const double val = tiles[x];
+                    if (val == 0.0) continue;
+                    tiles[x] = 0.0;
+                    const u32 t = nbt[x / nn];
+                    own_add(&r2[r2idx(n, (int)(t / (u32)n), (int)(t % (u32)n), 0, 0) + x % nn], val);
                 }
-                for (int k = 0; k < n; ++k) {
-                    const double Y = slot[1 + k];
-                    if (Y != 0.0) own_add(&r2[r2idx(n, u, v, k, k)], Y);
-                }
-            }
-            __syncthreads();
-        }
-        // beta singles: rdm1 and the alpha spectators from the sum
-        for (int x = (int)tid; x < nn; x += RDM_BLOCK) {
-            const double X = s1b2[x];
-            if (X == 0.0) continue;
-            const int u = x / n, v = x % n;
-            own_add(&r1[x], X);
-            for (u64 m = A; m; m &= m - 1) own_add(&r2[r2idx(n, u, v, ctz64(m), ctz64(m))], X);
-        }
-        __syncthreads();
-        if (P.b3) {
-            for (int x = (int)tid; x < nn * n; x += RDM_BLOCK) {
-                const double X = s1b3[x];
-                if (X == 0.0) continue;
-                const int u = x / nn, v = (x / n) % n, k = x % n;
-                own_add(&r2[r2idx(n, u, v, k, k)], X);
-                own_add(&r2[r2idx(n, u, k, k, v)], -X);
+                __syncthreads();
             }
         }
-        __syncthreads();
     }
-}
-
-__global__ void rdm_nchunk_kernel(const u32* __restrict__ aoff, i64 nua, u32* __restrict__ out) {
-    const i64 a = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a < nua) out[a] = (aoff[a + 1] - aoff[a] + RDM_CHUNK - 1) / RDM_CHUNK;
-    if (a == nua) out[a] = 0;
 }
 
 // beta-major copies: out[k] = in[permb[k]]
@@ -632,48 +618,44 @@ __global__ void rdm_sum_copies_kernel(const double* __restrict__ priv, int P, i6
     out[e] = s;
 }
 
-// LDS layout of the kernel for this context within `budget` bytes, with W
-// bitmap words per neighbour (0: scan the neighbour buckets).  Neighbour
-// groups should keep every wavefront busy (G >= RDM_WAVES): the tiles stay
-// in LDS only when they allow that, else they go straight into the private
-// copy (each entry still has one owner, the neighbour's wavefront); bitmaps
-// only when at least RDM_WAVES of them fit (else the buckets are scanned and
-// one group holds every neighbour).  False when W > 0 and the bitmaps do not
-// fit (the caller retries with W = 0).
-bool rdm_plan(int n, int na, int budget, int W, RdmPlan& P) {
-    const int dmax = na * (n - na);
+// LDS layout of rdm_nb_kernel within `budget` bytes, with W bitmap words per
+// neighbour (0: scan the neighbour buckets).  Groups should keep every
+// wavefront busy (G >= RDM_WAVES): tiles stay in LDS only when that holds,
+// else they go straight into the private copy (each entry still has one
+// owner, the neighbour's wavefront).  False when W > 0 and no group of
+// RDM_WAVES bitmaps fits (the caller retries with W = 0).
+bool nb_plan(int n, int na, int nb, int budget, int W, NbPlan& P) {
+    const int gmax = std::max(1, na * (n - na));  // alpha singles of a string
+    const int ds = std::max(1, nb * (n - nb));    // beta singles of a string
     const int nn = n * n;
     P.n = n;
     P.W = W;
-    int want = std::min(RDM_WAVES / 2, std::max(dmax, 1));
-    if (const char* e = std::getenv("HCI_RDM_GROUP_MIN")) {  // smallest acceptable group (tuning)
-        const int k = std::atoi(e);
-        if (k >= 1) want = std::min(k, std::max(dmax, 1));
-    }
-    auto place = [&](bool tile, bool s1a_lds, bool b3) -> bool {
-        const int s1a = s1a_lds ? dmax * (1 + n) : 0;
-        const int s1b3 = b3 ? nn * n : 0;
-        const int rest = s1a + nn + s1b3;
-        const int per = (tile ? 8 * nn : 0) + 6 * W;
-        int G = per > 0 ? (budget - 8 * rest) / per : (1 << 20);
-        if (G < want) return false;
-        if (G > dmax) G = dmax > 0 ? dmax : 1;
+    P.ds = ds;
+    P.R = W > 0 ? std::max(1, std::min<int>(RDM_CHUNK, 16384 / (8 * ds))) : 64;
+    const int fixed_sing = W > 0 ? 8 * P.R * ds : 0;
+    const int fixed_rows = 16 * P.R;
+    for (int tile = 1; tile >= 0; --tile) {
+        const int per = (tile ? 8 * nn : 0) + 6 * W + 24;
+        const int room = budget - fixed_sing - fixed_rows - 64;
+        int G = room / per;
+        if (G < RDM_WAVES && !(tile == 0 && W == 0)) continue;
+        if (G < 1) return false;
+        G = std::min(G, gmax);
         P.G = G;
-        P.tile = tile;
-        P.s1a = s1a_lds;
-        P.b3 = b3;
-        P.o_p11 = 0;
-        P.o_s1a = tile ? G * nn : 0;
-        P.o_s1b2 = P.o_s1a + s1a;
-        P.o_s1b3 = P.o_s1b2 + nn;
-        P.total = P.o_s1b3 + s1b3;
-        P.o_bm = 8 * P.total;
-        P.bytes = P.o_bm + ((6 * G * W + 15) & ~15);
-        return 8 * rest <= budget;
-    };
-    for (int tile = 1; tile >= 0; --tile)
-        for (int variant = 0; variant < 3; ++variant)
-            if (place(tile != 0, variant <= 1, variant == 0)) return true;
+        P.tile = tile != 0;
+        int off = P.tile ? 8 * G * nn : 0;
+        P.o_sing = off;
+        off += fixed_sing;
+        P.o_row = off;
+        off += fixed_rows;
+        P.o_nb = off;
+        off += 12 * G + 8 + 8 * G;
+        off = (off + 15) & ~15;
+        P.o_bm = off;
+        off += (6 * G * W + 15) & ~15;
+        P.bytes = off;
+        return P.bytes <= budget;
+    }
     return false;
 }
 
@@ -698,6 +680,59 @@ void rdm_add_diag(hci_ctx_s* ctx, const u64* alpha, const u64* beta, const doubl
                D.as<double>(), n, rdm1, rdm2);
 }
 
+namespace {
+// Row chunks of the buckets (off: nbuck + 1 offsets) assigned to P
+// workgroups: largest estimated cost first, each to the least loaded
+// workgroup (ties: lowest index), so the assignment depends only on the
+// space.  cost(bucket, rows) estimates a chunk's time.
+template <class Cost>
+void plan_chunks(hci_ctx_s* ctx, const u32* off_dev, i64 nbuck, int P, Cost cost, RdmChunks& C, hipStream_t s) {
+    std::vector<u32> off(nbuck + 1);
+    HIP_CHECK(hipMemcpyAsync(off.data(), off_dev, sizeof(u32) * (nbuck + 1), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    struct Ch {
+        u32 b, r0, r1;
+        double cost;
+    };
+    std::vector<Ch> ch;
+    for (i64 b = 0; b < nbuck; ++b)
+        for (u32 r0 = off[b]; r0 < off[b + 1]; r0 += RDM_CHUNK) {
+            const u32 r1 = std::min(r0 + RDM_CHUNK, off[b + 1]);
+            ch.push_back({(u32)b, r0, r1, cost((u32)b, off[b + 1] - off[b], r1 - r0)});
+        }
+    std::vector<u32> order(ch.size());
+    for (size_t i = 0; i < ch.size(); ++i) order[i] = (u32)i;
+    std::stable_sort(order.begin(), order.end(), [&](u32 x, u32 y) { return ch[x].cost > ch[y].cost; });
+    using Load = std::pair<double, int>;
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (int p = 0; p < P; ++p) heap.push({0.0, p});
+    std::vector<std::vector<u32>> per(P);
+    for (u32 i : order) {
+        Load l = heap.top();
+        heap.pop();
+        per[l.second].push_back(i);
+        l.first += ch[i].cost;
+        heap.push(l);
+    }
+    std::vector<u32> list, wptr(P + 1, 0);
+    list.reserve(3 * ch.size());
+    for (int p = 0; p < P; ++p) {
+        for (u32 i : per[p]) {
+            list.push_back(ch[i].b);
+            list.push_back(ch[i].r0);
+            list.push_back(ch[i].r1);
+        }
+        wptr[p + 1] = (u32)(list.size() / 3);
+    }
+    C.list = dev_alloc(ctx, sizeof(u32) * std::max<size_t>(list.size(), 3), s);
+    C.wptr = dev_alloc(ctx, sizeof(u32) * (P + 1), s);
+    HIP_CHECK(hipMemcpyAsync(C.list.ptr, list.data(), sizeof(u32) * list.size(), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(C.wptr.ptr, wptr.data(), sizeof(u32) * (P + 1), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipStreamSynchronize(s));  // the host vectors go out of scope
+    C.P = P;
+}
+}  // namespace
+
 void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket, double* rdm1,
                  double* rdm2, hipStream_t s) {
     const int n = ctx->n;
@@ -708,48 +743,74 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
     HIP_CHECK(hipGetDevice(&dev));
     HIP_CHECK(hipDeviceGetAttribute(&max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const int budget = std::min(79 * 1024, max_shared);  // two workgroups per CU
+    // same-string kernel: rows (16 B each), S2, S3 when it fits
+    const int same_base = 16 * (int)RDM_CHUNK + 8 * (int)n2;
+    const bool s3 = same_base + 8 * (int)(n2 * n) <= budget;
+    HCI_REQUIRE(same_base <= budget, HCI_E_UNSUPPORTED, "density matrices: no on-chip plan fits this orbital count");
+    const int same_bytes = same_base + (s3 ? 8 * (int)(n2 * n) : 0);
     const char* force_search = std::getenv("HCI_AB_SEARCH");  // "1": always search (tests)
     const int W = sp->nub <= 65535 && !(force_search && force_search[0] == '1') ? (int)ceil_div(sp->nub, 32) : 0;
-    RdmPlan P;
-    const bool planned = (W > 0 && rdm_plan(n, ctx->na, budget, W, P)) || rdm_plan(n, ctx->na, budget, 0, P);
+    NbPlan P;
+    const bool planned = (W > 0 && nb_plan(n, ctx->na, ctx->nb, budget, W, P)) ||
+                         nb_plan(n, ctx->na, ctx->nb, budget, 0, P);
     HCI_REQUIRE(planned, HCI_E_UNSUPPORTED, "density matrices: no on-chip plan fits this orbital count");
-    if (!sp->rdm_cptr.ptr) {
-        DevMem cnt = dev_alloc(ctx, sizeof(u32) * (sp->nua + 1), s);
-        HCI_LAUNCH(ctx, "rdm_nchunk", s, rdm_nchunk_kernel, ceil_div(sp->nua + 1, 256), 256, 0, sp->aoff.as<u32>(),
-                   sp->nua, cnt.as<u32>());
-        sp->rdm_cptr = dev_alloc(ctx, sizeof(u32) * (sp->nua + 1), s);
-        scan_u32_to_u32(ctx, cnt.as<u32>(), sp->rdm_cptr.as<u32>(), sp->nua + 1, s);
-        sp->rdm_nchunk = read_scalar(sp->rdm_cptr.as<u32>() + sp->nua, s);
-    }
-    // private copies of T and rdm1, one per workgroup of the persistent grid:
+    // private copies of T and rdm1, one per workgroup of the persistent grids:
     // two workgroups per CU, within 8 GiB of copies
     int cus = 0;
     HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const i64 stride = n4 + n2;
     const i64 by_mem = std::max<i64>(1, ((i64)8 << 30) / (stride * (i64)sizeof(double)));
-    const i64 Pw = std::max<i64>(1, std::min<i64>({(i64)2 * cus, by_mem, sp->rdm_nchunk}));
+    const int Pw = (int)std::max<i64>(1, std::min<i64>({(i64)2 * cus, by_mem, N}));
+    if (sp->rdm_sa.P != Pw) {
+        // a row of a same-string chunk costs a barrier per piece of its bucket;
+        // an alpha single x beta single chunk one pass per alpha neighbour
+        const u32 piece = SS_PIECE;
+        auto same_cost = [&](u32, u32 size, u32 rows) { return (double)rows * (1.0 + (double)ceil_div(size, piece)); };
+        plan_chunks(ctx, sp->aoff.as<u32>(), sp->nua, Pw, same_cost, sp->rdm_sa, s);
+        plan_chunks(ctx, sp->boff.as<u32>(), sp->nub, Pw, same_cost, sp->rdm_sb, s);
+        std::vector<u32> asp(sp->nua + 1);
+        HIP_CHECK(hipMemcpyAsync(asp.data(), sp->as_ptr.as<u32>(), sizeof(u32) * (sp->nua + 1), hipMemcpyDeviceToHost,
+                                 s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        auto nb_cost = [&](u32 b, u32, u32 rows) { return (double)rows * (1.0 + (double)(asp[b + 1] - asp[b])); };
+        plan_chunks(ctx, sp->aoff.as<u32>(), sp->nua, Pw, nb_cost, sp->rdm_nb, s);
+    }
     if (!sp->alpha_b.ptr) {  // alpha word of each beta-major position (cached with the space)
         sp->alpha_b = dev_alloc(ctx, sizeof(u64) * N, s);
         HCI_LAUNCH(ctx, "rdm_permute", s, rdm_permute_kernel<u64>, ceil_div(N, 256), 256, 0, sp->alpha.as<u64>(),
                    sp->permb.as<u32>(), N, sp->alpha_b.as<u64>());
     }
-    DevMem ket_b = dev_alloc(ctx, sizeof(double) * N, s);
+    DevMem ket_b = dev_alloc(ctx, sizeof(double) * N, s), bra_b = dev_alloc(ctx, sizeof(double) * N, s);
     HCI_LAUNCH(ctx, "rdm_permute", s, rdm_permute_kernel<double>, ceil_div(N, 256), 256, 0, ket, sp->permb.as<u32>(),
                N, ket_b.as<double>());
+    HCI_LAUNCH(ctx, "rdm_permute", s, rdm_permute_kernel<double>, ceil_div(N, 256), 256, 0, bra, sp->permb.as<u32>(),
+               N, bra_b.as<double>());
     DevMem priv = dev_alloc(ctx, sizeof(double) * Pw * stride, s);
     HCI_LAUNCH(ctx, "rdm_zero", s, rdm_zero_kernel, std::min<i64>(ceil_div(Pw * stride, 256), 65536), 256, 0,
                priv.as<double>(), Pw * stride);
-    auto kern = P.W ? rdm_det_kernel<true> : rdm_det_kernel<false>;
-    HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+    auto same = s3 ? rdm_same_kernel<true> : rdm_same_kernel<false>;
+    HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(same), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  same_bytes));
+    // same alpha string (beta singles and doubles), then same beta string in beta-major order
+    SameArgs ga{n, sp->rdm_sa.list.as<u32>(), sp->rdm_sa.wptr.as<u32>(), sp->aoff.as<u32>(), sp->ua.as<u64>(),
+                sp->beta.as<u64>(), bra, ket, priv.as<double>(), stride};
+    SameArgs gb{n, sp->rdm_sb.list.as<u32>(), sp->rdm_sb.wptr.as<u32>(), sp->boff.as<u32>(), sp->ub.as<u64>(),
+                sp->alpha_b.as<u64>(), bra_b.as<double>(), ket_b.as<double>(), priv.as<double>(), stride};
+    HCI_LAUNCH(ctx, "rdm_same", s, same, Pw, RDM_BLOCK, (size_t)same_bytes, ga);
+    HCI_LAUNCH(ctx, "rdm_same", s, same, Pw, RDM_BLOCK, (size_t)same_bytes, gb);
+    // alpha single x beta single
+    auto nbk = P.W ? (P.tile ? rdm_nb_kernel<true, true> : rdm_nb_kernel<true, false>)
+                   : (P.tile ? rdm_nb_kernel<false, true> : rdm_nb_kernel<false, false>);
+    HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(nbk), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   P.bytes));
-    HCI_LAUNCH(ctx, "rdm_offdiag", s, kern, Pw, RDM_BLOCK, (size_t)P.bytes, S, P, sp->nua, sp->rdm_nchunk,
-               sp->rdm_cptr.as<u32>(), bra, ket, sp->alpha_b.as<u64>(), ket_b.as<double>(), priv.as<double>());
+    HCI_LAUNCH(ctx, "rdm_nb", s, nbk, Pw, RDM_BLOCK, (size_t)P.bytes, S, P, sp->rdm_nb.list.as<u32>(),
+               sp->rdm_nb.wptr.as<u32>(), bra, ket, priv.as<double>(), stride);
     HCI_LAUNCH(ctx, "rdm_sum", s, rdm_sum_copies_kernel, ceil_div(n2, 256), 256, 0, priv.as<double>() + n4, (int)Pw,
                stride, n2, rdm1);
     if (rdm2) {
         HCI_LAUNCH(ctx, "rdm_sum", s, rdm_sum_copies_kernel, ceil_div(n4, 256), 256, 0, priv.as<double>(), (int)Pw,
                    stride, n4, rdm2);
-        // the off-diagonal pass accumulates one entry of each (pq|rs), (rs|pq) pair
+        // the off-diagonal passes accumulate one entry of each (pq|rs), (rs|pq) pair
         HCI_LAUNCH(ctx, "rdm_swap_sym", s, swap_sym_kernel, ceil_div(n4, 256), 256, 0, rdm2, n);
     }
     rdm_add_diag(ctx, sp->alpha.as<u64>(), sp->beta.as<u64>(), bra, ket, N, rdm1, rdm2, s);

@@ -340,9 +340,10 @@ def test_stage_window_rejects_bad_values(cas8, lib_mod):
 
 @pytest.mark.parametrize("n,na,nb,m", [(20, 10, 9, 500), (24, 12, 12, 300), (44, 22, 22, 20)])
 def test_rdm_larger_orbital_counts(lib_mod, n, na, nb, m):
-    """Density matrices where the on-chip accumulators shrink (n = 20: no
-    same-spin spectator block; n = 24: no alpha-double slots) or do not fit
-    (n = 44: per-pair global accumulation), against the oracle."""
+    """Density matrices where the on-chip accumulators shrink or do not fit
+    (n = 20: the same-spin spectator sums go straight into the private copies;
+    n = 24 and 44: so do the alpha single x beta single tiles), against the
+    oracle; a second call gives the same bytes."""
     h, g = hs.make_integrals(n, 3 * n, n)
     V = hs.random_dets(n, na, nb, m, seed=n, bias=0.1)
     bra = hs.random_coeffs(len(V), n)
@@ -353,3 +354,6 @@ def test_rdm_larger_orbital_counts(lib_mod, n, na, nb, m):
     o1, o2 = O.rdm12(n, V, bra, ket)
     assert np.abs(r1.cpu().numpy() - o1).max() < 1e-11
     assert np.abs(r2.cpu().numpy() - o2).max() < 1e-11
+    s1, s2 = ctx.rdm12(V, bra, ket)
+    assert s1.cpu().numpy().tobytes() == r1.cpu().numpy().tobytes()
+    assert s2.cpu().numpy().tobytes() == r2.cpu().numpy().tobytes()
