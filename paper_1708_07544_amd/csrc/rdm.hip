@@ -348,7 +348,8 @@ __global__ void swap_sym_kernel(double* __restrict__ r2, int n) {
 constexpr int RDM_BLOCK = 1024;
 constexpr int RDM_WAVES = RDM_BLOCK / HCI_WAVE;
 constexpr u32 RDM_CHUNK = 1024;
-constexpr u32 SS_PIECE = RDM_BLOCK;  // candidates of the bucket staged at a time: one per thread
+constexpr int SS_PER_THREAD = 4;     // bucket candidates held per thread
+constexpr u32 SS_PIECE = SS_PER_THREAD * RDM_BLOCK;  // candidates of the bucket taken at a time
 
 // non-atomic update of an entry this thread (or wavefront) alone writes at this moment
 __device__ __forceinline__ void own_add(double* p, double v) { *p += v; }
@@ -367,7 +368,7 @@ struct SameArgs {
 };
 
 // LDS: rows (string, bra) | S2 [n][n] | S3 [n][n][n]; a piece of candidates sits in
-// registers, one per thread
+// registers, up to SS_PER_THREAD per thread
 template <bool S3>
 __global__ void __launch_bounds__(RDM_BLOCK) rdm_same_kernel(SameArgs G) {
     extern __shared__ double lds[];
@@ -394,44 +395,49 @@ __global__ void __launch_bounds__(RDM_BLOCK) rdm_same_kernel(SameArgs G) {
         }
         for (u32 p0 = lo; p0 < hi; p0 += SS_PIECE) {
             const u32 np = min(SS_PIECE, hi - p0);
-            const bool have = tid < np;
-            u64 Yj = 0;
-            double kj = 0.0;
-            if (have) {
-                Yj = G.ys[p0 + tid];
-                kj = G.ket[p0 + tid];
+            u64 Yc[SS_PER_THREAD];
+            double kc[SS_PER_THREAD];
+#pragma unroll
+            for (int t = 0; t < SS_PER_THREAD; ++t) {
+                const u32 j = tid + (u32)t * RDM_BLOCK;
+                Yc[t] = j < np ? G.ys[p0 + j] : 0ull;
+                kc[t] = j < np ? G.ket[p0 + j] : 0.0;
             }
             __syncthreads();  // rows staged, accumulators cleared
             for (u32 i = 0; i < nr; ++i) {
                 const double wb = rw[i];
                 if (wb == 0.0) continue;  // uniform
                 const u64 Yi = ry[i];
-                const u64 xy = Yi ^ Yj;  // 0 for the row itself
-                const int d = have ? popc64(xy) : 0;
-                if (d == 2) {
-                    const int u = ctz64(Yi & xy), v = ctz64(Yj & xy);
-                    const double x = wb * kj * sign_between(Yj, v, u);
-                    own_add(&s2[u * n + v], x);
-                    for (u64 m = Yi & Yj; m; m &= m - 1) {  // same-spin spectators
-                        const int k = ctz64(m);
-                        if constexpr (S3) {
-                            own_add(&s3[(u * n + v) * n + k], x);
-                        } else {
-                            own_add(&r2[r2idx(n, u, v, k, k)], x);
-                            own_add(&r2[r2idx(n, u, k, k, v)], -x);
+#pragma unroll
+                for (int t = 0; t < SS_PER_THREAD; ++t) {
+                    const u64 Yj = Yc[t];
+                    const u64 xy = Yi ^ Yj;  // 0 for the row itself
+                    const int d = tid + (u32)t * RDM_BLOCK < np ? popc64(xy) : 0;
+                    if (d == 2) {
+                        const int u = ctz64(Yi & xy), v = ctz64(Yj & xy);
+                        const double x = wb * kc[t] * sign_between(Yj, v, u);
+                        own_add(&s2[u * n + v], x);
+                        for (u64 m = Yi & Yj; m; m &= m - 1) {  // same-spin spectators
+                            const int k = ctz64(m);
+                            if constexpr (S3) {
+                                own_add(&s3[(u * n + v) * n + k], x);
+                            } else {
+                                own_add(&r2[r2idx(n, u, v, k, k)], x);
+                                own_add(&r2[r2idx(n, u, k, k, v)], -x);
+                            }
                         }
+                    } else if (d == 4) {
+                        u64 parts = Yi & xy, holes = Yj & xy;
+                        const int u1 = ctz64(parts);
+                        parts &= parts - 1;
+                        const int u2 = ctz64(parts);
+                        const int v1 = ctz64(holes);
+                        holes &= holes - 1;
+                        const int v2 = ctz64(holes);
+                        const double x = wb * kc[t] * sign_double(Yj, v1, u1, v2, u2);
+                        own_add(&r2[r2idx(n, u1, v1, u2, v2)], x);
+                        own_add(&r2[r2idx(n, u1, v2, u2, v1)], -x);
                     }
-                } else if (d == 4) {
-                    u64 parts = Yi & xy, holes = Yj & xy;
-                    const int u1 = ctz64(parts);
-                    parts &= parts - 1;
-                    const int u2 = ctz64(parts);
-                    const int v1 = ctz64(holes);
-                    holes &= holes - 1;
-                    const int v2 = ctz64(holes);
-                    const double x = wb * kj * sign_double(Yj, v1, u1, v2, u2);
-                    own_add(&r2[r2idx(n, u1, v1, u2, v2)], x);
-                    own_add(&r2[r2idx(n, u1, v2, u2, v1)], -x);
                 }
                 __syncthreads();  // the next row may add to the same entries
             }
