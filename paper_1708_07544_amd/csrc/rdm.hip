@@ -331,12 +331,16 @@ __global__ void swap_sym_kernel(double* __restrict__ r2, int n) {
 //     alpha string: beta singles and doubles) and once over the beta buckets
 //     in beta-major order (the same beta string: alpha singles and doubles).
 //     The chunk's rows are staged in LDS and the bucket's candidates are read
-//     a piece at a time, one per thread; the rows are taken one after another, with a barrier after each row (one row's
-//     contributions fall on distinct entries, two rows' may not).  A single
-//     v -> u adds x to S2[u][v] (later rdm1[u][v] and the opposite-spin
-//     spectators, which the bucket's fixed string gives) and to S3[u][v][k]
-//     for the same-spin spectators k (in LDS when it fits, else straight into
-//     the copy); a double goes straight into the copy.
+//     a piece at a time, up to SS_PER_THREAD per thread; the rows are taken
+//     one after another, with a barrier after each row (one row's
+//     contributions fall on distinct entries, two rows' may not), and each
+//     wavefront gathers a row's connections among its candidates into a
+//     queue so the contribution code runs once per row.  A single v -> u
+//     adds x to S2[u][v] (later rdm1[u][v] and the opposite-spin spectators,
+//     which the bucket's fixed string gives) and to S3[u][v][k] for the
+//     same-spin spectators k (in LDS when it fits, else straight into the
+//     copy); a double goes into an LDS table of the particle and hole pairs
+//     when it fits (small n), else straight into the copy.
 //   * rdm_nb_kernel, over the alpha buckets: alpha single x beta single
 //     connections.  For a group of alpha neighbours A' of the chunk's bucket A
 //     the kernel keeps bitmaps of the beta strings present in each A'
@@ -354,6 +358,29 @@ constexpr u32 SS_PIECE = SS_PER_THREAD * RDM_BLOCK;  // candidates of the bucket
 // non-atomic update of an entry this thread (or wavefront) alone writes at this moment
 __device__ __forceinline__ void own_add(double* p, double v) { *p += v; }
 
+// Candidates of one row gathered per wavefront: slot l in lane l (the
+// candidate's string and ket coefficient), filled from a ballot mask by
+// shuffles; every lane calls push together.
+struct HitQueue {
+    int n = 0;  // queued, wave-uniform
+    u64 y = 0;
+    double w = 0.0;
+    __device__ __forceinline__ bool full_for(u64 m) const { return n + popc64(m) > HCI_WAVE; }
+    __device__ __forceinline__ void push(u64 m, u64 yy, double ww) {
+        const int cnt = popc64(m);
+        const int l = lane_id();
+        const bool mine = l >= n && l < n + cnt;
+        const int src = mine ? nth_set_bit(m, l - n) : l;
+        const u64 sy = __shfl(yy, src, HCI_WAVE);
+        const double sw = __shfl(ww, src, HCI_WAVE);
+        if (mine) {
+            y = sy;
+            w = sw;
+        }
+        n += cnt;
+    }
+};
+
 struct SameArgs {
     int n;
     const u32* list;    // chunks of this workgroup: list[wptr[p] .. wptr[p + 1])
@@ -367,32 +394,40 @@ struct SameArgs {
     i64 stride;
 };
 
-// LDS: rows (string, bra) | S2 [n][n] | S3 [n][n][n]; a piece of candidates sits in
-// registers, up to SS_PER_THREAD per thread
-template <bool S3>
+// LDS: rows (string, bra) | S2 [n][n] | S3 [n][n][n] | XD [P][P] | pair table; a piece of
+// candidates sits in registers, up to SS_PER_THREAD per thread.  With DX (small
+// n: the whole table fits on chip, one workgroup per CU) the doubles add into
+// XD, indexed by the particle pair u1 < u2 and the hole pair v1 < v2 (P = n(n-1)/2
+// pairs), instead of the private copy, so no row waits for global memory.
+template <bool S3, bool DX>
 __global__ void __launch_bounds__(RDM_BLOCK) rdm_same_kernel(SameArgs G) {
     extern __shared__ double lds[];
+    constexpr u32 RS = DX ? RDM_CHUNK / 2 : RDM_CHUNK;  // rows staged at a time
     const u32 tid = threadIdx.x;
     const int n = G.n;
     const int nn = n * n;
+    const int np2 = n * (n - 1) / 2;
     const i64 n4 = (i64)nn * nn;
     u64* ry = reinterpret_cast<u64*>(lds);
-    double* rw = lds + RDM_CHUNK;
-    double* s2 = lds + 2 * RDM_CHUNK;
+    double* rw = lds + RS;
+    double* s2 = lds + 2 * RS;
     double* s3 = s2 + nn;
+    double* xd = s3 + (S3 ? nn * n : 0);
+    u16* pairs = reinterpret_cast<u16*>(xd + (DX ? np2 * np2 : 0));  // pair index -> a | b << 8
     double* r2 = G.priv + (i64)blockIdx.x * G.stride;
     double* r1 = r2 + n4;
     const int nacc = nn + (S3 ? nn * n : 0);
+    if constexpr (DX) {
+        for (int x = (int)tid; x < np2 * np2; x += RDM_BLOCK) xd[x] = 0.0;
+        for (int b = 1; b < n; ++b)
+            for (int a = (int)tid; a < b; a += RDM_BLOCK) pairs[b * (b - 1) / 2 + a] = (u16)(a | b << 8);
+    }
     for (u32 t = G.wptr[blockIdx.x]; t < G.wptr[blockIdx.x + 1]; ++t) {
         const u32 bk = G.list[3 * (i64)t], row0 = G.list[3 * (i64)t + 1], row1 = G.list[3 * (i64)t + 2];
         const u32 lo = G.off[bk], hi = G.off[bk + 1];
         const u64 X = G.xs[bk];
-        const u32 nr = row1 - row0;
+        const u32 nrow = row1 - row0;
         for (int x = (int)tid; x < nacc; x += RDM_BLOCK) s2[x] = 0.0;
-        for (u32 i = tid; i < nr; i += RDM_BLOCK) {
-            ry[i] = G.ys[row0 + i];
-            rw[i] = G.bra[row0 + i];
-        }
         for (u32 p0 = lo; p0 < hi; p0 += SS_PIECE) {
             const u32 np = min(SS_PIECE, hi - p0);
             u64 Yc[SS_PER_THREAD];
@@ -403,43 +438,70 @@ __global__ void __launch_bounds__(RDM_BLOCK) rdm_same_kernel(SameArgs G) {
                 Yc[t] = j < np ? G.ys[p0 + j] : 0ull;
                 kc[t] = j < np ? G.ket[p0 + j] : 0.0;
             }
-            __syncthreads();  // rows staged, accumulators cleared
-            for (u32 i = 0; i < nr; ++i) {
-                const double wb = rw[i];
-                if (wb == 0.0) continue;  // uniform
-                const u64 Yi = ry[i];
-#pragma unroll
-                for (int t = 0; t < SS_PER_THREAD; ++t) {
-                    const u64 Yj = Yc[t];
-                    const u64 xy = Yi ^ Yj;  // 0 for the row itself
-                    const int d = tid + (u32)t * RDM_BLOCK < np ? popc64(xy) : 0;
-                    if (d == 2) {
-                        const int u = ctz64(Yi & xy), v = ctz64(Yj & xy);
-                        const double x = wb * kc[t] * sign_between(Yj, v, u);
-                        own_add(&s2[u * n + v], x);
-                        for (u64 m = Yi & Yj; m; m &= m - 1) {  // same-spin spectators
-                            const int k = ctz64(m);
-                            if constexpr (S3) {
-                                own_add(&s3[(u * n + v) * n + k], x);
+            for (u32 rs0 = 0; rs0 < nrow; rs0 += RS) {
+                const u32 nr = min(RS, nrow - rs0);
+                __syncthreads();  // the previous rows are done (and the accumulators cleared)
+                for (u32 i = tid; i < nr; i += RDM_BLOCK) {
+                    ry[i] = G.ys[row0 + rs0 + i];
+                    rw[i] = G.bra[row0 + rs0 + i];
+                }
+                __syncthreads();
+                for (u32 i = 0; i < nr; ++i) {
+                    const double wb = rw[i];
+                    if (wb == 0.0) continue;  // uniform
+                    const u64 Yi = ry[i];
+                    // the row's connections among this thread's candidates, gathered per
+                    // wavefront (slot l in lane l) so the contribution code runs once for
+                    // up to 64 of them; they are distinct excitations, so distinct entries
+                    HitQueue q;
+                    auto contribute = [&]() {
+                        if (lane_id() < q.n) {
+                            const u64 Yj = q.y;
+                            const u64 xy = Yi ^ Yj;
+                            if (popc64(xy) == 2) {
+                                const int u = ctz64(Yi & xy), v = ctz64(Yj & xy);
+                                const double x = wb * q.w * sign_between(Yj, v, u);
+                                own_add(&s2[u * n + v], x);
+                                for (u64 m = Yi & Yj; m; m &= m - 1) {  // same-spin spectators
+                                    const int k = ctz64(m);
+                                    if constexpr (S3) {
+                                        own_add(&s3[(u * n + v) * n + k], x);
+                                    } else {
+                                        own_add(&r2[r2idx(n, u, v, k, k)], x);
+                                        own_add(&r2[r2idx(n, u, k, k, v)], -x);
+                                    }
+                                }
                             } else {
-                                own_add(&r2[r2idx(n, u, v, k, k)], x);
-                                own_add(&r2[r2idx(n, u, k, k, v)], -x);
+                                u64 parts = Yi & xy, holes = Yj & xy;
+                                const int u1 = ctz64(parts);
+                                parts &= parts - 1;
+                                const int u2 = ctz64(parts);
+                                const int v1 = ctz64(holes);
+                                holes &= holes - 1;
+                                const int v2 = ctz64(holes);
+                                const double x = wb * q.w * sign_double(Yj, v1, u1, v2, u2);
+                                if constexpr (DX) {
+                                    own_add(&xd[(u2 * (u2 - 1) / 2 + u1) * np2 + v2 * (v2 - 1) / 2 + v1], x);
+                                } else {
+                                    own_add(&r2[r2idx(n, u1, v1, u2, v2)], x);
+                                    own_add(&r2[r2idx(n, u1, v2, u2, v1)], -x);
+                                }
                             }
                         }
-                    } else if (d == 4) {
-                        u64 parts = Yi & xy, holes = Yj & xy;
-                        const int u1 = ctz64(parts);
-                        parts &= parts - 1;
-                        const int u2 = ctz64(parts);
-                        const int v1 = ctz64(holes);
-                        holes &= holes - 1;
-                        const int v2 = ctz64(holes);
-                        const double x = wb * kc[t] * sign_double(Yj, v1, u1, v2, u2);
-                        own_add(&r2[r2idx(n, u1, v1, u2, v2)], x);
-                        own_add(&r2[r2idx(n, u1, v2, u2, v1)], -x);
+                        q.n = 0;
+                    };
+#pragma unroll
+                    for (int t = 0; t < SS_PER_THREAD; ++t) {
+                        const int d = tid + (u32)t * RDM_BLOCK < np ? popc64(Yi ^ Yc[t]) : 0;  // 0 for the row itself
+                        const u64 m = ballot(d == 2 || d == 4);
+                        if (m) {
+                            if (q.full_for(m)) contribute();
+                            q.push(m, Yc[t], kc[t]);
+                        }
                     }
+                    if (q.n) contribute();
+                    __syncthreads();  // the next row may add to the same entries
                 }
-                __syncthreads();  // the next row may add to the same entries
             }
         }
         // S2: rdm1 and the opposite-spin spectators (the bucket's fixed string)
@@ -458,6 +520,18 @@ __global__ void __launch_bounds__(RDM_BLOCK) rdm_same_kernel(SameArgs G) {
                 const int u = x / nn, v = (x / n) % n, k = x % n;
                 own_add(&r2[r2idx(n, u, v, k, k)], val);
                 own_add(&r2[r2idx(n, u, k, k, v)], -val);
+            }
+        }
+        if constexpr (DX) {
+            // doubles: [u1 v1 u2 v2] += X and [u1 v2 u2 v1] -= X, distinct entries for distinct pairs
+            for (int x = (int)tid; x < np2 * np2; x += RDM_BLOCK) {
+                const double val = xd[x];
+                if (val == 0.0) continue;
+                xd[x] = 0.0;
+                const u32 pu = pairs[x / np2], pv = pairs[x % np2];
+                const int u1 = (int)(pu & 0xffu), u2 = (int)(pu >> 8), v1 = (int)(pv & 0xffu), v2 = (int)(pv >> 8);
+                own_add(&r2[r2idx(n, u1, v1, u2, v2)], val);
+                own_add(&r2[r2idx(n, u1, v2, u2, v1)], -val);
             }
         }
         __syncthreads();  // LDS is reused by the next chunk
@@ -749,11 +823,15 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
     HIP_CHECK(hipGetDevice(&dev));
     HIP_CHECK(hipDeviceGetAttribute(&max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const int budget = std::min(79 * 1024, max_shared);  // two workgroups per CU
-    // same-string kernel: rows (16 B each), S2, S3 when it fits
+    // same-string kernel: rows (16 B each), S2, S3 when it fits; for small n the
+    // table of doubles too (then one workgroup per CU, half the rows staged)
+    const int np2 = n * (n - 1) / 2;
+    const int dx_bytes = 8 * (int)RDM_CHUNK + 8 * (int)(n2 + n2 * n) + 8 * np2 * np2 + ((2 * np2 + 15) & ~15);
+    const bool dx = dx_bytes <= max_shared;
     const int same_base = 16 * (int)RDM_CHUNK + 8 * (int)n2;
-    const bool s3 = same_base + 8 * (int)(n2 * n) <= budget;
+    const bool s3 = dx || same_base + 8 * (int)(n2 * n) <= budget;
     HCI_REQUIRE(same_base <= budget, HCI_E_UNSUPPORTED, "density matrices: no on-chip plan fits this orbital count");
-    const int same_bytes = same_base + (s3 ? 8 * (int)(n2 * n) : 0);
+    const int same_bytes = dx ? dx_bytes : same_base + (s3 ? 8 * (int)(n2 * n) : 0);
     const char* force_search = std::getenv("HCI_AB_SEARCH");  // "1": always search (tests)
     const int W = sp->nub <= 65535 && !(force_search && force_search[0] == '1') ? (int)ceil_div(sp->nub, 32) : 0;
     NbPlan P;
@@ -767,13 +845,17 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
     const i64 stride = n4 + n2;
     const i64 by_mem = std::max<i64>(1, ((i64)8 << 30) / (stride * (i64)sizeof(double)));
     const int Pw = (int)std::max<i64>(1, std::min<i64>({(i64)2 * cus, by_mem, N}));
-    if (sp->rdm_sa.P != Pw) {
-        // a row of a same-string chunk costs a barrier per piece of its bucket;
-        // an alpha single x beta single chunk one pass per alpha neighbour
+    // the same-string kernel with the table of doubles holds a CU alone: as many
+    // workgroups as CUs, each with a longer list
+    const int Ps = dx ? std::min(Pw, cus) : Pw;
+    if (sp->rdm_sa.P != Ps || sp->rdm_nb.P != Pw) {
+        // a row of a same-string chunk costs a barrier per piece of its bucket
+        // (and a chunk about two rows for its flush); an alpha single x beta
+        // single chunk one pass per alpha neighbour
         const u32 piece = SS_PIECE;
-        auto same_cost = [&](u32, u32 size, u32 rows) { return (double)rows * (1.0 + (double)ceil_div(size, piece)); };
-        plan_chunks(ctx, sp->aoff.as<u32>(), sp->nua, Pw, same_cost, sp->rdm_sa, s);
-        plan_chunks(ctx, sp->boff.as<u32>(), sp->nub, Pw, same_cost, sp->rdm_sb, s);
+        auto same_cost = [&](u32, u32 size, u32 rows) { return (double)rows * (double)ceil_div(size, piece) + 2.0; };
+        plan_chunks(ctx, sp->aoff.as<u32>(), sp->nua, Ps, same_cost, sp->rdm_sa, s);
+        plan_chunks(ctx, sp->boff.as<u32>(), sp->nub, Ps, same_cost, sp->rdm_sb, s);
         std::vector<u32> asp(sp->nua + 1);
         HIP_CHECK(hipMemcpyAsync(asp.data(), sp->as_ptr.as<u32>(), sizeof(u32) * (sp->nua + 1), hipMemcpyDeviceToHost,
                                  s));
@@ -794,7 +876,7 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
     DevMem priv = dev_alloc(ctx, sizeof(double) * Pw * stride, s);
     HCI_LAUNCH(ctx, "rdm_zero", s, rdm_zero_kernel, std::min<i64>(ceil_div(Pw * stride, 256), 65536), 256, 0,
                priv.as<double>(), Pw * stride);
-    auto same = s3 ? rdm_same_kernel<true> : rdm_same_kernel<false>;
+    auto same = dx ? rdm_same_kernel<true, true> : s3 ? rdm_same_kernel<true, false> : rdm_same_kernel<false, false>;
     HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(same), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   same_bytes));
     // same alpha string (beta singles and doubles), then same beta string in beta-major order
@@ -802,8 +884,8 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
                 sp->beta.as<u64>(), bra, ket, priv.as<double>(), stride};
     SameArgs gb{n, sp->rdm_sb.list.as<u32>(), sp->rdm_sb.wptr.as<u32>(), sp->boff.as<u32>(), sp->ub.as<u64>(),
                 sp->alpha_b.as<u64>(), bra_b.as<double>(), ket_b.as<double>(), priv.as<double>(), stride};
-    HCI_LAUNCH(ctx, "rdm_same", s, same, Pw, RDM_BLOCK, (size_t)same_bytes, ga);
-    HCI_LAUNCH(ctx, "rdm_same", s, same, Pw, RDM_BLOCK, (size_t)same_bytes, gb);
+    HCI_LAUNCH(ctx, "rdm_same", s, same, Ps, RDM_BLOCK, (size_t)same_bytes, ga);
+    HCI_LAUNCH(ctx, "rdm_same", s, same, Ps, RDM_BLOCK, (size_t)same_bytes, gb);
     // alpha single x beta single
     auto nbk = P.W ? (P.tile ? rdm_nb_kernel<true, true> : rdm_nb_kernel<true, false>)
                    : (P.tile ? rdm_nb_kernel<false, true> : rdm_nb_kernel<false, false>);
