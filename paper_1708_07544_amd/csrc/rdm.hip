@@ -351,6 +351,8 @@ __global__ void swap_sym_kernel(double* __restrict__ r2, int n) {
 //     LDS, so the owner only tests its bitmap, gathers ket and adds.
 constexpr int RDM_BLOCK = 1024;
 constexpr int RDM_WAVES = RDM_BLOCK / HCI_WAVE;
+// two workgroups of 16 wavefronts per CU: 8 per SIMD, which caps the kernels at 64 VGPRs
+constexpr int RDM_WAVES_PER_SIMD = 8;
 constexpr u32 RDM_CHUNK = 1024;
 constexpr int SS_PER_THREAD = 4;     // bucket candidates held per thread
 constexpr u32 SS_PIECE = SS_PER_THREAD * RDM_BLOCK;  // candidates of the bucket taken at a time
@@ -400,7 +402,7 @@ struct SameArgs {
 // XD, indexed by the particle pair u1 < u2 and the hole pair v1 < v2 (P = n(n-1)/2
 // pairs), instead of the private copy, so no row waits for global memory.
 template <bool S3, bool DX>
-__global__ void __launch_bounds__(RDM_BLOCK) rdm_same_kernel(SameArgs G) {
+__global__ void __launch_bounds__(RDM_BLOCK, DX ? RDM_WAVES_PER_SIMD / 2 : RDM_WAVES_PER_SIMD) rdm_same_kernel(SameArgs G) {
     extern __shared__ double lds[];
     constexpr u32 RS = DX ? RDM_CHUNK / 2 : RDM_CHUNK;  // rows staged at a time
     const u32 tid = threadIdx.x;
@@ -549,9 +551,10 @@ struct NbPlan {
 };
 
 constexpr u32 NB_NONE = 0xffffffffu;
+constexpr int NB_ROWS = 2;  // rows whose gathers one wavefront keeps in flight
 
 template <bool BM, bool TILE>
-__global__ void __launch_bounds__(RDM_BLOCK) rdm_nb_kernel(SpaceView S, NbPlan P, const u32* __restrict__ list,
+__global__ void __launch_bounds__(RDM_BLOCK, RDM_WAVES_PER_SIMD) rdm_nb_kernel(SpaceView S, NbPlan P, const u32* __restrict__ list,
                                                            const u32* __restrict__ wptr,
                                                            const double* __restrict__ bra,
                                                            const double* __restrict__ ket, double* __restrict__ priv,
@@ -630,17 +633,30 @@ __global__ void __launch_bounds__(RDM_BLOCK) rdm_nb_kernel(SpaceView S, NbPlan P
                     if constexpr (BM) {
                         const u32* bmq = bm + q * (u32)P.W;
                         const u16* preq = pre + q * (u32)P.W;
-                        for (u32 i = 0; i < nr; ++i) {
-                            const double w = rW[i] * sa;
-                            if (w == 0.0) continue;  // uniform
+                        // NB_ROWS rows at a time: their ket gathers are in flight
+                        // together, then the tile additions follow in row order
+                        for (u32 i0 = 0; i0 < nr; i0 += NB_ROWS) {
                             for (u32 e = (u32)lane; e < (u32)P.ds; e += HCI_WAVE) {
-                                const uint2 sv = sing[i * (u32)P.ds + e];
-                                if (sv.x == NB_NONE) continue;
-                                const u32 word = bmq[sv.x >> 5], bit = sv.x & 31u;
-                                if (((word >> bit) & 1u) == 0u) continue;
-                                const u32 j = lo2 + (u32)preq[sv.x >> 5] + (u32)__popc(word & ((1u << bit) - 1u));
-                                const double x = w * ket[j];
-                                own_add(&tile[sv.y & 0x7fffffffu], (sv.y >> 31) ? -x : x);
+                                double x[NB_ROWS];
+                                u32 slot[NB_ROWS];
+#pragma unroll
+                                for (int r = 0; r < NB_ROWS; ++r) {
+                                    x[r] = 0.0;
+                                    slot[r] = 0u;
+                                    const u32 i = i0 + (u32)r;
+                                    if (i >= nr) continue;
+                                    const uint2 sv = sing[i * (u32)P.ds + e];
+                                    if (sv.x == NB_NONE) continue;
+                                    const u32 word = bmq[sv.x >> 5], bit = sv.x & 31u;
+                                    if (((word >> bit) & 1u) == 0u) continue;
+                                    const u32 j = lo2 + (u32)preq[sv.x >> 5] + (u32)__popc(word & ((1u << bit) - 1u));
+                                    const double w = rW[i] * sa;
+                                    x[r] = ((sv.y >> 31) ? -w : w) * ket[j];
+                                    slot[r] = sv.y & 0x7fffffffu;
+                                }
+#pragma unroll
+                                for (int r = 0; r < NB_ROWS; ++r)
+                                    if (x[r] != 0.0) own_add(&tile[slot[r]], x[r]);
                             }
                         }
                     } else {  // scan the neighbour bucket
