@@ -44,6 +44,31 @@ __global__ void zaxpby(double a, const double* __restrict__ x, double b, double*
     if (i < n) y[i] = a * x[i] + b * y[i];
 }
 
+// CG scalars on the device, so an iteration reads back only what its stop
+// test needs: s[0] = rz, s[1] = p.q, s[2] = r.r, s[3] = rz', s[4] = alpha,
+// s[5] = beta, s[6] = 1 when p.q <= 0 (alpha is then 0: x and r stay as they were)
+__global__ void zcg_alpha(double* __restrict__ sc) {
+    const bool ok = sc[1] > 0.0;
+    sc[4] = ok ? sc[0] / sc[1] : 0.0;
+    sc[6] = ok ? 0.0 : 1.0;
+}
+__global__ void zcg_beta(double* __restrict__ sc) {
+    sc[5] = sc[3] / sc[0];
+    sc[0] = sc[3];
+}
+// y = sgn * (*a) * x + y
+__global__ void zaxpy_dev(const double* __restrict__ a, double sgn, const double* __restrict__ x,
+                          double* __restrict__ y, i64 n) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += sgn * (*a) * x[i];
+}
+// p = y + (*b) p
+__global__ void zxpby_dev(const double* __restrict__ y, const double* __restrict__ b, double* __restrict__ p,
+                          i64 n) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = y[i] + (*b) * p[i];
+}
+
 // out = x - (*cx) c   (projection with a device scalar)
 __global__ void zproject(const double* __restrict__ x, const double* __restrict__ c,
                          const double* __restrict__ cx, double* __restrict__ out, i64 n) {
@@ -89,7 +114,7 @@ struct Vec {
     DevMem part, scal;
     Vec(hci_ctx_s* c, i64 nn, hipStream_t st) : ctx(c), s(st), n(nn), g(ceil_div(nn, 256)) {
         part = dev_alloc(c, sizeof(double) * ZNBLK, st);
-        scal = dev_alloc(c, sizeof(double) * 8, st);
+        scal = dev_alloc(c, sizeof(double) * 16, st);
     }
     double* sc(int k) { return scal.as<double>() + k; }
     void dot_dev(const double* x, const double* y, double* out) {
@@ -174,21 +199,26 @@ int zvector_solve(hci_ctx_s* ctx, Space* sp, const double* c, double e, const do
         HIP_CHECK(hipMemcpyAsync(rr, res, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
         precond(rr, y);
         HIP_CHECK(hipMemcpyAsync(p, y, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-        double rz = v.dot(rr, y);
+        double* cg = v.sc(8);  // the CG scalars (zcg_alpha)
+        v.dot_dev(rr, y, cg);
         for (int it = 0; it < 1000 && products < max_products; ++it) {
             apply(p, q, inner_prec);
-            const double pq = v.dot(p, q);
-            if (!(pq > 0.0)) break;
-            const double alpha = rz / pq;
-            v.axpby(alpha, p, 1.0, x);
-            v.axpby(-alpha, q, 1.0, rr);
-            const double rrn = sqrt(std::max(v.dot(rr, rr), 0.0));
-            if (rrn <= target) break;
+            v.dot_dev(p, q, cg + 1);
+            HCI_LAUNCH(ctx, "z_cg", s, zcg_alpha, 1, 1, 0, cg);
+            HCI_LAUNCH(ctx, "z_axpby", s, zaxpy_dev, g, 256, 0, (const double*)(cg + 4), 1.0, (const double*)p, x, N);
+            HCI_LAUNCH(ctx, "z_axpby", s, zaxpy_dev, g, 256, 0, (const double*)(cg + 4), -1.0, (const double*)q, rr, N);
+            v.dot_dev(rr, rr, cg + 2);
+            // the next direction is enqueued before the stop test is read back
+            // (one read per iteration; the last direction is not used)
             precond(rr, y);
-            const double rz2 = v.dot(rr, y);
-            const double beta = rz2 / rz;
-            rz = rz2;
-            v.axpby(1.0, y, beta, p);
+            v.dot_dev(rr, y, cg + 3);
+            HCI_LAUNCH(ctx, "z_cg", s, zcg_beta, 1, 1, 0, cg);
+            HCI_LAUNCH(ctx, "z_axpby", s, zxpby_dev, g, 256, 0, (const double*)y, (const double*)(cg + 5), p, N);
+            double h[7];
+            HIP_CHECK(hipMemcpyAsync(h, cg, sizeof(double) * 7, hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            if (h[6] != 0.0) break;  // p.q <= 0: alpha was 0, x and r unchanged
+            if (sqrt(std::max(h[2], 0.0)) <= target) break;
         }
         // z += Q x
         v.project(x, c, x);
