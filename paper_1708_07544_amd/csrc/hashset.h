@@ -57,9 +57,11 @@ struct HashSet {
     u64* sb;        // beta strings
     u64 sb_mask;
     int packed;     // 1: key = alpha << 32 | beta
-    unsigned long long* overflow;
+    unsigned long long* overflow;  // bit 0: the determinant table, bit 1: a string table
     unsigned long long* strings;  // [0] alpha, [1] beta strings interned
 };
+
+constexpr unsigned long long OVER_DET = 1ull, OVER_STR = 2ull;
 
 // Determinant key, interning the strings when keys are two-level.
 __device__ __forceinline__ bool det_key(const HashSet& H, u64 a, u64 b, u64& key) {
@@ -77,9 +79,10 @@ __device__ __forceinline__ bool det_key(const HashSet& H, u64 a, u64 b, u64& key
     return true;
 }
 
+// t[0, n) = v, striding over a grid that may be smaller than n (tables of
+// 2^32 slots would pass the 2^32 work-items of one launch)
 __global__ void fill_kernel(u64* __restrict__ t, i64 n, u64 v) {
-    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) t[i] = v;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) t[i] = v;
 }
 
 __global__ void insert_v_kernel(HashSet H, const u64* __restrict__ dets, i64 N) {
@@ -87,8 +90,8 @@ __global__ void insert_v_kernel(HashSet H, const u64* __restrict__ dets, i64 N) 
     if (i >= N) return;
     u64 key;
     bool fresh;
-    if (!det_key(H, dets[2 * i], dets[2 * i + 1], key) || hash_insert(H.det, H.det_mask, key, fresh) < 0)
-        atomicOr(H.overflow, 1ull);
+    if (!det_key(H, dets[2 * i], dets[2 * i + 1], key)) atomicOr(H.overflow, OVER_STR);
+    else if (hash_insert(H.det, H.det_mask, key, fresh) < 0) atomicOr(H.overflow, OVER_DET);
 }
 
 

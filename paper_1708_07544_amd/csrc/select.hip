@@ -37,10 +37,12 @@ struct InsertVis {
     bool stop;
     __device__ __forceinline__ void operator()(bool ok, u64 aa, u64 ab) {
         if (stop) return;
-        bool fresh = false, failed = false;
+        bool fresh = false, failed = false, sfailed = false;
         u64 key = 0;
         if (ok) {
-            if (!det_key(H, aa, ab, key) || hash_insert(H.det, H.det_mask, key, fresh) < 0) {
+            if (!det_key(H, aa, ab, key)) {
+                sfailed = true;
+            } else if (hash_insert(H.det, H.det_mask, key, fresh) < 0) {
                 failed = true;
                 fresh = false;
             }
@@ -53,8 +55,10 @@ struct InsertVis {
             const i64 at = (i64)base + rank_in(m);
             if (at < cap) out[at] = key;
         }
-        if (ballot(failed) != 0 || (m && (i64)base + __popcll(m) > limit)) {
-            if (lane_id() == 0) atomicOr(H.overflow, 1ull);
+        const bool sfail = ballot(sfailed) != 0;
+        const bool dfail = ballot(failed) != 0 || (m && (i64)base + __popcll(m) > limit);
+        if (sfail || dfail) {
+            if (lane_id() == 0) atomicOr(H.overflow, (sfail ? OVER_STR : 0ull) | (dfail ? OVER_DET : 0ull));
             stop = true;
         }
     }
@@ -210,19 +214,19 @@ i64 select_run(hci_ctx_s* ctx, const u64* dets, const double* c, i64 N, double e
     DevMem table, sa, sb, keys;
     i64 m = 0;
     for (int attempt = 0;; ++attempt) {
-        HCI_REQUIRE(attempt < 6 && det_slots <= ((i64)1 << 32), HCI_E_NOMEM,
-                    "selection hash set cannot grow further");
+        HCI_REQUIRE(attempt < 10 && det_slots <= ((i64)1 << 32) && str_slots <= ((i64)1 << 32), HCI_E_NOMEM,
+                    "selection hash set cannot grow further (more than 2^31 determinants or strings)");
         table = dev_alloc(ctx, sizeof(u64) * det_slots, s);
-        HCI_LAUNCH(ctx, "select_fill", s, fill_kernel, ceil_div(det_slots, 256), 256, 0,
+        HCI_LAUNCH(ctx, "select_fill", s, fill_kernel, std::min<i64>(ceil_div(det_slots, 256), 1 << 20), 256, 0,
                    table.as<u64>(), det_slots, EMPTY);
         HashSet H{table.as<u64>(), (u64)(det_slots - 1), nullptr, 0, nullptr, 0, packed ? 1 : 0,
                   overflow, strings};
         if (!packed) {
             sa = dev_alloc(ctx, sizeof(u64) * str_slots, s);
             sb = dev_alloc(ctx, sizeof(u64) * str_slots, s);
-            HCI_LAUNCH(ctx, "select_fill", s, fill_kernel, ceil_div(str_slots, 256), 256, 0,
+            HCI_LAUNCH(ctx, "select_fill", s, fill_kernel, std::min<i64>(ceil_div(str_slots, 256), 1 << 20), 256, 0,
                        sa.as<u64>(), str_slots, EMPTY);
-            HCI_LAUNCH(ctx, "select_fill", s, fill_kernel, ceil_div(str_slots, 256), 256, 0,
+            HCI_LAUNCH(ctx, "select_fill", s, fill_kernel, std::min<i64>(ceil_div(str_slots, 256), 1 << 20), 256, 0,
                        sb.as<u64>(), str_slots, EMPTY);
             H.sa = sa.as<u64>();
             H.sb = sb.as<u64>();
@@ -241,12 +245,18 @@ i64 select_run(hci_ctx_s* ctx, const u64* dets, const double* c, i64 N, double e
         HIP_CHECK(hipMemcpyAsync(hv, flags.ptr, sizeof(hv), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         m = (i64)hv[0];
-        // keep every load factor at most 1/2: otherwise grow and walk again
+        // keep every load factor at most 1/2: otherwise grow the table that
+        // filled (only that one) and walk again
         const i64 nstr = (i64)std::max(hv[2], hv[3]);
-        const bool str_ok = packed || nstr <= str_slots / 2;
-        if (hv[1] == 0 && N + m <= det_slots / 2 && m <= kcap && str_ok) break;
-        det_slots = pow2_at_least(std::max<i64>(4 * (N + m), 8 * det_slots));
-        if (!str_ok || hv[1]) str_slots = pow2_at_least(std::max<i64>(4 * nstr, 2 * str_slots));
+        const bool det_full = (hv[1] & OVER_DET) != 0 || N + m > det_slots / 2 || m > kcap;
+        const bool str_full = !packed && ((hv[1] & OVER_STR) != 0 || nstr > str_slots / 2);
+        if (!det_full && !str_full) break;
+        // (a table already at 2^32 slots cannot grow: the next attempt fails)
+        const i64 top = (i64)1 << 32;
+        if (det_full)
+            det_slots = det_slots >= top ? 2 * top : std::min(top, pow2_at_least(std::max<i64>(4 * (N + m), 8 * det_slots)));
+        if (str_full)
+            str_slots = str_slots >= top ? 2 * top : std::min(top, pow2_at_least(std::max<i64>(4 * nstr, 2 * str_slots)));
     }
     const i64 M = N + m;
     if (M > cap) return M;
