@@ -297,7 +297,11 @@ int hci_spin_square(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const doub
  * the same single and double connections as sigma).
  *   bra, ket: device float64 [n_var] (may be the same pointer).
  *   rdm1: device float64 [norb][norb]; rdm2: device float64 [norb]^4 (layout
- *   in the header comment); both overwritten.  rdm2 may be NULL. */
+ *   in the header comment); both overwritten.  rdm2 may be NULL.
+ * Every sum is taken in an order fixed by the determinant list (no
+ * floating-point atomics), so the result is the same bit for bit on every
+ * call and device; so are the relaxed density matrices of
+ * hci_energy_backward. */
 int hci_rdm12(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* bra,
               const double* ket, double* rdm1, double* rdm2, void* stream);
 
