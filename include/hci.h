@@ -299,9 +299,9 @@ int hci_spin_square(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const doub
  *   rdm1: device float64 [norb][norb]; rdm2: device float64 [norb]^4 (layout
  *   in the header comment); both overwritten.  rdm2 may be NULL.
  * Every sum is taken in an order fixed by the determinant list (no
- * floating-point atomics), so the result is the same bit for bit on every
- * call and device; so are the relaxed density matrices of
- * hci_energy_backward. */
+ * floating-point atomics) and by the device's CU count, so the result is
+ * the same bit for bit on every call on a given GPU model; so are the relaxed
+ * density matrices of hci_energy_backward. */
 int hci_rdm12(hci_ctx ctx, const uint64_t* dets, int64_t n_var, const double* bra,
               const double* ket, double* rdm1, double* rdm2, void* stream);
 
