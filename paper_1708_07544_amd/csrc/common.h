@@ -178,6 +178,7 @@ struct RdmChunks {
     DevMem list;  // u32 [n][3]
     DevMem wptr;  // u32 [P + 1]
     int P = 0;
+    int key = -1;  // what else the estimated costs depended on
 };
 
 struct Space {

@@ -457,6 +457,11 @@ __global__ void __launch_bounds__(RDM_BLOCK, DX ? RDM_WAVES_PER_SIMD / 2 : RDM_W
                     // up to 64 of them; they are distinct excitations, so distinct entries
                     HitQueue q;
                     auto contribute = [&]() {
+                        // a single's same-spin spectators when S3 is not on chip:
+                        // (hit, spectator) pairs spread over the lanes below
+                        u64 sm = 0;
+                        int su = 0, sv = 0;
+                        double sx = 0.0;
                         if (lane_id() < q.n) {
                             const u64 Yj = q.y;
                             const u64 xy = Yi ^ Yj;
@@ -464,14 +469,14 @@ __global__ void __launch_bounds__(RDM_BLOCK, DX ? RDM_WAVES_PER_SIMD / 2 : RDM_W
                                 const int u = ctz64(Yi & xy), v = ctz64(Yj & xy);
                                 const double x = wb * q.w * sign_between(Yj, v, u);
                                 own_add(&s2[u * n + v], x);
-                                for (u64 m = Yi & Yj; m; m &= m - 1) {  // same-spin spectators
-                                    const int k = ctz64(m);
-                                    if constexpr (S3) {
-                                        own_add(&s3[(u * n + v) * n + k], x);
-                                    } else {
-                                        own_add(&r2[r2idx(n, u, v, k, k)], x);
-                                        own_add(&r2[r2idx(n, u, k, k, v)], -x);
-                                    }
+                                if constexpr (S3) {
+                                    for (u64 m = Yi & Yj; m; m &= m - 1)  // same-spin spectators
+                                        own_add(&s3[(u * n + v) * n + ctz64(m)], x);
+                                } else {
+                                    sm = Yi & Yj;
+                                    su = u;
+                                    sv = v;
+                                    sx = x;
                                 }
                             } else {
                                 u64 parts = Yi & xy, holes = Yj & xy;
@@ -487,6 +492,38 @@ __global__ void __launch_bounds__(RDM_BLOCK, DX ? RDM_WAVES_PER_SIMD / 2 : RDM_W
                                 } else {
                                     own_add(&r2[r2idx(n, u1, v1, u2, v2)], x);
                                     own_add(&r2[r2idx(n, u1, v2, u2, v1)], -x);
+                                }
+                            }
+                        }
+                        if constexpr (!S3) {
+                            // lane l takes pair base + l: the hit is the last lane whose
+                            // exclusive offset is <= it, the spectator its rank in sm
+                            // (distinct (u, v, k) within a row, so distinct entries)
+                            const int cnt = popc64(sm);
+                            int incl = cnt;
+#pragma unroll
+                            for (int off = 1; off < HCI_WAVE; off <<= 1) {
+                                const int y = __shfl_up(incl, off, HCI_WAVE);
+                                if (lane_id() >= off) incl += y;
+                            }
+                            const int excl = incl - cnt;
+                            const int total = __shfl(incl, HCI_WAVE - 1, HCI_WAVE);
+                            for (int base = 0; base < total; base += HCI_WAVE) {
+                                const int p = base + lane_id();
+                                int lo = 0, hi = HCI_WAVE - 1;
+                                while (lo < hi) {  // uniform trip count: every lane shuffles
+                                    const int mid = (lo + hi + 1) >> 1;
+                                    if (__shfl(excl, mid, HCI_WAVE) <= p) lo = mid;
+                                    else hi = mid - 1;
+                                }
+                                const u64 hm = __shfl(sm, lo, HCI_WAVE);
+                                const int hu = __shfl(su, lo, HCI_WAVE), hv = __shfl(sv, lo, HCI_WAVE);
+                                const double hx = __shfl(sx, lo, HCI_WAVE);
+                                const int r = p - __shfl(excl, lo, HCI_WAVE);
+                                if (p < total) {
+                                    const int k = nth_set_bit(hm, r);
+                                    own_add(&r2[r2idx(n, hu, hv, k, k)], hx);
+                                    own_add(&r2[r2idx(n, hu, k, k, hv)], -hx);
                                 }
                             }
                         }
@@ -552,6 +589,7 @@ struct NbPlan {
 
 constexpr u32 NB_NONE = 0xffffffffu;
 constexpr int NB_ROWS = 2;  // rows whose gathers one wavefront keeps in flight
+constexpr u32 NB_SCAN = 4;  // without bitmaps: scan a neighbour bucket of at most NB_SCAN beta singles per row
 
 template <bool BM, bool TILE>
 __global__ void __launch_bounds__(RDM_BLOCK, RDM_WAVES_PER_SIMD) rdm_nb_kernel(SpaceView S, NbPlan P, const u32* __restrict__ list,
@@ -606,7 +644,7 @@ __global__ void __launch_bounds__(RDM_BLOCK, RDM_WAVES_PER_SIMD) rdm_nb_kernel(S
                     rB[i] = S.beta[s0 + i];
                     rW[i] = bra[s0 + i];
                 }
-                if constexpr (BM) {
+                {
                     for (u32 x = tid; x < nr * (u32)P.ds; x += RDM_BLOCK) {
                         const u32 i = x / (u32)P.ds, e = x % (u32)P.ds;
                         const u32 b = S.ib[s0 + i];
@@ -659,7 +697,7 @@ __global__ void __launch_bounds__(RDM_BLOCK, RDM_WAVES_PER_SIMD) rdm_nb_kernel(S
                                     if (x[r] != 0.0) own_add(&tile[slot[r]], x[r]);
                             }
                         }
-                    } else {  // scan the neighbour bucket
+                    } else if (nbh[q] - lo2 <= NB_SCAN * (u32)P.ds) {  // scan a small neighbour bucket
                         const u32 hi2 = nbh[q];
                         for (u32 i = 0; i < nr; ++i) {
                             const double w = rW[i] * sa;
@@ -671,6 +709,21 @@ __global__ void __launch_bounds__(RDM_BLOCK, RDM_WAVES_PER_SIMD) rdm_nb_kernel(S
                                 if (popc64(xb) != 2) continue;
                                 const int v2 = ctz64(bj & xb), u2 = ctz64(B & xb);
                                 own_add(&tile[u2 * n + v2], w * ket[j] * sign_between(bj, v2, u2));
+                            }
+                        }
+                    } else {  // look each beta single of the row up in a large one (sorted by beta)
+                        const u32 len2 = nbh[q] - lo2;
+                        for (u32 i = 0; i < nr; ++i) {
+                            const double w = rW[i] * sa;
+                            if (w == 0.0) continue;  // uniform
+                            for (u32 e = (u32)lane; e < (u32)P.ds; e += HCI_WAVE) {
+                                const uint2 sv = sing[i * (u32)P.ds + e];
+                                if (sv.x == NB_NONE) continue;
+                                const u64 bj = S.ub[sv.x];
+                                const u32 pos = lower_bound_u64(S.beta + lo2, len2, bj);
+                                if (pos >= len2 || S.beta[lo2 + pos] != bj) continue;
+                                const double x = w * ket[lo2 + pos];
+                                own_add(&tile[sv.y & 0x7fffffffu], (sv.y >> 31) ? -x : x);
                             }
                         }
                     }
@@ -690,6 +743,23 @@ __global__ void __launch_bounds__(RDM_BLOCK, RDM_WAVES_PER_SIMD) rdm_nb_kernel(S
             }
         }
     }
+}
+
+// Estimated time of one row of bucket a in the alpha single x beta single
+// kernel: a pass per alpha neighbour, plus (without bitmaps) the scan of a
+// small neighbour bucket or a binary search per beta single of a large one.
+__global__ void nb_cost_kernel(SpaceView S, i64 nua, int W, int ds, float* __restrict__ out) {
+    const i64 a = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nua) return;
+    float c = 1.0f;
+    for (u32 t = S.as_ptr[a]; t < S.as_ptr[a + 1]; ++t) {
+        const u32 a2 = S.as_idx[t];
+        const u32 len = S.aoff[a2 + 1] - S.aoff[a2];
+        if (W > 0) c += 1.0f;
+        else if (len <= NB_SCAN * (u32)ds) c += 1.0f + (float)len / HCI_WAVE;
+        else c += 1.0f + (float)ds / HCI_WAVE * (float)(32 - __clz(len));
+    }
+    out[a] = c;
 }
 
 // beta-major copies: out[k] = in[permb[k]]
@@ -727,8 +797,8 @@ bool nb_plan(int n, int na, int nb, int budget, int W, NbPlan& P) {
     P.n = n;
     P.W = W;
     P.ds = ds;
-    P.R = W > 0 ? std::max(1, std::min<int>(RDM_CHUNK, 16384 / (8 * ds))) : 64;
-    const int fixed_sing = W > 0 ? 8 * P.R * ds : 0;
+    P.R = std::max(1, std::min<int>(RDM_CHUNK, 16384 / (8 * ds)));
+    const int fixed_sing = 8 * P.R * ds;
     const int fixed_rows = 16 * P.R;
     for (int tile = 1; tile >= 0; --tile) {
         const int per = (tile ? 8 * nn : 0) + 6 * W + 24;
@@ -864,7 +934,7 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
     // the same-string kernel with the table of doubles holds a CU alone: as many
     // workgroups as CUs, each with a longer list
     const int Ps = dx ? std::min(Pw, cus) : Pw;
-    if (sp->rdm_sa.P != Ps || sp->rdm_nb.P != Pw) {
+    if (sp->rdm_sa.P != Ps || sp->rdm_nb.P != Pw || sp->rdm_nb.key != (P.W > 0)) {
         // a row of a same-string chunk costs a barrier per piece of its bucket
         // (and a chunk about two rows for its flush); an alpha single x beta
         // single chunk one pass per alpha neighbour
@@ -872,12 +942,15 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
         auto same_cost = [&](u32, u32 size, u32 rows) { return (double)rows * (double)ceil_div(size, piece) + 2.0; };
         plan_chunks(ctx, sp->aoff.as<u32>(), sp->nua, Ps, same_cost, sp->rdm_sa, s);
         plan_chunks(ctx, sp->boff.as<u32>(), sp->nub, Ps, same_cost, sp->rdm_sb, s);
-        std::vector<u32> asp(sp->nua + 1);
-        HIP_CHECK(hipMemcpyAsync(asp.data(), sp->as_ptr.as<u32>(), sizeof(u32) * (sp->nua + 1), hipMemcpyDeviceToHost,
-                                 s));
+        DevMem bc = dev_alloc(ctx, sizeof(float) * sp->nua, s);
+        HCI_LAUNCH(ctx, "rdm_plan", s, nb_cost_kernel, ceil_div(sp->nua, 256), 256, 0, S, sp->nua, P.W, P.ds,
+                   bc.as<float>());
+        std::vector<float> bcost(sp->nua);
+        HIP_CHECK(hipMemcpyAsync(bcost.data(), bc.ptr, sizeof(float) * sp->nua, hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
-        auto nb_cost = [&](u32 b, u32, u32 rows) { return (double)rows * (1.0 + (double)(asp[b + 1] - asp[b])); };
+        auto nb_cost = [&](u32 b, u32, u32 rows) { return (double)rows * (double)bcost[b]; };
         plan_chunks(ctx, sp->aoff.as<u32>(), sp->nua, Pw, nb_cost, sp->rdm_nb, s);
+        sp->rdm_nb.key = P.W > 0;
     }
     if (!sp->alpha_b.ptr) {  // alpha word of each beta-major position (cached with the space)
         sp->alpha_b = dev_alloc(ctx, sizeof(u64) * N, s);
