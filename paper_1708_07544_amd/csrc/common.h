@@ -235,7 +235,7 @@ struct Space {
     // then alpha single x beta single) and of the beta buckets in beta-major
     // order, each list assigned to the workgroups of a persistent grid
     RdmChunks rdm_sa, rdm_nb, rdm_sb;
-    DevMem alpha_b;       // u64 [N]: alpha word of each beta-major position (density matrices)
+    DevMem alpha_b;       // u64 [N]: alpha word of each beta-major position (build, density matrices)
     bool st_have32 = false, st_have64 = false;
 };
 
@@ -256,6 +256,7 @@ struct SpaceView {
     const u32* as_idx;
     const u32* bs_ptr;
     const u32* bs_idx;
+    const u64* alpha_b;  // alpha word of each beta-major position (null until ensure_alpha_b)
 };
 
 struct IntView {
@@ -380,6 +381,7 @@ inline SpaceView space_view(const Space& s, int n) {
     v.as_idx = s.as_idx.as<u32>();
     v.bs_ptr = s.bs_ptr.as<u32>();
     v.bs_idx = s.bs_idx.as<u32>();
+    v.alpha_b = s.alpha_b.as<u64>();
     return v;
 }
 
@@ -430,6 +432,8 @@ i64 unique128_capped(hci_ctx_s* ctx, const u64* hi, const u64* lo, u64* out_pair
 void integrals_stage(hci_ctx_s* ctx, const double* h, const double* g, hipStream_t s);
 Space* get_space(hci_ctx_s* ctx, const u64* dets, i64 n_var, hipStream_t s);
 void ensure_diag(hci_ctx_s* ctx, Space* sp, hipStream_t s);
+// sp->alpha_b: the alpha word of each beta-major position (cached with the space)
+void ensure_alpha_b(hci_ctx_s* ctx, Space* sp, hipStream_t s);
 void ensure_csr(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s);
 i64 count_connections(hci_ctx_s* ctx, Space* sp, hipStream_t s);
 void sigma_apply(hci_ctx_s* ctx, Space* sp, const double* c, double* sigma, int precision, int mode,

@@ -952,11 +952,7 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
         plan_chunks(ctx, sp->aoff.as<u32>(), sp->nua, Pw, nb_cost, sp->rdm_nb, s);
         sp->rdm_nb.key = P.W > 0;
     }
-    if (!sp->alpha_b.ptr) {  // alpha word of each beta-major position (cached with the space)
-        sp->alpha_b = dev_alloc(ctx, sizeof(u64) * N, s);
-        HCI_LAUNCH(ctx, "rdm_permute", s, rdm_permute_kernel<u64>, ceil_div(N, 256), 256, 0, sp->alpha.as<u64>(),
-                   sp->permb.as<u32>(), N, sp->alpha_b.as<u64>());
-    }
+    ensure_alpha_b(ctx, sp, s);
     DevMem ket_b = dev_alloc(ctx, sizeof(double) * N, s), bra_b = dev_alloc(ctx, sizeof(double) * N, s);
     HCI_LAUNCH(ctx, "rdm_permute", s, rdm_permute_kernel<double>, ceil_div(N, 256), 256, 0, ket, sp->permb.as<u32>(),
                N, ket_b.as<double>());

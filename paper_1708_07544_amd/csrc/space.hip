@@ -181,6 +181,21 @@ void build_adjacency(hci_ctx_s* ctx, const DevMem& uniq, i64 m, int n, DevMem& p
 
 // Strings, groups, the beta-major permutation and the single-excitation
 // adjacency of a validated list.
+namespace {
+__global__ void permute_u64_kernel(const u64* __restrict__ in, const u32* __restrict__ permb, i64 N,
+                                   u64* __restrict__ out) {
+    const i64 k = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < N) out[k] = in[permb[k]];
+}
+}  // namespace
+
+void ensure_alpha_b(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
+    if (sp->alpha_b.ptr) return;
+    sp->alpha_b = dev_alloc(ctx, sizeof(u64) * sp->N, s);
+    HCI_LAUNCH(ctx, "alpha_beta_major", s, permute_u64_kernel, ceil_div(sp->N, 256), 256, 0, sp->alpha.as<u64>(),
+               sp->permb.as<u32>(), sp->N, sp->alpha_b.as<u64>());
+}
+
 static void build_structure(hci_ctx_s* ctx, Space* sp, int n, hipStream_t s) {
     const i64 N = sp->N;
     // alpha-major groups

@@ -181,12 +181,11 @@ __device__ __forceinline__ void enumerate_row_staged(const SpaceView& S, const u
             u32 j = 0, seg = gseg, col = k - lo;
             u64 aj = 0;
             if (ok) {
-                j = S.permb[k];
-                ok = j != i;
+                aj = S.alpha_b[k];  // contiguous; the position j only for the hits
+                const int d = popc64(A ^ aj);
+                ok = d == 2 || d == 4;  // (d = 0 is the row itself: same alpha and beta)
                 if (ok) {
-                    aj = S.alpha[j];
-                    const int d = popc64(A ^ aj);
-                    ok = d <= 4;
+                    j = S.permb[k];
                     if (d == 2) {
                         const u32 a2 = S.ia[j];
                         const u32 r = lower_bound_u32(S.as_idx + t0, t1 - t0, a2);
@@ -858,6 +857,7 @@ bool staged_prepare(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
     const i64 N = sp->N, nua = sp->nua, nub = sp->nub;
     // the build passes take one wavefront per row in one launch
     if (ceil_div(N, ST_ROWS_PER_BLOCK) * ST_ROW_BLOCK >= ((i64)1 << 32)) return false;
+    ensure_alpha_b(ctx, sp, s);  // the same-beta scans read the alpha words in beta-major order
     SpaceView S = space_view(*sp, ctx->n);
     sp->st_wlog = (u32)wlog;
     sp->st_xpos = dev_alloc(ctx, sizeof(u32) * (nua + sp->n_as), s);
@@ -991,6 +991,7 @@ void staged_ensure_vals(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s)
     const bool f32 = precision == HCI_FP32_MIXED;
     if (f32 ? sp->st_have32 : sp->st_have64) return;
     const i64 nnz = sp->st_nnz;
+    ensure_alpha_b(ctx, sp, s);
     SpaceView S = space_view(*sp, ctx->n);
     const i64 grid = ceil_div(sp->N, ST_ROWS_PER_BLOCK);
     if (!sp->st_cols.ptr) {
