@@ -53,7 +53,8 @@ def parse():
                     help="time a mixed-precision Davidson from a cold start on the final space (0 skips it)")
     ap.add_argument("--cas8", type=int, default=1,
                     help="time the (8e,8o) full-CI workload on the GPU and in the oracle (0 skips it)")
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU oracle legs and the copy-peak probe")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy a 4 GiB buffer once (calibrates HBM byte counters)")
     ap.add_argument("--pt2-batches", type=int, default=16,
@@ -242,9 +243,24 @@ def main():
     oracle_check = None
     if not args.no_cpu:
         cpu, oracle_check = cpu_baseline(h, g, P.dets_to_numpy(V2), c_mixed.cpu().numpy(), e_mixed, nv, pairs)
+    copy_peak = None
+    cpu_rows = None
+    if not args.no_cpu:
+        copy_peak = copy_peak_leg()
+        if roofline:
+            roofline["copy_peak_gbs"] = round(copy_peak, 1)
+            roofline["frac_of_copy"] = round(roofline["achieved"] / copy_peak, 4)
+        cpu_rows = cpu_rows_leg(h, g, P.dets_to_numpy(V2), c_mixed.cpu().numpy(), cpu)
     cold = None
     if args.cold_davidson:
         cold = cold_leg(ctx, V2, pairs, args)
+        if cpu_rows is not None:
+            # the full oracle HCI on this space: as many of the oracle's products
+            # as the library's cold solve needs, at the timed rate, plus selection
+            cpu_rows["oracle_hci_cas16"] = {
+                "run": False, "estimate_s": round(cold["products"] * pairs / cpu["value"], 1),
+                "reason": "not run: a solve takes about %d oracle products of %.1f s each on %d threads"
+                          % (cold["products"], pairs / cpu["value"], cpu["cores"])}
     small = None
     if args.cas8:
         small = cas8_leg(args)
@@ -290,6 +306,7 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_oracle_rows": cpu_rows,
         "pt2": pt2,
         "orbital": orbital,
         "extrapolation": extrap,
@@ -545,6 +562,73 @@ def cpu_baseline(h, g, V, c, e, nv, pairs):
     check = {"energy_library": e, "energy_oracle_rayleigh": rq, "abs_error": abs(e - rq),
              "oracle_residual_norm": res}
     return base, check
+
+
+def copy_peak_leg():
+    """A plain device copy of 4 GiB (one read and one write stream) timed with
+    events: the bandwidth a streaming kernel reaches on this GPU."""
+    import torch
+    src = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    gbs = 2 * (4 << 30) / (best * 1e-3) / 1e9
+    log(f"[bench] copy peak: 4 GiB copied in {best:.3f} ms, {gbs:.0f} GB/s")
+    return gbs
+
+
+def cpu_rows_leg(h, g, V2, c2, base):
+    """The oracle's product on sampled rows: the (16e,16o) final space with one
+    thread (against the all-core rate of cpu_baseline), and the first spaces
+    of the (30e,30o) and porphyrin-shaped (44e,44o) workloads (aufbau + C(eps1)
+    by the oracle's selection) with all threads, as rows per second."""
+    import ctypes
+
+    import numpy as np
+
+    import hci_synth as hs
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    gomp = None
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        pass
+    rng = np.random.default_rng(7)
+    out = {"cores": threads}
+    if gomp is not None:
+        rows = rng.choice(len(V2), 2000, replace=False)
+        gomp.omp_set_num_threads(1)
+        t = time.perf_counter()
+        O.sigma(h, g, V2, c2, rows=rows)
+        dt = time.perf_counter() - t
+        gomp.omp_set_num_threads(threads)
+        out["cas16_single_thread_rows_per_s"] = 2000 / dt
+        out["cas16_all_threads_rows_per_s"] = base["rows_per_s"] if base else None
+        log(f"[bench] cpu oracle (16e,16o): 2000 rows on one thread in {dt:.2f} s")
+    for name, nrows in (("cas30", 1000), ("cas44", 200)):
+        w = hs.WORKLOADS[name]
+        hh, gg = hs.workload_integrals(w)
+        V0 = hs.aufbau_det(w.nalpha, w.nbeta)
+        V = O.merge(V0, O.select(hh, gg, V0, np.array([1.0]), w.eps1))
+        c = hs.random_coeffs(len(V), 11)
+        rows = rng.choice(len(V), nrows, replace=False)
+        t = time.perf_counter()
+        _, npairs = O.sigma(hh, gg, V, c, rows=rows, with_pairs=True)
+        dt = time.perf_counter() - t
+        out[name] = {"n_det": len(V), "rows": nrows, "rows_per_s": nrows / dt,
+                     "det_pairs_per_s": float(np.sum(npairs)) / dt, "threads": threads}
+        log(f"[bench] cpu oracle {name}: {nrows} of {len(V)} rows in {dt:.2f} s on {threads} threads")
+    return out
 
 
 def cold_leg(ctx, V2, pairs, args):
