@@ -65,11 +65,16 @@ __global__ void __launch_bounds__(DV_BLOCK) dots_kernel(const double* __restrict
     }
 }
 
-// out[j * ostride] = sum_b partial[j * nblk + b] (fixed order); block 0 also
-// copies *copy_src to *copy_dst when given (scalars the host reads together).
+// out[j * ostride] = sum_b partial[j * nblk + b] (fixed order), or, when out0
+// is given, column 0 to *out0 and column j > 0 to out[(j - 1) * ostride];
+// block 0 also copies *copy_src to *copy_dst when given (scalars the host
+// reads together).  (A last-block reduction inside the producing kernels was
+// tried: the device-scope fence each block then needs before its ticket costs
+// ~0.1 ms per kernel on this GPU, more than the separate launch.)
 __global__ void reduce_partials_kernel(const double* __restrict__ partial, int k, int nblk,
                                        double* __restrict__ out, i64 ostride,
-                                       const double* __restrict__ copy_src, double* __restrict__ copy_dst) {
+                                       const double* __restrict__ copy_src, double* __restrict__ copy_dst,
+                                       double* __restrict__ out0) {
     __shared__ double lds[DV_BLOCK / 64];
     const int j = blockIdx.x;
     if (j >= k) return;
@@ -77,7 +82,9 @@ __global__ void reduce_partials_kernel(const double* __restrict__ partial, int k
     for (int b = threadIdx.x; b < nblk; b += DV_BLOCK) acc += partial[(i64)j * nblk + b];
     const double v = block_sum_f64<DV_BLOCK>(acc, lds);
     if (threadIdx.x == 0) {
-        out[(i64)j * ostride] = v;
+        if (out0 == nullptr) out[(i64)j * ostride] = v;
+        else if (j == 0) *out0 = v;
+        else out[(i64)(j - 1) * ostride] = v;
         if (j == 0 && copy_dst) *copy_dst = *copy_src;
     }
 }
@@ -149,18 +156,22 @@ __global__ void normalize_guard_kernel(const double* __restrict__ src, const dou
     if (i == 0 && !ok) *dead = 1.0;
 }
 
-// x = V y, w = W y, r = w - theta x, t = r / guard(H_ii - theta); partial |r|^2.
-// ritz[0] = theta, ritz[1..k] = y.
+// x = V y, w = W y, r = w - theta x, t = r / guard(H_ii - theta); partial
+// sums of |r|^2 (column 0) and, for kd > 0, of the first Gram-Schmidt
+// sweep's coefficients V_j . t, j < kd (columns 1..kd, with the partition and
+// order of dots_kernel).  ritz[0] = theta, ritz[1..k] = y.
 __global__ void __launch_bounds__(DV_BLOCK) combine_kernel(
-    const double* __restrict__ V, const double* __restrict__ W, i64 ld, int k,
+    const double* __restrict__ V, const double* __restrict__ W, i64 ld, int k, int kd,
     const double* __restrict__ ritz, const double* __restrict__ hd, double* __restrict__ x,
     double* __restrict__ w, double* __restrict__ t, i64 N, double* __restrict__ partial, int nblk) {
-    __shared__ double lds[DV_BLOCK / 64];
+    __shared__ double wsum[DV_BLOCK / 64][DV_MAXK];
     __shared__ double y[DV_MAXK + 1];
     if (threadIdx.x <= k) y[threadIdx.x] = ritz[threadIdx.x];
     __syncthreads();
     const double theta = y[0];
-    double acc = 0.0;
+    double acc[DV_MAXK];  // acc[0] = |r|^2, acc[1 + j] = V_j . t
+#pragma unroll
+    for (int j = 0; j < DV_MAXK; ++j) acc[j] = 0.0;
     for (i64 i = (i64)blockIdx.x * DV_BLOCK + threadIdx.x; i < N; i += (i64)nblk * DV_BLOCK) {
         double xi = 0.0, wi = 0.0;
         for (int j = 0; j < k; ++j) {
@@ -170,13 +181,31 @@ __global__ void __launch_bounds__(DV_BLOCK) combine_kernel(
         const double ri = wi - theta * xi;
         double den = hd[i] - theta;
         if (fabs(den) < 1e-4) den = den < 0 ? -1e-4 : 1e-4;
+        const double ti = ri / den;
         x[i] = xi;
         w[i] = wi;
-        t[i] = ri / den;
-        acc += ri * ri;
+        t[i] = ti;
+        acc[0] += ri * ri;
+        // V_j[i] again: the line was just read by this thread (a cache hit)
+#pragma unroll
+        for (int j = 0; j + 1 < DV_MAXK; ++j)
+            if (j < kd) acc[j + 1] += V[(i64)j * ld + i] * ti;
     }
-    const double v = block_sum_f64<DV_BLOCK>(acc, lds);
-    if (threadIdx.x == 0) partial[blockIdx.x] = v;
+    const int wv = threadIdx.x / 64;
+#pragma unroll
+    for (int j = 0; j < DV_MAXK; ++j) {
+        if (j <= kd) {
+            const double v = wave_sum_f64(acc[j]);
+            if (lane_id() == 0) wsum[wv][j] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x <= kd) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < DV_BLOCK / 64; ++q) v += wsum[q][threadIdx.x];
+        partial[(i64)threadIdx.x * nblk + blockIdx.x] = v;
+    }
 }
 
 // Lowest eigenpair of the k x k projected matrix (upper triangle of G),
@@ -203,12 +232,29 @@ __global__ void __launch_bounds__(64) lowest_eig_kernel(const double* __restrict
     // a dead newest direction (zero vector) is left out of the eigenproblem
     const int k = (dead != nullptr && *dead != 0.0) ? kall - 1 : kall;
     __shared__ double A[DV_MAXK][DV_MAXK + 1];
+    __shared__ double A0[DV_MAXK][DV_MAXK + 1];  // the matrix itself, for the Rayleigh quotient
     __shared__ double H[DV_MAXK][DV_MAXK];  // Householder vector of step j in row j
     __shared__ double vv[DV_MAXK], pw[DV_MAXK], d[DV_MAXK], e[DV_MAXK], y[DV_MAXK];
     const int l = threadIdx.x;
-    for (int x = l; x < k * k; x += 64) {
-        const int r = x / k, c = x % k;
-        A[r][c] = G[(r < c ? r : c) * ldg + (r < c ? c : r)];
+    {  // every load in flight before the first store
+        constexpr int PER = DV_MAXK * DV_MAXK / 64;
+        const int kq = k > 0 ? k : 1;  // (no entries when k = 0)
+        double g[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int x = l + 64 * u;
+            const int r = x / kq, c = x % kq;
+            g[u] = x < k * k ? G[(r < c ? r : c) * ldg + (r < c ? c : r)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int x = l + 64 * u;
+            if (x < k * k) {
+                const int r = x / kq, c = x % kq;
+                A[r][c] = g[u];
+                A0[r][c] = g[u];
+            }
+        }
     }
     __syncthreads();
     // Householder: column j's entries below the subdiagonal are annihilated
@@ -318,7 +364,7 @@ __global__ void __launch_bounds__(64) lowest_eig_kernel(const double* __restrict
     const double yl = l < k ? y[l] : 0.0;
     double ay = 0.0;
     if (l < k)
-        for (int c = 0; c < k; ++c) ay += G[(l < c ? l : c) * ldg + (l < c ? c : l)] * y[c];
+        for (int c = 0; c < k; ++c) ay += A0[l][c] * y[c];
     const double nrm = wave_sum_f64(yl * yl);
     const double th = wave_sum_f64(yl * ay) / nrm;
     if (l == 0) out[0] = th;
@@ -512,13 +558,17 @@ struct Workspace {
         reduce(k, out, ostride);
     }
     void reduce(int k, double* out, i64 ostride = 1, const double* copy_src = nullptr,
-                double* copy_dst = nullptr) {
+                double* copy_dst = nullptr, double* out0 = nullptr) {
         HCI_LAUNCH(ctx, "dv_reduce", s, reduce_partials_kernel, k, DV_BLOCK, 0, partial.as<double>(),
-                   k, nblk, out, ostride, copy_src, copy_dst);
+                   k, nblk, out, ostride, copy_src, copy_dst, out0);
     }
     // two-sweep classical Gram-Schmidt of t against X_0..X_{k-1}; nrm2 = |t|^2
     void cgs2(const double* X, i64 ld, int k, double* t, double* coef, double* nrm2) {
         dots(X, ld, k, t, coef);
+        cgs2_after_dots(X, ld, k, t, coef, nrm2);
+    }
+    // the same with coef = X^T t already computed
+    void cgs2_after_dots(const double* X, i64 ld, int k, double* t, double* coef, double* nrm2) {
         HCI_LAUNCH(ctx, "dv_subcombo", s, sub_dots_kernel<false>, nblk, DV_BLOCK, 0, X, ld, k,
                    (const double*)coef, t, N, partial.as<double>(), nblk);
         reduce(k, coef);
@@ -637,10 +687,14 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
                        k, (const double*)dead, ritz.as<double>());
             std::swap(xc, xp);
             std::swap(wc, wp);
-            HCI_LAUNCH(ctx, "dv_combine", s, combine_kernel, ws.nblk, DV_BLOCK, 0, V, W, N, k,
+            // without locked vectors the first sweep of the next direction's
+            // orthogonalisation comes with the combination (unused when the
+            // basis is full or the iteration ends here)
+            const int kd = (nlock == 0 && k < kmax) ? k : 0;
+            HCI_LAUNCH(ctx, "dv_combine", s, combine_kernel, ws.nblk, DV_BLOCK, 0, V, W, N, k, kd,
                        ritz.as<double>(), hd, xc, wc, t, N, ws.partial.as<double>(), ws.nblk);
+            ws.reduce(kd + 1, sc, 1, ritz.as<double>(), theta_h, rr);
             have_prev = true;
-            ws.reduce(1, rr, 1, ritz.as<double>(), theta_h);
             double hv[4];
             HIP_CHECK(hipMemcpyAsync(hv, rr, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
             HIP_CHECK(hipStreamSynchronize(s));
@@ -662,8 +716,12 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
             if (k == kmax) break;  // thick restart
             // orthogonalise the preconditioned residual against the locked
             // vectors and the basis (CGS2)
-            if (nlock > 0) ws.cgs2(lock, N, nlock, t, sc, nrm_t);
-            ws.cgs2(V, N, k, t, sc, nrm_t);
+            if (nlock > 0) {
+                ws.cgs2(lock, N, nlock, t, sc, nrm_t);
+                ws.cgs2(V, N, k, t, sc, nrm_t);
+            } else {
+                ws.cgs2_after_dots(V, N, k, t, sc, nrm_t);
+            }
             HCI_LAUNCH(ctx, "dv_normalize", s, normalize_guard_kernel, g1, 256, 0, t, nrm_t,
                        V + (i64)k * N, N, dead);
             sigma_apply(ctx, sp, V + (i64)k * N, W + (i64)k * N, phase_prec, phase_mode, s);

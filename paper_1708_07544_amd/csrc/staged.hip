@@ -467,14 +467,43 @@ __global__ void __launch_bounds__(ST_BLOCK) st_ab_kernel(SpaceView S, StView T, 
     }
 }
 
+// Single excitations queued across the rows of a wavefront: lane l holds the
+// l-th queued entry (its index, the bra's beta string and the ket), so the
+// costly single elements are evaluated 64 at a time however few each row
+// segment has (the bra's alpha string is the workgroup's bucket).
+struct BraSinglesQueue {
+    int n = 0;  // queued, wave-uniform
+    i64 k = 0;
+    u64 bi = 0, a = 0, b = 0;
+    __device__ __forceinline__ bool full_for(u64 m) const { return n + popc64(m) > HCI_WAVE; }
+    __device__ __forceinline__ void push(u64 m, i64 kk, u64 bra_b, u64 aa, u64 bb) {
+        const int cnt = popc64(m);
+        const int l = lane_id();
+        const bool mine = l >= n && l < n + cnt;
+        const int src = mine ? nth_set_bit(m, l - n) : l;
+        const i64 sk = __shfl(kk, src, HCI_WAVE);
+        const u64 sa = __shfl(aa, src, HCI_WAVE);
+        const u64 sb = __shfl(bb, src, HCI_WAVE);
+        if (mine) {
+            k = sk;
+            bi = bra_b;  // wave-uniform: the row being scanned
+            a = sa;
+            b = sb;
+        }
+        n += cnt;
+    }
+};
+
 // Element pass: decode each stored column back to its determinant and
 // evaluate H_ij in float64 (written rounded to float32 when OUT & 1, as
 // float64 when OUT & 2; the float32-mixed solver refines with float64
 // products, so it asks for both).  Workgroup = a chunk of rows of one alpha
-// bucket, as the product: the bucket's stage ranges (start position, first
-// row and alpha string of each range) sit in LDS, so decoding a window
-// column is a binary search there; a beta-group entry has the row's beta
-// string.
+// bucket, as the product, and window by window as the product: the window's
+// beta strings are copied into LDS once (the ket's alpha string is that of
+// the stage range holding the position, found by a binary search over the
+// bucket's ranges in LDS), then every row of the chunk decodes its segment
+// of that window from LDS.  The beta-group segments (same beta string) read
+// the ket's alpha string from the beta-major copy of the alpha words.
 template <int OUT>
 __global__ void __launch_bounds__(ST_BLOCK) st_vals_kernel(SpaceView S, IntView I, StView T,
                                                            float* __restrict__ v32,
@@ -482,79 +511,118 @@ __global__ void __launch_bounds__(ST_BLOCK) st_vals_kernel(SpaceView S, IntView 
     extern __shared__ __align__(16) unsigned char st_smem[];
     const u32 tid = threadIdx.x;
     const u32 wave = tid / HCI_WAVE;
+    const int lane = lane_id();
     // bucket and rows of this workgroup's chunk
     const u32* ce = T.chunk + 3 * (i64)blockIdx.x;
     const u32 a = ce[0], r0 = ce[1], r1 = ce[2];
     const u32 t0 = S.as_ptr[a];
     const u32 nr = 1u + S.as_ptr[a + 1] - t0;
-    u64* ralpha = reinterpret_cast<u64*>(st_smem);        // [nr]
-    u32* rx = reinterpret_cast<u32*>(ralpha + nr);         // [nr] stage start of each range
-    u32* rbase = rx + nr;                                  // [nr] first row of each range
+    const u32 ns = T.nseg[a];
+    const u32 slen = T.len[a];
+    const u32 wsize = 1u << T.wlog;
+    u64* sbeta = reinterpret_cast<u64*>(st_smem);  // [wsize] beta strings of the window
+    u64* ralpha = sbeta + wsize;                    // [nr] alpha string of each range
+    u32* rx = reinterpret_cast<u32*>(ralpha + nr);  // [nr] stage start of each range
+    u32* rsrc = rx + nr;                            // [nr] first row of each range
     for (u32 e = tid; e < nr; e += ST_BLOCK) {
         const u32 a2 = e == 0 ? a : S.as_idx[t0 + e - 1];
         ralpha[e] = S.ua[a2];
         rx[e] = T.xpos[t0 + a + e];
-        rbase[e] = S.aoff[a2];
+        rsrc[e] = S.aoff[a2];
     }
-    __syncthreads();
-    const u32 ns = T.nseg[a];
     const u64 ai = S.ua[a];
-    for (u32 i = r0 + wave; i < r1; i += ST_WAVES) {
-        const u64 bi = S.beta[i];
-        const i64 sb = T.rsb[i];
-        const u32 gb = S.boff[S.ib[i]];
-        SinglesQueue q;
-        auto flush = [&]() {
-            if (lane_id() < q.n) {
-                const double v = hij_f64(I, ai, bi, q.a, q.b);
-                if constexpr ((OUT & 1) != 0) v32[q.k] = (float)v;
-                if constexpr ((OUT & 2) != 0) v64[q.k] = v;
+    BraSinglesQueue q;
+    auto flush = [&]() {
+        if (lane < q.n) {
+            const double v = hij_f64(I, ai, q.bi, q.a, q.b);
+            if constexpr ((OUT & 1) != 0) v32[q.k] = (float)v;
+            if constexpr ((OUT & 2) != 0) v64[q.k] = v;
+        }
+        q.n = 0;
+    };
+    // one row segment [k0, k0 + cnt) padded to ST_VEC; dec(k, col) -> (aj, bj)
+    auto segment = [&](u64 bi, i64 k0, u32 cnt, auto dec) {
+        const i64 k1 = k0 + pad_vec(cnt);
+        const i64 kr = k0 + cnt;
+        // uniform trip count: the queue's ballots and shuffles need every lane
+        for (i64 kb = k0; kb < k1; kb += HCI_WAVE) {
+            const i64 k = kb + lane;
+            double v = 0.0;
+            bool single = false;
+            u64 aj = 0, bj = 0;
+            if (k < kr) {
+                dec(T.cols[k], aj, bj);
+                single = popc64(ai ^ aj) + popc64(bi ^ bj) == 2;
+                if (!single) v = hij_f64(I, ai, bi, aj, bj);
             }
-            q.n = 0;
-        };
-        for (u32 sg = 0; sg < ns; ++sg) {
-            const i64 k0 = T.sstart[sb + sg];
-            const u32 cnt = T.segcnt[sb + sg];
-            const i64 k1 = k0 + pad_vec(cnt);
-            const i64 kr = k0 + cnt;
-            // uniform trip count: the queue's ballots and shuffles need every lane
-            for (i64 kb = k0; kb < k1; kb += HCI_WAVE) {
-                const i64 k = kb + lane_id();
-                double v = 0.0;
-                bool single = false;
-                u64 aj = 0, bj = 0;
-                if (k < kr) {
-                    const u32 col = T.cols[k];
-                    if (sg + 1 < ns) {
-                        const u32 P = (sg << T.wlog) + col;
-                        u32 lo = 0, hi = nr - 1u;  // last range starting at or before P
-                        while (lo < hi) {
-                            const u32 mid = (lo + hi + 1u) >> 1;
-                            if (rx[mid] <= P) lo = mid;
-                            else hi = mid - 1u;
-                        }
-                        aj = ralpha[lo];
-                        bj = S.beta[rbase[lo] + (P - rx[lo])];
-                    } else {
-                        aj = S.alpha[S.permb[gb + col]];
-                        bj = bi;
-                    }
-                    single = popc64(ai ^ aj) + popc64(bi ^ bj) == 2;
-                    if (!single) v = hij_f64(I, ai, bi, aj, bj);
+            if (!single && k < k1) {
+                if constexpr ((OUT & 1) != 0) v32[k] = (float)v;
+                if constexpr ((OUT & 2) != 0) v64[k] = v;
+            }
+            const u64 m = ballot(single);
+            if (m) {
+                if (q.full_for(m)) flush();
+                q.push(m, k, bi, aj, bj);
+            }
+        }
+    };
+    for (u32 g = 0; g + 1 < ns; ++g) {
+        __syncthreads();  // the previous window is consumed (and the ranges are in)
+        const u32 wstart = g << T.wlog;
+        const u32 wend = min(wstart + wsize, slen);
+        u32 p = wstart + tid;
+        if (p < wend) {
+            // last range starting at or before p, then forward as p grows
+            u32 e = 0, hi = nr - 1u;
+            while (e < hi) {
+                const u32 mid = (e + hi + 1u) >> 1;
+                if (rx[mid] <= p) e = mid;
+                else hi = mid - 1u;
+            }
+            for (; p < wend; p += ST_CPY * ST_BLOCK) {
+                u32 sidx[ST_CPY];
+#pragma unroll
+                for (int j = 0; j < ST_CPY; ++j) {
+                    const u32 pj = p + (u32)j * ST_BLOCK;
+                    while (e + 1 < nr && rx[e + 1] <= pj) ++e;
+                    sidx[j] = rsrc[e] + (pj - rx[e]);
                 }
-                if (!single && k < k1) {
-                    if constexpr ((OUT & 1) != 0) v32[k] = (float)v;
-                    if constexpr ((OUT & 2) != 0) v64[k] = v;
-                }
-                const u64 m = ballot(single);
-                if (m) {
-                    if (q.full_for(m)) flush();
-                    q.push(m, k, aj, bj);
+                u64 v[ST_CPY];
+#pragma unroll
+                for (int j = 0; j < ST_CPY; ++j) v[j] = p + (u32)j * ST_BLOCK < wend ? S.beta[sidx[j]] : 0ull;
+#pragma unroll
+                for (int j = 0; j < ST_CPY; ++j) {
+                    const u32 pj = p + (u32)j * ST_BLOCK;
+                    if (pj < wend) sbeta[pj - wstart] = v[j];
                 }
             }
         }
-        if (q.n) flush();
+        __syncthreads();
+        for (u32 i = r0 + wave; i < r1; i += ST_WAVES) {
+            const i64 slot = T.rsb[i] + g;
+            segment(S.beta[i], T.sstart[slot], T.segcnt[slot], [&](u32 col, u64& aj, u64& bj) {
+                const u32 P = wstart + col;
+                u32 lo = 0, hi = nr - 1u;  // last range starting at or before P
+                while (lo < hi) {
+                    const u32 mid = (lo + hi + 1u) >> 1;
+                    if (rx[mid] <= P) lo = mid;
+                    else hi = mid - 1u;
+                }
+                aj = ralpha[lo];
+                bj = sbeta[col];
+            });
+        }
     }
+    for (u32 i = r0 + wave; i < r1; i += ST_WAVES) {
+        const u64 bi = S.beta[i];
+        const i64 slot = T.rsb[i] + ns - 1u;
+        const u64* __restrict__ ga = S.alpha_b + S.boff[S.ib[i]];
+        segment(bi, T.sstart[slot], T.segcnt[slot], [&](u32 col, u64& aj, u64& bj) {
+            aj = ga[col];
+            bj = bi;
+        });
+    }
+    if (q.n) flush();
 }
 
 __global__ void st_sum_kernel(const u32* __restrict__ x, i64 n, unsigned long long* __restrict__ out) {
@@ -845,6 +913,10 @@ void launch_spmv(hci_ctx_s* ctx, Space* sp, const char* name, const char* gname,
 
 size_t ab_lds(const Space& sp) { return (size_t)6 * sp.st_abW * sp.st_abG; }
 
+size_t vals_lds(const hci_ctx_s* ctx, u32 wlog) {
+    return (sizeof(u64) << wlog) + 2 * st_range_lds(ctx);
+}
+
 }  // namespace
 
 bool staged_prepare(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
@@ -853,7 +925,7 @@ bool staged_prepare(hci_ctx_s* ctx, Space* sp, hipStream_t s) {
     int dev = 0, max_shared = 0;
     HIP_CHECK(hipGetDevice(&dev));
     HIP_CHECK(hipDeviceGetAttribute(&max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    if (((i64)sizeof(double) << wlog) + (i64)st_range_lds(ctx) > (i64)max_shared) return false;
+    if ((i64)vals_lds(ctx, (u32)wlog) > (i64)max_shared) return false;
     const i64 N = sp->N, nua = sp->nua, nub = sp->nub;
     // the build passes take one wavefront per row in one launch
     if (ceil_div(N, ST_ROWS_PER_BLOCK) * ST_ROW_BLOCK >= ((i64)1 << 32)) return false;
@@ -1016,9 +1088,14 @@ void staged_ensure_vals(hci_ctx_s* ctx, Space* sp, int precision, hipStream_t s)
                     "internal: " + std::to_string(nbad) + " row segments disagree with the count pass");
     }
     IntView I = int_view(ctx->ints);
-    // element pass per row chunk; LDS: alpha string, stage start and first
-    // row of each of the bucket's ranges (at most 1 + N_alpha (n - N_alpha))
-    const size_t vlds = (size_t)16 * (1 + (size_t)ctx->na * (ctx->n - ctx->na));
+    // element pass per row chunk; LDS: the window's beta strings, then the
+    // alpha string, stage start and first row of each of the bucket's ranges
+    // (at most 1 + N_alpha (n - N_alpha))
+    const size_t vlds = vals_lds(ctx, sp->st_wlog);
+    for (const void* k : {reinterpret_cast<const void*>(st_vals_kernel<1>),
+                          reinterpret_cast<const void*>(st_vals_kernel<2>),
+                          reinterpret_cast<const void*>(st_vals_kernel<3>)})
+        HIP_CHECK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)vlds));
     if (f32 && !sp->st_have64 && nnz * (i64)(2 + 4 + 8) <= ctx->stored_budget) {
         sp->st_vals32 = dev_alloc(ctx, sizeof(float) * (nnz > 0 ? nnz : 1), s);
         sp->st_vals64 = dev_alloc(ctx, sizeof(double) * (nnz > 0 ? nnz : 1), s);
