@@ -229,6 +229,7 @@ int hci_ctx_destroy(hci_ctx ctx) {
             (void)hipEventDestroy(p.stop);
         }
         for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+        if (ctx->host_scal) (void)hipHostFree(ctx->host_scal);
         delete ctx;
         return HCI_OK;
     });

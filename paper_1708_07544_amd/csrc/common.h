@@ -295,6 +295,10 @@ struct hci_ctx_s {
     i64 stored_budget = (i64)64 << 30;
     i64 pt2_budget = (i64)64 << 30;  // screened PT2 pairs held at once
     int stage_wlog = 14;  // log2 of the staged layout's window; 0 = plain CSR
+    // pinned, coherent host words the Davidson reduction writes every
+    // iteration (four scalars, then a sequence number the host polls)
+    double* host_scal = nullptr;
+    unsigned long long host_seq = 0;
     bool timing = false;
     std::map<std::string, KernelTimer> timers;
     std::vector<PendingEvent> pending;

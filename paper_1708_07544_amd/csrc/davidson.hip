@@ -22,7 +22,9 @@
 // there is the next state, and its residual is orthogonal to L.  For several
 // states every start vector gets a small fixed pseudo-random component, so
 // that the lowest state of the complement is reached whatever its symmetry.
+#include <atomic>
 #include <cfloat>
+#include <chrono>
 
 #include "common.h"
 
@@ -71,10 +73,13 @@ __global__ void __launch_bounds__(DV_BLOCK) dots_kernel(const double* __restrict
 // reads together).  (A last-block reduction inside the producing kernels was
 // tried: the device-scope fence each block then needs before its ticket costs
 // ~0.1 ms per kernel on this GPU, more than the separate launch.)
+// With host given, block 0 then copies the four scalars out0[0..4) into
+// host[0..4) (pinned, coherent host memory) and, after a system-scope fence,
+// writes seq into host[4] for the host to poll.
 __global__ void reduce_partials_kernel(const double* __restrict__ partial, int k, int nblk,
                                        double* __restrict__ out, i64 ostride,
-                                       const double* __restrict__ copy_src, double* __restrict__ copy_dst,
-                                       double* __restrict__ out0) {
+                                       const double* __restrict__ copy_src, double* copy_dst,
+                                       double* out0, double* host, unsigned long long seq) {
     __shared__ double lds[DV_BLOCK / 64];
     const int j = blockIdx.x;
     if (j >= k) return;
@@ -86,6 +91,12 @@ __global__ void reduce_partials_kernel(const double* __restrict__ partial, int k
         else if (j == 0) *out0 = v;
         else out[(i64)(j - 1) * ostride] = v;
         if (j == 0 && copy_dst) *copy_dst = *copy_src;
+        if (j == 0 && host != nullptr) {
+            const volatile double* src = out0;  // (this thread wrote out0[0] and out0[3])
+            for (int q = 0; q < 4; ++q) host[q] = src[q];
+            __threadfence_system();
+            *reinterpret_cast<volatile unsigned long long*>(host + 4) = seq;
+        }
     }
 }
 
@@ -558,9 +569,10 @@ struct Workspace {
         reduce(k, out, ostride);
     }
     void reduce(int k, double* out, i64 ostride = 1, const double* copy_src = nullptr,
-                double* copy_dst = nullptr, double* out0 = nullptr) {
+                double* copy_dst = nullptr, double* out0 = nullptr, double* host = nullptr,
+                unsigned long long seq = 0) {
         HCI_LAUNCH(ctx, "dv_reduce", s, reduce_partials_kernel, k, DV_BLOCK, 0, partial.as<double>(),
-                   k, nblk, out, ostride, copy_src, copy_dst, out0);
+                   k, nblk, out, ostride, copy_src, copy_dst, out0, host, seq);
     }
     // two-sweep classical Gram-Schmidt of t against X_0..X_{k-1}; nrm2 = |t|^2
     void cgs2(const double* X, i64 ld, int k, double* t, double* coef, double* nrm2) {
@@ -585,6 +597,25 @@ struct Workspace {
                    (const double*)coef, w, N, partial.as<double>(), nblk);
     }
 };
+
+// The four scalars {|r|^2, |t|^2, dead, theta} of the iteration whose
+// reduction was given sequence number seq: poll the pinned words, and after
+// 0.2 s (a long product ahead of them) wait on the stream instead.
+void wait_host_scalars(hci_ctx_s* ctx, unsigned long long seq, hipStream_t s, double* hv) {
+    const volatile unsigned long long* flag =
+        reinterpret_cast<const volatile unsigned long long*>(ctx->host_scal + 4);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned spins = 1; *flag != seq; ++spins) {
+        if ((spins & 1023u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(200)) {
+            HIP_CHECK(hipStreamSynchronize(s));
+            HCI_REQUIRE(*flag == seq, HCI_E_HIP, "internal: Davidson scalars were not written");
+            break;
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    const volatile double* h = ctx->host_scal;
+    for (int q = 0; q < 4; ++q) hv[q] = h[q];
+}
 
 }  // namespace
 
@@ -619,6 +650,12 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
     double* theta_h = sc + DV_MAXK + 4;  // rr, nrm_t, dead, theta: read back together
     HIP_CHECK(hipMemsetAsync(dead, 0, sizeof(double), s));
     const i64 g1 = ceil_div(N, 256);
+    if (!ctx->host_scal) {
+        void* hp = nullptr;
+        HIP_CHECK(hipHostMalloc(&hp, 8 * sizeof(double), hipHostMallocCoherent));
+        ctx->host_scal = static_cast<double*>(hp);
+        *reinterpret_cast<volatile unsigned long long*>(ctx->host_scal + 4) = 0ull;
+    }
 
     // start vector (a zero vector selects the lowest diagonal determinant);
     // deflated: its part outside the locked vectors, or a seed when nothing
@@ -693,11 +730,11 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
             const int kd = (nlock == 0 && k < kmax) ? k : 0;
             HCI_LAUNCH(ctx, "dv_combine", s, combine_kernel, ws.nblk, DV_BLOCK, 0, V, W, N, k, kd,
                        ritz.as<double>(), hd, xc, wc, t, N, ws.partial.as<double>(), ws.nblk);
-            ws.reduce(kd + 1, sc, 1, ritz.as<double>(), theta_h, rr);
+            const unsigned long long seq = ++ctx->host_seq;
+            ws.reduce(kd + 1, sc, 1, ritz.as<double>(), theta_h, rr, ctx->host_scal, seq);
             have_prev = true;
             double hv[4];
-            HIP_CHECK(hipMemcpyAsync(hv, rr, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
-            HIP_CHECK(hipStreamSynchronize(s));
+            wait_host_scalars(ctx, seq, s, hv);
             rnorm = sqrt(std::max(hv[0], 0.0));
             const bool was_dead = hv[2] != 0.0;  // the newest direction had no norm
             theta = hv[3];
