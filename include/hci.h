@@ -168,7 +168,12 @@ const char* hci_last_error(void);
  *   dets: device [n_var][2] sorted unique list V; c: device float64 [n_var].
  *   out_dets: device [cap][2]; may not alias dets.  n_out (host) receives the
  *   size of V + C; on HCI_E_CAPACITY it holds the required capacity and
- *   out_dets is unspecified.  Synchronises the stream. */
+ *   out_dets is unspecified.  Such a refused call keeps its result in the
+ *   context (up to 2^28 determinants, 16 B each, when the memory is there):
+ *   the next selection call with the same dets and c by content, the same
+ *   eps1 and room for it copies the kept list instead of walking again.  Any
+ *   other selection call, a change of cached space, hci_ctx_release_cache and
+ *   hci_ctx_update_integrals drop it.  Synchronises the stream. */
 int hci_select(hci_ctx ctx, const uint64_t* dets, const double* c, int64_t n_var,
                double eps1, uint64_t* out_dets, int64_t cap, int64_t* n_out, void* stream);
 

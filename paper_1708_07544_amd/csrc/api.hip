@@ -120,9 +120,25 @@ DevMem dev_alloc(hci_ctx_s* ctx, size_t bytes, hipStream_t stream) {
     return m;
 }
 
+void* host_staging(hci_ctx_s* ctx, size_t bytes) {
+    if (ctx->host_stage_bytes < bytes) {
+        if (ctx->host_stage) HIP_CHECK(hipHostFree(ctx->host_stage));
+        ctx->host_stage = nullptr;
+        ctx->host_stage_bytes = 0;
+        const size_t want = std::max<size_t>(bytes, (size_t)1 << 16);
+        void* p = nullptr;
+        HIP_CHECK(hipHostMalloc(&p, want, hipHostMallocDefault));
+        ctx->host_stage = static_cast<unsigned char*>(p);
+        ctx->host_stage_bytes = want;
+    }
+    return ctx->host_stage;
+}
+
 void drop_space(hci_ctx_s* ctx) {
     delete ctx->space;
     ctx->space = nullptr;
+    delete ctx->sel_kept;
+    ctx->sel_kept = nullptr;
 }
 
 static hipEvent_t take_event(hci_ctx_s* ctx) {
@@ -230,6 +246,7 @@ int hci_ctx_destroy(hci_ctx ctx) {
         }
         for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
         if (ctx->host_scal) (void)hipHostFree(ctx->host_scal);
+        if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
         delete ctx;
         return HCI_OK;
     });

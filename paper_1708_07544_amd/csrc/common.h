@@ -283,6 +283,16 @@ struct PendingEvent {
     hipEvent_t start, stop;
 };
 
+// The result of the last selection that did not fit its caller's capacity,
+// kept for a retry with enough room on the same inputs (by content), so the
+// retry copies it instead of walking again.
+struct SelectKept {
+    DevMem out;  // u64 [M][2], sorted unique V + C
+    i64 M = 0, N = 0;
+    u64 dets_hash = 0, c_hash = 0;
+    double eps = 0.0;
+};
+
 struct hci_ctx_s {
     int n = 0, na = 0, nb = 0;
     int device = 0;
@@ -291,6 +301,7 @@ struct hci_ctx_s {
     bool has_alloc = false;
     Integrals ints;
     Space* space = nullptr;
+    SelectKept* sel_kept = nullptr;  // dropped with the space
     struct Pt2Frozen* frozen = nullptr;  // screened PT2 pairs frozen by hci_pt2_freeze
     i64 stored_budget = (i64)64 << 30;
     i64 pt2_budget = (i64)64 << 30;  // screened PT2 pairs held at once
@@ -299,6 +310,10 @@ struct hci_ctx_s {
     // iteration (four scalars, then a sequence number the host polls)
     double* host_scal = nullptr;
     unsigned long long host_seq = 0;
+    // pinned staging for small planner copies (grown on demand, only while
+    // no copy through it is pending)
+    unsigned char* host_stage = nullptr;
+    size_t host_stage_bytes = 0;
     bool timing = false;
     std::map<std::string, KernelTimer> timers;
     std::vector<PendingEvent> pending;
@@ -309,6 +324,9 @@ struct hci_ctx_s {
 DevMem dev_alloc(hci_ctx_s* ctx, size_t bytes, hipStream_t stream);
 // release a cached space
 void drop_space(hci_ctx_s* ctx);
+// Pinned host memory of at least bytes (the context's staging area; its
+// previous contents are lost when it grows).
+void* host_staging(hci_ctx_s* ctx, size_t bytes);
 // release the frozen PT2 pair set
 void drop_frozen(hci_ctx_s* ctx);
 

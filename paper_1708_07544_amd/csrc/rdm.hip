@@ -14,6 +14,7 @@
 // result is the same bit for bit from run to run.
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
 #include <queue>
 #include <vector>
 
@@ -852,10 +853,7 @@ namespace {
 // workgroup (ties: lowest index), so the assignment depends only on the
 // space.  cost(bucket, rows) estimates a chunk's time.
 template <class Cost>
-void plan_chunks(hci_ctx_s* ctx, const u32* off_dev, i64 nbuck, int P, Cost cost, RdmChunks& C, hipStream_t s) {
-    std::vector<u32> off(nbuck + 1);
-    HIP_CHECK(hipMemcpyAsync(off.data(), off_dev, sizeof(u32) * (nbuck + 1), hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
+void plan_chunks(const u32* off, i64 nbuck, int P, Cost cost, std::vector<u32>& list, std::vector<u32>& wptr) {
     struct Ch {
         u32 b, r0, r1;
         double cost;
@@ -872,30 +870,27 @@ void plan_chunks(hci_ctx_s* ctx, const u32* off_dev, i64 nbuck, int P, Cost cost
     using Load = std::pair<double, int>;
     std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
     for (int p = 0; p < P; ++p) heap.push({0.0, p});
-    std::vector<std::vector<u32>> per(P);
+    std::vector<u32> owner(ch.size());
+    std::vector<u32> count(P, 0);
     for (u32 i : order) {
         Load l = heap.top();
         heap.pop();
-        per[l.second].push_back(i);
+        owner[i] = (u32)l.second;
+        ++count[l.second];
         l.first += ch[i].cost;
         heap.push(l);
     }
-    std::vector<u32> list, wptr(P + 1, 0);
-    list.reserve(3 * ch.size());
-    for (int p = 0; p < P; ++p) {
-        for (u32 i : per[p]) {
-            list.push_back(ch[i].b);
-            list.push_back(ch[i].r0);
-            list.push_back(ch[i].r1);
-        }
-        wptr[p + 1] = (u32)(list.size() / 3);
+    // workgroup p's chunks in the order it received them
+    wptr.assign(P + 1, 0);
+    for (int p = 0; p < P; ++p) wptr[p + 1] = wptr[p] + count[p];
+    std::vector<u32> cur(wptr.begin(), wptr.end() - 1);
+    list.assign(3 * ch.size(), 0);
+    for (u32 i : order) {
+        const u32 at = cur[owner[i]]++;
+        list[3 * at] = ch[i].b;
+        list[3 * at + 1] = ch[i].r0;
+        list[3 * at + 2] = ch[i].r1;
     }
-    C.list = dev_alloc(ctx, sizeof(u32) * std::max<size_t>(list.size(), 3), s);
-    C.wptr = dev_alloc(ctx, sizeof(u32) * (P + 1), s);
-    HIP_CHECK(hipMemcpyAsync(C.list.ptr, list.data(), sizeof(u32) * list.size(), hipMemcpyHostToDevice, s));
-    HIP_CHECK(hipMemcpyAsync(C.wptr.ptr, wptr.data(), sizeof(u32) * (P + 1), hipMemcpyHostToDevice, s));
-    HIP_CHECK(hipStreamSynchronize(s));  // the host vectors go out of scope
-    C.P = P;
 }
 }  // namespace
 
@@ -935,21 +930,50 @@ void rdm_compute(hci_ctx_s* ctx, Space* sp, const double* bra, const double* ket
     // workgroups as CUs, each with a longer list
     const int Ps = dx ? std::min(Pw, cus) : Pw;
     if (sp->rdm_sa.P != Ps || sp->rdm_nb.P != Pw || sp->rdm_nb.key != (P.W > 0)) {
+        // bucket offsets and the alpha single x beta single cost per bucket
+        // in one read-back through pinned memory
+        const i64 nua = sp->nua, nub = sp->nub;
+        DevMem bc = dev_alloc(ctx, sizeof(float) * nua, s);
+        HCI_LAUNCH(ctx, "rdm_plan", s, nb_cost_kernel, ceil_div(nua, 256), 256, 0, S, nua, P.W, P.ds,
+                   bc.as<float>());
+        u32* hs = static_cast<u32*>(host_staging(ctx, sizeof(u32) * (size_t)(2 * nua + nub + 2)));
+        HIP_CHECK(hipMemcpyAsync(hs, sp->aoff.ptr, sizeof(u32) * (nua + 1), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(hs + nua + 1, sp->boff.ptr, sizeof(u32) * (nub + 1), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(hs + nua + nub + 2, bc.ptr, sizeof(float) * nua, hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        const std::vector<u32> aoff(hs, hs + nua + 1), boff(hs + nua + 1, hs + nua + nub + 2);
+        std::vector<float> bcost(nua);
+        std::memcpy(bcost.data(), hs + nua + nub + 2, sizeof(float) * nua);
         // a row of a same-string chunk costs a barrier per piece of its bucket
         // (and a chunk about two rows for its flush); an alpha single x beta
         // single chunk one pass per alpha neighbour
         const u32 piece = SS_PIECE;
         auto same_cost = [&](u32, u32 size, u32 rows) { return (double)rows * (double)ceil_div(size, piece) + 2.0; };
-        plan_chunks(ctx, sp->aoff.as<u32>(), sp->nua, Ps, same_cost, sp->rdm_sa, s);
-        plan_chunks(ctx, sp->boff.as<u32>(), sp->nub, Ps, same_cost, sp->rdm_sb, s);
-        DevMem bc = dev_alloc(ctx, sizeof(float) * sp->nua, s);
-        HCI_LAUNCH(ctx, "rdm_plan", s, nb_cost_kernel, ceil_div(sp->nua, 256), 256, 0, S, sp->nua, P.W, P.ds,
-                   bc.as<float>());
-        std::vector<float> bcost(sp->nua);
-        HIP_CHECK(hipMemcpyAsync(bcost.data(), bc.ptr, sizeof(float) * sp->nua, hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
         auto nb_cost = [&](u32 b, u32, u32 rows) { return (double)rows * (double)bcost[b]; };
-        plan_chunks(ctx, sp->aoff.as<u32>(), sp->nua, Pw, nb_cost, sp->rdm_nb, s);
+        std::vector<u32> list[3], wptr[3];
+        plan_chunks(aoff.data(), nua, Ps, same_cost, list[0], wptr[0]);
+        plan_chunks(boff.data(), nub, Ps, same_cost, list[1], wptr[1]);
+        plan_chunks(aoff.data(), nua, Pw, nb_cost, list[2], wptr[2]);
+        // all three plans up through the staging area, one wait
+        size_t words = 0;
+        for (int q = 0; q < 3; ++q) words += list[q].size() + wptr[q].size();
+        u32* up = static_cast<u32*>(host_staging(ctx, sizeof(u32) * words));
+        RdmChunks* dst[3] = {&sp->rdm_sa, &sp->rdm_sb, &sp->rdm_nb};
+        const int Pq[3] = {Ps, Ps, Pw};
+        size_t at = 0;
+        for (int q = 0; q < 3; ++q) {
+            RdmChunks& C = *dst[q];
+            C.list = dev_alloc(ctx, sizeof(u32) * std::max<size_t>(list[q].size(), 3), s);
+            C.wptr = dev_alloc(ctx, sizeof(u32) * wptr[q].size(), s);
+            std::memcpy(up + at, list[q].data(), sizeof(u32) * list[q].size());
+            HIP_CHECK(hipMemcpyAsync(C.list.ptr, up + at, sizeof(u32) * list[q].size(), hipMemcpyHostToDevice, s));
+            at += list[q].size();
+            std::memcpy(up + at, wptr[q].data(), sizeof(u32) * wptr[q].size());
+            HIP_CHECK(hipMemcpyAsync(C.wptr.ptr, up + at, sizeof(u32) * wptr[q].size(), hipMemcpyHostToDevice, s));
+            at += wptr[q].size();
+            C.P = Pq[q];
+        }
+        HIP_CHECK(hipStreamSynchronize(s));  // the staging area is free again
         sp->rdm_nb.key = P.W > 0;
     }
     ensure_alpha_b(ctx, sp, s);

@@ -157,6 +157,32 @@ __global__ void roots_weight_kernel(const double* __restrict__ C, int nroots, i6
     w[i] = m;
 }
 
+// Content hash of a float64 vector (wrapping sum of position-mixed words:
+// order independent, so the integer atomics give one value).
+__global__ void hash_f64_kernel(const double* __restrict__ x, i64 n, unsigned long long* __restrict__ h) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    u64 v = 0;
+    if (i < n) {
+        u64 z = (u64)__double_as_longlong(x[i]) * 0x9e3779b97f4a7c15ull ^ ((u64)i + 0x632be59bd9b4e019ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        v = z ^ (z >> 31);
+    }
+    v = wave_sum_u64(v);
+    if (lane_id() == 0 && v) atomicAdd(h, (unsigned long long)v);
+}
+
+u64 hash_f64(hci_ctx_s* ctx, const double* x, i64 n, hipStream_t s) {
+    DevMem h = dev_alloc(ctx, sizeof(u64), s);
+    HIP_CHECK(hipMemsetAsync(h.ptr, 0, sizeof(u64), s));
+    HCI_LAUNCH(ctx, "select_hash", s, hash_f64_kernel, ceil_div(n, 256), 256, 0, x, n,
+               (unsigned long long*)h.as<u64>());
+    return read_scalar(h.as<u64>(), s);
+}
+
+// Largest result kept for a capacity retry (larger ones walk again).
+constexpr i64 SELECT_KEEP_MAX = (i64)1 << 28;  // determinants (4 GiB)
+
 }  // namespace
 
 i64 select_roots_run(hci_ctx_s* ctx, const u64* dets, const double* C, int nroots, i64 N, double eps,
@@ -199,6 +225,24 @@ double heat_bath_max(hci_ctx_s* ctx, hipStream_t s) {
 i64 select_run(hci_ctx_s* ctx, const u64* dets, const double* c, i64 N, double eps, u64* out,
                i64 cap, hipStream_t s) {
     const int n = ctx->n;
+    // the caller validated dets as the context's space: its content hash
+    // and that of c key a result kept by an earlier call that did not fit
+    HCI_REQUIRE(ctx->space != nullptr && ctx->space->N == N, HCI_E_HIP, "internal: selection without its space");
+    const u64 d_hash = ctx->space->hash;
+    const u64 c_hash = hash_f64(ctx, c, N, s);
+    if (SelectKept* k = ctx->sel_kept) {
+        const bool same = k->N == N && k->dets_hash == d_hash && k->c_hash == c_hash && k->eps == eps;
+        if (same && k->M <= cap) {
+            const i64 M = k->M;
+            HIP_CHECK(hipMemcpyAsync(out, k->out.ptr, sizeof(u64) * 2 * M, hipMemcpyDeviceToDevice, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            delete k;
+            ctx->sel_kept = nullptr;
+            return M;
+        }
+        delete k;
+        ctx->sel_kept = nullptr;
+    }
     const double hbm = heat_bath_max(ctx, s);
     HBView T = hb_view(ctx->ints);
     IntView I = int_view(ctx->ints);
@@ -259,18 +303,41 @@ i64 select_run(hci_ctx_s* ctx, const u64* dets, const double* c, i64 N, double e
             str_slots = str_slots >= top ? 2 * top : std::min(top, pow2_at_least(std::max<i64>(4 * nstr, 2 * str_slots)));
     }
     const i64 M = N + m;
-    if (M > cap) return M;
-    HashSet H{table.as<u64>(), (u64)(det_slots - 1), sa.as<u64>(), (u64)(str_slots - 1),
-              sb.as<u64>(), (u64)(str_slots - 1), packed ? 1 : 0, overflow, strings};
-    DevMem hi = dev_alloc(ctx, sizeof(u64) * M, s), lo = dev_alloc(ctx, sizeof(u64) * M, s);
-    HCI_LAUNCH(ctx, "select_gather", s, gather_kernel, ceil_div(M, 256), 256, 0, dets, N,
-               keys.as<u64>(), m, H, hi.as<u64>(), lo.as<u64>());
-    {
-        DevMem thi = dev_alloc(ctx, sizeof(u64) * M, s), tlo = dev_alloc(ctx, sizeof(u64) * M, s);
-        radix_sort128(ctx, hi.as<u64>(), lo.as<u64>(), nullptr, thi.as<u64>(), tlo.as<u64>(), nullptr,
-                      M, n, n, s);
+    // V + C sorted into dst
+    auto write_to = [&](u64* dst) {
+        HashSet H{table.as<u64>(), (u64)(det_slots - 1), sa.as<u64>(), (u64)(str_slots - 1),
+                  sb.as<u64>(), (u64)(str_slots - 1), packed ? 1 : 0, overflow, strings};
+        DevMem hi = dev_alloc(ctx, sizeof(u64) * M, s), lo = dev_alloc(ctx, sizeof(u64) * M, s);
+        HCI_LAUNCH(ctx, "select_gather", s, gather_kernel, ceil_div(M, 256), 256, 0, dets, N,
+                   keys.as<u64>(), m, H, hi.as<u64>(), lo.as<u64>());
+        {
+            DevMem thi = dev_alloc(ctx, sizeof(u64) * M, s), tlo = dev_alloc(ctx, sizeof(u64) * M, s);
+            radix_sort128(ctx, hi.as<u64>(), lo.as<u64>(), nullptr, thi.as<u64>(), tlo.as<u64>(), nullptr,
+                          M, n, n, s);
+        }
+        HCI_LAUNCH(ctx, "select_write", s, interleave_kernel, ceil_div(M, 256), 256, 0, hi.as<u64>(),
+                   lo.as<u64>(), M, dst);
+    };
+    if (M > cap) {
+        // the caller retries with capacity M: keep the result for it (when
+        // it is of a size worth holding and the memory is there)
+        if (M <= SELECT_KEEP_MAX) {
+            try {
+                std::unique_ptr<SelectKept> keep(new SelectKept());
+                keep->out = dev_alloc(ctx, sizeof(u64) * 2 * M, s);
+                keep->M = M;
+                keep->N = N;
+                keep->dets_hash = d_hash;
+                keep->c_hash = c_hash;
+                keep->eps = eps;
+                write_to(keep->out.as<u64>());
+                ctx->sel_kept = keep.release();
+            } catch (const HciError& e) {
+                if (e.code != HCI_E_NOMEM) throw;
+            }
+        }
+        return M;
     }
-    HCI_LAUNCH(ctx, "select_write", s, interleave_kernel, ceil_div(M, 256), 256, 0, hi.as<u64>(),
-               lo.as<u64>(), M, out);
+    write_to(out);
     return M;
 }

@@ -174,6 +174,44 @@ def test_select_capacity_reports_required(cas8, lib_mod):
     assert n_out.value == 361
 
 
+def test_select_capacity_retry_keeps_result(lib_mod):
+    """A call refused for capacity keeps its result for the retry: the retry
+    with room returns the oracle's V + C(eps) bit for bit, and a retry whose c
+    changed in between (same buffer) selects from the new c."""
+    n, na, nb, eps = 12, 5, 5, 2e-3
+    h, g = hs.make_integrals(n, 3 * n, 21)
+    V = hs.random_dets(n, na, nb, 300, seed=21, bias=0.2)
+    c1 = hs.random_coeffs(len(V), 121)
+    c2 = hs.random_coeffs(len(V), 122)
+    ctx = lib_mod.HCIContext(h, g, na, nb)
+    L = lib_mod._lib
+    d = lib_mod.dets_to_device(V)
+    cd = torch.as_tensor(c1, dtype=torch.float64, device="cuda").contiguous()
+    n_out = ctypes.c_int64()
+
+    def call(cap):
+        out = torch.zeros((max(cap, 1), 2), dtype=torch.int64, device="cuda")
+        code = L.lib().hci_select(ctx.handle, L._ptr(d), L._ptr(cd), len(V), eps, L._ptr(out), cap,
+                                  ctypes.byref(n_out), L._stream())
+        return code, out
+
+    for c, change_to in [(c1, None), (c1, c2)]:
+        cd.copy_(torch.as_tensor(c, dtype=torch.float64))
+        code, _ = call(2)
+        assert code == L.HCI_E_CAPACITY
+        m = n_out.value
+        if change_to is not None:
+            cd.copy_(torch.as_tensor(change_to, dtype=torch.float64))
+            c = change_to
+        ref = O.merge(V, O.select(h, g, V, c, eps))
+        code, out = call(max(m, len(ref)))
+        assert code == L.HCI_OK
+        got = lib_mod.dets_to_numpy(out[: n_out.value])
+        print(f"[select retry] refused at 2, required {m}, retry gives {len(got)}, oracle {len(ref)}", flush=True)
+        assert np.array_equal(got, ref)
+    ctx.close()
+
+
 def test_stored_matrix_rebuilds_agree(lib_mod):
     """The stored Hamiltonian built in several fresh contexts gives the
     oracle's product every time (guards against build-order dependence)."""
