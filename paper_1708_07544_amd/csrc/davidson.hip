@@ -247,21 +247,21 @@ __global__ void __launch_bounds__(64) lowest_eig_kernel(const double* __restrict
     __shared__ double H[DV_MAXK][DV_MAXK];  // Householder vector of step j in row j
     __shared__ double vv[DV_MAXK], pw[DV_MAXK], d[DV_MAXK], e[DV_MAXK], y[DV_MAXK];
     const int l = threadIdx.x;
+    static_assert(DV_MAXK == 32, "entries of the projected matrix are addressed as r * 32 + c");
     {  // every load in flight before the first store
         constexpr int PER = DV_MAXK * DV_MAXK / 64;
-        const int kq = k > 0 ? k : 1;  // (no entries when k = 0)
         double g[PER];
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int x = l + 64 * u;
-            const int r = x / kq, c = x % kq;
-            g[u] = x < k * k ? G[(r < c ? r : c) * ldg + (r < c ? c : r)] : 0.0;
+            const int r = x >> 5, c = x & 31;
+            g[u] = r < k && c < k ? G[(r < c ? r : c) * ldg + (r < c ? c : r)] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int x = l + 64 * u;
-            if (x < k * k) {
-                const int r = x / kq, c = x % kq;
+            const int r = x >> 5, c = x & 31;
+            if (r < k && c < k) {
                 A[r][c] = g[u];
                 A0[r][c] = g[u];
             }
@@ -288,15 +288,21 @@ __global__ void __launch_bounds__(64) lowest_eig_kernel(const double* __restrict
             vv[l] = vi;
         }
         __syncthreads();
+        // p = A v: row l & 31 by lanes l and l + 32, each over half the columns
+        const int pr = l & 31, half = l >> 5;
         double pi = 0.0;
-        if (l < m)
-            for (int c = 0; c < m; ++c) pi += A[j + 1 + l][j + 1 + c] * vv[c];
+        if (pr < m)
+            for (int c = half; c < m; c += 2) pi += A[j + 1 + pr][j + 1 + c] * vv[c];
+        pi += __shfl_xor(pi, 32, 64);
+        if (l >= 32) pi = 0.0;
         const double K = wave_sum_f64(vi * pi);
         if (l < m) pw[l] = pi - K * vi;
         __syncthreads();
-        for (int x = l; x < m * m; x += 64) {
-            const int r = x / m, c = x % m;
-            A[j + 1 + r][j + 1 + c] -= 2.0 * (vv[r] * pw[c] + pw[r] * vv[c]);
+#pragma unroll
+        for (int u = 0; u < DV_MAXK * DV_MAXK / 64; ++u) {
+            const int x = l + 64 * u;
+            const int r = x >> 5, c = x & 31;
+            if (r < m && c < m) A[j + 1 + r][j + 1 + c] -= 2.0 * (vv[r] * pw[c] + pw[r] * vv[c]);
         }
         if (l == 0) {
             A[j + 1][j] = alpha;

@@ -499,11 +499,18 @@ struct BraSinglesQueue {
 // float64 when OUT & 2; the float32-mixed solver refines with float64
 // products, so it asks for both).  Workgroup = a chunk of rows of one alpha
 // bucket, as the product, and window by window as the product: the window's
-// beta strings are copied into LDS once (the ket's alpha string is that of
-// the stage range holding the position, found by a binary search over the
-// bucket's ranges in LDS), then every row of the chunk decodes its segment
-// of that window from LDS.  The beta-group segments (same beta string) read
-// the ket's alpha string from the beta-major copy of the alpha words.
+// beta strings are copied into LDS once, with the index of the stage range
+// holding each position in the word's top 16 bits when n <= 48 (else a
+// binary search over the bucket's ranges finds it), then every row of the
+// chunk decodes its segment of that window from LDS.  A range other than the
+// bucket's own is an alpha single A -> A' whose hole, particle and phase are
+// fixed, so its alpha x beta doubles need only the beta part: sign_A sign_B
+// (rp|sq) with the range's (r, p) offset into g kept in LDS.  The beta-group
+// segments (same beta string) read the ket's alpha string from the
+// beta-major copy of the alpha words.
+constexpr u32 ST_NO_LINK = 0xffffffffu;
+constexpr int ST_PACK_MAXN = 48;  // beta strings leave 16 bits for the range index
+
 template <int OUT>
 __global__ void __launch_bounds__(ST_BLOCK) st_vals_kernel(SpaceView S, IntView I, StView T,
                                                            float* __restrict__ v32,
@@ -512,6 +519,9 @@ __global__ void __launch_bounds__(ST_BLOCK) st_vals_kernel(SpaceView S, IntView 
     const u32 tid = threadIdx.x;
     const u32 wave = tid / HCI_WAVE;
     const int lane = lane_id();
+    const int n = I.n;
+    const bool pk = n <= ST_PACK_MAXN;
+    constexpr u64 LOW48 = (1ull << 48) - 1ull;
     // bucket and rows of this workgroup's chunk
     const u32* ce = T.chunk + 3 * (i64)blockIdx.x;
     const u32 a = ce[0], r0 = ce[1], r1 = ce[2];
@@ -520,17 +530,26 @@ __global__ void __launch_bounds__(ST_BLOCK) st_vals_kernel(SpaceView S, IntView 
     const u32 ns = T.nseg[a];
     const u32 slen = T.len[a];
     const u32 wsize = 1u << T.wlog;
+    const u64 ai = S.ua[a];
     u64* sbeta = reinterpret_cast<u64*>(st_smem);  // [wsize] beta strings of the window
     u64* ralpha = sbeta + wsize;                    // [nr] alpha string of each range
     u32* rx = reinterpret_cast<u32*>(ralpha + nr);  // [nr] stage start of each range
     u32* rsrc = rx + nr;                            // [nr] first row of each range
+    u32* rinfo = rsrc + nr;                         // [nr] g offset of (r, p) | sign bit
     for (u32 e = tid; e < nr; e += ST_BLOCK) {
         const u32 a2 = e == 0 ? a : S.as_idx[t0 + e - 1];
-        ralpha[e] = S.ua[a2];
+        const u64 A2 = S.ua[a2];
+        ralpha[e] = A2;
         rx[e] = T.xpos[t0 + a + e];
         rsrc[e] = S.aoff[a2];
+        u32 info = ST_NO_LINK;
+        if (e > 0) {  // alpha single p -> r
+            const u64 xa = ai ^ A2;
+            const int p = ctz64(ai & xa), r = ctz64(A2 & xa);
+            info = (u32)gidx(n, r, p, 0, 0) | (sign_between(ai, p, r) < 0.0 ? 0x80000000u : 0u);
+        }
+        rinfo[e] = info;
     }
-    const u64 ai = S.ua[a];
     BraSinglesQueue q;
     auto flush = [&]() {
         if (lane < q.n) {
@@ -540,7 +559,8 @@ __global__ void __launch_bounds__(ST_BLOCK) st_vals_kernel(SpaceView S, IntView 
         }
         q.n = 0;
     };
-    // one row segment [k0, k0 + cnt) padded to ST_VEC; dec(k, col) -> (aj, bj)
+    // one row segment [k0, k0 + cnt) padded to ST_VEC; dec(k, col) -> (aj,
+    // bj, the range's link info or ST_NO_LINK)
     auto segment = [&](u64 bi, i64 k0, u32 cnt, auto dec) {
         const i64 k1 = k0 + pad_vec(cnt);
         const i64 kr = k0 + cnt;
@@ -551,9 +571,20 @@ __global__ void __launch_bounds__(ST_BLOCK) st_vals_kernel(SpaceView S, IntView 
             bool single = false;
             u64 aj = 0, bj = 0;
             if (k < kr) {
-                dec(T.cols[k], aj, bj);
-                single = popc64(ai ^ aj) + popc64(bi ^ bj) == 2;
-                if (!single) v = hij_f64(I, ai, bi, aj, bj);
+                u32 info;
+                dec(T.cols[k], aj, bj, info);
+                const u64 xb = bi ^ bj;
+                if (info != ST_NO_LINK) {  // alpha single, or alpha x beta double
+                    single = xb == 0;
+                    if (!single) {
+                        const int qo = ctz64(bi & xb), so = ctz64(bj & xb);
+                        const double sa = (info >> 31) ? -1.0 : 1.0;
+                        v = (sa * sign_between(bi, qo, so)) * I.g[(i64)(info & 0x7fffffffu) + (i64)so * n + qo];
+                    }
+                } else {
+                    single = popc64(ai ^ aj) + popc64(xb) == 2;
+                    if (!single) v = hij_f64(I, ai, bi, aj, bj);
+                }
             }
             if (!single && k < k1) {
                 if constexpr ((OUT & 1) != 0) v32[k] = (float)v;
@@ -580,12 +611,13 @@ __global__ void __launch_bounds__(ST_BLOCK) st_vals_kernel(SpaceView S, IntView 
                 else hi = mid - 1u;
             }
             for (; p < wend; p += ST_CPY * ST_BLOCK) {
-                u32 sidx[ST_CPY];
+                u32 sidx[ST_CPY], ej[ST_CPY];
 #pragma unroll
                 for (int j = 0; j < ST_CPY; ++j) {
                     const u32 pj = p + (u32)j * ST_BLOCK;
                     while (e + 1 < nr && rx[e + 1] <= pj) ++e;
                     sidx[j] = rsrc[e] + (pj - rx[e]);
+                    ej[j] = e;
                 }
                 u64 v[ST_CPY];
 #pragma unroll
@@ -593,23 +625,32 @@ __global__ void __launch_bounds__(ST_BLOCK) st_vals_kernel(SpaceView S, IntView 
 #pragma unroll
                 for (int j = 0; j < ST_CPY; ++j) {
                     const u32 pj = p + (u32)j * ST_BLOCK;
-                    if (pj < wend) sbeta[pj - wstart] = v[j];
+                    if (pj < wend) sbeta[pj - wstart] = pk ? v[j] | ((u64)ej[j] << 48) : v[j];
                 }
             }
         }
         __syncthreads();
         for (u32 i = r0 + wave; i < r1; i += ST_WAVES) {
             const i64 slot = T.rsb[i] + g;
-            segment(S.beta[i], T.sstart[slot], T.segcnt[slot], [&](u32 col, u64& aj, u64& bj) {
-                const u32 P = wstart + col;
-                u32 lo = 0, hi = nr - 1u;  // last range starting at or before P
-                while (lo < hi) {
-                    const u32 mid = (lo + hi + 1u) >> 1;
-                    if (rx[mid] <= P) lo = mid;
-                    else hi = mid - 1u;
+            segment(S.beta[i], T.sstart[slot], T.segcnt[slot], [&](u32 col, u64& aj, u64& bj, u32& info) {
+                const u64 w = sbeta[col];
+                u32 lo;
+                if (pk) {
+                    lo = (u32)(w >> 48);
+                    bj = w & LOW48;
+                } else {
+                    const u32 P = wstart + col;
+                    u32 hi = nr - 1u;  // last range starting at or before P
+                    lo = 0;
+                    while (lo < hi) {
+                        const u32 mid = (lo + hi + 1u) >> 1;
+                        if (rx[mid] <= P) lo = mid;
+                        else hi = mid - 1u;
+                    }
+                    bj = w;
                 }
                 aj = ralpha[lo];
-                bj = sbeta[col];
+                info = rinfo[lo];
             });
         }
     }
@@ -617,9 +658,10 @@ __global__ void __launch_bounds__(ST_BLOCK) st_vals_kernel(SpaceView S, IntView 
         const u64 bi = S.beta[i];
         const i64 slot = T.rsb[i] + ns - 1u;
         const u64* __restrict__ ga = S.alpha_b + S.boff[S.ib[i]];
-        segment(bi, T.sstart[slot], T.segcnt[slot], [&](u32 col, u64& aj, u64& bj) {
+        segment(bi, T.sstart[slot], T.segcnt[slot], [&](u32 col, u64& aj, u64& bj, u32& info) {
             aj = ga[col];
             bj = bi;
+            info = ST_NO_LINK;
         });
     }
     if (q.n) flush();
@@ -914,7 +956,9 @@ void launch_spmv(hci_ctx_s* ctx, Space* sp, const char* name, const char* gname,
 size_t ab_lds(const Space& sp) { return (size_t)6 * sp.st_abW * sp.st_abG; }
 
 size_t vals_lds(const hci_ctx_s* ctx, u32 wlog) {
-    return (sizeof(u64) << wlog) + 2 * st_range_lds(ctx);
+    // window of beta strings, then 20 B per range (alpha string, stage start,
+    // first row, link info)
+    return (sizeof(u64) << wlog) + st_range_lds(ctx) / 8 * 20;
 }
 
 }  // namespace

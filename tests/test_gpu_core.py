@@ -277,6 +277,9 @@ def _layout_space(name):
     if name == "n12":
         h, g = hs.make_integrals(12, 36, 12)
         return 12, 6, 5, h, g, hs.random_dets(12, 6, 5, 3000, seed=12, bias=0.15)
+    if name == "n52":
+        h, g = hs.make_integrals(52, 60, 52)
+        return 52, 3, 3, h, g, hs.random_dets(52, 3, 3, 2000, seed=52, bias=0.3)
     # (10e,10o) full space: stage lists of 6552 entries, more than 63
     # windows of 64, so the staged layout declines and plain CSR is used
     h, g = hs.make_integrals(10, 30, 10)
@@ -284,11 +287,14 @@ def _layout_space(name):
 
 
 @pytest.mark.parametrize("space,wlog", [("cas8", 0), ("cas8", 6), ("cas8", 8), ("cas8", 13),
-                                        ("n12", 0), ("n12", 6), ("n12", 13), ("fci10", 6)])
+                                        ("n12", 0), ("n12", 6), ("n12", 13), ("fci10", 6),
+                                        ("n52", 6), ("n52", 13)])
 def test_stored_layouts(lib_mod, space, wlog):
     """Plain CSR (window 0) and the alpha-bucket-staged layout at several
     window sizes (2^6 splits the stage lists into many windows) give the
-    oracle's products in both precisions and the oracle's pair count."""
+    oracle's products in both precisions and the oracle's pair count.  n52
+    (52 orbitals) takes the element pass's search for the stage range of a
+    position (beta strings wider than 48 bits leave no room for its index)."""
     n, na, nb, h, g, V = _layout_space(space)
     c = hs.random_coeffs(len(V), 31)
     ref = O.sigma(h, g, V, c)
