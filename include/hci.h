@@ -119,7 +119,11 @@ int hci_ctx_update_integrals(hci_ctx ctx, const double* h, const double* g, doub
 int hci_ctx_destroy(hci_ctx ctx);
 
 /* Release the cached structure of the last determinant list (buckets,
- * adjacency, stored Hamiltonian).  The next call on any list rebuilds it. */
+ * adjacency, stored Hamiltonian, a selection result kept for a capacity
+ * retry).  The next call on any list rebuilds it.  Two small pinned host
+ * buffers the context allocates on first use (the Davidson iteration's
+ * scalars, the density-matrix planner's staging) stay until
+ * hci_ctx_destroy. */
 int hci_ctx_release_cache(hci_ctx ctx);
 
 /* Memory budget (bytes) for the stored Hamiltonian in HCI_SIGMA_AUTO mode
@@ -253,7 +257,10 @@ int hci_diagonal(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* hdiag
  *   best iterate).  The start vector is used as given: one confined to a
  *   symmetry sector of H (see hci_davidson_roots) gives the lowest state of
  *   that sector, as a warm start from the previous state of the same
- *   symmetry intends.  Synchronises the stream. */
+ *   symmetry intends.  Each iteration's convergence scalars reach the host
+ *   through pinned memory the context owns (the host polls them), so one
+ *   context must not run two Davidson solves at once.  Synchronises the
+ *   stream. */
 int hci_davidson(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* c_inout,
                  double* e_out, double tol, int max_iter, int precision, int mode,
                  int* iters_out, void* stream);

@@ -247,33 +247,44 @@ __device__ __forceinline__ double rc_row(const RcInts<VT>& T, const RcLds<VT>& L
         }
 #pragma unroll
         for (u32 u = 0; u < RC_UNROLL; ++u) {
-            const u32 k = k0 + u * HCI_WAVE + lane;
-            const bool in_own = k < own;
-            const bool sgl = in_own && d[u] == 2;
-            const bool dbl = in_own && d[u] == 4;
-            const bool crs = !in_own && d[u] == 2;
-            const u64 ms = ballot(sgl), md = ballot(dbl), mx = ballot(crs);
-            if (sgl) qs[ns + rank_in(ms)] = (u16)k;
-            if (dbl) qd[nd + rank_in(md)] = (u16)k;
-            if (crs) qx[nx + rank_in(mx)] = (u16)k;
-            ns += (u32)popc64(ms);
-            nd += (u32)popc64(md);
-            nx += (u32)popc64(mx);
+            const u32 kb = k0 + u * HCI_WAVE;  // wave-uniform
+            const u32 k = kb + lane;
+            // a step wholly past the chunk's own bucket can only hold alpha x
+            // beta hits, one wholly inside it only singles and doubles
+            const bool any_own = kb < own, all_own = kb + HCI_WAVE <= own;
+            if (!all_own) {
+                const bool crs = k >= own && d[u] == 2;
+                const u64 mx = ballot(crs);
+                if (crs) qx[nx + rank_in(mx)] = (u16)k;
+                nx += (u32)popc64(mx);
+            }
+            if (any_own) {
+                const bool in_own = k < own;
+                const bool sgl = in_own && d[u] == 2;
+                const bool dbl = in_own && d[u] == 4;
+                const u64 ms = ballot(sgl), md = ballot(dbl);
+                if (sgl) qs[ns + rank_in(ms)] = (u16)k;
+                if (dbl) qd[nd + rank_in(md)] = (u16)k;
+                ns += (u32)popc64(ms);
+                nd += (u32)popc64(md);
+            }
             __builtin_amdgcn_wave_barrier();
             if (nx >= HCI_WAVE) {
                 rc_flush_x<VT>(T, L, qx, HCI_WAVE, X, acc);
                 rc_shift(qx, nx);
                 nx -= HCI_WAVE;
             }
-            if (nd >= HCI_WAVE) {
-                rc_flush_d<VT>(T, L, qd, HCI_WAVE, X, acc);
-                rc_shift(qd, nd);
-                nd -= HCI_WAVE;
-            }
-            if (ns >= HCI_WAVE) {
-                rc_flush_s<VT>(T, L, qs, HCI_WAVE, X, acc);
-                rc_shift(qs, ns);
-                ns -= HCI_WAVE;
+            if (any_own) {
+                if (nd >= HCI_WAVE) {
+                    rc_flush_d<VT>(T, L, qd, HCI_WAVE, X, acc);
+                    rc_shift(qd, nd);
+                    nd -= HCI_WAVE;
+                }
+                if (ns >= HCI_WAVE) {
+                    rc_flush_s<VT>(T, L, qs, HCI_WAVE, X, acc);
+                    rc_shift(qs, ns);
+                    ns -= HCI_WAVE;
+                }
             }
         }
     }
