@@ -258,9 +258,10 @@ int hci_diagonal(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* hdiag
  *   symmetry sector of H (see hci_davidson_roots) gives the lowest state of
  *   that sector, as a warm start from the previous state of the same
  *   symmetry intends.  Each iteration's convergence scalars reach the host
- *   through pinned memory the context owns (the host polls them), so one
- *   context must not run two Davidson solves at once.  Synchronises the
- *   stream. */
+ *   through pinned memory the context owns (the host polls them for up to
+ *   HCI_DAVIDSON_POLL_MS milliseconds, default 200, then waits on the
+ *   stream), so one context must not run two Davidson solves at once.
+ *   Synchronises the stream. */
 int hci_davidson(hci_ctx ctx, const uint64_t* dets, int64_t n_var, double* c_inout,
                  double* e_out, double tol, int max_iter, int precision, int mode,
                  int* iters_out, void* stream);

@@ -25,6 +25,7 @@
 #include <atomic>
 #include <cfloat>
 #include <chrono>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -605,18 +606,20 @@ struct Workspace {
 };
 
 // The four scalars {|r|^2, |t|^2, dead, theta} of the iteration whose
-// reduction was given sequence number seq: poll the pinned words, and after
-// 0.2 s (a long product ahead of them) wait on the stream instead.
-void wait_host_scalars(hci_ctx_s* ctx, unsigned long long seq, hipStream_t s, double* hv) {
+// reduction was given sequence number seq: poll the pinned words for up to
+// poll_ms (a long product ahead of them), then wait on the stream instead.
+void wait_host_scalars(hci_ctx_s* ctx, unsigned long long seq, hipStream_t s, double* hv, int poll_ms) {
     const volatile unsigned long long* flag =
         reinterpret_cast<const volatile unsigned long long*>(ctx->host_scal + 4);
-    const auto t0 = std::chrono::steady_clock::now();
-    for (unsigned spins = 1; *flag != seq; ++spins) {
-        if ((spins & 1023u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(200)) {
-            HIP_CHECK(hipStreamSynchronize(s));
-            HCI_REQUIRE(*flag == seq, HCI_E_HIP, "internal: Davidson scalars were not written");
-            break;
-        }
+    if (*flag != seq && poll_ms > 0) {
+        const auto t0 = std::chrono::steady_clock::now();
+        for (unsigned spins = 1; *flag != seq; ++spins)
+            if ((spins & 1023u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(poll_ms))
+                break;
+    }
+    if (*flag != seq) {
+        HIP_CHECK(hipStreamSynchronize(s));
+        HCI_REQUIRE(*flag == seq, HCI_E_HIP, "internal: Davidson scalars were not written");
     }
     std::atomic_thread_fence(std::memory_order_acquire);
     const volatile double* h = ctx->host_scal;
@@ -656,6 +659,10 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
     double* theta_h = sc + DV_MAXK + 4;  // rr, nrm_t, dead, theta: read back together
     HIP_CHECK(hipMemsetAsync(dead, 0, sizeof(double), s));
     const i64 g1 = ceil_div(N, 256);
+    // how long the host polls for an iteration's scalars before it waits on
+    // the stream (HCI_DAVIDSON_POLL_MS, default 200; 0 always waits)
+    const char* poll_env = std::getenv("HCI_DAVIDSON_POLL_MS");
+    const int poll_ms = poll_env ? std::max(0, std::atoi(poll_env)) : 200;
     if (!ctx->host_scal) {
         void* hp = nullptr;
         HIP_CHECK(hipHostMalloc(&hp, 8 * sizeof(double), hipHostMallocCoherent));
@@ -740,7 +747,7 @@ int davidson_run(hci_ctx_s* ctx, Space* sp, double* c, double* e_out, double tol
             ws.reduce(kd + 1, sc, 1, ritz.as<double>(), theta_h, rr, ctx->host_scal, seq);
             have_prev = true;
             double hv[4];
-            wait_host_scalars(ctx, seq, s, hv);
+            wait_host_scalars(ctx, seq, s, hv, poll_ms);
             rnorm = sqrt(std::max(hv[0], 0.0));
             const bool was_dead = hv[2] != 0.0;  // the newest direction had no norm
             theta = hv[3];

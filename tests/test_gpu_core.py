@@ -82,6 +82,23 @@ def test_davidson_cas8(cas8, precision):
     assert abs(abs(c @ cas8["c"]) - 1.0) < 1e-10
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_davidson_scalars_by_stream_wait(cas8, monkeypatch, precision):
+    """Each iteration's convergence scalars reach the host through pinned
+    memory that the host polls; after the poll time (HCI_DAVIDSON_POLL_MS,
+    0 here) it waits on the stream instead.  Both ways give the oracle's
+    eigenpair and the same bytes."""
+    ctx, sp = cas8["ctx"], cas8["sp"]
+    e1, c1, it1 = ctx.davidson(sp, None, tol=1e-10, precision=precision)
+    monkeypatch.setenv("HCI_DAVIDSON_POLL_MS", "0")
+    e2, c2, it2 = ctx.davidson(sp, None, tol=1e-10, precision=precision)
+    monkeypatch.delenv("HCI_DAVIDSON_POLL_MS", raising=False)
+    print(f"[davidson wait {precision}] products {it1} / {it2}", flush=True)
+    assert abs(e2 - cas8["e"]) < 1e-8
+    assert e1 == e2 and it1 == it2
+    assert torch.equal(c1, c2)
+
+
 @pytest.mark.parametrize("n,na,nb,m,seed", [(8, 4, 4, 300, 1), (10, 3, 5, 700, 2), (12, 6, 6, 1500, 3),
                                            (7, 2, 0, 9, 4), (14, 7, 6, 64, 5)])
 @pytest.mark.parametrize("eps", [0.0, 1e-4, 1e-2])
