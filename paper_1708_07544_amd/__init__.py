@@ -382,7 +382,7 @@ class HCIContext:
                                            _lib._stream()))
         return float(e2.value), float(err.value), float(e2d.value)
 
-    # ---------------------------------------------------------------- driver
+    # ------------------------------------------------------------ HCI loop
     def hci(self, eps1: float, max_macro: int = 20, tol: float = 1e-8, precision="fp64",
             mode="auto", dets0=None, log=None, nroots: int = 1):
         """HCI variational stage: V0 = aufbau (or dets0), then repeatedly
